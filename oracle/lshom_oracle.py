@@ -1,0 +1,466 @@
+"""Plain FP64 CPU reference for the FFT-accelerated CG homogenisation solver.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute this module: it exists so that the tests, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` can check the HIP library against
+an implementation that is slow, obviously correct and independent of it.  It
+shares no code with the GPU path.
+
+The method is Zeman, Vondrejc, Novak, Marek, "Accelerating a FFT-based solver
+for numerical homogenization of periodic media by conjugate gradients"
+(J. Comput. Phys., 2010).  Every function below names the passage it follows.
+
+Conventions (documented readings of the paper, see also the repository notes):
+
+* A field with ``d`` components on an ``N_1 x ... x N_d`` grid is an array of
+  shape ``(d, N_1, ..., N_d)``; array index ``j`` sits at coordinate
+  ``x = j / N`` of the unit cell (a cyclic shift of the paper's centred node
+  numbering, Sec. 2.2, Eq. (10)).
+* Phases are isotropic, ``L(x) = lambda(x) I`` and ``L0 = l0 I`` (Sec. 3).
+* The DFT is unnormalised forward, ``1/|N|`` inverse.  The ``|Y|^{-1/2}`` and
+  ``|Y|^{1/2}`` factors of the Vandermonde matrices (Sec. 2.2, Eqs. (13)-(14))
+  cancel inside the operator ``B`` of Eq. (16).
+* Integer frequencies ``k`` of the set ``Z^N`` (Sec. 2.2, Eq. (9)) are exact
+  for a cubic cell.  For even ``N_alpha`` the Green operator is set to zero on
+  every mode with ``k_alpha = N_alpha / 2`` (the paper only uses odd grids;
+  this reading keeps the discrete operator real).
+* CG is the unpreconditioned Hestenes-Stiefel method cited in Sec. 3 as
+  Saad's Algorithm 6.18, with Euclidean inner products over all ``d |N|``
+  entries and ``x0 = e0``.  It stops when ``||r_m||_2 <= tol ||e0||_2`` (the
+  relative residual; the paper's ``eta_r`` of Eq. (22) is reported beside it).
+* The homogenised conductivity is ``L_eff E = <lambda e>``, the cell average
+  of the current ``j = L e`` of Sec. 2.1, Eq. (1); the full tensor comes from
+  ``d`` load cases.
+
+Parity pins: every function here is checked by the ``not gpu`` tests against
+values fixed by the mathematics (explicit Vandermonde matrices, a dense direct
+solve, closed-form laminates, bounds, duality, an independent fixed-point
+solver).  See ``tests/test_oracle_pins.py``.
+"""
+
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+try:  # scipy.fft keeps float32 in single precision and can use threads
+    import scipy.fft as _sfft
+except Exception:  # pragma: no cover - scipy is present in this image
+    _sfft = None
+
+__all__ = [
+    "frequencies",
+    "grid_frequencies",
+    "green_hat",
+    "apply_B",
+    "apply_A",
+    "cg",
+    "ffth",
+    "dense_operator",
+    "dense_solve",
+    "leff",
+    "homogenize",
+    "eta_r",
+    "eta_e",
+    "project_gradient",
+    "optimal_reference",
+    "reference_omega",
+    "voigt_reuss",
+    "cg_rate_bound_iterations",
+]
+
+_WORKERS = int(os.environ.get("LSHOM_ORACLE_WORKERS", os.cpu_count() or 1))
+
+
+def _fftn(a, axes):
+    if _sfft is not None:
+        return _sfft.fftn(a, axes=axes, workers=_WORKERS)
+    return np.fft.fftn(a, axes=axes)
+
+
+def _ifftn(a, axes):
+    if _sfft is not None:
+        return _sfft.ifftn(a, axes=axes, workers=_WORKERS)
+    return np.fft.ifftn(a, axes=axes)
+
+
+# ---------------------------------------------------------------------------
+# Frequencies and the Green operator (Sec. 2.1, Eq. (7); Sec. 2.2, Eq. (9))
+# ---------------------------------------------------------------------------
+
+def frequencies(n: int) -> np.ndarray:
+    """Integer frequencies of one axis, in DFT index order.
+
+    The set ``Z^N = {k : -N/2 < k <= N/2}`` (Sec. 2.2, Eq. (9)); DFT index
+    ``m`` carries frequency ``m`` if ``m <= N/2`` and ``m - N`` otherwise.
+    """
+    m = np.arange(n)
+    return np.where(m <= n // 2, m, m - n).astype(np.float64)
+
+
+def grid_frequencies(shape):
+    """Per-axis integer frequency arrays broadcast over the grid ``shape``."""
+    d = len(shape)
+    out = []
+    for a, n in enumerate(shape):
+        k = frequencies(n)
+        view = [1] * d
+        view[a] = n
+        out.append(np.broadcast_to(k.reshape(view), shape))
+    return out
+
+
+def _nyquist_mask(shape):
+    """True on modes kept by the Green operator (all but k_alpha = N_alpha/2)."""
+    keep = np.ones(shape, dtype=bool)
+    for a, n in enumerate(shape):
+        if n % 2 == 0:
+            idx = [slice(None)] * len(shape)
+            idx[a] = n // 2
+            keep[tuple(idx)] = False
+    return keep
+
+
+def _green_factors(shape, l0):
+    """Integer frequencies and ``1 / (k . L0 . k)`` (zero where Gamma0 is 0)."""
+    ks = grid_frequencies(shape)
+    k2 = sum(k * k for k in ks)
+    keep = _nyquist_mask(shape) & (k2 > 0)
+    inv = np.zeros(shape)
+    inv[keep] = 1.0 / (l0 * k2[keep])
+    return ks, inv
+
+
+def green_hat(shape, l0: float) -> np.ndarray:
+    """Blocks of the reference Green operator on the DFT grid.
+
+    ``G[alpha, beta][k] = k_alpha k_beta / (k . L0 . k)`` for ``k != 0`` and
+    ``0`` at ``k = 0`` (Sec. 2.1, Eq. (7)), with ``L0 = l0 I``.  Returns an
+    array of shape ``(d, d, *shape)``.
+    """
+    ks = grid_frequencies(shape)
+    d = len(shape)
+    k2 = sum(k * k for k in ks)
+    keep = _nyquist_mask(shape) & (k2 > 0)
+    inv = np.zeros(shape)
+    inv[keep] = 1.0 / (l0 * k2[keep])
+    g = np.empty((d, d) + tuple(shape))
+    for a in range(d):
+        for b in range(d):
+            g[a, b] = ks[a] * ks[b] * inv
+    return g
+
+
+# ---------------------------------------------------------------------------
+# The operator of the collocation system (Sec. 2.2, Eqs. (15)-(17))
+# ---------------------------------------------------------------------------
+
+def apply_B(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+    """``B p = F^{-1} Gamma0_hat F (dL p)`` with ``dL = lambda - l0``.
+
+    Sec. 2.2, Eq. (16): polarisation by the diagonal blocks ``dL`` (Eq. (3)
+    and Eq. (17)), forward DFT of each component, the block-diagonal Green
+    operator of Eq. (7), inverse DFT.  The result is real for real input.
+    """
+    shape = lam.shape
+    d = len(shape)
+    axes = tuple(range(1, d + 1))
+    tau = (lam - l0)[None, ...] * p
+    tau_hat = _fftn(tau, axes)
+    ks, inv = _green_factors(shape, l0)
+    w_hat = np.zeros_like(tau_hat)
+    for a in range(d):
+        for b in range(d):
+            # block (a, b) of Eq. (16): diagonal Gamma0_hat_ab times tau_hat_b
+            w_hat[a] += (ks[a] * ks[b] * inv) * tau_hat[b]
+    return _ifftn(w_hat, axes).real
+
+
+def apply_A(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+    """``(I + B) p``, the left-hand side of the collocation system, Eq. (15)."""
+    return p + apply_B(p, lam, l0)
+
+
+def _dot(u, v) -> float:
+    return float(np.dot(u.ravel(), v.ravel()))
+
+
+def _rhs(E, shape):
+    E = np.asarray(E, dtype=np.float64)
+    d = len(shape)
+    if E.shape != (d,):
+        raise ValueError(f"E must have {d} components")
+    return np.broadcast_to(E.reshape((d,) + (1,) * d), (d,) + tuple(shape)).copy()
+
+
+def optimal_reference(lam: np.ndarray) -> float:
+    """``l0 = (lambda_min + lambda_max) / 2``, Sec. 2.3, Eq. (19)."""
+    return 0.5 * (float(lam.min()) + float(lam.max()))
+
+
+def reference_omega(omega: float, rho: float) -> float:
+    """``l0(omega) = 1 - omega + rho omega``, Sec. 3, Eq. (20)."""
+    return 1.0 - omega + rho * omega
+
+
+# ---------------------------------------------------------------------------
+# Conjugate gradients (Sec. 2.3 and Sec. 3: Saad, Algorithm 6.18)
+# ---------------------------------------------------------------------------
+
+def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
+       history=False, apply=None):
+    """Solve ``(I + B) e = e0`` by Hestenes-Stiefel CG.
+
+    Follows the CG method the paper applies to the collocation system
+    (Sec. 2.3; Sec. 3 names it Saad's Algorithm 6.18):
+
+    ``r0 = b - A x0``, ``p0 = r0``; per iteration ``q = A p``,
+    ``alpha = (r, r) / (p, q)``, ``x += alpha p``, ``r -= alpha q``,
+    ``beta = (r_new, r_new) / (r, r)``, ``p = r + beta p``.
+
+    The test ``||r|| <= tol ||b||`` is made before each iteration, so the
+    returned iteration count is the number of operator applies in the loop.
+    ``n_iter`` forces exactly that many iterations (used to compare with the
+    GPU at an equal iteration count).  ``x0`` defaults to ``b``.
+
+    Returns a dict with the field ``e``, ``iterations``, ``rel_res`` (the
+    recursive residual), ``converged``, ``breakdown`` and optionally the
+    residual ``history``.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    shape = lam.shape
+    A = apply if apply is not None else (lambda v: apply_A(v, lam, l0))
+    b = _rhs(E, shape)
+    bnorm = math.sqrt(_dot(b, b))
+    if bnorm == 0.0:
+        return dict(e=np.zeros_like(b), iterations=0, rel_res=0.0,
+                    converged=True, breakdown=False, r=np.zeros_like(b),
+                    history=[0.0])
+    x = b.copy() if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    r = b - A(x)
+    p = r.copy()
+    rr = _dot(r, r)
+    hist = [math.sqrt(rr) / bnorm]
+    m = 0
+    limit = max_iter if n_iter is None else n_iter
+    converged = False
+    breakdown = False
+    while True:
+        if n_iter is None and math.sqrt(rr) <= tol * bnorm:
+            converged = True
+            break
+        if m >= limit:
+            break
+        q = A(p)
+        pq = _dot(p, q)
+        if not (pq > 0.0) or not math.isfinite(pq):
+            breakdown = True
+            break
+        alpha = rr / pq
+        x += alpha * p
+        r -= alpha * q
+        rr_new = _dot(r, r)
+        beta = rr_new / rr
+        p = r + beta * p
+        rr = rr_new
+        m += 1
+        hist.append(math.sqrt(rr) / bnorm)
+    if n_iter is not None:
+        converged = math.sqrt(rr) <= tol * bnorm
+    out = dict(e=x, iterations=m, rel_res=math.sqrt(rr) / bnorm,
+               converged=converged, breakdown=breakdown, r=r)
+    if history:
+        out["history"] = hist
+    return out
+
+
+def true_residual(lam, l0, E, e) -> float:
+    """``||b - (I + B) e|| / ||b||`` evaluated afresh (Eq. (15))."""
+    b = _rhs(E, lam.shape)
+    bn = math.sqrt(_dot(b, b))
+    res = b - apply_A(e, lam, l0)
+    return math.sqrt(_dot(res, res)) / bn if bn > 0 else 0.0
+
+
+# ---------------------------------------------------------------------------
+# The basic Moulinec-Suquet scheme (Sec. 2.3, Eq. (18))
+# ---------------------------------------------------------------------------
+
+def ffth(lam, l0, E, tol=1e-8, max_iter=100000):
+    """Neumann-series iterate ``e^(m) = sum_{j<=m} (-B)^j e0``.
+
+    Sec. 2.3, Eq. (18), evaluated as ``e^(m+1) = e0 - B e^(m)``.  Stops when
+    ``||e^(m+1) - e^(m)|| <= tol ||e0||`` (``eta_r / l0`` of Eq. (22)).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    b = _rhs(E, lam.shape)
+    bnorm = math.sqrt(_dot(b, b))
+    e = b.copy()
+    for m in range(1, max_iter + 1):
+        e_new = b - apply_B(e, lam, l0)
+        diff = e_new - e
+        e = e_new
+        if math.sqrt(_dot(diff, diff)) <= tol * bnorm:
+            return dict(e=e, iterations=m, converged=True)
+    return dict(e=e, iterations=max_iter, converged=False)
+
+
+# ---------------------------------------------------------------------------
+# Dense matrices of the collocation system (Sec. 2.2, Eqs. (13)-(17))
+# ---------------------------------------------------------------------------
+
+def _centred_indices(n):
+    """The centred index set ``Z^N`` of one axis (Sec. 2.2, Eq. (9))."""
+    return np.array([k for k in range(-(n // 2), n // 2 + 1)
+                     if -n / 2 < k <= n / 2], dtype=np.int64)
+
+
+def dense_operator(lam, l0, cell_measure=1.0):
+    """The matrix ``I + B`` built entry by entry from Sec. 2.2.
+
+    Nodes and frequencies are both numbered by the centred set ``Z^N``
+    (Eq. (9)) exactly as in the paper; ``F`` and ``F^{-1}`` are the
+    Vandermonde matrices of Eqs. (13)-(14) including the ``|Y|`` factors,
+    ``Gamma0_hat`` and ``dL`` are the diagonal blocks of Eq. (17), and ``B``
+    is the product of Eq. (16).  Only for tiny grids.
+
+    Returns ``(M, order)`` where ``M`` acts on vectors stacked as
+    ``[component][node]`` with nodes in the centred order, and ``order`` maps
+    each centred node to its flat array index (``j = k mod N``).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    shape = lam.shape
+    d = len(shape)
+    idx = [_centred_indices(n) for n in shape]
+    grids = np.meshgrid(*idx, indexing="ij")
+    K = np.stack([g.ravel() for g in grids], axis=1)  # (|N|, d) centred ints
+    nn = K.shape[0]
+    Nvec = np.array(shape, dtype=np.float64)
+    phase = -2j * np.pi * ((K[:, None, :] * K[None, :, :]) / Nvec).sum(axis=2)
+    F = cell_measure ** -0.5 * np.exp(phase)
+    Finv = cell_measure ** 0.5 / nn * np.exp(-phase)
+    flat = np.ravel_multi_index(tuple((K % np.array(shape)).T), shape)
+    dl = lam.ravel()[flat] - l0
+    k2 = (K.astype(np.float64) ** 2).sum(axis=1)
+    keep = k2 > 0
+    for a, n in enumerate(shape):
+        if n % 2 == 0:
+            keep &= K[:, a] != n // 2
+    B = np.zeros((d * nn, d * nn), dtype=np.complex128)
+    FD = F * dl[None, :]
+    for a in range(d):
+        for b in range(d):
+            gdiag = np.where(keep, K[:, a] * K[:, b] / (l0 * np.where(keep, k2, 1.0)), 0.0)
+            B[a * nn:(a + 1) * nn, b * nn:(b + 1) * nn] = Finv @ (gdiag[:, None] * FD)
+    M = np.eye(d * nn) + B
+    return M, flat
+
+
+def dense_solve(lam, l0, E, cell_measure=1.0):
+    """Direct solution of Eq. (15) with the dense matrix of ``dense_operator``."""
+    lam = np.asarray(lam, dtype=np.float64)
+    shape = lam.shape
+    d = len(shape)
+    M, flat = dense_operator(lam, l0, cell_measure)
+    nn = flat.size
+    rhs = np.concatenate([np.full(nn, float(E[a])) for a in range(d)]).astype(np.complex128)
+    sol = np.linalg.solve(M, rhs)
+    e = np.zeros((d, lam.size))
+    for a in range(d):
+        e[a, flat] = sol[a * nn:(a + 1) * nn].real
+    return e.reshape((d,) + shape), float(np.abs(sol.imag).max())
+
+
+# ---------------------------------------------------------------------------
+# Outputs and norms
+# ---------------------------------------------------------------------------
+
+def leff(lam, e) -> np.ndarray:
+    """``L_eff E = <lambda e>``: cell average of the current ``j = L e``.
+
+    Sec. 2.1, Eqs. (1)-(2): ``j = L e`` with ``<e> = e0``; the macroscopic
+    current is the average of ``j``.  Returns ``d`` numbers (one column of the
+    effective tensor for the load case that produced ``e``).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    d = lam.ndim
+    return np.array([float(np.mean(lam * e[a])) for a in range(d)])
+
+
+def homogenize(lam, l0=None, tol=1e-10, max_iter=10000):
+    """Full effective tensor from the ``d`` load cases ``E = e_beta``."""
+    lam = np.asarray(lam, dtype=np.float64)
+    d = lam.ndim
+    l0 = optimal_reference(lam) if l0 is None else l0
+    L = np.zeros((d, d))
+    iters = []
+    for b in range(d):
+        E = np.zeros(d)
+        E[b] = 1.0
+        res = cg(lam, l0, E, tol=tol, max_iter=max_iter)
+        L[:, b] = leff(lam, res["e"])
+        iters.append(res["iterations"])
+    return L, iters
+
+
+def eta_r(r, l0, E, shape) -> float:
+    """Residual norm ``l0 ||r|| / ||e0||`` (Sec. 3, Eq. (22))."""
+    b = _rhs(E, shape)
+    return l0 * math.sqrt(_dot(r, r)) / math.sqrt(_dot(b, b))
+
+
+def eta_e(lam, e) -> float:
+    """Equilibrium norm of Sec. 3, Eq. (21).
+
+    ``eta_e^2 = sum_k |k . j_hat(k)|^2 / |j_hat(0)|^2`` with ``j = lambda e``
+    and integer frequencies; the ratio does not depend on DFT scaling.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    d = lam.ndim
+    axes = tuple(range(1, d + 1))
+    j_hat = _fftn(lam[None, ...] * e, axes)
+    ks = grid_frequencies(lam.shape)
+    div = sum(ks[a] * j_hat[a] for a in range(d))
+    num = float(np.sum(np.abs(div) ** 2))
+    zero = (0,) * d
+    den = float(sum(abs(j_hat[a][zero]) ** 2 for a in range(d)))
+    return math.sqrt(num / den)
+
+
+def project_gradient(v: np.ndarray) -> np.ndarray:
+    """Orthogonal projection onto zero-mean curl-free grid fields.
+
+    ``P v = F^{-1}[ k (k . v_hat) / |k|^2 ]`` with ``P v_hat(0) = 0``: the
+    Green operator of Eq. (7) with ``L0 = I``.  Used to make a warm start
+    admissible, ``x0 = E + P(x_pred)``.
+    """
+    shape = v.shape[1:]
+    d = len(shape)
+    axes = tuple(range(1, d + 1))
+    ks, inv = _green_factors(shape, 1.0)
+    v_hat = _fftn(v, axes)
+    s = sum(ks[b] * v_hat[b] for b in range(d)) * inv
+    w_hat = np.stack([ks[a] * s for a in range(d)])
+    return _ifftn(w_hat, axes).real
+
+
+def voigt_reuss(lam):
+    """Arithmetic (Voigt) and harmonic (Reuss) means of the nodal values."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return float(np.mean(lam)), float(1.0 / np.mean(1.0 / lam))
+
+
+def cg_rate_bound_iterations(rho: float, tol: float) -> int:
+    """Iteration bound from the CG rate of Sec. 3.2, Eq. (23).
+
+    ``||r_m|| <= 2 sqrt(kappa) gamma^m ||r_0||`` with
+    ``gamma = (sqrt(rho) - 1) / (sqrt(rho) + 1)`` and ``kappa <= rho`` on the
+    subspace CG works in; returns the smallest ``m`` that guarantees
+    ``||r_m|| <= tol ||r_0||``.
+    """
+    g = (math.sqrt(rho) - 1.0) / (math.sqrt(rho) + 1.0)
+    if g <= 0.0:
+        return 1
+    return int(math.ceil(math.log(tol / (2.0 * math.sqrt(rho))) / math.log(g)))

@@ -1,0 +1,339 @@
+"""Pins of the CPU reference against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the explicit
+Vandermonde matrices of Sec. 2.2, a dense direct solve of Eq. (15), closed
+forms (homogeneous medium, laminates), variational bounds, Keller duality, an
+independent fixed-point solver (Eq. (18)) and the CG rate of Eq. (23).  The
+paper prints no worked numbers (its figures are lost), so no test compares
+with a printed value.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lshom_oracle as o
+from paper_1004_1122_amd import microstructure as ms
+
+
+def _rand_lam(shape, seed, lo=1.0, hi=30.0):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(lo, hi, size=shape)
+
+
+# ---------------------------------------------------------------------------
+# DFT conventions and the frequency set (Sec. 2.2, Eqs. (9), (12)-(14))
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 9])
+def test_frequency_set_is_ZN(n):
+    k = o.frequencies(n)
+    expected = [float(v) for v in range(-n, n + 1) if -n / 2 < v <= n / 2]
+    assert sorted(k.tolist()) == expected
+    # DFT index m and its frequency are congruent mod n
+    assert all((m - k[m]) % n == 0 for m in range(n))
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 4, 5)])
+def test_fft_matches_vandermonde(shape):
+    """The library FFT the oracle uses equals the paper's F and F^-1."""
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    nn = f.size
+    idx = np.stack(np.unravel_index(np.arange(nn), shape), axis=1)
+    ph = (idx[:, None, :] * idx[None, :, :] / np.array(shape)).sum(axis=2)
+    F = np.exp(-2j * np.pi * ph)          # Eq. (13) with |Y| = 1
+    Finv = np.exp(2j * np.pi * ph) / nn   # Eq. (14)
+    axes = tuple(range(len(shape)))
+    np.testing.assert_allclose(o._fftn(f, axes).ravel(), F @ f.ravel(), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(o._ifftn(f, axes).ravel(), Finv @ f.ravel(), rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# The operator (Sec. 2.2, Eqs. (15)-(17)) against the dense matrices
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(5, 5), (3, 7), (7, 5), (4, 6), (3, 3, 3), (5, 3, 4)])
+def test_apply_matches_dense_matrix(shape):
+    lam = _rand_lam(shape, 2)
+    l0 = 11.0
+    d = len(shape)
+    rng = np.random.default_rng(3)
+    p = rng.standard_normal((d,) + shape)
+    M, flat = o.dense_operator(lam, l0, cell_measure=2.5)
+    nn = lam.size
+    vec = np.concatenate([p[a].ravel()[flat] for a in range(d)])
+    ref = (M @ vec).real
+    assert np.abs((M @ vec).imag).max() < 1e-12
+    got = o.apply_A(p, lam, l0)
+    got_vec = np.concatenate([got[a].ravel()[flat] for a in range(d)])
+    np.testing.assert_allclose(got_vec, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    assert nn == flat.size
+
+
+def test_dense_matrix_is_nonsymmetric():
+    """Sec. 2.2: B is non-symmetric on the full space."""
+    lam = _rand_lam((5, 5), 4)
+    M, _ = o.dense_operator(lam, 15.0)
+    assert np.abs(M - M.T.conj()).max() > 1e-3
+
+
+@pytest.mark.parametrize("shape,rho", [((7, 7), 30.0), ((5, 9), 100.0), ((5, 5, 3), 10.0)])
+def test_cg_matches_dense_solve(shape, rho):
+    rng = np.random.default_rng(5)
+    lam = np.where(rng.random(shape) < 0.4, rho, 1.0)
+    l0 = o.optimal_reference(lam)
+    E = np.arange(1, len(shape) + 1, dtype=float)
+    e_dense, imag = o.dense_solve(lam, l0, E)
+    assert imag < 1e-10
+    res = o.cg(lam, l0, E, tol=1e-14, max_iter=500)
+    err = np.linalg.norm(res["e"] - e_dense) / np.linalg.norm(e_dense)
+    assert err < 1e-12, err
+
+
+# ---------------------------------------------------------------------------
+# Structure of the operator on U (zero-mean curl-free fields)
+# ---------------------------------------------------------------------------
+
+def _curl_free_residual(w):
+    shape = w.shape[1:]
+    d = len(shape)
+    axes = tuple(range(1, d + 1))
+    wh = np.fft.fftn(w, axes=axes)
+    ks = o.grid_frequencies(shape)
+    worst = 0.0
+    for a in range(d):
+        for b in range(a + 1, d):
+            worst = max(worst, float(np.abs(ks[a] * wh[b] - ks[b] * wh[a]).max()))
+    return worst / max(1.0, float(np.abs(wh).max()))
+
+
+@pytest.mark.parametrize("shape", [(9, 15), (5, 7, 9)])
+def test_B_maps_into_U(shape):
+    lam = _rand_lam(shape, 6)
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal((len(shape),) + shape)
+    w = o.apply_B(p, lam, 9.0)
+    assert np.abs(w.reshape(len(shape), -1).mean(axis=1)).max() < 1e-13
+    assert _curl_free_residual(w) < 1e-12
+
+
+def test_A_symmetric_on_U():
+    shape = (11, 9)
+    lam = _rand_lam(shape, 8)
+    rng = np.random.default_rng(9)
+    u = o.project_gradient(rng.standard_normal((2,) + shape))
+    v = o.project_gradient(rng.standard_normal((2,) + shape))
+    au = o.apply_A(u, lam, 7.0)
+    av = o.apply_A(v, lam, 7.0)
+    assert abs(np.vdot(au, v) - np.vdot(u, av)) < 1e-12 * abs(np.vdot(au, v))
+
+
+def test_projection_properties():
+    shape = (9, 7, 5)
+    rng = np.random.default_rng(10)
+    v = rng.standard_normal((3,) + shape)
+    pv = o.project_gradient(v)
+    np.testing.assert_allclose(o.project_gradient(pv), pv, atol=1e-13)
+    assert _curl_free_residual(pv) < 1e-12
+    const = np.ones((3,) + shape) * np.array([1.0, -2.0, 0.5])[:, None, None, None]
+    assert np.abs(o.project_gradient(const)).max() < 1e-14
+    # a gradient of a smooth periodic potential is left unchanged
+    x = np.arange(9) / 9
+    phi_x = np.cos(2 * np.pi * x)
+    g = np.zeros((3,) + shape)
+    g[0] = (-2 * np.pi * np.sin(2 * np.pi * x))[:, None, None]
+    np.testing.assert_allclose(o.project_gradient(g), g, atol=1e-12)
+    assert phi_x.shape == (9,)
+
+
+def test_true_residual_identity():
+    """At x in E + U, l0 (b - A x) = -P(lambda x): eta_r is l0-invariant."""
+    ms_ = ms.square_inclusion()
+    lam = ms_.lam()
+    E = np.array([1.0, 0.0])
+    for l0 in (2.0, 5.5, 20.0):
+        res = o.cg(lam, l0, E, n_iter=6)
+        x = res["e"]
+        b = np.broadcast_to(E[:, None, None], x.shape)
+        lhs = l0 * (b - o.apply_A(x, lam, l0))
+        rhs = -o.project_gradient(lam[None] * x)
+        # both sides are differences of O(l0 * lambda) terms: absolute rounding
+        np.testing.assert_allclose(lhs, rhs, rtol=0, atol=1e-13 * l0 * lam.max())
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(15, 21), (7, 9, 5)])
+def test_homogeneous_medium(shape):
+    lam = np.full(shape, 3.7)
+    d = len(shape)
+    E = np.linspace(1.0, 2.0, d)
+    res = o.cg(lam, 2.0, E, tol=1e-12)
+    assert res["iterations"] == 0
+    assert np.abs(res["e"] - E.reshape((d,) + (1,) * d)).max() == 0.0
+    # from a random admissible start: exactly one iteration
+    rng = np.random.default_rng(11)
+    x0 = E.reshape((d,) + (1,) * d) + o.project_gradient(rng.standard_normal((d,) + shape))
+    res = o.cg(lam, 2.0, E, tol=1e-12, x0=x0)
+    assert res["iterations"] == 1
+    assert np.abs(res["e"] - E.reshape((d,) + (1,) * d)).max() < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(27, 27), (9, 7, 5)])
+def test_laminate_closed_forms(shape):
+    rng = np.random.default_rng(12)
+    layers = (rng.random(shape[0]) < 0.45).astype(np.uint8)
+    layers[0], layers[1] = 0, 1
+    phase = ms.laminate(shape, layers)
+    lam = ms.lam_field(phase, [1.0, 100.0])
+    d = len(shape)
+    l0 = o.optimal_reference(lam)
+    harmonic = 1.0 / np.mean(1.0 / lam)
+    arithmetic = float(np.mean(lam))
+    # field across the layers: harmonic mean, one iteration for two phases
+    E = np.zeros(d)
+    E[0] = 1.0
+    res = o.cg(lam, l0, E, tol=1e-12)
+    assert res["iterations"] == 1
+    L = o.leff(lam, res["e"])
+    assert abs(L[0] - harmonic) < 1e-12 * harmonic
+    assert np.abs(L[1:]).max() < 1e-12
+    # the current is uniform: equilibrium norm vanishes
+    assert o.eta_e(lam, res["e"]) < 1e-12
+    # field along the layers: arithmetic mean, e = E, zero iterations
+    E = np.zeros(d)
+    E[1] = 1.0
+    res = o.cg(lam, l0, E, tol=1e-12)
+    assert res["iterations"] == 0
+    L = o.leff(lam, res["e"])
+    assert abs(L[1] - arithmetic) < 1e-14 * arithmetic
+
+
+def test_eta_e_closed_form():
+    """j = lambda E with lambda = 2 + cos(2 pi x1): eta_e = 1 / (2 sqrt 2)."""
+    n = 16
+    x = np.arange(n) / n
+    lam = np.broadcast_to((2.0 + np.cos(2 * np.pi * x))[:, None], (n, n)).copy()
+    e = np.zeros((2, n, n))
+    e[0] = 1.0
+    # j_hat(0) = 2 n^2, j_hat(+-1, 0) = n^2 / 2 -> sum |k.j|^2 = 2 (n^2/2)^2
+    assert abs(o.eta_e(lam, e) - math.sqrt(2 * 0.25) / 2.0) < 1e-14
+
+
+def test_E_zero_returns_zero():
+    lam = ms.square_inclusion().lam()
+    res = o.cg(lam, 5.5, [0.0, 0.0], tol=1e-8)
+    assert res["iterations"] == 0 and not np.any(res["e"])
+
+
+# ---------------------------------------------------------------------------
+# Invariants of the converged solution
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def square_solution():
+    m = ms.square_inclusion()
+    lam = m.lam()
+    L, iters = o.homogenize(lam, 5.5, tol=1e-12)
+    return m, lam, L, iters
+
+
+def test_square_symmetry(square_solution):
+    _, _, L, _ = square_solution
+    assert abs(L[0, 0] - L[1, 1]) < 1e-11
+    assert abs(L[0, 1]) < 1e-12 and abs(L[1, 0]) < 1e-12
+
+
+def test_square_bounds(square_solution):
+    _, lam, L, _ = square_solution
+    voigt, reuss = o.voigt_reuss(lam)
+    assert reuss < L[0, 0] < voigt
+
+
+def test_bounds_3d():
+    m = ms.rsa_inclusions(15, 3, 6, 0.1, 0.2, seed=4, rho=50.0)
+    lam = m.lam()
+    L, _ = o.homogenize(lam, tol=1e-10)
+    voigt, reuss = o.voigt_reuss(lam)
+    for a in range(3):
+        assert reuss < L[a, a] < voigt
+    np.testing.assert_allclose(L, L.T, atol=1e-8 * L[0, 0])
+
+
+def test_hill_mandel(square_solution):
+    _, lam, L, _ = square_solution
+    E = np.array([0.6, -0.8])
+    res = o.cg(lam, 5.5, E, tol=1e-13)
+    e = res["e"]
+    energy = float(np.mean(np.sum(e * lam[None] * e, axis=0)))
+    assert abs(energy - E @ L @ E) < 1e-10 * energy
+
+
+def test_keller_duality(square_solution):
+    """2-D: lambda -> c / lambda maps L_eff to c L_eff / det L_eff."""
+    m, lam, L, _ = square_solution
+    dual = 10.0 / lam
+    Ld, _ = o.homogenize(dual, tol=1e-12)
+    np.testing.assert_allclose(Ld, 10.0 * L / np.linalg.det(L), rtol=1e-9, atol=1e-10)
+
+
+def test_l0_invariance_of_iterates():
+    """A restricted to U is P lambda P / l0: CG iterates do not depend on l0."""
+    lam = ms.square_inclusion().lam()
+    fields = [o.cg(lam, l0, [1.0, 0.0], n_iter=12)["e"] for l0 in (2.0, 5.5, 20.0)]
+    # identical in exact arithmetic; rounding differs with l0 (~1e-11 seen)
+    for f in fields[1:]:
+        assert np.linalg.norm(f - fields[0]) / np.linalg.norm(fields[0]) < 1e-9
+
+
+def test_ffth_converges_to_cg_solution():
+    """The Neumann series of Eq. (18) reaches the same discrete solution."""
+    lam = ms.square_inclusion().lam()
+    E = [1.0, 0.0]
+    a = o.ffth(lam, 5.5, E, tol=1e-13)
+    b = o.cg(lam, 5.5, E, tol=1e-13)
+    assert a["converged"] and a["iterations"] > 3 * b["iterations"]
+    assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(b["e"]) < 1e-11
+
+
+def test_square_iterations_and_value(square_solution):
+    """Regression of the stored square-inclusion numbers (written by
+    tests/golden/make_golden.py from this oracle)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "square63.json")
+    ref = json.load(open(path))
+    lam = ms.square_inclusion().lam()
+    res = o.cg(lam, 5.5, [1.0, 0.0], tol=1e-8)
+    assert res["iterations"] == ref["iterations_tol1e-8"]
+    assert abs(o.leff(lam, res["e"])[0] - ref["leff11_tol1e-8"]) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Convergence rate (Sec. 3.2, Eq. (23))
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("rho", [10.0, 100.0, 1000.0])
+def test_cg_within_rate_bound(rho):
+    m = ms.square_inclusion(rho=rho)
+    lam = m.lam()
+    res = o.cg(lam, o.optimal_reference(lam), [1.0, 0.0], tol=1e-6)
+    assert res["converged"]
+    assert res["iterations"] <= o.cg_rate_bound_iterations(rho, 1e-6)
+
+
+def test_cg_grows_like_sqrt_rho_ffth_like_rho():
+    its_cg, its_ff = [], []
+    for rho in (10.0, 100.0):
+        lam = ms.square_inclusion(rho=rho).lam()
+        l0 = o.optimal_reference(lam)
+        its_cg.append(o.cg(lam, l0, [1.0, 0.0], tol=1e-6)["iterations"])
+        its_ff.append(o.ffth(lam, l0, [1.0, 0.0], tol=1e-6)["iterations"])
+    # tenfold contrast: CG grows by ~sqrt(10), FFTH by ~10
+    assert its_cg[1] / its_cg[0] < 5.0
+    assert its_ff[1] / its_ff[0] > 5.0
+    assert its_cg[1] < its_ff[1]
