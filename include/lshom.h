@@ -1,0 +1,183 @@
+/*
+ * lshom - FFT-accelerated conjugate-gradient solver for the periodic
+ * unit-cell (Lippmann-Schwinger) conduction problem on MI355X (gfx950).
+ *
+ * Method: Zeman, Vondrejc, Novak, Marek, "Accelerating a FFT-based solver for
+ * numerical homogenization of periodic media by conjugate gradients",
+ * J. Comput. Phys. 2010.  The library solves the collocation system
+ * (I + B) e = e0 of Sec. 2.2, Eq. (15), with B = F^-1 Gamma0_hat F dL
+ * (Eq. (16)), by the conjugate-gradient method of Sec. 2.3 (Saad's
+ * Algorithm 6.18, named in Sec. 3), for isotropic phases L = lambda I and a
+ * reference medium L0 = l0 I.
+ *
+ * Conventions shared by every entry point:
+ *  - Grids are d = 2 or 3 dimensional, N[0..d) nodes per axis, C order (the
+ *    last axis is contiguous).  Node j of an axis sits at coordinate j / N of
+ *    the unit cell.  Every N[a] >= 3 and N[a] has no prime factor above 7.
+ *  - A real field with d components is stored component-major, FP64:
+ *    field[a * |N| + flat_index], |N| = N[0] * ... * N[d-1].
+ *  - Device pointers (suffix _dev) are HIP device memory owned by the caller;
+ *    host pointers (suffix _host or plain arrays) are read during the call.
+ *  - The library never allocates device memory: the caller provides one
+ *    workspace (lshom_workspace_size / lshom_set_workspace).
+ *  - Calls are blocking: work is queued on the context's stream after the
+ *    caller's stream and the call returns when it has finished.
+ *  - Errors are reported by status codes; no C++ exception crosses the ABI.
+ *    lshom_last_error() returns a message owned by the context, valid until
+ *    the next call on that context.
+ */
+#ifndef LSHOM_H
+#define LSHOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lshom_status;
+
+#define LSHOM_OK 0
+#define LSHOM_ERR_INVALID_ARG (-1)   /* an argument is out of its domain */
+#define LSHOM_ERR_STATE (-2)         /* call order: microstructure/workspace missing */
+#define LSHOM_ERR_WORKSPACE (-3)     /* workspace absent or too small */
+#define LSHOM_ERR_HIP (-4)           /* a HIP runtime call failed */
+#define LSHOM_ERR_NOT_CONVERGED (-5) /* max_iter reached; last iterate returned */
+#define LSHOM_ERR_BREAKDOWN (-6)     /* (p, A p) <= 0 or not finite; last iterate returned */
+#define LSHOM_ERR_UNSUPPORTED (-7)   /* valid input outside what this build handles */
+
+#define LSHOM_PRECISION_FP64 0  /* every step in FP64 */
+#define LSHOM_PRECISION_MIXED 1 /* FP32 operator and vectors, FP64 dots and refresh */
+
+typedef struct lshom_ctx lshom_ctx;
+
+/* Solver options; lshom_default_opts() fills the defaults shown. */
+typedef struct lshom_solve_opts {
+  int32_t max_iter;      /* 10000: CG iterations (operator applies in the loop) */
+  int32_t precision;     /* LSHOM_PRECISION_FP64 */
+  int32_t refresh_every; /* 50: mixed only, FP64 refresh at least this often */
+  double refresh_drop;   /* 0.1: mixed only, refresh when ||r|| fell by this factor */
+  int32_t graph_block;   /* 16: iterations per captured HIP graph launch (0: no graph) */
+  int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop */
+} lshom_solve_opts;
+
+/* Per-solve report. */
+typedef struct lshom_solve_info {
+  int32_t iterations;     /* CG iterations */
+  int32_t applies_fp32;   /* FP32 operator applies in the loop (mixed) */
+  int32_t applies_fp64;   /* FP64 operator applies, loop and refreshes */
+  int32_t status;         /* status of this solve */
+  int32_t warm_start_used;/* 1 if x0 was used (not rejected) */
+  int32_t refreshes;      /* mixed: FP64 refreshes */
+  double rel_res;         /* ||r|| / ||b|| of the recursive residual */
+  double rel_res_true;    /* ||b - A x|| / ||b|| in FP64 (if computed, else -1) */
+  double eta_r;           /* l0 ||r|| / ||b||, the residual norm of Sec. 3, Eq. (22) */
+} lshom_solve_info;
+
+/* Fixed-size message for a status code (static storage). */
+const char* lshom_status_string(lshom_status s);
+
+/* Message of the last failed call on ctx ("" if none).  ctx may be NULL. */
+const char* lshom_last_error(const lshom_ctx* ctx);
+
+void lshom_default_opts(lshom_solve_opts* opts);
+
+/*
+ * Host-only validation of a problem statement (no device is touched):
+ * d in {2, 3}; 3 <= N[a] <= 4096 with prime factors in {2, 3, 5, 7};
+ * 1 <= n_phases <= 256 with finite cond > 0; l0 finite > 0, or exactly 0 to
+ * mean "the default (min + max) / 2" of Sec. 2.3, Eq. (19); E (d values, may
+ * be NULL) finite; tol finite >= 0 (tol < 0 skips the check).
+ * Returns LSHOM_OK or LSHOM_ERR_INVALID_ARG / LSHOM_ERR_UNSUPPORTED.
+ */
+lshom_status lshom_check_problem(int d, const int64_t* N, int n_phases, const double* cond,
+                                 double l0, const double* E, double tol);
+
+/*
+ * Create a context on HIP device `device`.  hip_stream is the caller's
+ * hipStream_t (NULL = the null stream); the context queues its work on a
+ * private stream ordered after it.  *out is NULL on failure.
+ */
+lshom_status lshom_create(lshom_ctx** out, int device, void* hip_stream);
+void lshom_destroy(lshom_ctx* ctx);
+
+/*
+ * The periodic microstructure: a digital image of phases sampled at the grid
+ * nodes (Sec. 2.2, Eq. (17): dL is diagonal with entries dL(x^k)), with an
+ * isotropic conductivity per phase (Sec. 3).  phase_dev holds prod(N) bytes,
+ * C order, each < n_phases; it stays owned by the caller and must stay valid
+ * until the next set_microstructure or destroy.  cond_host is copied.  Sets
+ * l0 to the optimal (min + max) / 2 of Sec. 2.3, Eq. (19).  Invalidates the
+ * workspace.
+ */
+lshom_status lshom_set_microstructure(lshom_ctx* ctx, int d, const int64_t* N,
+                                      const uint8_t* phase_dev, int n_phases,
+                                      const double* cond_host);
+
+/* Reference medium L0 = l0 I (Sec. 2.1, Eq. (3); Sec. 3, Eq. (20)); finite, > 0. */
+lshom_status lshom_set_reference(lshom_ctx* ctx, double l0);
+
+/* Bytes of device workspace the current problem needs (both precisions). */
+lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* bytes);
+
+/* Attach caller-owned device workspace (256-byte aligned, >= the size above). */
+lshom_status lshom_set_workspace(lshom_ctx* ctx, void* dev, size_t bytes);
+
+/*
+ * Solve (I + B) e = e0 with e0 = E at every node (Sec. 2.2, Eq. (15)) by CG.
+ * Stops when ||r|| <= tol ||e0|| (recursive residual), or after max_iter.
+ * x0_dev: NULL starts from e = E; otherwise a d x |N| FP64 field whose
+ * admissible part E + P(x0) is used (P: projection on zero-mean curl-free
+ * fields); it is rejected (start from E) if its residual is not finite or not
+ * below the residual of E.
+ * e_dev (d x |N| FP64, may be NULL) receives the field; leff_host (d values,
+ * may be NULL) receives <lambda e> = L_eff E; info (may be NULL) the report.
+ * NOT_CONVERGED and BREAKDOWN still write the last iterate and info; other
+ * errors leave the outputs untouched.  E = 0 returns e = 0 at once.
+ */
+lshom_status lshom_solve(lshom_ctx* ctx, const double* E_host, double tol,
+                         const lshom_solve_opts* opts, const double* x0_dev, double* e_dev,
+                         double* leff_host, lshom_solve_info* info);
+
+/*
+ * Effective conductivity tensor from the d load cases E = e_b: column b of
+ * leff_host (d x d, row-major) is <lambda e> for E = e_b.  infos: d reports
+ * (may be NULL).  Returns the worst status.
+ */
+lshom_status lshom_homogenize(lshom_ctx* ctx, double tol, const lshom_solve_opts* opts,
+                              double* leff_host, lshom_solve_info* infos);
+
+/*
+ * One FP64 operator apply on an arbitrary real field: q = (I + B) p of
+ * Sec. 2.2, Eqs. (15)-(16).  p_dev and q_dev are d x |N| FP64 (may not alias).
+ */
+lshom_status lshom_apply(lshom_ctx* ctx, const double* p_dev, double* q_dev);
+
+/* Kernel classes reported by lshom_time_passes. */
+#define LSHOM_PASS_AXIS0_INVERSE 0  /* p = r + beta p, i khat p, inverse FFT along axis 0 */
+#define LSHOM_PASS_AXIS1_INVERSE 1  /* 3-D: inverse FFT along axis 1 */
+#define LSHOM_PASS_ROW 2            /* last axis: inverse FFT, dL (E + u), forward FFT */
+#define LSHOM_PASS_AXIS1_FORWARD 3  /* 3-D: forward FFT along axis 1 */
+#define LSHOM_PASS_AXIS0_FORWARD 4  /* forward FFT along axis 0, Gamma0 projection, q, (p, q) */
+#define LSHOM_PASS_UPDATE 5         /* x += alpha p, r -= alpha q, (r, r) */
+#define LSHOM_PASS_COUNT 6
+
+/*
+ * Device time of each pass kernel of one CG iteration (Sec. 2.3: the apply of
+ * Eq. (16) plus the CG vector updates) for the current problem at `precision`:
+ * every kernel is launched `reps` times back to back on the context stream,
+ * with the same launch shape and buffers as in lshom_solve, between two HIP
+ * events.  ms_out[LSHOM_PASS_COUNT] receives the average milliseconds per
+ * launch (0 for passes a 2-D problem does not have); bytes_out (may be NULL)
+ * the minimum HBM bytes each launch must move (its algorithmic traffic).
+ * Overwrites the solver's internal vectors: call it between solves.
+ */
+lshom_status lshom_time_passes(lshom_ctx* ctx, int precision, int reps, double* ms_out,
+                               double* bytes_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSHOM_H */

@@ -1,0 +1,241 @@
+// Batched 1-D FFTs in LDS for gfx950: register-level radix butterflies and a
+// self-sorting (Stockham) stage loop.  Used by every pass kernel of the
+// operator apply: the discrete Fourier transforms F and F^-1 of the
+// collocation system (Sec. 2.2, Eqs. (12)-(14); Sec. 2.3 costs the operator by
+// them).  Forward transforms carry exp(-2 pi i k m / N), inverse ones
+// exp(+2 pi i k m / N); neither is normalised here.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "radix_consts.hpp"
+
+namespace lshom {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+// multiply by S*i (S = +1 or -1)
+template <typename T, int S>
+__device__ __forceinline__ cx<T> mul_si(cx<T> a) {
+  return S > 0 ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+// Multiply by exp(S * 2 pi i m / R) for a compile-time-foldable m.
+template <typename T, int R, int S>
+__device__ __forceinline__ cx<T> rot(cx<T> x, int m) {
+  m = m % R;
+  if (m == 0) return x;
+  if (2 * m == R) return {-x.re, -x.im};
+  if (4 * m == R) return mul_si<T, S>(x);
+  if (4 * m == 3 * R) return mul_si<T, -S>(x);
+  const T c = (T)RadixConst<R>::c[m];
+  const T s = (T)(S * RadixConst<R>::s[m]);
+  return {x.re * c - x.im * s, x.re * s + x.im * c};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers.  y_k = sum_j x_j exp(S 2 pi i j k / R).
+// ---------------------------------------------------------------------------
+
+template <typename T, int R, int S>
+__device__ __forceinline__ void dft(cx<T>* x);
+
+// Prime R: pair j with R-j so that each cosine/sine multiplies a sum/difference.
+template <typename T, int R, int S>
+__device__ __forceinline__ void dft_prime(cx<T>* x) {
+  constexpr int H = (R - 1) / 2;
+  cx<T> a[H + 1], b[H + 1];
+  cx<T> y0 = x[0];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    a[j] = cadd(x[j], x[R - j]);
+    b[j] = csub(x[j], x[R - j]);
+    y0 = cadd(y0, a[j]);
+  }
+  cx<T> out[R];
+  out[0] = y0;
+#pragma unroll
+  for (int m = 1; m <= H; ++m) {
+    cx<T> P = x[0];
+    cx<T> Q = {T(0), T(0)};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const int idx = (j * m) % R;
+      const T c = (T)RadixConst<R>::c[idx];
+      const T s = (T)RadixConst<R>::s[idx];
+      P = {P.re + c * a[j].re, P.im + c * a[j].im};
+      Q = {Q.re + s * b[j].re, Q.im + s * b[j].im};
+    }
+    const cx<T> iQ = mul_si<T, S>(Q);
+    out[m] = cadd(P, iQ);
+    out[R - m] = csub(P, iQ);
+  }
+#pragma unroll
+  for (int m = 0; m < R; ++m) x[m] = out[m];
+}
+
+// Composite R = R1 * R2 (Cooley-Tukey in registers): index j = R2 j1 + j2,
+// output k = k1 + R1 k2.
+template <typename T, int R1, int R2, int S>
+__device__ __forceinline__ void dft_ct(cx<T>* x) {
+  constexpr int R = R1 * R2;
+  cx<T> z[R];
+#pragma unroll
+  for (int j2 = 0; j2 < R2; ++j2) {
+    cx<T> t[R1];
+#pragma unroll
+    for (int j1 = 0; j1 < R1; ++j1) t[j1] = x[R2 * j1 + j2];
+    dft<T, R1, S>(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) z[j2 * R1 + k1] = rot<T, R, S>(t[k1], j2 * k1);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cx<T> t[R2];
+#pragma unroll
+    for (int j2 = 0; j2 < R2; ++j2) t[j2] = z[j2 * R1 + k1];
+    dft<T, R2, S>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = t[k2];
+  }
+}
+
+template <typename T, int R, int S>
+__device__ __forceinline__ void dft(cx<T>* x) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    const cx<T> a = x[0], b = x[1];
+    x[0] = cadd(a, b);
+    x[1] = csub(a, b);
+  } else if constexpr (R == 3 || R == 5 || R == 7) {
+    dft_prime<T, R, S>(x);
+  } else if constexpr (R == 4) {
+    dft_ct<T, 2, 2, S>(x);
+  } else if constexpr (R == 6) {
+    dft_ct<T, 2, 3, S>(x);
+  } else if constexpr (R == 8) {
+    dft_ct<T, 2, 4, S>(x);
+  } else if constexpr (R == 9) {
+    dft_ct<T, 3, 3, S>(x);
+  } else {
+    static_assert(R <= 9, "unsupported radix");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plans and the LDS stage loop
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxStages = 16;
+
+// Radix schedule of one axis; the product of radix[0..nstages) is n.
+struct FftPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+};
+
+// Butterflies held per thread across the stage barrier, per radix.  The host
+// sizes every batch so that nseq * n / R <= jobs_per_thread(R) * threads.
+__host__ __device__ constexpr int jobs_per_thread(int R) {
+  return R <= 3 ? 6 : (R <= 5 ? 4 : (R <= 7 ? 3 : 2));
+}
+
+// Largest number of points (nseq * n) one batch may hold for a plan.
+__host__ __device__ inline int plan_batch_cap(const FftPlan& p, int threads) {
+  int cap = 1 << 30;
+  for (int s = 0; s < p.nstages; ++s) {
+    const int c = jobs_per_thread(p.radix[s]) * p.radix[s] * threads;
+    cap = c < cap ? c : cap;
+  }
+  return cap;
+}
+
+// One self-sorting stage, in place: every thread loads its butterflies into
+// registers, the block synchronises, then every thread stores them.
+// Sequence s, element e lives at buf[s * ss + e].  Twiddle table tw[m] holds
+// exp(-2 pi i m / n) (conjugated for the inverse direction, S = +1).
+template <typename T, int R, int S, int NT>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, int Ns,
+                                          const cx<T>* __restrict__ tw, int tid) {
+  constexpr int JM = jobs_per_thread(R);
+  const int NR = n / R;
+  const int jobs = nseq * NR;
+  const int step = n / (Ns * R);
+  cx<T> v[JM][R];
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int job = tid + q * NT;
+    if (job < jobs) {
+      const int s = job / NR;
+      const int j = job - s * NR;
+      const cx<T>* b = buf + s * ss + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = b[r * NR];
+      if (Ns > 1) {
+        const int k = j % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * k * step];
+          if (S > 0) w.im = -w.im;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      dft<T, R, S>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < JM; ++q) {
+    const int job = tid + q * NT;
+    if (job < jobs) {
+      const int s = job / NR;
+      const int j = job - s * NR;
+      const int k = j % Ns;
+      cx<T>* b = buf + s * ss + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) b[r * Ns] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform nseq sequences of length plan.n in LDS.  Callers synchronise
+// before (data written) and may read the result right after.
+template <typename T, int S, int NT>
+__device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
+                        const cx<T>* __restrict__ tw, int tid) {
+  int Ns = 1;
+  for (int st = 0; st < plan.nstages; ++st) {
+    const int R = plan.radix[st];
+    switch (R) {
+      case 2: fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 3: fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 4: fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 5: fft_stage<T, 5, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 6: fft_stage<T, 6, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+}  // namespace lshom

@@ -1,0 +1,125 @@
+#include "plan.hpp"
+
+#include <cmath>
+
+namespace lshom {
+
+bool fft_size_ok(int64_t n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+FftPlan default_plan(int n) {
+  FftPlan p{};
+  p.n = n;
+  p.nstages = 0;
+  int rest = n;
+  const int order[] = {9, 8, 7, 5, 6, 4, 3, 2};
+  while (rest > 1 && p.nstages < kMaxStages) {
+    for (int r : order) {
+      if (rest % r == 0) {
+        p.radix[p.nstages++] = r;
+        rest /= r;
+        break;
+      }
+    }
+  }
+  if (p.nstages == 0) {  // n == 1
+    p.radix[0] = 1;
+  }
+  return p;
+}
+
+bool make_plan(int n, const int* radices, int nstages, FftPlan* plan) {
+  if (nstages < 1 || nstages > kMaxStages) return false;
+  long long prod = 1;
+  for (int i = 0; i < nstages; ++i) {
+    const int r = radices[i];
+    if (r < 2 || r > 9) return false;
+    prod *= r;
+  }
+  if (prod != n) return false;
+  plan->n = n;
+  plan->nstages = nstages;
+  for (int i = 0; i < nstages; ++i) plan->radix[i] = radices[i];
+  return true;
+}
+
+void twiddles(int n, std::vector<double>* re_im) {
+  re_im->assign(2 * (size_t)n, 0.0);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int m = 0; m < n; ++m) {
+    // long double carries 64 mantissa bits: the rounded double is within
+    // about half an ulp of exp(-2 pi i m / n)
+    const long double a = two_pi * (long double)m / (long double)n;
+    (*re_im)[2 * m] = (double)std::cos(a);
+    (*re_im)[2 * m + 1] = (double)(-std::sin(a));
+  }
+}
+
+static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
+                        size_t lds_budget, long long min_blocks) {
+  PassShape s{1, 1, 1};
+  const int last = d - 1;
+  const int n_last = (int)N[last];
+  const long long h = n_last / 2 + 1;
+  long long nrows = 1;
+  for (int a = 0; a < last; ++a) nrows *= N[a];
+
+  // row pass: pairs of real signals, npairs * n points per FFT batch
+  {
+    const int cap = plan_batch_cap(plans[last], kThreads);
+    int best = 1;
+    for (int r = 1; r <= 64; ++r) {
+      const int npairs = (d * r + 1) / 2;
+      if ((long long)npairs * n_last > cap) break;
+      if (row_lds_bytes(n_last, r, d, elem_bytes, nullptr) > lds_budget) break;
+      if (d == 3 && (r & 1)) continue;
+      best = r;
+    }
+    while (best > 1 && ceil_div(nrows, best) < min_blocks) best -= (d == 3 && best > 2) ? 2 : 1;
+    s.rows_per_block = best;
+  }
+  // axis 0: inner = (N1 ...) * h
+  auto pick_tile = [&](int L, long long inner, long long outer, const FftPlan& pl) {
+    const int cap = plan_batch_cap(pl, kThreads);
+    int best = 1;
+    for (int c = 1; c <= 64; ++c) {
+      if ((long long)d * c * L > cap) break;
+      if (col_lds_bytes(L, c, d, elem_bytes, nullptr) > lds_budget) break;
+      if (c > inner) break;
+      best = c;
+    }
+    while (best > 1 && outer * ceil_div(inner, best) < min_blocks) best -= 1;
+    return best;
+  };
+  long long inner0 = h;
+  for (int a = 1; a < last; ++a) inner0 *= N[a];
+  s.tile0 = pick_tile((int)N[0], inner0, 1, plans[0]);
+  if (d == 3) s.tile1 = pick_tile((int)N[1], h, N[0], plans[1]);
+  return s;
+}
+
+bool shape_fits(int d, const int64_t* N, const FftPlan* plans, const PassShape& s, int elem_bytes,
+                size_t lds_budget) {
+  const int last = d - 1;
+  const int n_last = (int)N[last];
+  {
+    const int npairs = (d * s.rows_per_block + 1) / 2;
+    if ((long long)npairs * n_last > plan_batch_cap(plans[last], kThreads)) return false;
+    if (row_lds_bytes(n_last, s.rows_per_block, d, elem_bytes, nullptr) > lds_budget) return false;
+  }
+  if ((long long)d * s.tile0 * N[0] > plan_batch_cap(plans[0], kThreads)) return false;
+  if (col_lds_bytes((int)N[0], s.tile0, d, elem_bytes, nullptr) > lds_budget) return false;
+  if (d == 3) {
+    if ((long long)d * s.tile1 * N[1] > plan_batch_cap(plans[1], kThreads)) return false;
+    if (col_lds_bytes((int)N[1], s.tile1, d, elem_bytes, nullptr) > lds_budget) return false;
+  }
+  return true;
+}
+
+}  // namespace lshom

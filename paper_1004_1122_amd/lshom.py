@@ -1,0 +1,265 @@
+"""ctypes binding of liblshom.so: the C ABI of include/lshom.h, same names.
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch provides the device memory (phase image, workspace, fields) and the
+stream.  ``load()`` fails loudly when the library has not been built; there is
+no fallback.
+
+High-level use::
+
+    s = Solver(phase_gpu_uint8, cond=[1.0, 10.0])
+    e, leff, info = s.solve([1.0, 0.0], tol=1e-8)
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblshom.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "lshom.h")
+
+LSHOM_OK = 0
+LSHOM_ERR_INVALID_ARG = -1
+LSHOM_ERR_STATE = -2
+LSHOM_ERR_WORKSPACE = -3
+LSHOM_ERR_HIP = -4
+LSHOM_ERR_NOT_CONVERGED = -5
+LSHOM_ERR_BREAKDOWN = -6
+LSHOM_ERR_UNSUPPORTED = -7
+
+PRECISION_FP64 = 0
+PRECISION_MIXED = 1
+
+
+class lshom_solve_opts(Structure):
+    _fields_ = [
+        ("max_iter", c_int32),
+        ("precision", c_int32),
+        ("refresh_every", c_int32),
+        ("refresh_drop", c_double),
+        ("graph_block", c_int32),
+        ("true_residual", c_int32),
+    ]
+
+
+class lshom_solve_info(Structure):
+    _fields_ = [
+        ("iterations", c_int32),
+        ("applies_fp32", c_int32),
+        ("applies_fp64", c_int32),
+        ("status", c_int32),
+        ("warm_start_used", c_int32),
+        ("refreshes", c_int32),
+        ("rel_res", c_double),
+        ("rel_res_true", c_double),
+        ("eta_r", c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblshom.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1004_1122_amd.build`"
+                           " (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "lshom_status_string": (c_char_p, [c_int32]),
+        "lshom_last_error": (c_char_p, [P]),
+        "lshom_default_opts": (None, [POINTER(lshom_solve_opts)]),
+        "lshom_check_problem": (c_int32, [c_int, POINTER(c_int64), c_int, POINTER(c_double), c_double,
+                                          POINTER(c_double), c_double]),
+        "lshom_create": (c_int32, [POINTER(c_void_p), c_int, P]),
+        "lshom_destroy": (None, [P]),
+        "lshom_set_microstructure": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
+        "lshom_set_reference": (c_int32, [P, c_double]),
+        "lshom_workspace_size": (c_int32, [P, c_int, POINTER(c_size_t)]),
+        "lshom_set_workspace": (c_int32, [P, P, c_size_t]),
+        "lshom_solve": (c_int32, [P, POINTER(c_double), c_double, POINTER(lshom_solve_opts), P, P,
+                                  POINTER(c_double), POINTER(lshom_solve_info)]),
+        "lshom_homogenize": (c_int32, [P, c_double, POINTER(lshom_solve_opts), POINTER(c_double),
+                                       POINTER(lshom_solve_info)]),
+        "lshom_apply": (c_int32, [P, P, P]),
+        "lshom_time_passes": (c_int32, [P, c_int, c_int, POINTER(c_double), POINTER(c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Names of the functions include/lshom.h declares."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lshom_[a-z0-9_]+)\s*\(", text)))
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def _dbl_array(vals):
+    vals = [float(v) for v in vals]
+    return (c_double * max(1, len(vals)))(*vals)
+
+
+def lshom_status_string(status: int) -> str:
+    return load().lshom_status_string(status).decode()
+
+
+def lshom_default_opts() -> lshom_solve_opts:
+    o = lshom_solve_opts()
+    load().lshom_default_opts(ctypes.byref(o))
+    return o
+
+
+def lshom_check_problem(d, N, cond, l0=0.0, E=None, tol=-1.0) -> int:
+    lib = load()
+    Narr = (c_int64 * max(1, len(N)))(*[int(v) for v in N])
+    carr = _dbl_array(cond)
+    Earr = _dbl_array(E) if E is not None else None
+    return lib.lshom_check_problem(int(d), Narr, len(cond), carr, float(l0), Earr, float(tol))
+
+
+class LshomError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lshom_status_string(status)} ({status}): {msg}")
+        self.status = status
+
+
+def _check(ctx, status, allow=()):
+    if status != LSHOM_OK and status not in allow:
+        msg = load().lshom_last_error(ctx).decode() if ctx else ""
+        raise LshomError(status, msg)
+    return status
+
+
+def lshom_create(device: int = 0, stream: int | None = None) -> c_void_p:
+    lib = load()
+    h = c_void_p()
+    _check(None, lib.lshom_create(ctypes.byref(h), int(device), c_void_p(stream or 0)))
+    return h
+
+
+def lshom_destroy(ctx) -> None:
+    if ctx:
+        load().lshom_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# High-level solver object (torch owns device memory)
+# ---------------------------------------------------------------------------
+
+class Solver:
+    """One microstructure on one device; owns a context and its workspace."""
+
+    def __init__(self, phase, cond, device: int = 0, precision: int = PRECISION_MIXED):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("lshom.Solver needs a GPU")
+        dev = torch.device("cuda", device)
+        if not isinstance(phase, torch.Tensor):
+            phase = torch.as_tensor(np.ascontiguousarray(phase, dtype=np.uint8))
+        self.phase = phase.to(device=dev, dtype=torch.uint8).contiguous()
+        self.shape = tuple(self.phase.shape)
+        self.d = len(self.shape)
+        self.nvox = int(np.prod(self.shape))
+        self.cond = [float(c) for c in cond]
+        self.device = dev
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.ctx = lshom_create(device, stream)
+        Narr = (c_int64 * self.d)(*self.shape)
+        _check(self.ctx, self.lib.lshom_set_microstructure(self.ctx, self.d, Narr,
+                                                           c_void_p(self.phase.data_ptr()),
+                                                           len(self.cond), _dbl_array(self.cond)))
+        size = c_size_t()
+        _check(self.ctx, self.lib.lshom_workspace_size(self.ctx, int(precision), ctypes.byref(size)))
+        self.ws_bytes = int(size.value)
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self.ws_ptr = raw.data_ptr() + off
+        _check(self.ctx, self.lib.lshom_set_workspace(self.ctx, c_void_p(self.ws_ptr), self.ws_bytes))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lshom_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_reference(self, l0: float):
+        _check(self.ctx, self.lib.lshom_set_reference(self.ctx, float(l0)))
+
+    def opts(self, **kw) -> lshom_solve_opts:
+        o = lshom_default_opts()
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    def solve(self, E, tol=1e-8, x0=None, want_field=True, allow_fail=False, **opt_kw):
+        """Returns (e [d, *N] float64 device tensor or None, leff ndarray, info dict)."""
+        torch = self.torch
+        o = self.opts(**opt_kw)
+        e = torch.empty((self.d,) + self.shape, dtype=torch.float64, device=self.device) if want_field else None
+        leff = (c_double * self.d)()
+        info = lshom_solve_info()
+        x0p = None
+        if x0 is not None:
+            x0 = x0.to(device=self.device, dtype=torch.float64).contiguous()
+            assert tuple(x0.shape) == (self.d,) + self.shape
+            x0p = c_void_p(x0.data_ptr())
+        st = self.lib.lshom_solve(self.ctx, _dbl_array(E), float(tol), ctypes.byref(o), x0p,
+                                  c_void_p(e.data_ptr()) if e is not None else None, leff,
+                                  ctypes.byref(info))
+        allow = (LSHOM_ERR_NOT_CONVERGED, LSHOM_ERR_BREAKDOWN) if allow_fail else ()
+        _check(self.ctx, st, allow)
+        return e, np.array(leff[:]), info.as_dict()
+
+    def homogenize(self, tol=1e-8, **opt_kw):
+        o = self.opts(**opt_kw)
+        out = (c_double * (self.d * self.d))()
+        infos = (lshom_solve_info * self.d)()
+        _check(self.ctx, self.lib.lshom_homogenize(self.ctx, float(tol), ctypes.byref(o), out, infos))
+        return np.array(out[:]).reshape(self.d, self.d), [i.as_dict() for i in infos]
+
+    PASS_NAMES = ["axis0_inverse", "axis1_inverse", "row", "axis1_forward", "axis0_forward", "update"]
+
+    def time_passes(self, precision=PRECISION_FP64, reps=50):
+        """Average device ms and algorithmic bytes per launch of each pass kernel."""
+        ms = (c_double * 6)()
+        by = (c_double * 6)()
+        _check(self.ctx, self.lib.lshom_time_passes(self.ctx, int(precision), int(reps), ms, by))
+        return {n: (ms[i], by[i]) for i, n in enumerate(self.PASS_NAMES) if ms[i] > 0}
+
+    def apply(self, p):
+        """q = (I + B) p for an arbitrary real FP64 field p of shape (d, *N)."""
+        torch = self.torch
+        p = p.to(device=self.device, dtype=torch.float64).contiguous()
+        q = torch.empty_like(p)
+        _check(self.ctx, self.lib.lshom_apply(self.ctx, c_void_p(p.data_ptr()), c_void_p(q.data_ptr())))
+        return q
