@@ -23,6 +23,7 @@ LIB = os.path.join(PKG, "liblshom.so")
 SOURCES = [
     "passes.hip",
     "plan.cpp",
+    "driver.cpp",
     "lshom_api.cpp",
 ]
 

@@ -9,71 +9,85 @@
 
 namespace lshom {
 
-constexpr int kThreads = 256;   // every pass kernel runs 4 wave64s per block
 constexpr int kMaxDim = 3;
+constexpr int kUpdateBlocks = 512;   // grid of the elementwise kernels (one partial each)
 
-// Device-resident CG scalars.  Written only by the last block of a reduction
-// (fixed summation order), read by every kernel at entry.
+// Device-resident CG scalars.
+//
+// Inner products are reduced without atomics or fences: every block of a
+// producing kernel stores one partial sum, and the consuming kernel (which
+// starts after the producer has finished) sums the partials in block order in
+// each of its blocks, so all blocks obtain the same value.  Each field below
+// is written by block 0 of exactly one kernel kind and never read by that
+// kernel kind, so blocks of one kernel do not race on it.
 struct DevState {
-  double rr;            // (r, r) of the recursive residual
-  double pq;            // (p, A p)
-  double alpha, beta;
   double tol2b2;        // (tol * ||b||)^2
   double b2;            // ||b||^2 = |E|^2 |N|
-  double rr0;           // (r0, r0)
-  double rr_true;       // last FP64 true residual squared
-  double leff[3];       // <lambda e>
-  double dot_aux;       // scratch result of a plain reduction
+  double rr_log;        // (r_k, r_k) seen by the last direction kernel / check
+  double pq_log;        // (p_k, A p_k)
+  double alpha_log;
+  double rr_true;       // FP64 true residual squared (refresh / final check)
+  double dot_aux;       // a plain reduction result
   double rr_ref;        // mixed: (r, r) at the last refresh
   double drop2;         // mixed: refresh when rr < drop2 * rr_ref
-  int iter;             // CG iterations done (operator applies in the loop)
+  double leff[3];       // <lambda e>
+  int iter_a;           // iterations completed (written by the update kernel)
+  int iter_u;           // iteration in progress (written by the direction kernel)
   int max_iter;
-  int done;             // nonzero: every iteration kernel returns at entry
+  int done;             // nonzero: iteration kernels return at entry
   int status;           // 0 ok, -5 not converged, -6 breakdown
   int refresh;          // mixed: the refresh sequence runs when nonzero
-  int since_refresh;
-  int refresh_every;
+  int refresh_every;    // mixed: > 0 selects the mixed-precision decisions
+  int k_ref;            // mixed: iteration count at the last refresh
   int n_refresh;
-  int applies32, applies64;
-  unsigned counter;     // arrival counter of the last-block reductions
-  int pad[5];
+  int nparts[2];        // number of partials in the two (r, r) buffers
+  int pad[3];
 };
 
-// When a kernel returns at entry (it reads the device state first).
+// When a kernel returns at entry.
 enum Gate : int {
   GATE_ALWAYS = 0,      // set-up and output kernels
-  GATE_ACTIVE = 1,      // CG iteration kernels: skip once done
+  GATE_ACTIVE = 1,      // FP64 CG kernels: skip once done
   GATE_REFRESH = 2,     // mixed refresh kernels: run only when a refresh is due
-  GATE_NO_REFRESH = 3,  // skip when done or a refresh is due
+  GATE_NO_REFRESH = 3,  // mixed FP32 kernels: skip when done or a refresh is due
 };
 
-// What the last block of a reducing kernel does with the grid-wide sum(s).
-enum Finalize : int {
-  FIN_NONE = 0,
-  FIN_ALPHA = 1,      // pq -> alpha; breakdown if pq <= 0 or not finite
-  FIN_RR_INIT = 2,    // rr0 = rr = sum; done if converged at the start
-  FIN_UPDATE = 3,     // rr_new -> beta, iter++, convergence / iteration limit
-  FIN_RR_TRUE = 4,    // rr_true = sum
-  FIN_LEFF = 5,       // leff[0..d) = sums / |N|
-  FIN_AUX = 6,        // dot_aux = sum
-  FIN_REFRESH = 7,    // mixed: true residual of the refresh -> rr, rr_ref, done
-  FIN_CLEAR_REFRESH = 8,  // mixed: the refresh sequence has finished
+// Regions of the partial-sum array (each `stride` doubles; AUX holds 3 per block).
+enum PartRegion : int { PART_RR0 = 0, PART_RR1 = 1, PART_PQ = 2, PART_AUX = 3 };
+
+struct Partials {
+  double* base;
+  long long stride;     // doubles per region
+  __host__ __device__ double* region(int r) const { return base + (long long)r * stride; }
+};
+
+// Scalar steps of the single-block finalize kernel.
+enum FinMode : int {
+  FZ_CHECK = 0,         // FP64: convergence / limit test on (r_m, r_m), m = iter_a
+  FZ_AUX = 1,           // dot_aux = sum(AUX)
+  FZ_RR_TRUE = 2,       // rr_true = sum(AUX)
+  FZ_LEFF = 3,          // leff[c] = sum(AUX[3 b + c]) / |N|
+  FZ_REFRESH = 4,       // mixed: rr_true = sum(AUX); new reference; done tests
+  FZ_REFRESH_INIT = 5,  // mixed: as FZ_REFRESH without counting a refresh
 };
 
 // ---------------------------------------------------------------------------
-// Row pass: FFTs along the contiguous (last) axis, on rows of the half
-// spectrum.  Pairs of real signals share one complex transform.
+// Row pass: FFTs along the contiguous (last) real-space axis.  A block owns
+// rows_per_block consecutive rows (an even number) and pairs row 2j with row
+// 2j+1 of the same component into one complex transform.
+// Spectral element (row, k) of a component lives at row * rs_row + k * rs_k:
+// natural layout rs_row = h, rs_k = 1; transposed (2-D) rs_row = 1, rs_k = nrows.
 // ---------------------------------------------------------------------------
 enum RowMode : int {
-  ROW_FUSED = 0,   // spectrum A -> real u -> dL (E + u) -> spectrum T
-  ROW_INV = 1,     // spectrum A -> real out = add + E + u (FP64); optional <lambda out>
-  ROW_FWD = 2,     // real in (FP64, or constant E) -> [dL] in -> spectrum T
+  ROW_FUSED = 0,   // spectrum -> real u -> dL (E + u) -> spectrum
+  ROW_INV = 1,     // spectrum -> real out = add + E + u (FP64); optional <lambda out>
+  ROW_FWD = 2,     // real in (FP64, or constant E) -> [dL] in -> spectrum
 };
 enum RowFlags : int {
   ROWF_DL = 1,        // ROW_FWD: multiply the input by dL = lambda - l0
   ROWF_CONST_E = 2,   // ROW_FWD: the input is the constant field E
   ROWF_ADD = 4,       // ROW_INV: add real_add to the output
-  ROWF_LEFF = 8,      // ROW_INV: reduce <lambda out> into leff
+  ROWF_LEFF = 8,      // ROW_INV: partial sums of <lambda out> into AUX
 };
 
 template <typename T>
@@ -81,31 +95,34 @@ struct RowArgs {
   int n;                 // row length (last axis)
   int h;                 // n / 2 + 1
   long long nrows;       // product of the other axes
-  int rows_per_block;
+  int rows_per_block;    // even
   int d;
   int mode, flags;
   int ss;                // LDS stride between sequences (odd, >= n)
-  cx<T>* spec[kMaxDim];          // half-spectrum components [nrows][h]
+  long long rs_row, rs_k;
+  int row_fast;          // thread order for global spectral access: rows fastest
+  cx<T>* spec[kMaxDim];
   const double* real_in[kMaxDim];
   double* real_out[kMaxDim];
   const double* real_add[kMaxDim];
   const uint8_t* phase;          // [nrows][n]
-  const T* cond;                 // conductivity per phase
+  const T* cond;                 // conductivity per phase (n_phases entries)
+  int n_phases;
   T l0;
   T E[kMaxDim];
   T inv_n;                       // 1 / |N|
   FftPlan plan;
   const cx<T>* tw;               // exp(-2 pi i m / n)
   DevState* st;
-  double* partials;
-  int fin;
+  Partials parts;
   int gate;
 };
 
 // ---------------------------------------------------------------------------
 // Strided-axis pass: FFTs along a non-contiguous axis of the half spectrum.
-// The array is [outer][L][inner]; a block owns `tile` consecutive inner
-// indices of one outer slice for all d components.
+// Element (o, l, ii) lives at o * L * inner + l * sl + ii * sii (natural:
+// sl = inner, sii = 1; transposed 2-D: sl = 1, sii = L).  A block owns `tile`
+// consecutive ii of one outer slice for all d components.
 // ---------------------------------------------------------------------------
 enum ColMode : int {
   COL_INV_C = 0,    // scalar c -> i khat_a c (a < d) -> inverse FFT -> comp[a]
@@ -115,89 +132,102 @@ enum ColMode : int {
 
 template <typename T>
 struct ColArgs {
-  int L;                 // axis length
-  long long inner;       // contiguous extent after the axis (in elements)
-  long long outer;       // slices before the axis
-  int tile;              // inner elements per block
+  int L;
+  long long inner;
+  long long outer;
+  long long sl, sii;
+  int tile;
   int tiles_per_outer;
   int d;
   int mode, dir;
   int ss;
   cx<T>* comp[kMaxDim];
-  // spectral frequency data (axis-0 passes: L = N[0])
   int nd[kMaxDim];       // full grid sizes
   int dims;
   int h;                 // half length of the last axis
   // COL_INV_C
-  const cx<T>* c_in;     // used when fuse_p == 0
-  cx<T>* p_io;           // fuse_p: p = r + beta p (written back)
+  const cx<T>* c_in;     // used when cg_step == 0
+  cx<T>* p_io;           // cg_step: p = r + beta p (written back)
   const cx<T>* r_in;
-  int fuse_p;
+  int cg_step;           // this launch is the CG direction step (decides beta, stop)
   // COL_FWD_PROJ: out = coef_base * base + coef_s * s
   cx<T>* out;
   const cx<T>* base;
   T coef_base, coef_s;
   int dot;               // 0 none, 1 (base, out), 2 (out, out)
+  int dot_region;        // partial region; PART_RR0 also sets nparts[0]
   FftPlan plan;
   const cx<T>* tw;
   DevState* st;
-  double* partials;
-  int fin;
+  Partials parts;
   int gate;
-  double inv_n;          // scales the dot to real-space inner products
+  double inv_n;          // scales spectral sums to real-space inner products
 };
 
 // ---------------------------------------------------------------------------
-// Elementwise CG update on the half spectrum
+// Elementwise CG update on the half spectrum: x += alpha p, r -= alpha q
 // ---------------------------------------------------------------------------
 template <typename T>
 struct UpdArgs {
-  long long n;           // elements
-  int h;                 // half length of the last axis
-  int n_last;            // full length of the last axis
+  long long n;
+  int h, n_last;
+  long long klast_div;   // k_last = (i / klast_div) % h
   cx<T>* x;
   cx<T>* r;
   const cx<T>* p;
   const cx<T>* q;
   DevState* st;
-  double* partials;
+  Partials parts;
+  int n_pq;              // partials of (p, q) to sum
   double inv_n;
-  int blocks;
   int gate;
 };
 
-// ---------------------------------------------------------------------------
-// Mixed precision: fold the FP32 correction into the FP64 iterate and hand
-// the FP64 true residual back to the FP32 recursion.
-// ---------------------------------------------------------------------------
+// Mixed precision: x64 += x32, x32 = 0 (accumulate); r32 = r64 and the
+// partials of (r32, r32) into the (r, r) buffer of the current iteration
+// (convert).
 struct MixArgs {
   long long n;
+  int h, n_last;
+  long long klast_div;
   cx<double>* x64;
   cx<float>* x32;
   const cx<double>* r64;
   cx<float>* r32;
   DevState* st;
-  double* partials;
+  Partials parts;
+  double inv_n;
   int gate;
-  int clear_refresh;     // convert: the last block clears the refresh flag
-  int blocks;
 };
 
-// Host launchers (defined in passes.hip).
+struct FinArgs {
+  DevState* st;
+  Partials parts;
+  int mode;
+  int n;                 // partials to sum (AUX modes)
+  int d;
+  double inv_n;
+  int gate;
+};
+
+// Host launchers (passes.hip).
 template <typename T> hipError_t launch_row(const RowArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_col(const ColArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s);
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);
+hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);
 hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);
-hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);   // x64 += x32, x32 = 0
-hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);      // r32 = r64
 template <typename T> hipError_t launch_fill_zero(cx<T>* p, long long n, hipStream_t s);
+hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipStream_t s);
 
-// Number of blocks a launch uses (so the host can size partials).
 template <typename T> long long row_blocks(const RowArgs<T>& a);
 template <typename T> long long col_blocks(const ColArgs<T>& a);
 long long update_blocks(long long n);
 
-size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int* ss_out);
+// Dynamic LDS of a launch (sequence data + twiddles + phase bytes).
+size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int n_phases, int* ss_out);
 size_t col_lds_bytes(int L, int tile, int d, int elem_bytes, int* ss_out);
+int lds_odd_stride(int n);
 
 }  // namespace lshom

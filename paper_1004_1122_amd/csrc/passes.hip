@@ -17,6 +17,8 @@
 //   [axis-1 pass (COL_PLAIN):   forward FFT along axis 1]               (3-D)
 //   axis-0 pass  (COL_FWD_PROJ): forward FFT along axis 0, projection on
 //                               khat, q = p + s / l0 and the dot (p, q).
+// Twiddles (and, in the row pass, phase bytes and conductivities) are staged
+// in LDS at block start.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -65,116 +67,164 @@ __device__ __forceinline__ double half_weight(long long k_last, int n_last) {
   return 2.0;
 }
 
+template <typename T, int NT>
+__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+}
+
+static __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
 // ---------------------------------------------------------------------------
 // Row pass
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void row_kernel(RowArgs<T> a) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   if (gated_out(a.st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = a.n, h = a.h, ss = a.ss, d = a.d, R = a.rows_per_block;
+  const int half_rows = R / 2;
+  const int npairs = d * half_rows;
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
+  size_t off = align16((size_t)npairs * ss * sizeof(cx<T>));
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + off);
+  off = align16(off + (size_t)n * sizeof(cx<T>));
+  T* cond = reinterpret_cast<T*>(smem_raw + off);
+  off = align16(off + (size_t)a.n_phases * sizeof(T));
+  uint8_t* ph = smem_raw + off;  // [R][n] phase bytes of this block's rows
   const int tid = threadIdx.x;
-  const int n = a.n, h = a.h, ss = a.ss, d = a.d;
-  const long long row0 = (long long)blockIdx.x * a.rows_per_block;
-  const int nsig = d * a.rows_per_block;
-  const int npairs = (nsig + 1) / 2;
+  const long long row0 = (long long)blockIdx.x * R;
+  const int rows_here = (int)((a.nrows - row0) < R ? (a.nrows - row0) : R);
 
-  auto sig_valid = [&](int sg) -> bool { return sg < nsig && row0 + sg / d < a.nrows; };
-  auto sig_row = [&](int sg) -> long long { return row0 + sg / d; };
-  auto sig_comp = [&](int sg) -> int { return sg % d; };
-  auto dl_at = [&](long long row, int x) -> T {
-    return a.cond[a.phase[row * n + x]] - a.l0;
-  };
+  // stage twiddles, conductivities and phases (they overlap the data loads)
+  stage_twiddles<T, NT>(tw, a.tw, n);
+  for (int i = tid; i < a.n_phases; i += NT) cond[i] = a.cond[i];
+  const bool need_phase = (a.mode == ROW_FUSED) || (a.mode == ROW_FWD && (a.flags & ROWF_DL)) ||
+                          (a.mode == ROW_INV && (a.flags & ROWF_LEFF));
+  if (need_phase) {
+    const uint8_t* src = a.phase + row0 * n;
+    const int nb = rows_here * n;
+    // 4-byte loads where the row block is aligned
+    if (((reinterpret_cast<uintptr_t>(src) & 3) == 0) && ((nb & 3) == 0)) {
+      const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
+      uint32_t* d4 = reinterpret_cast<uint32_t*>(ph);
+      for (int i = tid; i < nb / 4; i += NT) d4[i] = s4[i];
+    } else {
+      for (int i = tid; i < nb; i += NT) ph[i] = src[i];
+    }
+  }
+
+  // pair p: component c = p / half_rows, rows 2j and 2j+1 with j = p % half_rows
+  auto pair_comp = [&](int p) -> int { return p / half_rows; };
+  auto pair_row = [&](int p) -> int { return 2 * (p - (p / half_rows) * half_rows); };
 
   if (a.mode == ROW_FWD) {
-    for (int idx = tid; idx < npairs * n; idx += kThreads) {
+    __syncthreads();
+    for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = idx / n;
       const int x = idx - p * n;
+      const int c = pair_comp(p);
+      const int ra = pair_row(p);
       T v[2] = {T(0), T(0)};
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int sg = 2 * p + u;
-        if (!sig_valid(sg)) continue;
-        const long long row = sig_row(sg);
-        const int c = sig_comp(sg);
-        T val = (a.flags & ROWF_CONST_E) ? a.E[c] : (T)a.real_in[c][row * n + x];
-        if (a.flags & ROWF_DL) val *= dl_at(row, x);
+        const int rl = ra + u;
+        if (rl >= rows_here) continue;
+        T val = (a.flags & ROWF_CONST_E) ? a.E[c] : (T)a.real_in[c][(row0 + rl) * n + x];
+        if (a.flags & ROWF_DL) val *= cond[ph[rl * n + x]] - a.l0;
         v[u] = val;
       }
       Z[p * ss + x] = cx<T>{v[0], v[1]};
     }
     __syncthreads();
   } else {
-    // Hermitian half rows of two signals -> one full complex row
-    for (int idx = tid; idx < npairs * h; idx += kThreads) {
-      const int p = idx / h;
-      const int k = idx - p * h;
+    // Hermitian half rows of two rows -> one full complex row
+    const int total = npairs * h;
+    for (int idx = tid; idx < total; idx += NT) {
+      int p, k;
+      if (a.row_fast) {
+        k = idx / npairs;
+        p = idx - k * npairs;
+      } else {
+        p = idx / h;
+        k = idx - p * h;
+      }
+      const int c = pair_comp(p);
+      const int ra = pair_row(p);
       cx<T> sa = {T(0), T(0)}, sb = {T(0), T(0)};
-      if (sig_valid(2 * p)) sa = a.spec[sig_comp(2 * p)][sig_row(2 * p) * h + k];
-      if (sig_valid(2 * p + 1)) sb = a.spec[sig_comp(2 * p + 1)][sig_row(2 * p + 1) * h + k];
+      const cx<T>* sp = a.spec[c];
+      if (ra < rows_here) sa = sp[(row0 + ra) * a.rs_row + k * a.rs_k];
+      if (ra + 1 < rows_here) sb = sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k];
       Z[p * ss + k] = cx<T>{sa.re - sb.im, sa.im + sb.re};
       if (k >= 1 && n - k >= h) Z[p * ss + n - k] = cx<T>{sa.re + sb.im, sb.re - sa.im};
     }
     __syncthreads();
-    fft_lds<T, +1, kThreads>(Z, npairs, ss, a.plan, a.tw, tid);
+    fft_lds<T, +1, NT>(Z, npairs, ss, a.plan, tw, tid);
 
     if (a.mode == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
-      for (int idx = tid; idx < npairs * n; idx += kThreads) {
+      for (int idx = tid; idx < npairs * n; idx += NT) {
         const int p = idx / n;
         const int x = idx - p * n;
+        const int c = pair_comp(p);
+        const int ra = pair_row(p);
         const cx<T> z = Z[p * ss + x];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const int sg = 2 * p + u;
-          if (!sig_valid(sg)) continue;
-          const long long row = sig_row(sg);
-          const int c = sig_comp(sg);
-          const long long g = row * n + x;
+          const int rl = ra + u;
+          if (rl >= rows_here) continue;
+          const long long g = (row0 + rl) * n + x;
           double val = (double)a.E[c] + (double)((u == 0 ? z.re : z.im) * a.inv_n);
           if (a.flags & ROWF_ADD) val += a.real_add[c][g];
           if (a.real_out[c]) a.real_out[c][g] = val;
-          if (a.flags & ROWF_LEFF) acc[c] += (double)a.cond[a.phase[g]] * val;
+          if (a.flags & ROWF_LEFF) acc[c] += (double)cond[ph[rl * n + x]] * val;
         }
       }
-      if (a.flags & ROWF_LEFF) grid_reduce_finalize<kThreads>(acc, d, a.partials, a.st, a.fin, (double)a.inv_n);
+      if (a.flags & ROWF_LEFF) {
+        double* dst = a.parts.region(PART_AUX) + (long long)blockIdx.x * 3;
+        for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);
+      }
       return;
     }
 
     // ROW_FUSED: polarisation dL (E + u) at the nodes (Sec. 2.2, Eq. (17))
-    for (int idx = tid; idx < npairs * n; idx += kThreads) {
+    for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = idx / n;
       const int x = idx - p * n;
+      const int c = pair_comp(p);
+      const int ra = pair_row(p);
       const cx<T> z = Z[p * ss + x];
-      T t[2] = {T(0), T(0)};
-      const T zz[2] = {z.re, z.im};
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int sg = 2 * p + u;
-        if (!sig_valid(sg)) continue;
-        const long long row = sig_row(sg);
-        const int c = sig_comp(sg);
-        t[u] = dl_at(row, x) * (a.E[c] + zz[u] * a.inv_n);
-      }
-      Z[p * ss + x] = cx<T>{t[0], t[1]};
+      T t0 = T(0), t1 = T(0);
+      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - a.l0) * (a.E[c] + z.re * a.inv_n);
+      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - a.l0) * (a.E[c] + z.im * a.inv_n);
+      Z[p * ss + x] = cx<T>{t0, t1};
     }
     __syncthreads();
   }
 
-  fft_lds<T, -1, kThreads>(Z, npairs, ss, a.plan, a.tw, tid);
+  fft_lds<T, -1, NT>(Z, npairs, ss, a.plan, tw, tid);
 
-  // split the two real signals' spectra and store the half rows
-  for (int idx = tid; idx < npairs * h; idx += kThreads) {
-    const int p = idx / h;
-    const int k = idx - p * h;
+  // split the two rows' spectra and store the half rows
+  const int total = npairs * h;
+  for (int idx = tid; idx < total; idx += NT) {
+    int p, k;
+    if (a.row_fast) {
+      k = idx / npairs;
+      p = idx - k * npairs;
+    } else {
+      p = idx / h;
+      k = idx - p * h;
+    }
+    const int c = pair_comp(p);
+    const int ra = pair_row(p);
     const cx<T> Y = Z[p * ss + k];
     const cx<T> Ym = Z[p * ss + (k == 0 ? 0 : n - k)];
     const T half = T(0.5);
-    const cx<T> ta = {(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
-    const cx<T> tb = {(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
-    if (sig_valid(2 * p)) a.spec[sig_comp(2 * p)][sig_row(2 * p) * h + k] = ta;
-    if (sig_valid(2 * p + 1)) a.spec[sig_comp(2 * p + 1)][sig_row(2 * p + 1) * h + k] = tb;
+    cx<T>* sp = a.spec[c];
+    if (ra < rows_here)
+      sp[(row0 + ra) * a.rs_row + k * a.rs_k] = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
+    if (ra + 1 < rows_here)
+      sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k] = cx<T>{(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
   }
 }
 
@@ -182,32 +232,50 @@ __global__ __launch_bounds__(kThreads) void row_kernel(RowArgs<T> a) {
 // Strided-axis pass
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void col_kernel(ColArgs<T> a) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   if (gated_out(a.st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   const int L = a.L, C = a.tile, ss = a.ss, d = a.d;
+  const int nseq = d * C;
+  cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + align16((size_t)nseq * ss * sizeof(cx<T>)));
+  stage_twiddles<T, NT>(tw, a.tw, L);
+
   const long long o = blockIdx.x / a.tiles_per_outer;
   const long long i0 = (long long)(blockIdx.x - o * a.tiles_per_outer) * C;
   const long long rem = a.inner - i0;
   const int width = rem < C ? (int)rem : C;
-  const int nseq = d * C;
+  const long long base_o = o * (long long)L * a.inner;
   const cx<T> zero = {T(0), T(0)};
+  // thread order over (l, c): c fastest in the natural layout, l fastest in
+  // the transposed one, so that global accesses are contiguous
+  const bool l_fast = a.sl == 1;
+  auto split = [&](int idx, int& l, int& c) {
+    if (l_fast) {
+      c = idx / L;
+      l = idx - c * L;
+    } else {
+      l = idx / C;
+      c = idx - l * C;
+    }
+  };
 
   if (a.mode == COL_INV_C) {
-    const T beta = a.fuse_p ? (T)a.st->beta : T(0);
-    for (int idx = tid; idx < L * C; idx += kThreads) {
-      const int l = idx / C;
-      const int c = idx - l * C;
+    double beta = 0.0;
+    if (a.cg_step && !cg_direction<NT>(a.st, a.parts, a.inv_n, &beta)) return;
+    const T tb = (T)beta;
+    for (int idx = tid; idx < L * C; idx += NT) {
+      int l, c;
+      split(idx, l, c);
       if (c < width) {
-        const long long g = (o * L + l) * a.inner + i0 + c;
+        const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
         cx<T> cv;
-        if (a.fuse_p) {
+        if (a.cg_step) {
           const cx<T> r = a.r_in[g];
           const cx<T> p = a.p_io[g];
-          cv = cx<T>{r.re + beta * p.re, r.im + beta * p.im};
+          cv = cx<T>{r.re + tb * p.re, r.im + tb * p.im};
           a.p_io[g] = cv;
         } else {
           cv = a.c_in[g];
@@ -223,23 +291,23 @@ __global__ __launch_bounds__(kThreads) void col_kernel(ColArgs<T> a) {
       }
     }
     __syncthreads();
-    fft_lds<T, +1, kThreads>(Z, nseq, ss, a.plan, a.tw, tid);
-    for (int idx = tid; idx < L * C; idx += kThreads) {
-      const int l = idx / C;
-      const int c = idx - l * C;
+    fft_lds<T, +1, NT>(Z, nseq, ss, a.plan, tw, tid);
+    for (int idx = tid; idx < L * C; idx += NT) {
+      int l, c;
+      split(idx, l, c);
       if (c < width) {
-        const long long g = (o * L + l) * a.inner + i0 + c;
+        const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
         for (int al = 0; al < d; ++al) a.comp[al][g] = Z[(al * C + c) * ss + l];
       }
     }
     return;
   }
 
-  for (int idx = tid; idx < L * C; idx += kThreads) {
-    const int l = idx / C;
-    const int c = idx - l * C;
+  for (int idx = tid; idx < L * C; idx += NT) {
+    int l, c;
+    split(idx, l, c);
     if (c < width) {
-      const long long g = (o * L + l) * a.inner + i0 + c;
+      const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
       for (int al = 0; al < d; ++al) Z[(al * C + c) * ss + l] = a.comp[al][g];
     } else {
       for (int al = 0; al < d; ++al) Z[(al * C + c) * ss + l] = zero;
@@ -249,14 +317,14 @@ __global__ __launch_bounds__(kThreads) void col_kernel(ColArgs<T> a) {
 
   if (a.mode == COL_PLAIN) {
     if (a.dir > 0)
-      fft_lds<T, +1, kThreads>(Z, nseq, ss, a.plan, a.tw, tid);
+      fft_lds<T, +1, NT>(Z, nseq, ss, a.plan, tw, tid);
     else
-      fft_lds<T, -1, kThreads>(Z, nseq, ss, a.plan, a.tw, tid);
-    for (int idx = tid; idx < L * C; idx += kThreads) {
-      const int l = idx / C;
-      const int c = idx - l * C;
+      fft_lds<T, -1, NT>(Z, nseq, ss, a.plan, tw, tid);
+    for (int idx = tid; idx < L * C; idx += NT) {
+      int l, c;
+      split(idx, l, c);
       if (c < width) {
-        const long long g = (o * L + l) * a.inner + i0 + c;
+        const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
         for (int al = 0; al < d; ++al) a.comp[al][g] = Z[(al * C + c) * ss + l];
       }
     }
@@ -264,14 +332,14 @@ __global__ __launch_bounds__(kThreads) void col_kernel(ColArgs<T> a) {
   }
 
   // COL_FWD_PROJ
-  fft_lds<T, -1, kThreads>(Z, nseq, ss, a.plan, a.tw, tid);
+  fft_lds<T, -1, NT>(Z, nseq, ss, a.plan, tw, tid);
   double acc = 0.0;
   const int n_last = a.nd[a.dims - 1];
-  for (int idx = tid; idx < L * C; idx += kThreads) {
-    const int l = idx / C;
-    const int c = idx - l * C;
+  for (int idx = tid; idx < L * C; idx += NT) {
+    int l, c;
+    split(idx, l, c);
     if (c < width) {
-      const long long g = (o * L + l) * a.inner + i0 + c;
+      const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
       double kh[kMaxDim];
       const bool nz = khat_axis0(a, l, i0 + c, kh);
       cx<T> t = zero;
@@ -301,40 +369,68 @@ __global__ __launch_bounds__(kThreads) void col_kernel(ColArgs<T> a) {
       }
     }
   }
-  if (a.dot) grid_reduce_finalize<kThreads>(&acc, 1, a.partials, a.st, a.fin, a.inv_n);
+  if (a.dot) {
+    store_partial<NT>(acc, a.parts.region(a.dot_region) + blockIdx.x);
+    if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) a.st->nparts[0] = (int)gridDim.x;
+  }
 }
 
 // ---------------------------------------------------------------------------
-// CG update: x += alpha p, r -= alpha q, (r, r)
+// CG update: alpha = (r, r) / (p, q); x += alpha p, r -= alpha q, (r, r)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void update_kernel(UpdArgs<T> a) {
+__global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
+  constexpr int NT = 256;
   if (gated_out(a.st, a.gate)) return;
-  const T alpha = (T)a.st->alpha;
+  const int k = a.st->iter_u;
+  const double rr = sum_partials<NT>(a.parts.region(k & 1), a.st->nparts[k & 1]) * a.inv_n;
+  const double pq = sum_partials<NT>(a.parts.region(PART_PQ), a.n_pq) * a.inv_n;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (lead) {
+      a.st->pq_log = pq;
+      a.st->status = -6;
+      a.st->done = 1;
+    }
+    return;
+  }
+  const double alpha = rr / pq;
+  const T ta = (T)alpha;
   double acc = 0.0;
-  const long long stride = (long long)gridDim.x * kThreads;
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < a.n; i += stride) {
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) {
     const cx<T> p = a.p[i];
     const cx<T> q = a.q[i];
     cx<T> x = a.x[i];
     cx<T> r = a.r[i];
-    x.re += alpha * p.re;
-    x.im += alpha * p.im;
-    r.re -= alpha * q.re;
-    r.im -= alpha * q.im;
+    x.re += ta * p.re;
+    x.im += ta * p.im;
+    r.re -= ta * q.re;
+    r.im -= ta * q.im;
     a.x[i] = x;
     a.r[i] = r;
-    const double w = half_weight(i % a.h, a.n_last);
+    const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
     acc += w * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
   }
-  grid_reduce_finalize<kThreads>(&acc, 1, a.partials, a.st, FIN_UPDATE, a.inv_n);
+  const int nxt = (k + 1) & 1;
+  store_partial<NT>(acc, a.parts.region(nxt) + blockIdx.x);
+  if (lead) {
+    a.st->nparts[nxt] = (int)gridDim.x;
+    a.st->iter_a = k + 1;
+    a.st->alpha_log = alpha;
+    a.st->pq_log = pq;
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void mix_accumulate_kernel(MixArgs a) {
+// ---------------------------------------------------------------------------
+// Mixed precision helpers
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void mix_accumulate_kernel(MixArgs a) {
   if (gated_out(a.st, a.gate)) return;
-  const long long stride = (long long)gridDim.x * kThreads;
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < a.n; i += stride) {
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
     const cx<float> y = a.x32[i];
     cx<double> x = a.x64[i];
     x.re += (double)y.re;
@@ -344,26 +440,99 @@ __global__ __launch_bounds__(kThreads) void mix_accumulate_kernel(MixArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kThreads) void mix_convert_kernel(MixArgs a) {
+__global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
   if (gated_out(a.st, a.gate)) return;
-  const long long stride = (long long)gridDim.x * kThreads;
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < a.n; i += stride) {
+  const int k = a.st->iter_a;
+  double acc = 0.0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
     const cx<double> r = a.r64[i];
-    a.r32[i] = cx<float>{(float)r.re, (float)r.im};
+    const cx<float> f = cx<float>{(float)r.re, (float)r.im};
+    a.r32[i] = f;
+    const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
+    acc += w * ((double)f.re * (double)f.re + (double)f.im * (double)f.im);
   }
-  if (a.clear_refresh) {
-    // every block must have read the flag before it is cleared
-    double none = 0.0;
-    grid_reduce_finalize<kThreads>(&none, 1, a.partials, a.st, FIN_CLEAR_REFRESH, 1.0);
+  store_partial<256>(acc, a.parts.region(k & 1) + blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->nparts[k & 1] = (int)gridDim.x;
+}
+
+// ---------------------------------------------------------------------------
+// Single-block scalar steps
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+  constexpr int NT = 256;
+  if (gated_out(a.st, a.gate)) return;
+  DevState* st = a.st;
+  const bool lead = threadIdx.x == 0;
+  switch (a.mode) {
+    case FZ_CHECK: {
+      const int m = st->iter_a;
+      const double rr = sum_partials<NT>(a.parts.region(m & 1), st->nparts[m & 1]) * a.inv_n;
+      if (lead) {
+        st->rr_log = rr;
+        if (!isfinite(rr)) {
+          st->status = -6;
+          st->done = 1;
+        } else if (rr <= st->tol2b2) {
+          st->done = 1;
+        } else if (m >= st->max_iter) {
+          st->status = -5;
+          st->done = 1;
+        }
+      }
+      break;
+    }
+    case FZ_AUX: {
+      const double s = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      if (lead) st->dot_aux = s;
+      break;
+    }
+    case FZ_RR_TRUE: {
+      const double s = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      if (lead) st->rr_true = s;
+      break;
+    }
+    case FZ_LEFF: {
+      for (int c = 0; c < a.d; ++c) {
+        const double s = sum_partials<NT>(a.parts.region(PART_AUX) + c, a.n, 3) * a.inv_n;
+        if (lead) st->leff[c] = s;
+      }
+      break;
+    }
+    case FZ_REFRESH:
+    case FZ_REFRESH_INIT: {
+      const double rr = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      if (lead) {
+        st->rr_true = rr;
+        st->rr_ref = rr;
+        st->rr_log = rr;
+        st->k_ref = st->iter_a;
+        if (a.mode == FZ_REFRESH) st->n_refresh += 1;
+        st->refresh = 0;
+        if (!isfinite(rr)) {
+          st->status = -6;
+          st->done = 1;
+        } else if (rr <= st->tol2b2) {
+          st->done = 1;
+        } else if (st->iter_a >= st->max_iter) {
+          st->status = -5;
+          st->done = 1;
+        }
+      }
+      break;
+    }
+    default:
+      break;
   }
 }
 
 __global__ void state_init_kernel(DevState* st, DevState init) { *st = init; }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void fill_zero_kernel(cx<T>* p, long long n) {
-  const long long stride = (long long)gridDim.x * kThreads;
-  for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+__global__ __launch_bounds__(256) void fill_zero_kernel(cx<T>* p, long long n) {
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
     p[i] = cx<T>{T(0), T(0)};
 }
 
@@ -371,19 +540,22 @@ __global__ __launch_bounds__(kThreads) void fill_zero_kernel(cx<T>* p, long long
 // Host launchers
 // ---------------------------------------------------------------------------
 
-static int odd_stride(int n) { return (n & 1) ? n : n + 1; }
+int lds_odd_stride(int n) { return (n & 1) ? n : n + 1; }
 
-size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int* ss_out) {
-  const int ss = odd_stride(n);
+size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int n_phases, int* ss_out) {
+  const int ss = lds_odd_stride(n);
   if (ss_out) *ss_out = ss;
-  const int npairs = (d * rows_per_block + 1) / 2;
-  return (size_t)npairs * ss * elem_bytes;
+  const int npairs = d * (rows_per_block / 2);
+  size_t off = align16((size_t)npairs * ss * elem_bytes);
+  off = align16(off + (size_t)n * elem_bytes);
+  off = align16(off + (size_t)n_phases * (size_t)(elem_bytes / 2));
+  return off + (size_t)rows_per_block * n + 16;
 }
 
 size_t col_lds_bytes(int L, int tile, int d, int elem_bytes, int* ss_out) {
-  const int ss = odd_stride(L);
+  const int ss = lds_odd_stride(L);
   if (ss_out) *ss_out = ss;
-  return (size_t)d * tile * ss * elem_bytes;
+  return align16((size_t)d * tile * ss * elem_bytes) + (size_t)L * elem_bytes;
 }
 
 template <typename T>
@@ -397,15 +569,37 @@ long long col_blocks(const ColArgs<T>& a) {
 }
 
 long long update_blocks(long long n) {
-  long long b = (n + kThreads - 1) / kThreads;
-  return b > 2048 ? 2048 : (b < 1 ? 1 : b);
+  long long b = (n + 255) / 256;
+  return b > kUpdateBlocks ? kUpdateBlocks : (b < 1 ? 1 : b);
+}
+
+// Block size: 128 threads when the batch fits their butterfly capacity.
+static int pick_threads(int points, const FftPlan& plan) {
+  return points <= plan_batch_cap(plan, 128) ? 128 : 256;
+}
+
+// Largest phase index of a phase image (validation at workspace set-up).
+__global__ __launch_bounds__(256) void max_phase_kernel(const uint8_t* ph, long long n, unsigned* out) {
+  unsigned m = 0;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) m = max(m, (unsigned)ph[i]);
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_down((int)m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipStream_t s) {
+  hipLaunchKernelGGL(max_phase_kernel, dim3((unsigned)update_blocks(n)), dim3(256), 0, s, ph, n, out);
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_row(const RowArgs<T>& a, hipStream_t s) {
-  const size_t lds = row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), nullptr);
+  const size_t lds = row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), a.n_phases, nullptr);
   const long long nb = row_blocks(a);
-  hipLaunchKernelGGL(row_kernel<T>, dim3((unsigned)nb), dim3(kThreads), lds, s, a);
+  if (pick_threads(a.d * (a.rows_per_block / 2) * a.n, a.plan) == 128)
+    hipLaunchKernelGGL((row_kernel<T, 128>), dim3((unsigned)nb), dim3(128), lds, s, a);
+  else
+    hipLaunchKernelGGL((row_kernel<T, 256>), dim3((unsigned)nb), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
@@ -413,23 +607,31 @@ template <typename T>
 hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
   const size_t lds = col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), nullptr);
   const long long nb = col_blocks(a);
-  hipLaunchKernelGGL(col_kernel<T>, dim3((unsigned)nb), dim3(kThreads), lds, s, a);
+  if (pick_threads(a.d * a.tile * a.L, a.plan) == 128)
+    hipLaunchKernelGGL((col_kernel<T, 128>), dim3((unsigned)nb), dim3(128), lds, s, a);
+  else
+    hipLaunchKernelGGL((col_kernel<T, 256>), dim3((unsigned)nb), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)a.blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mix_accumulate_kernel, dim3((unsigned)a.blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(mix_accumulate_kernel, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mix_convert_kernel, dim3((unsigned)a.blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(mix_convert_kernel, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -440,8 +642,7 @@ hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s) 
 
 template <typename T>
 hipError_t launch_fill_zero(cx<T>* p, long long n, hipStream_t s) {
-  const long long nb = update_blocks(n);
-  hipLaunchKernelGGL(fill_zero_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, p, n);
+  hipLaunchKernelGGL(fill_zero_kernel<T>, dim3((unsigned)update_blocks(n)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

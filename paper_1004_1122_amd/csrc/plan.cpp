@@ -61,40 +61,46 @@ void twiddles(int n, std::vector<double>* re_im) {
 
 static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
+constexpr int kMaxThreads = 256;
+
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
-                        size_t lds_budget, long long min_blocks) {
-  PassShape s{1, 1, 1};
+                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases) {
+  PassShape s{2, 1, 1};
   const int last = d - 1;
   const int n_last = (int)N[last];
   const long long h = n_last / 2 + 1;
   long long nrows = 1;
   for (int a = 0; a < last; ++a) nrows *= N[a];
 
-  // row pass: pairs of real signals, npairs * n points per FFT batch
+  // row pass: even row counts; in the transposed layout each global access
+  // covers rows_per_block contiguous elements, so aim for 64-byte segments
   {
-    const int cap = plan_batch_cap(plans[last], kThreads);
-    int best = 1;
-    for (int r = 1; r <= 64; ++r) {
-      const int npairs = (d * r + 1) / 2;
-      if ((long long)npairs * n_last > cap) break;
-      if (row_lds_bytes(n_last, r, d, elem_bytes, nullptr) > lds_budget) break;
-      if (d == 3 && (r & 1)) continue;
+    const int cap = plan_batch_cap(plans[last], kMaxThreads);
+    const int target = transposed ? (64 / elem_bytes < 2 ? 2 : 64 / elem_bytes) : 64;
+    int best = 2;
+    for (int r = 2; r <= target; r += 2) {
+      if ((long long)d * (r / 2) * n_last > cap) break;
+      if (row_lds_bytes(n_last, r, d, elem_bytes, n_phases, nullptr) > lds_budget) break;
       best = r;
+      if (!transposed && (long long)d * (r / 2) * n_last >= 2048) break;
     }
-    while (best > 1 && ceil_div(nrows, best) < min_blocks) best -= (d == 3 && best > 2) ? 2 : 1;
+    while (best > 2 && ceil_div(nrows, best) < min_blocks) best -= 2;
     s.rows_per_block = best;
   }
-  // axis 0: inner = (N1 ...) * h
+  // strided passes: contiguous columns need no tile (transposed); in the
+  // natural layout a tile of `c` columns makes c * elem_bytes-byte segments
   auto pick_tile = [&](int L, long long inner, long long outer, const FftPlan& pl) {
-    const int cap = plan_batch_cap(pl, kThreads);
+    if (transposed) return 1;
+    const int cap = plan_batch_cap(pl, kMaxThreads);
     int best = 1;
-    for (int c = 1; c <= 64; ++c) {
+    for (int c = 1; c <= 16; c *= 2) {
       if ((long long)d * c * L > cap) break;
       if (col_lds_bytes(L, c, d, elem_bytes, nullptr) > lds_budget) break;
       if (c > inner) break;
       best = c;
+      if (c * elem_bytes >= 64) break;
     }
-    while (best > 1 && outer * ceil_div(inner, best) < min_blocks) best -= 1;
+    while (best > 1 && outer * ceil_div(inner, best) < min_blocks) best /= 2;
     return best;
   };
   long long inner0 = h;
@@ -105,18 +111,20 @@ PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_
 }
 
 bool shape_fits(int d, const int64_t* N, const FftPlan* plans, const PassShape& s, int elem_bytes,
-                size_t lds_budget) {
+                size_t lds_budget, int n_phases) {
   const int last = d - 1;
   const int n_last = (int)N[last];
+  if (s.rows_per_block < 2 || (s.rows_per_block & 1)) return false;
+  if (s.tile0 < 1 || s.tile1 < 1) return false;
   {
-    const int npairs = (d * s.rows_per_block + 1) / 2;
-    if ((long long)npairs * n_last > plan_batch_cap(plans[last], kThreads)) return false;
-    if (row_lds_bytes(n_last, s.rows_per_block, d, elem_bytes, nullptr) > lds_budget) return false;
+    const int npairs = d * (s.rows_per_block / 2);
+    if ((long long)npairs * n_last > plan_batch_cap(plans[last], kMaxThreads)) return false;
+    if (row_lds_bytes(n_last, s.rows_per_block, d, elem_bytes, n_phases, nullptr) > lds_budget) return false;
   }
-  if ((long long)d * s.tile0 * N[0] > plan_batch_cap(plans[0], kThreads)) return false;
+  if ((long long)d * s.tile0 * N[0] > plan_batch_cap(plans[0], kMaxThreads)) return false;
   if (col_lds_bytes((int)N[0], s.tile0, d, elem_bytes, nullptr) > lds_budget) return false;
   if (d == 3) {
-    if ((long long)d * s.tile1 * N[1] > plan_batch_cap(plans[1], kThreads)) return false;
+    if ((long long)d * s.tile1 * N[1] > plan_batch_cap(plans[1], kMaxThreads)) return false;
     if (col_lds_bytes((int)N[1], s.tile1, d, elem_bytes, nullptr) > lds_budget) return false;
   }
   return true;

@@ -24,19 +24,20 @@ void twiddles(int n, std::vector<double>* re_im);
 
 // Launch shape of the passes of one problem and precision.
 struct PassShape {
-  int rows_per_block;    // row pass
+  int rows_per_block;    // row pass (even)
   int tile0;             // axis-0 pass tile
   int tile1;             // axis-1 pass tile (3-D)
 };
 
-// Largest shapes that fit the FFT batch limit and lds_budget bytes of LDS,
-// reduced while a pass would have fewer than min_blocks blocks.
+// Default shapes within the FFT batch limit (256 threads) and lds_budget
+// bytes of LDS, reduced while a pass would have fewer than min_blocks blocks.
+// `transposed`: 2-D spectral arrays stored [k1][k0] (columns contiguous).
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
-                        size_t lds_budget, long long min_blocks);
+                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases);
 
 // True when every pass of the shape respects the FFT batch limit and the LDS
 // budget (otherwise the problem is unsupported at this precision).
 bool shape_fits(int d, const int64_t* N, const FftPlan* plans, const PassShape& s, int elem_bytes,
-                size_t lds_budget);
+                size_t lds_budget, int n_phases);
 
 }  // namespace lshom

@@ -265,9 +265,9 @@ def test_out_of_range_phase_is_loud():
     from paper_1004_1122_amd import lshom
     phase = np.zeros((27, 27), dtype=np.uint8)
     phase[3, 3] = 5                       # only 2 phases declared
-    s = _solver(phase, [1.0, 3.0])
-    with pytest.raises(lshom.LshomError):
-        s.solve([1.0, 0.0], tol=1e-8)
+    with pytest.raises(lshom.LshomError) as ex:
+        _solver(phase, [1.0, 3.0])        # rejected when the workspace is attached
+    assert ex.value.status == lshom.LSHOM_ERR_INVALID_ARG and "n_phases" in str(ex.value)
 
 
 # ---------------------------------------------------------------------------
