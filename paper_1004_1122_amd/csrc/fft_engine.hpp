@@ -153,7 +153,7 @@ struct FftPlan {
 // Butterflies held per thread across the stage barrier, per radix.  The host
 // sizes every batch so that nseq * n / R <= jobs_per_thread(R) * threads.
 __host__ __device__ constexpr int jobs_per_thread(int R) {
-  return R <= 3 ? 6 : (R <= 5 ? 4 : (R <= 7 ? 3 : 2));
+  return R <= 3 ? 4 : (R <= 5 ? 3 : 2);
 }
 
 // Largest number of points (nseq * n) one batch may hold for a plan.
@@ -215,27 +215,57 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
   __syncthreads();
 }
 
+// Radix sets a kernel is compiled for: the register footprint of a kernel is
+// that of its largest butterfly, so grids whose lengths are powers of 3 (or
+// of 2) get kernels without the radix-5/7 code.
+enum RadixSet : int { RADIX_POW3 = 0, RADIX_POW2 = 1, RADIX_ALL = 2 };
+
+__host__ __device__ inline bool radix_in_set(int R, int set) {
+  if (set == RADIX_POW3) return R == 3 || R == 9;
+  if (set == RADIX_POW2) return R == 2 || R == 4 || R == 8;
+  return R >= 2 && R <= 9;
+}
+
 // Transform nseq sequences of length plan.n in LDS.  Callers synchronise
-// before (data written) and may read the result right after.
-template <typename T, int S, int NT>
+// before (data written) and may read the result right after.  Every radix of
+// the plan must belong to RS.
+template <typename T, int S, int NT, int RS>
 __device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
                         const cx<T>* __restrict__ tw, int tid) {
   int Ns = 1;
   for (int st = 0; st < plan.nstages; ++st) {
     const int R = plan.radix[st];
-    switch (R) {
-      case 2: fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 3: fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 4: fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 5: fft_stage<T, 5, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 6: fft_stage<T, 6, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-      default: break;
+    if constexpr (RS == RADIX_POW3) {
+      if (R == 9) fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+      else fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+    } else if constexpr (RS == RADIX_POW2) {
+      if (R == 8) fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+      else if (R == 4) fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+      else fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+    } else {
+      switch (R) {
+        case 2: fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 3: fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 4: fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 5: fft_stage<T, 5, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 6: fft_stage<T, 6, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        default: break;
+      }
     }
     Ns *= R;
   }
+}
+
+__host__ __device__ inline int plan_radix_set(const FftPlan& p) {
+  bool p3 = true, p2 = true;
+  for (int s = 0; s < p.nstages; ++s) {
+    p3 = p3 && radix_in_set(p.radix[s], RADIX_POW3);
+    p2 = p2 && radix_in_set(p.radix[s], RADIX_POW2);
+  }
+  return p3 ? RADIX_POW3 : (p2 ? RADIX_POW2 : RADIX_ALL);
 }
 
 }  // namespace lshom

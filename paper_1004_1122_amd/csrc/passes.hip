@@ -43,19 +43,25 @@ __device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long
     idx[1] = (int)(ii / a.h);
     idx[2] = (int)(ii - (long long)idx[1] * a.h);
   }
+  if (a.dims == 2) idx[2] = 0;
   double k2 = 0.0;
   double kf[kMaxDim];
-  for (int t = 0; t < a.dims; ++t) {
-    const int n = a.nd[t];
-    if ((n & 1) == 0 && idx[t] == n / 2) return false;
-    // the last axis is stored as its non-negative half
-    const int k = (t == a.dims - 1) ? idx[t] : freq_of(idx[t], n);
-    kf[t] = (double)k;
-    k2 += kf[t] * kf[t];
+#pragma unroll
+  for (int t = 0; t < kMaxDim; ++t) {
+    kf[t] = 0.0;
+    if (t < a.dims) {
+      const int n = a.nd[t];
+      if ((n & 1) == 0 && idx[t] == n / 2) return false;
+      // the last axis is stored as its non-negative half
+      const int k = (t == a.dims - 1) ? idx[t] : freq_of(idx[t], n);
+      kf[t] = (double)k;
+      k2 += kf[t] * kf[t];
+    }
   }
   if (k2 == 0.0) return false;
   const double inv = 1.0 / sqrt(k2);
-  for (int t = 0; t < a.dims; ++t) kh[t] = kf[t] * inv;
+#pragma unroll
+  for (int t = 0; t < kMaxDim; ++t) kh[t] = kf[t] * inv;
   return true;
 }
 
@@ -67,18 +73,44 @@ __device__ __forceinline__ double half_weight(long long k_last, int n_last) {
   return 2.0;
 }
 
-template <typename T, int NT>
-__device__ __forceinline__ void stage_twiddles(cx<T>* dst, const cx<T>* __restrict__ src, int n) {
-  for (int i = threadIdx.x; i < n; i += NT) dst[i] = src[i];
+// Loads in flight per thread in the staging and data loops: with few blocks
+// per CU (small grids) latency, not bandwidth, bounds a pass, so every loop
+// issues kBatch independent global loads before it waits.
+constexpr int kBatch = 4;
+
+// Copy n elements global -> LDS with kBatch loads in flight per thread.
+template <typename V, int NT>
+__device__ __forceinline__ void copy_batched(V* dst, const V* __restrict__ src, int n) {
+  for (int base = 0; base < n; base += NT * kBatch) {
+    V r[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * NT + (int)threadIdx.x;
+      r[u] = V{};
+      if (i < n) r[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * NT + (int)threadIdx.x;
+      if (i < n) dst[i] = r[u];
+    }
+  }
 }
 
 static __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// arr[c] for a small runtime c without dynamic indexing (which would place
+// the array in scratch memory)
+template <typename V>
+__device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
+  return c == 0 ? arr[0] : (c == 1 ? arr[1] : arr[2]);
+}
 
 // ---------------------------------------------------------------------------
 // Row pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT>
+template <typename T, int NT, int RS>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   if (gated_out(a.st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -97,21 +129,18 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int rows_here = (int)((a.nrows - row0) < R ? (a.nrows - row0) : R);
 
   // stage twiddles, conductivities and phases (they overlap the data loads)
-  stage_twiddles<T, NT>(tw, a.tw, n);
-  for (int i = tid; i < a.n_phases; i += NT) cond[i] = a.cond[i];
+  copy_batched<cx<T>, NT>(tw, a.tw, n);
+  copy_batched<T, NT>(cond, a.cond, a.n_phases);
   const bool need_phase = (a.mode == ROW_FUSED) || (a.mode == ROW_FWD && (a.flags & ROWF_DL)) ||
                           (a.mode == ROW_INV && (a.flags & ROWF_LEFF));
   if (need_phase) {
     const uint8_t* src = a.phase + row0 * n;
     const int nb = rows_here * n;
     // 4-byte loads where the row block is aligned
-    if (((reinterpret_cast<uintptr_t>(src) & 3) == 0) && ((nb & 3) == 0)) {
-      const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
-      uint32_t* d4 = reinterpret_cast<uint32_t*>(ph);
-      for (int i = tid; i < nb / 4; i += NT) d4[i] = s4[i];
-    } else {
-      for (int i = tid; i < nb; i += NT) ph[i] = src[i];
-    }
+    if (((reinterpret_cast<uintptr_t>(src) & 3) == 0) && ((nb & 3) == 0))
+      copy_batched<uint32_t, NT>(reinterpret_cast<uint32_t*>(ph), reinterpret_cast<const uint32_t*>(src), nb / 4);
+    else
+      copy_batched<uint8_t, NT>(ph, src, nb);
   }
 
   // pair p: component c = p / half_rows, rows 2j and 2j+1 with j = p % half_rows
@@ -130,7 +159,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       for (int u = 0; u < 2; ++u) {
         const int rl = ra + u;
         if (rl >= rows_here) continue;
-        T val = (a.flags & ROWF_CONST_E) ? a.E[c] : (T)a.real_in[c][(row0 + rl) * n + x];
+        T val = (a.flags & ROWF_CONST_E) ? pick3(a.E, c) : (T)pick3(a.real_in, c)[(row0 + rl) * n + x];
         if (a.flags & ROWF_DL) val *= cond[ph[rl * n + x]] - a.l0;
         v[u] = val;
       }
@@ -140,26 +169,44 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   } else {
     // Hermitian half rows of two rows -> one full complex row
     const int total = npairs * h;
-    for (int idx = tid; idx < total; idx += NT) {
-      int p, k;
-      if (a.row_fast) {
-        k = idx / npairs;
-        p = idx - k * npairs;
-      } else {
-        p = idx / h;
-        k = idx - p * h;
+    for (int base = 0; base < total; base += NT * kBatch) {
+      cx<T> sa[kBatch], sb[kBatch];
+      int pk[kBatch], kk[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * NT + tid;
+        sa[u] = cx<T>{T(0), T(0)};
+        sb[u] = cx<T>{T(0), T(0)};
+        pk[u] = -1;
+        kk[u] = 0;
+        if (idx < total) {
+          int p, k;
+          if (a.row_fast) {
+            k = idx / npairs;
+            p = idx - k * npairs;
+          } else {
+            p = idx / h;
+            k = idx - p * h;
+          }
+          pk[u] = p;
+          kk[u] = k;
+          const int c = pair_comp(p);
+          const int ra = pair_row(p);
+          const cx<T>* sp = pick3(a.spec, c);
+          if (ra < rows_here) sa[u] = sp[(row0 + ra) * a.rs_row + k * a.rs_k];
+          if (ra + 1 < rows_here) sb[u] = sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k];
+        }
       }
-      const int c = pair_comp(p);
-      const int ra = pair_row(p);
-      cx<T> sa = {T(0), T(0)}, sb = {T(0), T(0)};
-      const cx<T>* sp = a.spec[c];
-      if (ra < rows_here) sa = sp[(row0 + ra) * a.rs_row + k * a.rs_k];
-      if (ra + 1 < rows_here) sb = sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k];
-      Z[p * ss + k] = cx<T>{sa.re - sb.im, sa.im + sb.re};
-      if (k >= 1 && n - k >= h) Z[p * ss + n - k] = cx<T>{sa.re + sb.im, sb.re - sa.im};
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        if (pk[u] < 0) continue;
+        const int p = pk[u], k = kk[u];
+        Z[p * ss + k] = cx<T>{sa[u].re - sb[u].im, sa[u].im + sb[u].re};
+        if (k >= 1 && n - k >= h) Z[p * ss + n - k] = cx<T>{sa[u].re + sb[u].im, sb[u].re - sa[u].im};
+      }
     }
     __syncthreads();
-    fft_lds<T, +1, NT>(Z, npairs, ss, a.plan, tw, tid);
+    fft_lds<T, +1, NT, RS>(Z, npairs, ss, a.plan, tw, tid);
 
     if (a.mode == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
@@ -174,10 +221,16 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           const int rl = ra + u;
           if (rl >= rows_here) continue;
           const long long g = (row0 + rl) * n + x;
-          double val = (double)a.E[c] + (double)((u == 0 ? z.re : z.im) * a.inv_n);
-          if (a.flags & ROWF_ADD) val += a.real_add[c][g];
-          if (a.real_out[c]) a.real_out[c][g] = val;
-          if (a.flags & ROWF_LEFF) acc[c] += (double)cond[ph[rl * n + x]] * val;
+          double val = (double)pick3(a.E, c) + (double)((u == 0 ? z.re : z.im) * a.inv_n);
+          if (a.flags & ROWF_ADD) val += pick3(a.real_add, c)[g];
+          double* out = pick3(a.real_out, c);
+          if (out) out[g] = val;
+          if (a.flags & ROWF_LEFF) {
+            const double jv = (double)cond[ph[rl * n + x]] * val;
+#pragma unroll
+            for (int cc = 0; cc < kMaxDim; ++cc)
+              if (cc == c) acc[cc] += jv;
+          }
         }
       }
       if (a.flags & ROWF_LEFF) {
@@ -195,14 +248,15 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       const int ra = pair_row(p);
       const cx<T> z = Z[p * ss + x];
       T t0 = T(0), t1 = T(0);
-      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - a.l0) * (a.E[c] + z.re * a.inv_n);
-      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - a.l0) * (a.E[c] + z.im * a.inv_n);
+      const T Ec = pick3(a.E, c);
+      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - a.l0) * (Ec + z.re * a.inv_n);
+      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - a.l0) * (Ec + z.im * a.inv_n);
       Z[p * ss + x] = cx<T>{t0, t1};
     }
     __syncthreads();
   }
 
-  fft_lds<T, -1, NT>(Z, npairs, ss, a.plan, tw, tid);
+  fft_lds<T, -1, NT, RS>(Z, npairs, ss, a.plan, tw, tid);
 
   // split the two rows' spectra and store the half rows
   const int total = npairs * h;
@@ -220,7 +274,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     const cx<T> Y = Z[p * ss + k];
     const cx<T> Ym = Z[p * ss + (k == 0 ? 0 : n - k)];
     const T half = T(0.5);
-    cx<T>* sp = a.spec[c];
+    cx<T>* sp = pick3(a.spec, c);
     if (ra < rows_here)
       sp[(row0 + ra) * a.rs_row + k * a.rs_k] = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
     if (ra + 1 < rows_here)
@@ -232,7 +286,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 // Strided-axis pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT>
+template <typename T, int NT, int RS>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   if (gated_out(a.st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -241,7 +295,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int nseq = d * C;
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + align16((size_t)nseq * ss * sizeof(cx<T>)));
-  stage_twiddles<T, NT>(tw, a.tw, L);
+  copy_batched<cx<T>, NT>(tw, a.tw, L);
 
   const long long o = blockIdx.x / a.tiles_per_outer;
   const long long i0 = (long long)(blockIdx.x - o * a.tiles_per_outer) * C;
@@ -266,85 +320,155 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
     double beta = 0.0;
     if (a.cg_step && !cg_direction<NT>(a.st, a.parts, a.inv_n, &beta)) return;
     const T tb = (T)beta;
-    for (int idx = tid; idx < L * C; idx += NT) {
-      int l, c;
-      split(idx, l, c);
-      if (c < width) {
-        const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-        cx<T> cv;
-        if (a.cg_step) {
-          const cx<T> r = a.r_in[g];
-          const cx<T> p = a.p_io[g];
-          cv = cx<T>{r.re + tb * p.re, r.im + tb * p.im};
-          a.p_io[g] = cv;
+    const int total = L * C;
+    for (int base = 0; base < total; base += NT * kBatch) {
+      cx<T> rv[kBatch], pv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * NT + tid;
+        rv[u] = zero;
+        pv[u] = zero;
+        if (idx < total) {
+          int l, c;
+          split(idx, l, c);
+          if (c < width) {
+            const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
+            if (a.cg_step) {
+              rv[u] = a.r_in[g];
+              pv[u] = a.p_io[g];
+            } else {
+              rv[u] = a.c_in[g];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * NT + tid;
+        if (idx >= total) continue;
+        int l, c;
+        split(idx, l, c);
+        if (c < width) {
+          const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
+          cx<T> cv = rv[u];
+          if (a.cg_step) {
+            cv = cx<T>{rv[u].re + tb * pv[u].re, rv[u].im + tb * pv[u].im};
+            a.p_io[g] = cv;
+          }
+          double kh[kMaxDim];
+          const bool nz = khat_axis0(a, l, i0 + c, kh);
+#pragma unroll
+          for (int al = 0; al < kMaxDim; ++al) {
+            if (al >= d) break;
+            const T k = nz ? (T)kh[al] : T(0);
+            Z[(al * C + c) * ss + l] = cx<T>{-k * cv.im, k * cv.re};  // i khat_a c
+          }
         } else {
-          cv = a.c_in[g];
+#pragma unroll
+          for (int al = 0; al < kMaxDim; ++al)
+            if (al < d) Z[(al * C + c) * ss + l] = zero;
         }
-        double kh[kMaxDim];
-        const bool nz = khat_axis0(a, l, i0 + c, kh);
-        for (int al = 0; al < d; ++al) {
-          const T k = nz ? (T)kh[al] : T(0);
-          Z[(al * C + c) * ss + l] = cx<T>{-k * cv.im, k * cv.re};  // i khat_a c
-        }
-      } else {
-        for (int al = 0; al < d; ++al) Z[(al * C + c) * ss + l] = zero;
       }
     }
     __syncthreads();
-    fft_lds<T, +1, NT>(Z, nseq, ss, a.plan, tw, tid);
+    fft_lds<T, +1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
     for (int idx = tid; idx < L * C; idx += NT) {
       int l, c;
       split(idx, l, c);
       if (c < width) {
         const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-        for (int al = 0; al < d; ++al) a.comp[al][g] = Z[(al * C + c) * ss + l];
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al)
+          if (al < d) a.comp[al][g] = Z[(al * C + c) * ss + l];
       }
     }
     return;
   }
 
-  for (int idx = tid; idx < L * C; idx += NT) {
-    int l, c;
-    split(idx, l, c);
-    if (c < width) {
-      const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-      for (int al = 0; al < d; ++al) Z[(al * C + c) * ss + l] = a.comp[al][g];
-    } else {
-      for (int al = 0; al < d; ++al) Z[(al * C + c) * ss + l] = zero;
+  {
+    const int total = L * C;
+    for (int base = 0; base < total; base += NT * kBatch) {
+      cx<T> v[kBatch][kMaxDim];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * NT + tid;
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al) v[u][al] = zero;
+        if (idx < total) {
+          int l, c;
+          split(idx, l, c);
+          if (c < width) {
+            const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
+#pragma unroll
+            for (int al = 0; al < kMaxDim; ++al)
+              if (al < d) v[u][al] = a.comp[al][g];
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = base + u * NT + tid;
+        if (idx >= total) continue;
+        int l, c;
+        split(idx, l, c);
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al)
+          if (al < d) Z[(al * C + c) * ss + l] = v[u][al];
+      }
     }
   }
   __syncthreads();
 
   if (a.mode == COL_PLAIN) {
     if (a.dir > 0)
-      fft_lds<T, +1, NT>(Z, nseq, ss, a.plan, tw, tid);
+      fft_lds<T, +1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
     else
-      fft_lds<T, -1, NT>(Z, nseq, ss, a.plan, tw, tid);
+      fft_lds<T, -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
     for (int idx = tid; idx < L * C; idx += NT) {
       int l, c;
       split(idx, l, c);
       if (c < width) {
         const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-        for (int al = 0; al < d; ++al) a.comp[al][g] = Z[(al * C + c) * ss + l];
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al)
+          if (al < d) a.comp[al][g] = Z[(al * C + c) * ss + l];
       }
     }
     return;
   }
 
   // COL_FWD_PROJ
-  fft_lds<T, -1, NT>(Z, nseq, ss, a.plan, tw, tid);
+  fft_lds<T, -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
   double acc = 0.0;
   const int n_last = a.nd[a.dims - 1];
-  for (int idx = tid; idx < L * C; idx += NT) {
-    int l, c;
-    split(idx, l, c);
-    if (c < width) {
+  const int total = L * C;
+  for (int base = 0; base < total; base += NT * kBatch) {
+    cx<T> bv[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int idx = base + u * NT + tid;
+      bv[u] = zero;
+      if (a.base && idx < total) {
+        int l, c;
+        split(idx, l, c);
+        if (c < width) bv[u] = a.base[base_o + l * a.sl + (i0 + c) * a.sii];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int idx = base + u * NT + tid;
+      if (idx >= total) continue;
+      int l, c;
+      split(idx, l, c);
+      if (c >= width) continue;
       const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
       double kh[kMaxDim];
       const bool nz = khat_axis0(a, l, i0 + c, kh);
       cx<T> t = zero;
       if (nz) {
-        for (int al = 0; al < d; ++al) {
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al) {
+          if (al >= d) break;
           const cx<T> v = Z[(al * C + c) * ss + l];
           const T k = (T)kh[al];
           t.re += k * v.re;
@@ -353,12 +477,9 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       }
       // s = -i khat . tau_hat
       cx<T> val = {a.coef_s * t.im, -a.coef_s * t.re};
-      cx<T> b = zero;
-      if (a.base) {
-        b = a.base[g];
-        val.re += a.coef_base * b.re;
-        val.im += a.coef_base * b.im;
-      }
+      const cx<T> b = bv[u];
+      val.re += a.coef_base * b.re;
+      val.im += a.coef_base * b.im;
       a.out[g] = val;
       if (a.dot) {
         const double w = half_weight((i0 + c) % a.h, n_last);
@@ -399,19 +520,31 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   const T ta = (T)alpha;
   double acc = 0.0;
   const long long stride = (long long)gridDim.x * NT;
-  for (long long i = (long long)blockIdx.x * NT + threadIdx.x; i < a.n; i += stride) {
-    const cx<T> p = a.p[i];
-    const cx<T> q = a.q[i];
-    cx<T> x = a.x[i];
-    cx<T> r = a.r[i];
-    x.re += ta * p.re;
-    x.im += ta * p.im;
-    r.re -= ta * q.re;
-    r.im -= ta * q.im;
-    a.x[i] = x;
-    a.r[i] = r;
-    const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
-    acc += w * ((double)r.re * (double)r.re + (double)r.im * (double)r.im);
+  for (long long i0 = (long long)blockIdx.x * NT + threadIdx.x; i0 < a.n; i0 += stride * kBatch) {
+    cx<T> p[kBatch], q[kBatch], x[kBatch], r[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long i = i0 + u * stride;
+      if (i < a.n) {
+        p[u] = a.p[i];
+        q[u] = a.q[i];
+        x[u] = a.x[i];
+        r[u] = a.r[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long i = i0 + u * stride;
+      if (i >= a.n) continue;
+      x[u].re += ta * p[u].re;
+      x[u].im += ta * p[u].im;
+      r[u].re -= ta * q[u].re;
+      r[u].im -= ta * q[u].im;
+      a.x[i] = x[u];
+      a.r[i] = r[u];
+      const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
+      acc += w * ((double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im);
+    }
   }
   const int nxt = (k + 1) & 1;
   store_partial<NT>(acc, a.parts.region(nxt) + blockIdx.x);
@@ -592,14 +725,32 @@ hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipSt
   return hipGetLastError();
 }
 
+template <typename T, int RS>
+static void launch_row_rs(const RowArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
+  if (nt == 128)
+    hipLaunchKernelGGL((row_kernel<T, 128, RS>), dim3((unsigned)nb), dim3(128), lds, s, a);
+  else
+    hipLaunchKernelGGL((row_kernel<T, 256, RS>), dim3((unsigned)nb), dim3(256), lds, s, a);
+}
+
+template <typename T, int RS>
+static void launch_col_rs(const ColArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
+  if (nt == 128)
+    hipLaunchKernelGGL((col_kernel<T, 128, RS>), dim3((unsigned)nb), dim3(128), lds, s, a);
+  else
+    hipLaunchKernelGGL((col_kernel<T, 256, RS>), dim3((unsigned)nb), dim3(256), lds, s, a);
+}
+
 template <typename T>
 hipError_t launch_row(const RowArgs<T>& a, hipStream_t s) {
   const size_t lds = row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), a.n_phases, nullptr);
   const long long nb = row_blocks(a);
-  if (pick_threads(a.d * (a.rows_per_block / 2) * a.n, a.plan) == 128)
-    hipLaunchKernelGGL((row_kernel<T, 128>), dim3((unsigned)nb), dim3(128), lds, s, a);
-  else
-    hipLaunchKernelGGL((row_kernel<T, 256>), dim3((unsigned)nb), dim3(256), lds, s, a);
+  const int nt = pick_threads(a.d * (a.rows_per_block / 2) * a.n, a.plan);
+  switch (plan_radix_set(a.plan)) {
+    case RADIX_POW3: launch_row_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
+    case RADIX_POW2: launch_row_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;
+    default: launch_row_rs<T, RADIX_ALL>(a, lds, nb, nt, s); break;
+  }
   return hipGetLastError();
 }
 
@@ -607,10 +758,12 @@ template <typename T>
 hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
   const size_t lds = col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), nullptr);
   const long long nb = col_blocks(a);
-  if (pick_threads(a.d * a.tile * a.L, a.plan) == 128)
-    hipLaunchKernelGGL((col_kernel<T, 128>), dim3((unsigned)nb), dim3(128), lds, s, a);
-  else
-    hipLaunchKernelGGL((col_kernel<T, 256>), dim3((unsigned)nb), dim3(256), lds, s, a);
+  const int nt = pick_threads(a.d * a.tile * a.L, a.plan);
+  switch (plan_radix_set(a.plan)) {
+    case RADIX_POW3: launch_col_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
+    case RADIX_POW2: launch_col_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;
+    default: launch_col_rs<T, RADIX_ALL>(a, lds, nb, nt, s); break;
+  }
   return hipGetLastError();
 }
 
