@@ -154,6 +154,99 @@ lshom_status lshom_homogenize(lshom_ctx* ctx, double tol, const lshom_solve_opts
  */
 lshom_status lshom_apply(lshom_ctx* ctx, const double* p_dev, double* q_dev);
 
+/*
+ * Many independent problems (each an isotropic microstructure, reference
+ * medium, load and tolerance as for lshom_solve) in one call.  Problems with
+ * the same grid share every kernel launch (one block row per problem) and
+ * advance together in captured graph blocks until each has met its own stop
+ * test; grids are processed in turn.  d, N, phase_dev, n_phases and cond_host
+ * as for lshom_set_microstructure; l0 <= 0 selects (min + max) / 2; E holds d
+ * values; e_dev (d x |N| FP64) may be NULL.
+ */
+typedef struct lshom_problem {
+  int32_t d;
+  int64_t N[3];
+  const uint8_t* phase_dev;
+  int32_t n_phases;
+  const double* cond_host;
+  double l0;
+  double E[3];
+  double tol;
+  double* e_dev;
+} lshom_problem;
+
+/* Device workspace bytes lshom_solve_batched needs for these problems. */
+lshom_status lshom_batch_workspace_size(lshom_ctx* ctx, int32_t n, const lshom_problem* probs,
+                                        int precision, size_t* bytes);
+
+/*
+ * Solve n problems (warm starts are not taken here).  ws_dev: caller-owned
+ * device workspace of at least lshom_batch_workspace_size bytes, 256-byte
+ * aligned (it is not kept after the call).  leff_host: n x 3 (row i is
+ * <lambda e> of problem i, zero-padded); infos: n reports; both may be NULL.
+ * Returns LSHOM_OK or the first non-OK per-problem status (each report holds
+ * its own); argument or HIP errors abort the call.
+ */
+lshom_status lshom_solve_batched(lshom_ctx* ctx, int32_t n, const lshom_problem* probs,
+                                 const lshom_solve_opts* opts, void* ws_dev, size_t ws_bytes,
+                                 double* leff_host, lshom_solve_info* infos);
+
+/*
+ * Launch schedule of one grid at one precision: the radix order of each
+ * axis's FFT (product = N[a]; radices 2..9) and the pass shapes (rows of the
+ * last axis per row-pass block, an even number; column tiles of the axis-0
+ * and axis-1 passes).  Results do not depend on the schedule beyond
+ * floating-point rounding.
+ */
+typedef struct lshom_schedule {
+  int32_t d;
+  int64_t N[3];
+  int32_t precision;
+  int32_t rows_per_block;
+  int32_t tile0;
+  int32_t tile1;
+  int32_t nstages[3];
+  int32_t radix[3][16];
+  double ms_per_iter;  /* autotuned device time of one CG iteration's passes (0: not measured) */
+} lshom_schedule;
+
+/* Schedule the current problem uses at `precision`. */
+lshom_status lshom_get_schedule(lshom_ctx* ctx, int precision, lshom_schedule* out);
+
+/*
+ * Register a schedule for its grid and precision (used by later solves of
+ * that grid, single or batched; applied at once to the current problem when
+ * the grid matches).  INVALID_ARG if it does not factor N or does not fit the
+ * FFT batch or LDS limits.
+ */
+lshom_status lshom_set_schedule(lshom_ctx* ctx, const lshom_schedule* s);
+
+/*
+ * Autotuner: time every pass kind of one CG iteration under candidate radix
+ * orders and launch shapes (HIP events over `reps` launches each) on the
+ * current problem, keep the fastest per pass kind, register and apply it;
+ * best (may be NULL) receives it.  Overwrites the internal vectors (call it
+ * between solves).
+ */
+lshom_status lshom_autotune(lshom_ctx* ctx, int precision, int reps, lshom_schedule* best);
+
+/*
+ * Autotuner for batched solves: for every distinct grid among the problems,
+ * tune on that grid's whole batch (same launches as lshom_solve_batched) and
+ * register the result.  ws_dev / ws_bytes as for lshom_solve_batched.
+ * best (may be NULL) receives up to *n_best schedules; *n_best (may be NULL)
+ * the number of grids.
+ */
+lshom_status lshom_autotune_batched(lshom_ctx* ctx, int32_t n, const lshom_problem* probs, int precision,
+                                    int reps, void* ws_dev, size_t ws_bytes, lshom_schedule* best,
+                                    int32_t* n_best);
+
+/* Write the registered schedules as JSON lines keyed by GPU architecture,
+ * d, N and precision (one object per line); read them back (entries of other
+ * architectures are skipped).  Returns INVALID_ARG on I/O or parse errors. */
+lshom_status lshom_save_schedules(lshom_ctx* ctx, const char* path);
+lshom_status lshom_load_schedules(lshom_ctx* ctx, const char* path);
+
 /* Kernel classes reported by lshom_time_passes. */
 #define LSHOM_PASS_AXIS0_INVERSE 0  /* p = r + beta p, i khat p, inverse FFT along axis 0 */
 #define LSHOM_PASS_AXIS1_INVERSE 1  /* 3-D: inverse FFT along axis 1 */

@@ -1,10 +1,12 @@
-// Library context, workspace layout and the solve drivers (internal).
+// Library context, problem groups, workspace layout and the solve drivers
+// (internal).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -12,32 +14,102 @@
 #include "lshom.h"
 #include "plan.hpp"
 
+struct lshom_ctx;
+
 namespace lshom {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxPhases = 256;
+constexpr int kMaxPhases = kCondStride;
 // dynamic LDS per block; the rest of the 64 KiB holds the reductions' statics
 constexpr size_t kLdsBudget = 63 * 1024;
 constexpr long long kMinBlocks = 128;
 
+// Offsets (bytes from the workspace base) of everything a group of nprob
+// problems of one grid needs.  Per-problem arrays are consecutive.
 struct Layout {
   size_t total = 0;
   size_t off_state = 0, off_partials = 0, off_cond64 = 0, off_cond32 = 0, off_scratch = 0;
+  size_t off_tab = 0;
   size_t off_tw64[3] = {0, 0, 0}, off_tw32[3] = {0, 0, 0};
   size_t off_v64[4] = {0, 0, 0, 0}, off_w64[3] = {0, 0, 0};
   size_t off_v32[4] = {0, 0, 0, 0}, off_w32[3] = {0, 0, 0};
   long long part_stride = 0;  // doubles per partial region
+  long long pstride = 0;      // doubles per problem (4 regions)
   bool has32 = false;
 };
 
 template <typename T>
 struct Bufs {
-  cx<T>* v[4];   // x, r, p, q (half spectrum)
-  cx<T>* w[3];   // per-component pass buffers
+  cx<T>* v[4];   // x, r, p, q (half spectrum) of problem 0
+  cx<T>* w[3];   // per-component pass buffers of problem 0
   const T* cond;
   const cx<T>* tw[3];
   PassShape shape;
+  FftPlan plan[3];
 };
+
+// Launch schedule of one grid at one precision: radix order per axis and
+// pass shapes (chosen by default heuristics or by the autotuner).
+struct Schedule {
+  FftPlan plan[3];
+  PassShape shape;
+  double ms_per_iter = 0.0;   // autotuned cost of one CG iteration's passes
+};
+
+using SchedKey = std::tuple<int, int64_t, int64_t, int64_t, int>;  // d, N0, N1, N2, precision
+
+// Problems that share one grid (d, N) and are advanced by the same launches.
+struct Group {
+  lshom_ctx* ctx = nullptr;     // errors and the context stream
+  int d = 0;
+  int64_t N[3] = {1, 1, 1};
+  long long nvox = 0, nrows = 0, nhalf = 0;
+  int h = 0;
+  bool transposed = false;      // 2-D spectral arrays stored [k1][k0]
+  FftPlan plan64[3], plan32[3];
+  PassShape shape64{2, 1, 1}, shape32{2, 1, 1};
+  int n_phases = 1;             // conductivity entries staged per problem
+  // single problem (nprob == 1, batched == false)
+  const uint8_t* phase = nullptr;
+  double l0 = 0.0;
+  // batch
+  int nprob = 1;
+  bool batched = false;         // per-problem data come from the device table
+  // device memory
+  char* ws = nullptr;
+  Layout lay;
+  std::vector<DevState> host_states;
+  int warm_used = 0;
+  std::map<std::pair<int, int>, hipGraphExec_t>* graph_cache = nullptr;
+};
+
+// Fills the geometry, plans and shapes of g (from the context's schedule
+// registry when it has an entry for the grid); UNSUPPORTED if a pass cannot
+// hold its FFT batch in LDS.
+lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases);
+bool schedule_fits(const Group& g, const Schedule& s, int precision);
+void apply_schedule(Group& g, const Schedule& s, int precision);
+Schedule current_schedule(const Group& g, int precision);
+
+// Times the passes of one CG iteration for candidate schedules on the group's
+// current data and returns the fastest (per pass, independently).
+lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best);
+Layout compute_layout(const Group& g, bool with32);
+
+// Uploads twiddles, conductivity tables (cond[p * n_phases + i]) and the
+// problem table; checks every phase index.
+lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const std::vector<ProbEntry>* tab,
+                               const std::vector<const uint8_t*>& phases);
+
+// Solve every problem of the group.  init[p]: initial scalars (b2, tol2b2,
+// max_iter, mixed controls).  x0 (single problem only) may be null.
+lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lshom_solve_opts& o,
+                         const double* E_single, const double* x0, double* e_single);
+lshom_status apply_real(Group& g, const double* p, double* q);
+lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out);
+
+lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg);
+void drop_graphs(std::map<std::pair<int, int>, hipGraphExec_t>& cache);
 
 }  // namespace lshom
 
@@ -47,42 +119,14 @@ struct lshom_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
   std::string err;
-  // problem
   bool have_problem = false;
-  int d = 0;
-  int64_t N[3] = {0, 0, 0};
-  long long nvox = 0, nrows = 0, nhalf = 0;
-  int h = 0;
-  bool transposed = false;     // 2-D spectral arrays stored [k1][k0]
-  const uint8_t* phase = nullptr;
-  std::vector<double> cond;
-  double l0 = 0.0;
-  lshom::FftPlan plan[3];
-  lshom::PassShape shape64{2, 1, 1}, shape32{2, 1, 1};
-  // workspace
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
   bool ws_ready = false;
-  lshom::Layout lay;
-  lshom::DevState* host_state = nullptr;  // pinned host copy of the device scalars
+  std::vector<double> cond;
+  lshom::Group g;               // the single problem of set_microstructure
+  size_t ws_bytes = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  std::map<lshom::SchedKey, lshom::Schedule> schedules;  // autotuned or set by the caller
 };
-
-namespace lshom {
-
-lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg);
-void drop_graphs(lshom_ctx* c);
-Layout compute_layout(const lshom_ctx* c, bool with32);
-lshom_status prepare_workspace(lshom_ctx* c);  // tables, phase check
-
-lshom_status solve_fp64(lshom_ctx* c, const double* E, double tol, const lshom_solve_opts& o,
-                        const double* x0, double* e_out, double* leff, lshom_solve_info* info);
-lshom_status solve_mixed(lshom_ctx* c, const double* E, double tol, const lshom_solve_opts& o,
-                         const double* x0, double* e_out, double* leff, lshom_solve_info* info);
-lshom_status apply_real(lshom_ctx* c, const double* p, double* q);
-lshom_status time_passes(lshom_ctx* c, int precision, int reps, double* ms_out, double* bytes_out);
-
-}  // namespace lshom
 
 #define HIP_TRY(ctx, expr)                                                                       \
   do {                                                                                           \

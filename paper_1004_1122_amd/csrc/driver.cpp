@@ -1,6 +1,9 @@
 // Solve drivers: queue the pass kernels of the operator apply (Sec. 2.2,
 // Eq. (16)) and of conjugate gradients (Sec. 2.3; Saad's Algorithm 6.18 as
 // named in Sec. 3) on the context stream, in captured HIP graph blocks.
+// A group advances one or many problems of the same grid with the same
+// launches (grid dimension y = problem).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -13,9 +16,9 @@ lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg) {
   return s;
 }
 
-void drop_graphs(lshom_ctx* c) {
-  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-  c->graphs.clear();
+void drop_graphs(std::map<std::pair<int, int>, hipGraphExec_t>& cache) {
+  for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
+  cache.clear();
 }
 
 namespace {
@@ -23,15 +26,66 @@ namespace {
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
-long long inner0_of(const lshom_ctx* c) {
-  long long inner = c->h;
-  for (int t = 1; t < c->d - 1; ++t) inner *= c->N[t];
+long long inner0_of(const Group& g) {
+  long long inner = g.h;
+  for (int t = 1; t < g.d - 1; ++t) inner *= g.N[t];
   return inner;
 }
 
 }  // namespace
 
-Layout compute_layout(const lshom_ctx* c, bool with32) {
+lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
+  g.d = d;
+  g.nvox = 1;
+  for (int a = 0; a < 3; ++a) g.N[a] = a < d ? N[a] : 1;
+  for (int a = 0; a < d; ++a) g.nvox *= N[a];
+  g.h = (int)(N[d - 1] / 2 + 1);
+  g.nrows = g.nvox / N[d - 1];
+  g.nhalf = g.nrows * g.h;
+  g.transposed = (d == 2);
+  g.n_phases = n_phases;
+  for (int a = 0; a < d; ++a) g.plan64[a] = g.plan32[a] = default_plan((int)N[a]);
+  g.shape64 = default_shape(d, g.N, g.plan64, (int)sizeof(cx<double>), kLdsBudget, kMinBlocks,
+                            g.transposed, n_phases);
+  g.shape32 = default_shape(d, g.N, g.plan32, (int)sizeof(cx<float>), kLdsBudget, kMinBlocks,
+                            g.transposed, n_phases);
+  if (!shape_fits(d, g.N, g.plan64, g.shape64, (int)sizeof(cx<double>), kLdsBudget, n_phases) ||
+      !shape_fits(d, g.N, g.plan32, g.shape32, (int)sizeof(cx<float>), kLdsBudget, n_phases))
+    return LSHOM_ERR_UNSUPPORTED;
+  if (g.ctx) {
+    for (int prec = 0; prec < 2; ++prec) {
+      auto it = g.ctx->schedules.find(SchedKey(d, g.N[0], g.N[1], g.N[2], prec));
+      if (it != g.ctx->schedules.end() && schedule_fits(g, it->second, prec)) apply_schedule(g, it->second, prec);
+    }
+  }
+  return LSHOM_OK;
+}
+
+bool schedule_fits(const Group& g, const Schedule& s, int precision) {
+  for (int a = 0; a < g.d; ++a) {
+    if (s.plan[a].n != g.N[a]) return false;
+    FftPlan chk;
+    if (!make_plan((int)g.N[a], s.plan[a].radix, s.plan[a].nstages, &chk)) return false;
+  }
+  const int es = precision == LSHOM_PRECISION_FP64 ? (int)sizeof(cx<double>) : (int)sizeof(cx<float>);
+  return shape_fits(g.d, g.N, s.plan, s.shape, es, kLdsBudget, g.n_phases);
+}
+
+void apply_schedule(Group& g, const Schedule& s, int precision) {
+  FftPlan* pl = precision == LSHOM_PRECISION_FP64 ? g.plan64 : g.plan32;
+  for (int a = 0; a < g.d; ++a) pl[a] = s.plan[a];
+  (precision == LSHOM_PRECISION_FP64 ? g.shape64 : g.shape32) = s.shape;
+}
+
+Schedule current_schedule(const Group& g, int precision) {
+  Schedule s;
+  const FftPlan* pl = precision == LSHOM_PRECISION_FP64 ? g.plan64 : g.plan32;
+  for (int a = 0; a < 3; ++a) s.plan[a] = a < g.d ? pl[a] : FftPlan{};
+  s.shape = precision == LSHOM_PRECISION_FP64 ? g.shape64 : g.shape32;
+  return s;
+}
+
+Layout compute_layout(const Group& g, bool with32) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -39,30 +93,34 @@ Layout compute_layout(const lshom_ctx* c, bool with32) {
     off = align_up(off + bytes);
     return o;
   };
-  L.off_state = take(sizeof(DevState));
+  const long long np = g.nprob;
+  L.off_state = take(sizeof(DevState) * np);
   L.off_scratch = take(256);
+  L.off_tab = take(sizeof(ProbEntry) * np);
   // partial sums: one slot (three in AUX) per block of the widest launch
+  // any schedule can make (two rows per row-pass block, tiles of one)
+  (void)with32;
   long long maxb = kUpdateBlocks;
-  for (int prec = 0; prec < (with32 ? 2 : 1); ++prec) {
-    const PassShape& s = prec == 0 ? c->shape64 : c->shape32;
-    maxb = std::max(maxb, ceil_div(c->nrows, s.rows_per_block));
-    maxb = std::max(maxb, ceil_div(inner0_of(c), s.tile0));
-    if (c->d == 3) maxb = std::max(maxb, c->N[0] * ceil_div(c->h, s.tile1));
-  }
+  maxb = std::max(maxb, ceil_div(g.nrows, 2));
+  maxb = std::max(maxb, inner0_of(g));
+  if (g.d == 3) maxb = std::max(maxb, g.N[0] * (long long)g.h);
   L.part_stride = 3 * maxb;
-  L.off_partials = take((size_t)L.part_stride * 4 * sizeof(double));
-  L.off_cond64 = take(kMaxPhases * sizeof(double));
-  L.off_cond32 = take(kMaxPhases * sizeof(float));
-  for (int a = 0; a < c->d; ++a) {
-    L.off_tw64[a] = take((size_t)c->N[a] * sizeof(cx<double>));
-    L.off_tw32[a] = take((size_t)c->N[a] * sizeof(cx<float>));
+  L.pstride = 4 * L.part_stride;
+  L.off_partials = take((size_t)L.pstride * np * sizeof(double));
+  L.off_cond64 = take((size_t)kCondStride * np * sizeof(double));
+  L.off_cond32 = take((size_t)kCondStride * np * sizeof(float));
+  for (int a = 0; a < g.d; ++a) {
+    L.off_tw64[a] = take((size_t)g.N[a] * sizeof(cx<double>));
+    L.off_tw32[a] = take((size_t)g.N[a] * sizeof(cx<float>));
   }
-  for (int i = 0; i < 4; ++i) L.off_v64[i] = take((size_t)c->nhalf * sizeof(cx<double>));
-  for (int a = 0; a < c->d; ++a) L.off_w64[a] = take((size_t)c->nhalf * sizeof(cx<double>));
+  const size_t v64 = (size_t)g.nhalf * np * sizeof(cx<double>);
+  const size_t v32 = (size_t)g.nhalf * np * sizeof(cx<float>);
+  for (int i = 0; i < 4; ++i) L.off_v64[i] = take(v64);
+  for (int a = 0; a < g.d; ++a) L.off_w64[a] = take(v64);
   L.has32 = with32;
   if (with32) {
-    for (int i = 0; i < 4; ++i) L.off_v32[i] = take((size_t)c->nhalf * sizeof(cx<float>));
-    for (int a = 0; a < c->d; ++a) L.off_w32[a] = take((size_t)c->nhalf * sizeof(cx<float>));
+    for (int i = 0; i < 4; ++i) L.off_v32[i] = take(v32);
+    for (int a = 0; a < g.d; ++a) L.off_w32[a] = take(v32);
   }
   L.total = off;
   return L;
@@ -70,55 +128,68 @@ Layout compute_layout(const lshom_ctx* c, bool with32) {
 
 namespace {
 
-DevState* dev_state(lshom_ctx* c) { return reinterpret_cast<DevState*>(c->ws + c->lay.off_state); }
+DevState* dev_state(Group& g) { return reinterpret_cast<DevState*>(g.ws + g.lay.off_state); }
 
-Partials dev_parts(lshom_ctx* c) {
+Partials dev_parts(Group& g) {
   Partials p;
-  p.base = reinterpret_cast<double*>(c->ws + c->lay.off_partials);
-  p.stride = c->lay.part_stride;
+  p.base = reinterpret_cast<double*>(g.ws + g.lay.off_partials);
+  p.stride = g.lay.part_stride;
   return p;
 }
 
+Batch batch_of(Group& g) {
+  Batch b{};
+  b.nprob = g.nprob;
+  b.vstride = g.nhalf;
+  b.pstride = g.lay.pstride;
+  b.tab = g.batched ? reinterpret_cast<const ProbEntry*>(g.ws + g.lay.off_tab) : nullptr;
+  return b;
+}
+
 template <typename T>
-Bufs<T> get_bufs(lshom_ctx* c);
+Bufs<T> get_bufs(Group& g);
 
 template <>
-Bufs<double> get_bufs<double>(lshom_ctx* c) {
+Bufs<double> get_bufs<double>(Group& g) {
   Bufs<double> b{};
-  for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<double>*>(c->ws + c->lay.off_v64[i]);
-  for (int a = 0; a < c->d; ++a) {
-    b.w[a] = reinterpret_cast<cx<double>*>(c->ws + c->lay.off_w64[a]);
-    b.tw[a] = reinterpret_cast<const cx<double>*>(c->ws + c->lay.off_tw64[a]);
+  for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<double>*>(g.ws + g.lay.off_v64[i]);
+  for (int a = 0; a < g.d; ++a) {
+    b.w[a] = reinterpret_cast<cx<double>*>(g.ws + g.lay.off_w64[a]);
+    b.tw[a] = reinterpret_cast<const cx<double>*>(g.ws + g.lay.off_tw64[a]);
   }
-  b.cond = reinterpret_cast<const double*>(c->ws + c->lay.off_cond64);
-  b.shape = c->shape64;
+  b.cond = reinterpret_cast<const double*>(g.ws + g.lay.off_cond64);
+  b.shape = g.shape64;
+  for (int a = 0; a < 3; ++a) b.plan[a] = g.plan64[a];
   return b;
 }
 
 template <>
-Bufs<float> get_bufs<float>(lshom_ctx* c) {
+Bufs<float> get_bufs<float>(Group& g) {
   Bufs<float> b{};
-  for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<float>*>(c->ws + c->lay.off_v32[i]);
-  for (int a = 0; a < c->d; ++a) {
-    b.w[a] = reinterpret_cast<cx<float>*>(c->ws + c->lay.off_w32[a]);
-    b.tw[a] = reinterpret_cast<const cx<float>*>(c->ws + c->lay.off_tw32[a]);
+  for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<float>*>(g.ws + g.lay.off_v32[i]);
+  for (int a = 0; a < g.d; ++a) {
+    b.w[a] = reinterpret_cast<cx<float>*>(g.ws + g.lay.off_w32[a]);
+    b.tw[a] = reinterpret_cast<const cx<float>*>(g.ws + g.lay.off_tw32[a]);
   }
-  b.cond = reinterpret_cast<const float*>(c->ws + c->lay.off_cond32);
-  b.shape = c->shape32;
+  b.cond = reinterpret_cast<const float*>(g.ws + g.lay.off_cond32);
+  b.shape = g.shape32;
+  for (int a = 0; a < 3; ++a) b.plan[a] = g.plan32[a];
   return b;
 }
+
+hipStream_t stream_of(Group& g) { return g.ctx->stream; }
 
 // ---------------------------------------------------------------------------
 // Pass argument builders
 // ---------------------------------------------------------------------------
 
 template <typename T>
-ColArgs<T> col0_args(lshom_ctx* c, const Bufs<T>& b) {
+ColArgs<T> col0_args(Group& g, const Bufs<T>& b) {
   ColArgs<T> a{};
-  a.L = (int)c->N[0];
-  a.inner = inner0_of(c);
+  a.L = (int)g.N[0];
+  a.inner = inner0_of(g);
   a.outer = 1;
-  if (c->transposed) {
+  if (g.transposed) {
     a.sl = 1;
     a.sii = a.L;
   } else {
@@ -127,107 +198,128 @@ ColArgs<T> col0_args(lshom_ctx* c, const Bufs<T>& b) {
   }
   a.tile = b.shape.tile0;
   a.tiles_per_outer = (int)ceil_div(a.inner, a.tile);
-  a.d = c->d;
+  a.d = g.d;
   col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), &a.ss);
-  for (int t = 0; t < c->d; ++t) {
+  for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
-    a.nd[t] = (int)c->N[t];
+    a.nd[t] = (int)g.N[t];
   }
-  a.dims = c->d;
-  a.h = c->h;
-  a.plan = c->plan[0];
+  a.dims = g.d;
+  a.h = g.h;
+  a.plan = b.plan[0];
   a.tw = b.tw[0];
-  a.st = dev_state(c);
-  a.parts = dev_parts(c);
-  a.inv_n = 1.0 / (double)c->nvox;
+  a.st = dev_state(g);
+  a.parts = dev_parts(g);
+  a.inv_n = 1.0 / (double)g.nvox;
   a.gate = GATE_ACTIVE;
+  a.l0 = g.l0;
+  a.bt = batch_of(g);
   return a;
 }
 
 template <typename T>
-ColArgs<T> col1_args(lshom_ctx* c, const Bufs<T>& b, int dir) {
+ColArgs<T> col1_args(Group& g, const Bufs<T>& b, int dir) {
   ColArgs<T> a{};
-  a.L = (int)c->N[1];
-  a.inner = c->h;
-  a.outer = c->N[0];
+  a.L = (int)g.N[1];
+  a.inner = g.h;
+  a.outer = g.N[0];
   a.sl = a.inner;
   a.sii = 1;
   a.tile = b.shape.tile1;
   a.tiles_per_outer = (int)ceil_div(a.inner, a.tile);
-  a.d = c->d;
+  a.d = g.d;
   col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), &a.ss);
-  for (int t = 0; t < c->d; ++t) {
+  for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
-    a.nd[t] = (int)c->N[t];
+    a.nd[t] = (int)g.N[t];
   }
-  a.dims = c->d;
-  a.h = c->h;
+  a.dims = g.d;
+  a.h = g.h;
   a.mode = COL_PLAIN;
   a.dir = dir;
-  a.plan = c->plan[1];
+  a.plan = b.plan[1];
   a.tw = b.tw[1];
-  a.st = dev_state(c);
-  a.parts = dev_parts(c);
-  a.inv_n = 1.0 / (double)c->nvox;
+  a.st = dev_state(g);
+  a.parts = dev_parts(g);
+  a.inv_n = 1.0 / (double)g.nvox;
   a.gate = GATE_ACTIVE;
+  a.l0 = g.l0;
+  a.bt = batch_of(g);
   return a;
 }
 
 template <typename T>
-RowArgs<T> row_args(lshom_ctx* c, const Bufs<T>& b) {
+RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
   RowArgs<T> a{};
-  const int last = c->d - 1;
-  a.n = (int)c->N[last];
-  a.h = c->h;
-  a.nrows = c->nrows;
+  const int last = g.d - 1;
+  a.n = (int)g.N[last];
+  a.h = g.h;
+  a.nrows = g.nrows;
   a.rows_per_block = b.shape.rows_per_block;
-  a.d = c->d;
-  row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), (int)c->cond.size(), &a.ss);
-  if (c->transposed) {
+  a.d = g.d;
+  row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), g.n_phases, &a.ss);
+  if (g.transposed) {
     a.rs_row = 1;
-    a.rs_k = c->nrows;
+    a.rs_k = g.nrows;
     a.row_fast = 1;
   } else {
-    a.rs_row = c->h;
+    a.rs_row = g.h;
     a.rs_k = 1;
     a.row_fast = 0;
   }
-  for (int t = 0; t < c->d; ++t) a.spec[t] = b.w[t];
-  a.phase = c->phase;
+  for (int t = 0; t < g.d; ++t) a.spec[t] = b.w[t];
+  a.phase = g.phase;
   a.cond = b.cond;
-  a.n_phases = (int)c->cond.size();
-  a.l0 = (T)c->l0;
-  a.inv_n = (T)(1.0 / (double)c->nvox);
-  a.plan = c->plan[last];
+  a.n_phases = g.n_phases;
+  a.l0 = (T)g.l0;
+  a.inv_n = (T)(1.0 / (double)g.nvox);
+  a.plan = b.plan[last];
   a.tw = b.tw[last];
-  a.st = dev_state(c);
-  a.parts = dev_parts(c);
+  a.st = dev_state(g);
+  a.parts = dev_parts(g);
   a.gate = GATE_ACTIVE;
+  a.bt = batch_of(g);
   return a;
 }
 
-long long klast_div_of(const lshom_ctx* c) { return c->transposed ? c->N[0] : 1; }
+long long klast_div_of(const Group& g) { return g.transposed ? g.N[0] : 1; }
 
 template <typename T>
-long long col0_block_count(lshom_ctx* c, const Bufs<T>& b) {
-  return col_blocks(col0_args(c, b));
+long long col0_block_count(Group& g, const Bufs<T>& b) {
+  return col_blocks(col0_args(g, b));
 }
 
-template <typename T>
-long long row_block_count(lshom_ctx* c, const Bufs<T>& b) {
-  return row_blocks(row_args(c, b));
-}
-
-hipError_t enq_finalize(lshom_ctx* c, int mode, long long n, int gate) {
+hipError_t enq_finalize(Group& g, int mode, long long n, int gate) {
   FinArgs f{};
-  f.st = dev_state(c);
-  f.parts = dev_parts(c);
+  f.st = dev_state(g);
+  f.parts = dev_parts(g);
   f.mode = mode;
   f.n = (int)n;
-  f.d = c->d;
-  f.inv_n = 1.0 / (double)c->nvox;
+  f.d = g.d;
+  f.inv_n = 1.0 / (double)g.nvox;
   f.gate = gate;
-  return launch_finalize(f, c->stream);
+  f.bt = batch_of(g);
+  return launch_finalize(f, stream_of(g));
+}
+
+template <typename T>
+UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
+  UpdArgs<T> u{};
+  u.n = g.nhalf;
+  u.h = g.h;
+  u.n_last = (int)g.N[g.d - 1];
+  u.klast_div = klast_div_of(g);
+  u.x = b.v[0];
+  u.r = b.v[1];
+  u.p = b.v[2];
+  u.q = b.v[3];
+  u.st = dev_state(g);
+  u.parts = dev_parts(g);
+  u.n_pq = (int)col0_block_count(g, b);
+  u.inv_n = 1.0 / (double)g.nvox;
+  u.gate = GATE_ACTIVE;
+  u.bt = batch_of(g);
+  return u;
 }
 
 // ---------------------------------------------------------------------------
@@ -235,254 +327,237 @@ hipError_t enq_finalize(lshom_ctx* c, int mode, long long n, int gate) {
 // ---------------------------------------------------------------------------
 
 // Forward half: [3-D axis-1 forward], axis-0 forward + projection.
+// out = coef_base * base + coef_s * [1 / l0] * (-i khat) . tau_hat
 template <typename T>
-hipError_t enq_forward_project(lshom_ctx* c, const Bufs<T>& b, cx<T>* out, const cx<T>* base,
-                               T coef_base, T coef_s, int dot, int dot_region, int gate) {
+hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<T>* base,
+                               T coef_base, T coef_s, int s_inv_l0, int dot, int dot_region, int gate) {
   hipError_t e;
-  if (c->d == 3) {
-    ColArgs<T> m = col1_args(c, b, -1);
+  if (g.d == 3) {
+    ColArgs<T> m = col1_args(g, b, -1);
     m.gate = gate;
-    if ((e = launch_col(m, c->stream)) != hipSuccess) return e;
+    if ((e = launch_col(m, stream_of(g))) != hipSuccess) return e;
   }
-  ColArgs<T> a = col0_args(c, b);
+  ColArgs<T> a = col0_args(g, b);
   a.mode = COL_FWD_PROJ;
   a.out = out;
   a.base = base;
   a.coef_base = coef_base;
   a.coef_s = coef_s;
+  a.s_inv_l0 = s_inv_l0;
   a.dot = dot;
   a.dot_region = dot_region;
   a.gate = gate;
-  return launch_col(a, c->stream);
+  return launch_col(a, stream_of(g));
 }
 
 // Inverse half: axis-0 inverse from the scalar c (or the CG direction step
 // p = r + beta p), [3-D axis-1 inverse].
 template <typename T>
-hipError_t enq_inverse_from_c(lshom_ctx* c, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
+hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
                               const cx<T>* r_in, int gate) {
   hipError_t e;
-  ColArgs<T> a = col0_args(c, b);
+  ColArgs<T> a = col0_args(g, b);
   a.mode = COL_INV_C;
   a.c_in = c_in;
   a.p_io = p_io;
   a.r_in = r_in;
   a.cg_step = p_io != nullptr;
   a.gate = gate;
-  if ((e = launch_col(a, c->stream)) != hipSuccess) return e;
-  if (c->d == 3) {
-    ColArgs<T> m = col1_args(c, b, +1);
+  if ((e = launch_col(a, stream_of(g))) != hipSuccess) return e;
+  if (g.d == 3) {
+    ColArgs<T> m = col1_args(g, b, +1);
     m.gate = gate;
-    if ((e = launch_col(m, c->stream)) != hipSuccess) return e;
+    if ((e = launch_col(m, stream_of(g))) != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-// out = coef_base * base + coef_s * (-i khat) . F[dL (E + u(c_in))]
+// out = coef_base * base + coef_s * (1/l0) (-i khat) . F[dL (E + u(c_in))]
 template <typename T>
-hipError_t enq_apply_spec(lshom_ctx* c, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
+hipError_t enq_apply_spec(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
                           const cx<T>* r_in, const double* E, cx<T>* out, const cx<T>* base,
                           T coef_base, T coef_s, int dot, int dot_region, int gate) {
   hipError_t e;
-  if ((e = enq_inverse_from_c(c, b, c_in, p_io, r_in, gate)) != hipSuccess) return e;
-  RowArgs<T> r = row_args(c, b);
+  if ((e = enq_inverse_from_c(g, b, c_in, p_io, r_in, gate)) != hipSuccess) return e;
+  RowArgs<T> r = row_args(g, b);
   r.mode = ROW_FUSED;
-  for (int t = 0; t < c->d; ++t) r.E[t] = E ? (T)E[t] : T(0);
+  for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
+  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
   r.gate = gate;
-  if ((e = launch_row(r, c->stream)) != hipSuccess) return e;
-  return enq_forward_project(c, b, out, base, coef_base, coef_s, dot, dot_region, gate);
+  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  return enq_forward_project(g, b, out, base, coef_base, coef_s, 1, dot, dot_region, gate);
 }
 
 // One CG iteration in the spectral coordinate:
 //   direction step (p = r + beta p, or stop), q = p + (1/l0) P dL u(p) with
 //   (p, q), then alpha = (r, r) / (p, q), x += alpha p, r -= alpha q, (r, r).
 template <typename T>
-hipError_t enq_cg_iteration(lshom_ctx* c, const Bufs<T>& b, int gate) {
+hipError_t enq_cg_iteration(Group& g, const Bufs<T>& b, int gate) {
   hipError_t e;
   cx<T>* r = b.v[1];
   cx<T>* p = b.v[2];
   cx<T>* q = b.v[3];
-  if ((e = enq_apply_spec<T>(c, b, nullptr, p, r, nullptr, q, p, T(1), T(1.0 / c->l0), 1, PART_PQ,
-                             gate)) != hipSuccess)
+  static const double kZero[3] = {0.0, 0.0, 0.0};
+  if ((e = enq_apply_spec<T>(g, b, nullptr, p, r, kZero, q, p, T(1), T(1), 1, PART_PQ, gate)) !=
+      hipSuccess)
     return e;
-  UpdArgs<T> u{};
-  u.n = c->nhalf;
-  u.h = c->h;
-  u.n_last = (int)c->N[c->d - 1];
-  u.klast_div = klast_div_of(c);
-  u.x = b.v[0];
-  u.r = r;
-  u.p = p;
-  u.q = q;
-  u.st = dev_state(c);
-  u.parts = dev_parts(c);
-  u.n_pq = (int)col0_block_count(c, b);
-  u.inv_n = 1.0 / (double)c->nvox;
+  UpdArgs<T> u = upd_args(g, b);
   u.gate = gate;
-  return launch_update(u, c->stream);
+  return launch_update(u, stream_of(g));
 }
 
 // Residual of the spectral iterate x for the load E:
 // r = -(x + (1/l0) P dL (E + u(x))).
 template <typename T>
-hipError_t enq_true_residual(lshom_ctx* c, const Bufs<T>& b, const cx<T>* x, const double* E,
+hipError_t enq_true_residual(Group& g, const Bufs<T>& b, const cx<T>* x, const double* E,
                              cx<T>* out, int dot_region, int gate) {
-  return enq_apply_spec<T>(c, b, x, nullptr, nullptr, E, out, x, T(-1), T(-1.0 / c->l0), 2,
-                           dot_region, gate);
+  return enq_apply_spec<T>(g, b, x, nullptr, nullptr, E, out, x, T(-1), T(-1), 2, dot_region, gate);
 }
 
 // r0 for x0 = E: r0 = -(1/l0) P dL E.
 template <typename T>
-hipError_t enq_residual_of_E(lshom_ctx* c, const Bufs<T>& b, const double* E, cx<T>* out,
-                             int dot_region) {
+hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>* out, int dot_region) {
   hipError_t e;
-  RowArgs<T> r = row_args(c, b);
+  RowArgs<T> r = row_args(g, b);
   r.mode = ROW_FWD;
   r.flags = ROWF_DL | ROWF_CONST_E;
-  for (int t = 0; t < c->d; ++t) r.E[t] = (T)E[t];
+  for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
+  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
   r.gate = GATE_ALWAYS;
-  if ((e = launch_row(r, c->stream)) != hipSuccess) return e;
-  return enq_forward_project<T>(c, b, out, nullptr, T(0), T(-1.0 / c->l0), 2, dot_region,
-                                GATE_ALWAYS);
+  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS);
 }
 
 // Real FP64 field v (d x |N|) -> spectral coordinate of P v (of P dL v / l0).
-hipError_t enq_project_real(lshom_ctx* c, const Bufs<double>& b, const double* v, bool with_dl,
+hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bool with_dl,
                             cx<double>* out) {
   hipError_t e;
-  RowArgs<double> r = row_args(c, b);
+  RowArgs<double> r = row_args(g, b);
   r.mode = ROW_FWD;
   r.flags = with_dl ? ROWF_DL : 0;
-  for (int t = 0; t < c->d; ++t) r.real_in[t] = v + (size_t)t * c->nvox;
+  for (int t = 0; t < g.d; ++t) r.real_in[t] = v + (size_t)t * g.nvox;
   r.gate = GATE_ALWAYS;
-  if ((e = launch_row(r, c->stream)) != hipSuccess) return e;
-  return enq_forward_project<double>(c, b, out, nullptr, 0.0, with_dl ? 1.0 / c->l0 : 1.0, 0,
-                                     PART_AUX, GATE_ALWAYS);
+  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, with_dl ? 1 : 0, 0, PART_AUX,
+                                     GATE_ALWAYS);
 }
 
 // Real field out = add + E + u(x); with leff, <lambda out> into state.leff.
-hipError_t enq_field_out(lshom_ctx* c, const Bufs<double>& b, const cx<double>* x, const double* E,
+hipError_t enq_field_out(Group& g, const Bufs<double>& b, const cx<double>* x, const double* E,
                          const double* add, double* out, bool leff) {
   hipError_t e;
-  if ((e = enq_inverse_from_c<double>(c, b, x, nullptr, nullptr, GATE_ALWAYS)) != hipSuccess) return e;
-  RowArgs<double> r = row_args(c, b);
+  if ((e = enq_inverse_from_c<double>(g, b, x, nullptr, nullptr, GATE_ALWAYS)) != hipSuccess) return e;
+  RowArgs<double> r = row_args(g, b);
   r.mode = ROW_INV;
   r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0);
-  for (int t = 0; t < c->d; ++t) {
+  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
+  for (int t = 0; t < g.d; ++t) {
     r.E[t] = E ? E[t] : 0.0;
-    r.real_out[t] = out ? out + (size_t)t * c->nvox : nullptr;
-    r.real_add[t] = add ? add + (size_t)t * c->nvox : nullptr;
+    r.real_out[t] = out ? out + (size_t)t * g.nvox : nullptr;
+    r.real_add[t] = add ? add + (size_t)t * g.nvox : nullptr;
   }
   r.gate = GATE_ALWAYS;
-  if ((e = launch_row(r, c->stream)) != hipSuccess) return e;
-  if (leff) return enq_finalize(c, FZ_LEFF, row_blocks(r), GATE_ALWAYS);
+  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  if (leff) return enq_finalize(g, FZ_LEFF, row_blocks(r), GATE_ALWAYS);
   return hipSuccess;
 }
 
-MixArgs mix_args(lshom_ctx* c, const Bufs<double>& b64, const Bufs<float>& b32, int gate) {
+MixArgs mix_args(Group& g, const Bufs<double>& b64, const Bufs<float>& b32, int gate) {
   MixArgs m{};
-  m.n = c->nhalf;
-  m.h = c->h;
-  m.n_last = (int)c->N[c->d - 1];
-  m.klast_div = klast_div_of(c);
+  m.n = g.nhalf;
+  m.h = g.h;
+  m.n_last = (int)g.N[g.d - 1];
+  m.klast_div = klast_div_of(g);
   m.x64 = b64.v[0];
   m.x32 = b32.v[0];
   m.r64 = b64.v[1];
   m.r32 = b32.v[1];
-  m.st = dev_state(c);
-  m.parts = dev_parts(c);
-  m.inv_n = 1.0 / (double)c->nvox;
+  m.st = dev_state(g);
+  m.parts = dev_parts(g);
+  m.inv_n = 1.0 / (double)g.nvox;
   m.gate = gate;
+  m.bt = batch_of(g);
   return m;
 }
 
 // Mixed precision refresh (reliable update): x64 += x32, x32 = 0;
 // r64 = b - A64 x64 in FP64; r32 = r64 with its (r, r) partials; the
 // finalize step decides convergence on the FP64 value and clears the request.
-hipError_t enq_mix_refresh(lshom_ctx* c, const Bufs<double>& b64, const Bufs<float>& b32,
+hipError_t enq_mix_refresh(Group& g, const Bufs<double>& b64, const Bufs<float>& b32,
                            const double* E, int gate) {
   hipError_t e;
-  MixArgs m = mix_args(c, b64, b32, gate);
-  if ((e = launch_mix_accumulate(m, c->stream)) != hipSuccess) return e;
-  if ((e = enq_true_residual<double>(c, b64, b64.v[0], E, b64.v[1], PART_AUX, gate)) != hipSuccess)
+  MixArgs m = mix_args(g, b64, b32, gate);
+  if ((e = launch_mix_accumulate(m, stream_of(g))) != hipSuccess) return e;
+  if ((e = enq_true_residual<double>(g, b64, b64.v[0], E, b64.v[1], PART_AUX, gate)) != hipSuccess)
     return e;
-  if ((e = launch_mix_convert(m, c->stream)) != hipSuccess) return e;
-  return enq_finalize(c, FZ_REFRESH, col0_block_count(c, b64), gate);
+  if ((e = launch_mix_convert(m, stream_of(g))) != hipSuccess) return e;
+  return enq_finalize(g, FZ_REFRESH, col0_block_count(g, b64), gate);
 }
 
-hipError_t sync_state(lshom_ctx* c) {
-  hipError_t e = hipMemcpyAsync(c->host_state, dev_state(c), sizeof(DevState),
-                                hipMemcpyDeviceToHost, c->stream);
+hipError_t sync_states(Group& g) {
+  hipError_t e = hipMemcpyAsync(g.host_states.data(), dev_state(g), sizeof(DevState) * g.nprob,
+                                hipMemcpyDeviceToHost, stream_of(g));
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(c->stream);
+  return hipStreamSynchronize(stream_of(g));
 }
 
-// Run blocks of work until the device reports done.  A block is captured
-// once into a HIP graph (key) and replayed; with K == 0 it is queued eagerly.
+bool all_done(const Group& g) {
+  for (const DevState& s : g.host_states)
+    if (!s.done) return false;
+  return true;
+}
+
+// Run blocks of work until the device reports every problem done.  A block is
+// captured once into a HIP graph and replayed (cached per key when the group
+// has a cache); with K == 0 it is queued eagerly.
 template <typename F>
-lshom_status run_blocks(lshom_ctx* c, int key, int K, long long max_blocks, F&& enqueue_block) {
-  HIP_TRY(c, sync_state(c));
+lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqueue_block) {
+  lshom_ctx* c = g.ctx;
+  HIP_TRY(c, sync_states(g));
   hipGraphExec_t ex = nullptr;
+  bool owned = false;
   if (K > 0) {
     auto gk = std::make_pair(key, K);
-    auto it = c->graphs.find(gk);
-    if (it == c->graphs.end()) {
-      hipGraph_t g = nullptr;
-      HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    if (g.graph_cache) {
+      auto it = g.graph_cache->find(gk);
+      if (it != g.graph_cache->end()) ex = it->second;
+    }
+    if (!ex) {
+      hipGraph_t gr = nullptr;
+      HIP_TRY(c, hipStreamBeginCapture(stream_of(g), hipStreamCaptureModeThreadLocal));
       hipError_t e = enqueue_block();
-      hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+      hipError_t e2 = hipStreamEndCapture(stream_of(g), &gr);
       if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
+        if (gr) (void)hipGraphDestroy(gr);
         return fail(c, LSHOM_ERR_HIP, std::string("graph capture failed: ") +
                                           hipGetErrorString(e != hipSuccess ? e : e2));
       }
-      hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
+      hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
       if (e3 != hipSuccess)
         return fail(c, LSHOM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
-      c->graphs.emplace(gk, ex);
-    } else {
-      ex = it->second;
+      if (g.graph_cache) g.graph_cache->emplace(gk, ex);
+      else owned = true;
     }
   }
+  lshom_status st = LSHOM_OK;
   // the device sets `done` at the latest after max_iter iterations; the
   // block bound only guards against a state that stopped advancing
   for (long long blocks = 0;; ++blocks) {
-    if (c->host_state->done) break;
-    if (blocks > max_blocks) return fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
-    if (ex) {
-      HIP_TRY(c, hipGraphLaunch(ex, c->stream));
-    } else {
-      HIP_TRY(c, enqueue_block());
+    if (all_done(g)) break;
+    if (blocks > max_blocks) {
+      st = fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
+      break;
     }
-    HIP_TRY(c, sync_state(c));
+    hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue_block();
+    if (e == hipSuccess) e = sync_states(g);
+    if (e != hipSuccess) {
+      st = fail(c, LSHOM_ERR_HIP, std::string("iteration block: ") + hipGetErrorString(e));
+      break;
+    }
   }
-  return LSHOM_OK;
-}
-
-DevState initial_state(const lshom_ctx* c, const double* E, double tol, int max_iter) {
-  DevState s{};
-  double e2 = 0.0;
-  for (int t = 0; t < c->d; ++t) e2 += E[t] * E[t];
-  s.b2 = e2 * (double)c->nvox;
-  s.tol2b2 = tol * tol * s.b2;
-  s.max_iter = max_iter;
-  return s;
-}
-
-void fill_info(lshom_ctx* c, const lshom_solve_opts& o, int warm_used, bool mixed, lshom_solve_info* info) {
-  const DevState& hs = *c->host_state;
-  if (!info) return;
-  info->iterations = hs.iter_a;
-  info->applies_fp32 = mixed ? hs.iter_a : 0;
-  info->applies_fp64 = mixed ? hs.n_refresh : hs.iter_a;
-  info->status = hs.status;
-  info->warm_start_used = warm_used;
-  info->refreshes = mixed ? hs.n_refresh : 0;
-  const double rr = mixed ? hs.rr_true : hs.rr_log;
-  info->rel_res = std::sqrt(rr / hs.b2);
-  info->rel_res_true = o.true_residual ? std::sqrt(hs.rr_true / hs.b2) : -1.0;
-  info->eta_r = c->l0 * std::sqrt(rr / hs.b2);
+  if (owned) (void)hipGraphExecDestroy(ex);
+  return st;
 }
 
 }  // namespace
@@ -491,175 +566,152 @@ void fill_info(lshom_ctx* c, const lshom_solve_opts& o, int warm_used, bool mixe
 // Workspace preparation
 // ---------------------------------------------------------------------------
 
-lshom_status prepare_workspace(lshom_ctx* c) {
-  const Layout& use = c->lay;
-  std::vector<double> c64(kMaxPhases, 0.0);
-  std::vector<float> c32(kMaxPhases, 0.0f);
-  for (size_t i = 0; i < c->cond.size(); ++i) {
-    c64[i] = c->cond[i];
-    c32[i] = (float)c->cond[i];
-  }
-  HIP_TRY(c, hipMemcpy(c->ws + use.off_cond64, c64.data(), kMaxPhases * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(c->ws + use.off_cond32, c32.data(), kMaxPhases * sizeof(float), hipMemcpyHostToDevice));
-  for (int a = 0; a < c->d; ++a) {
+lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const std::vector<ProbEntry>* tab,
+                               const std::vector<const uint8_t*>& phases) {
+  lshom_ctx* c = g.ctx;
+  const Layout& use = g.lay;
+  const int np = g.nprob;
+  std::vector<double> c64((size_t)kCondStride * np, 0.0);
+  std::vector<float> c32((size_t)kCondStride * np, 0.0f);
+  for (int p = 0; p < np; ++p)
+    for (int i = 0; i < g.n_phases; ++i) {
+      c64[(size_t)p * kCondStride + i] = cond[(size_t)p * g.n_phases + i];
+      c32[(size_t)p * kCondStride + i] = (float)cond[(size_t)p * g.n_phases + i];
+    }
+  HIP_TRY(c, hipMemcpy(g.ws + use.off_cond64, c64.data(), c64.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpy(g.ws + use.off_cond32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  for (int a = 0; a < g.d; ++a) {
     std::vector<double> tw;
-    twiddles((int)c->N[a], &tw);
+    twiddles((int)g.N[a], &tw);
     std::vector<float> tw32(tw.size());
     for (size_t i = 0; i < tw.size(); ++i) tw32[i] = (float)tw[i];
-    HIP_TRY(c, hipMemcpy(c->ws + use.off_tw64[a], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->ws + use.off_tw32[a], tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(g.ws + use.off_tw64[a], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(g.ws + use.off_tw32[a], tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
   }
-  DevState zero{};
-  HIP_TRY(c, hipMemcpy(c->ws + use.off_state, &zero, sizeof(DevState), hipMemcpyHostToDevice));
+  if (tab)
+    HIP_TRY(c, hipMemcpy(g.ws + use.off_tab, tab->data(), tab->size() * sizeof(ProbEntry), hipMemcpyHostToDevice));
+  std::vector<DevState> zero(np);
+  HIP_TRY(c, hipMemcpy(g.ws + use.off_state, zero.data(), sizeof(DevState) * np, hipMemcpyHostToDevice));
+  g.host_states.assign(np, DevState{});
   // every phase index must name a conductivity
-  unsigned* mx = reinterpret_cast<unsigned*>(c->ws + use.off_scratch);
-  unsigned host_max = 0;
-  HIP_TRY(c, hipMemcpy(mx, &host_max, sizeof(unsigned), hipMemcpyHostToDevice));
-  HIP_TRY(c, launch_max_phase(c->phase, c->nvox, mx, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  HIP_TRY(c, hipMemcpy(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost));
-  if (host_max >= c->cond.size())
-    return fail(c, LSHOM_ERR_INVALID_ARG, "phase image holds an index >= n_phases");
+  unsigned* mx = reinterpret_cast<unsigned*>(g.ws + use.off_scratch);
+  for (const uint8_t* ph : phases) {
+    unsigned host_max = 0;
+    HIP_TRY(c, hipMemcpy(mx, &host_max, sizeof(unsigned), hipMemcpyHostToDevice));
+    HIP_TRY(c, launch_max_phase(ph, g.nvox, mx, stream_of(g)));
+    HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+    HIP_TRY(c, hipMemcpy(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (host_max >= (unsigned)g.n_phases)
+      return fail(c, LSHOM_ERR_INVALID_ARG, "phase image holds an index >= n_phases");
+  }
   return LSHOM_OK;
 }
 
 // ---------------------------------------------------------------------------
-// FP64 solve: the plain method
+// Solve every problem of a group (plain FP64 or mixed precision)
 // ---------------------------------------------------------------------------
 
-lshom_status solve_fp64(lshom_ctx* c, const double* E, double tol, const lshom_solve_opts& o,
-                        const double* x0, double* e_out, double* leff, lshom_solve_info* info) {
-  Bufs<double> b = get_bufs<double>(c);
-  cx<double>* x = b.v[0];
-  cx<double>* r = b.v[1];
-  cx<double>* p = b.v[2];
-  cx<double>* q = b.v[3];
-  const long long ncol = col0_block_count(c, b);
-  DevState init = initial_state(c, E, tol, o.max_iter);
-  HIP_TRY(c, launch_state_init(dev_state(c), init, c->stream));
-  HIP_TRY(c, launch_fill_zero(x, c->nhalf, c->stream));
-  HIP_TRY(c, launch_fill_zero(p, c->nhalf, c->stream));
+lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lshom_solve_opts& o,
+                         const double* E_single, const double* x0, double* e_single) {
+  lshom_ctx* c = g.ctx;
+  const bool mixed = o.precision == LSHOM_PRECISION_MIXED;
+  Bufs<double> b64 = get_bufs<double>(g);
+  const long long ncol = col0_block_count(g, b64);
+  const long long nall = g.nhalf * g.nprob;
+  const double* E = g.batched ? nullptr : E_single;
+  cx<double>* x64 = b64.v[0];
+  cx<double>* r64 = b64.v[1];
+  DevState* init_dev = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);  // staged, then reused
+  // initial scalars: staged through the partials area (overwritten later)
+  HIP_TRY(c, hipMemcpyAsync(init_dev, init.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice,
+                            stream_of(g)));
+  HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, g.nprob, stream_of(g)));
+  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  HIP_TRY(c, launch_fill_zero(x64, nall, stream_of(g)));
+  Bufs<float> b32{};
+  if (mixed) {
+    b32 = get_bufs<float>(g);
+    HIP_TRY(c, launch_fill_zero(b32.v[0], nall, stream_of(g)));
+    HIP_TRY(c, launch_fill_zero(b32.v[2], nall, stream_of(g)));
+  } else {
+    HIP_TRY(c, launch_fill_zero(b64.v[2], nall, stream_of(g)));
+  }
+  const int fin_init = mixed ? FZ_REFRESH_INIT : FZ_CHECK;
+  const int init_region = mixed ? PART_AUX : PART_RR0;
   int warm_used = 0;
   if (x0) {
     // residual of E for the admissibility test, then of E + P x0
-    HIP_TRY(c, (enq_residual_of_E<double>(c, b, E, r, PART_AUX)));
-    HIP_TRY(c, enq_finalize(c, FZ_AUX, ncol, GATE_ALWAYS));
-    HIP_TRY(c, enq_project_real(c, b, x0, false, x));
-    HIP_TRY(c, (enq_true_residual<double>(c, b, x, E, r, PART_RR0, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(c, FZ_CHECK, 0, GATE_ALWAYS));
-    HIP_TRY(c, sync_state(c));
-    const DevState& hs = *c->host_state;
-    if (std::isfinite(hs.rr_log) && hs.rr_log < hs.dot_aux) {
+    HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, PART_AUX)));
+    HIP_TRY(c, enq_finalize(g, FZ_AUX, ncol, GATE_ALWAYS));
+    HIP_TRY(c, enq_project_real(g, b64, x0, false, x64));
+    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS)));
+    HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS));
+    HIP_TRY(c, sync_states(g));
+    const DevState& hs = g.host_states[0];
+    const double rr = mixed ? hs.rr_true : hs.rr_log;
+    if (std::isfinite(rr) && rr < hs.dot_aux) {
       warm_used = 1;
     } else {
-      HIP_TRY(c, launch_state_init(dev_state(c), init, c->stream));
-      HIP_TRY(c, launch_fill_zero(x, c->nhalf, c->stream));
+      HIP_TRY(c, launch_fill_zero(x64, nall, stream_of(g)));
     }
   }
   if (!warm_used) {
-    HIP_TRY(c, (enq_residual_of_E<double>(c, b, E, r, PART_RR0)));
-    HIP_TRY(c, enq_finalize(c, FZ_CHECK, 0, GATE_ALWAYS));
+    // the staged initial states were consumed above only in the warm path;
+    // reload them (the partials area is overwritten by the residual)
+    HIP_TRY(c, hipMemcpyAsync(init_dev, init.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice,
+                              stream_of(g)));
+    HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, g.nprob, stream_of(g)));
+    HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, init_region)));
+    HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS));
   }
+  if (mixed) HIP_TRY(c, launch_mix_convert(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
+  HIP_TRY(c, sync_states(g));
+  int max_iter = 0;
+  for (const DevState& s : init) max_iter = std::max(max_iter, s.max_iter);
   const int K = o.graph_block;
   const int per = K > 0 ? K : 8;
-  HIP_TRY(c, sync_state(c));
-  lshom_status s = run_blocks(c, 0, K, (long long)o.max_iter / per + 4, [&]() -> hipError_t {
-    for (int k = 0; k < per; ++k) {
-      hipError_t e = enq_cg_iteration<double>(c, b, GATE_ACTIVE);
-      if (e != hipSuccess) return e;
-    }
-    return enq_finalize(c, FZ_CHECK, 0, GATE_ACTIVE);
-  });
-  if (s != LSHOM_OK) return s;
-  if (o.true_residual) {
-    HIP_TRY(c, (enq_true_residual<double>(c, b, x, E, q, PART_AUX, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(c, FZ_RR_TRUE, ncol, GATE_ALWAYS));
+  lshom_status s;
+  if (!mixed) {
+    s = run_blocks(g, 0, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+      for (int k = 0; k < per; ++k) {
+        hipError_t e = enq_cg_iteration<double>(g, b64, GATE_ACTIVE);
+        if (e != hipSuccess) return e;
+      }
+      return enq_finalize(g, FZ_CHECK, 0, GATE_ACTIVE);
+    });
+  } else {
+    // a refresh may cut a block short: at least one iteration per block is certain
+    s = run_blocks(g, 1, K, (long long)max_iter + 4, [&]() -> hipError_t {
+      for (int k = 0; k < per; ++k) {
+        hipError_t e = enq_cg_iteration<float>(g, b32, GATE_NO_REFRESH);
+        if (e != hipSuccess) return e;
+      }
+      return enq_mix_refresh(g, b64, b32, E, GATE_REFRESH);
+    });
   }
-  HIP_TRY(c, enq_field_out(c, b, x, E, nullptr, e_out, true));
-  HIP_TRY(c, sync_state(c));
-  const DevState& hs = *c->host_state;
-  if (leff)
-    for (int t = 0; t < c->d; ++t) leff[t] = hs.leff[t];
-  fill_info(c, o, warm_used, false, info);
-  return hs.status;
-}
-
-// ---------------------------------------------------------------------------
-// Mixed precision: FP32 operator, FP32 vectors, FP64 dots; FP64 iterate and
-// FP64 true residual at every refresh (reliable update; p is kept).
-// ---------------------------------------------------------------------------
-
-lshom_status solve_mixed(lshom_ctx* c, const double* E, double tol, const lshom_solve_opts& o,
-                         const double* x0, double* e_out, double* leff, lshom_solve_info* info) {
-  Bufs<double> b64 = get_bufs<double>(c);
-  Bufs<float> b32 = get_bufs<float>(c);
-  cx<double>* x64 = b64.v[0];
-  cx<double>* r64 = b64.v[1];
-  const long long ncol = col0_block_count(c, b64);
-  DevState init = initial_state(c, E, tol, o.max_iter);
-  init.refresh_every = o.refresh_every;
-  init.drop2 = o.refresh_drop * o.refresh_drop;
-  HIP_TRY(c, launch_state_init(dev_state(c), init, c->stream));
-  HIP_TRY(c, launch_fill_zero(x64, c->nhalf, c->stream));
-  HIP_TRY(c, launch_fill_zero(b32.v[0], c->nhalf, c->stream));
-  HIP_TRY(c, launch_fill_zero(b32.v[2], c->nhalf, c->stream));
-  int warm_used = 0;
-  if (x0) {
-    HIP_TRY(c, (enq_residual_of_E<double>(c, b64, E, r64, PART_AUX)));
-    HIP_TRY(c, enq_finalize(c, FZ_AUX, ncol, GATE_ALWAYS));
-    HIP_TRY(c, enq_project_real(c, b64, x0, false, x64));
-    HIP_TRY(c, (enq_true_residual<double>(c, b64, x64, E, r64, PART_AUX, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(c, FZ_REFRESH_INIT, ncol, GATE_ALWAYS));
-    HIP_TRY(c, sync_state(c));
-    const DevState& hs = *c->host_state;
-    if (std::isfinite(hs.rr_true) && hs.rr_true < hs.dot_aux) {
-      warm_used = 1;
-    } else {
-      HIP_TRY(c, launch_state_init(dev_state(c), init, c->stream));
-      HIP_TRY(c, launch_fill_zero(x64, c->nhalf, c->stream));
-    }
-  }
-  if (!warm_used) {
-    HIP_TRY(c, (enq_residual_of_E<double>(c, b64, E, r64, PART_AUX)));
-    HIP_TRY(c, enq_finalize(c, FZ_REFRESH_INIT, ncol, GATE_ALWAYS));
-  }
-  HIP_TRY(c, launch_mix_convert(mix_args(c, b64, b32, GATE_ALWAYS), c->stream));
-  HIP_TRY(c, sync_state(c));
-  const int K = o.graph_block;
-  const int per = K > 0 ? K : 8;
-  // a refresh may cut a block short: at least one iteration per block is certain
-  lshom_status s = run_blocks(c, 1, K, (long long)o.max_iter + 4, [&]() -> hipError_t {
-    for (int k = 0; k < per; ++k) {
-      hipError_t e = enq_cg_iteration<float>(c, b32, GATE_NO_REFRESH);
-      if (e != hipSuccess) return e;
-    }
-    return enq_mix_refresh(c, b64, b32, E, GATE_REFRESH);
-  });
   if (s != LSHOM_OK) return s;
   // fold what a breakdown left in the FP32 correction (no-op after a refresh)
-  HIP_TRY(c, launch_mix_accumulate(mix_args(c, b64, b32, GATE_ALWAYS), c->stream));
+  if (mixed) HIP_TRY(c, launch_mix_accumulate(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
   if (o.true_residual) {
-    HIP_TRY(c, (enq_true_residual<double>(c, b64, x64, E, b64.v[3], PART_AUX, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(c, FZ_RR_TRUE, ncol, GATE_ALWAYS));
+    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, b64.v[3], PART_AUX, GATE_ALWAYS)));
+    HIP_TRY(c, enq_finalize(g, FZ_RR_TRUE, ncol, GATE_ALWAYS));
   }
-  HIP_TRY(c, enq_field_out(c, b64, x64, E, nullptr, e_out, true));
-  HIP_TRY(c, sync_state(c));
-  const DevState& hs = *c->host_state;
-  if (leff)
-    for (int t = 0; t < c->d; ++t) leff[t] = hs.leff[t];
-  fill_info(c, o, warm_used, true, info);
-  return hs.status;
+  HIP_TRY(c, enq_field_out(g, b64, x64, E, nullptr, e_single, true));
+  HIP_TRY(c, sync_states(g));
+  g.warm_used = warm_used;
+  return LSHOM_OK;
 }
 
 // ---------------------------------------------------------------------------
-// One FP64 apply on a real field: q = p + B p
+// One FP64 apply on a real field: q = p + B p (single problem)
 // ---------------------------------------------------------------------------
 
-lshom_status apply_real(lshom_ctx* c, const double* p, double* q) {
-  Bufs<double> b = get_bufs<double>(c);
-  HIP_TRY(c, enq_project_real(c, b, p, true, b.v[3]));
-  HIP_TRY(c, enq_field_out(c, b, b.v[3], nullptr, p, q, false));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+lshom_status apply_real(Group& g, const double* p, double* q) {
+  lshom_ctx* c = g.ctx;
+  Bufs<double> b = get_bufs<double>(g);
+  HIP_TRY(c, enq_project_real(g, b, p, true, b.v[3]));
+  HIP_TRY(c, enq_field_out(g, b, b.v[3], nullptr, p, q, false));
+  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
   return LSHOM_OK;
 }
 
@@ -670,8 +722,10 @@ lshom_status apply_real(lshom_ctx* c, const double* p, double* q) {
 namespace {
 
 template <typename T>
-lshom_status time_passes_t(lshom_ctx* c, const Bufs<T>& b, int reps, double* ms_out, double* bytes_out) {
-  cx<T>* x = b.v[0];
+lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out, double* bytes_out,
+                           unsigned mask) {
+  lshom_ctx* c = g.ctx;
+  hipStream_t sm = stream_of(g);
   cx<T>* r = b.v[1];
   cx<T>* p = b.v[2];
   cx<T>* q = b.v[3];
@@ -681,89 +735,85 @@ lshom_status time_passes_t(lshom_ctx* c, const Bufs<T>& b, int reps, double* ms_
   init.max_iter = 1 << 30;
   init.tol2b2 = -1.0;
   init.b2 = 1.0;
-  HIP_TRY(c, launch_state_init(dev_state(c), init, c->stream));
+  {
+    std::vector<DevState> all(g.nprob, init);
+    DevState* staged = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);
+    HIP_TRY(c, hipMemcpyAsync(staged, all.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice, sm));
+    HIP_TRY(c, launch_state_copy(dev_state(g), staged, g.nprob, sm));
+    HIP_TRY(c, hipStreamSynchronize(sm));
+  }
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
   const double cs = (double)sizeof(cx<T>);
-  const double nh = (double)c->nhalf;
-  const int d = c->d;
+  const double nh = (double)g.nhalf;
+  const int d = g.d;
   for (int k = 0; k < LSHOM_PASS_COUNT; ++k) {
     ms_out[k] = 0.0;
     if (bytes_out) bytes_out[k] = 0.0;
   }
   auto timed = [&](int cls, double bytes, auto&& launch) -> hipError_t {
+    if (!(mask & (1u << cls))) return hipSuccess;
     hipError_t e = launch();  // warm-up
     if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
+    if ((e = hipEventRecord(e0, sm)) != hipSuccess) return e;
     for (int i = 0; i < reps; ++i)
       if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) return e;
+    if ((e = hipEventRecord(e1, sm)) != hipSuccess) return e;
     if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
     float ms = 0.f;
     if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
     ms_out[cls] = (double)ms / reps;
-    if (bytes_out) bytes_out[cls] = bytes;
+    if (bytes_out) bytes_out[cls] = bytes * g.nprob;
     return hipSuccess;
   };
   hipError_t err;
   {
-    ColArgs<T> a = col0_args(c, b);
+    ColArgs<T> a = col0_args(g, b);
     a.mode = COL_INV_C;
     a.p_io = p;
     a.r_in = r;
     a.cg_step = 1;
     a.gate = GATE_ALWAYS;
     // reads r, p; writes p and the d pass components
-    err = timed(LSHOM_PASS_AXIS0_INVERSE, (3.0 + d) * nh * cs, [&] { return launch_col(a, c->stream); });
+    err = timed(LSHOM_PASS_AXIS0_INVERSE, (3.0 + d) * nh * cs, [&] { return launch_col(a, sm); });
   }
   if (err == hipSuccess && d == 3) {
-    ColArgs<T> m = col1_args(c, b, +1);
+    ColArgs<T> m = col1_args(g, b, +1);
     m.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_AXIS1_INVERSE, 2.0 * d * nh * cs, [&] { return launch_col(m, c->stream); });
+    err = timed(LSHOM_PASS_AXIS1_INVERSE, 2.0 * d * nh * cs, [&] { return launch_col(m, sm); });
     if (err == hipSuccess) {
-      ColArgs<T> f = col1_args(c, b, -1);
+      ColArgs<T> f = col1_args(g, b, -1);
       f.gate = GATE_ALWAYS;
-      err = timed(LSHOM_PASS_AXIS1_FORWARD, 2.0 * d * nh * cs, [&] { return launch_col(f, c->stream); });
+      err = timed(LSHOM_PASS_AXIS1_FORWARD, 2.0 * d * nh * cs, [&] { return launch_col(f, sm); });
     }
   }
   if (err == hipSuccess) {
-    RowArgs<T> rr = row_args(c, b);
+    RowArgs<T> rr = row_args(g, b);
     rr.mode = ROW_FUSED;
     rr.gate = GATE_ALWAYS;
     // reads and writes the d components, reads one phase byte per voxel
-    err = timed(LSHOM_PASS_ROW, 2.0 * d * nh * cs + (double)c->nvox, [&] { return launch_row(rr, c->stream); });
+    err = timed(LSHOM_PASS_ROW, 2.0 * d * nh * cs + (double)g.nvox, [&] { return launch_row(rr, sm); });
   }
   if (err == hipSuccess) {
-    ColArgs<T> a = col0_args(c, b);
+    ColArgs<T> a = col0_args(g, b);
     a.mode = COL_FWD_PROJ;
     a.out = q;
     a.base = p;
     a.coef_base = T(1);
-    a.coef_s = T(1.0 / c->l0);
+    a.coef_s = T(1);
+    a.s_inv_l0 = 1;
     a.dot = 1;
     a.dot_region = PART_PQ;
     a.gate = GATE_ALWAYS;
     // reads the d components and p; writes q
-    err = timed(LSHOM_PASS_AXIS0_FORWARD, (d + 2.0) * nh * cs, [&] { return launch_col(a, c->stream); });
+    err = timed(LSHOM_PASS_AXIS0_FORWARD, (d + 2.0) * nh * cs, [&] { return launch_col(a, sm); });
   }
   if (err == hipSuccess) {
-    UpdArgs<T> u{};
-    u.n = c->nhalf;
-    u.h = c->h;
-    u.n_last = (int)c->N[c->d - 1];
-    u.klast_div = klast_div_of(c);
-    u.x = x;
-    u.r = r;
-    u.p = p;
-    u.q = q;
-    u.st = dev_state(c);
-    u.parts = dev_parts(c);
-    u.n_pq = (int)col0_block_count(c, b);
-    u.inv_n = 1.0 / (double)c->nvox;
+    UpdArgs<T> u = upd_args(g, b);
     u.gate = GATE_ALWAYS;
     // reads x, r, p, q; writes x, r
-    err = timed(LSHOM_PASS_UPDATE, 6.0 * nh * cs, [&] { return launch_update(u, c->stream); });
+    err = timed(LSHOM_PASS_UPDATE, 6.0 * nh * cs, [&] { return launch_update(u, sm); });
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -773,9 +823,154 @@ lshom_status time_passes_t(lshom_ctx* c, const Bufs<T>& b, int reps, double* ms_
 
 }  // namespace
 
-lshom_status time_passes(lshom_ctx* c, int precision, int reps, double* ms_out, double* bytes_out) {
-  if (precision == LSHOM_PRECISION_FP64) return time_passes_t<double>(c, get_bufs<double>(c), reps, ms_out, bytes_out);
-  return time_passes_t<float>(c, get_bufs<float>(c), reps, ms_out, bytes_out);
+lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out) {
+  if (precision == LSHOM_PRECISION_FP64)
+    return time_passes_t<double>(g, get_bufs<double>(g), reps, ms_out, bytes_out, ~0u);
+  return time_passes_t<float>(g, get_bufs<float>(g), reps, ms_out, bytes_out, ~0u);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: each pass kind is tuned on its own (its radix order and launch
+// shape change only its own kernels), timing real launches on the group.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Radix orders to try for an axis: the default greedy schedule, its reverse,
+// and the schedules with radix-9 stages split into two radix-3 stages.
+std::vector<FftPlan> plan_candidates(int n) {
+  std::vector<FftPlan> out;
+  auto add = [&](const std::vector<int>& r) {
+    FftPlan p;
+    if (!make_plan(n, r.data(), (int)r.size(), &p)) return;
+    for (const FftPlan& q : out)
+      if (q.nstages == p.nstages && std::equal(q.radix, q.radix + q.nstages, p.radix)) return;
+    out.push_back(p);
+  };
+  FftPlan d = default_plan(n);
+  std::vector<int> base(d.radix, d.radix + d.nstages);
+  add(base);
+  std::vector<int> rev(base.rbegin(), base.rend());
+  add(rev);
+  std::vector<int> split;
+  for (int r : base) {
+    if (r == 9) {
+      split.push_back(3);
+      split.push_back(3);
+    } else {
+      split.push_back(r);
+    }
+  }
+  add(split);
+  // one radix-9 split (at the front)
+  std::vector<int> one;
+  bool done = false;
+  for (int r : base) {
+    if (r == 9 && !done) {
+      one.push_back(3);
+      one.push_back(3);
+      done = true;
+    } else {
+      one.push_back(r);
+    }
+  }
+  add(one);
+  if (out.size() > 5) out.resize(5);
+  return out;
+}
+
+template <typename T>
+double time_mask(Group& g, int precision, int reps, unsigned mask, lshom_status* st) {
+  double ms[LSHOM_PASS_COUNT];
+  *st = time_passes_t<T>(g, get_bufs<T>(g), reps, ms, nullptr, mask);
+  double t = 0.0;
+  for (int k = 0; k < LSHOM_PASS_COUNT; ++k)
+    if (mask & (1u << k)) t += ms[k];
+  (void)precision;
+  return t;
+}
+
+}  // namespace
+
+lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best) {
+  const bool f64 = precision == LSHOM_PRECISION_FP64;
+  Schedule cur = current_schedule(g, precision);
+  const int last = g.d - 1;
+  lshom_status st = LSHOM_OK;
+  auto time_of = [&](const Schedule& s, unsigned mask) -> double {
+    apply_schedule(g, s, precision);
+    return f64 ? time_mask<double>(g, precision, reps, mask, &st) : time_mask<float>(g, precision, reps, mask, &st);
+  };
+  // row pass: radix order of the last axis x rows per block
+  {
+    const unsigned mask = 1u << LSHOM_PASS_ROW;
+    double best_t = 1e300;
+    Schedule bs = cur;
+    for (const FftPlan& pl : plan_candidates((int)g.N[last])) {
+      for (int r = 2; r <= 16; r += 2) {
+        Schedule s = cur;
+        s.plan[last] = pl;
+        s.shape.rows_per_block = r;
+        if (!schedule_fits(g, s, precision)) continue;
+        const double t = time_of(s, mask);
+        if (st != LSHOM_OK) return st;
+        if (t < best_t) {
+          best_t = t;
+          bs = s;
+        }
+      }
+    }
+    cur.plan[last] = bs.plan[last];
+    cur.shape.rows_per_block = bs.shape.rows_per_block;
+  }
+  // axis-0 passes (inverse with the direction step, forward with the projection)
+  if (last != 0) {
+    const unsigned mask = (1u << LSHOM_PASS_AXIS0_INVERSE) | (1u << LSHOM_PASS_AXIS0_FORWARD);
+    double best_t = 1e300;
+    Schedule bs = cur;
+    for (const FftPlan& pl : plan_candidates((int)g.N[0])) {
+      for (int t0 = 1; t0 <= 16; t0 *= 2) {
+        Schedule s = cur;
+        s.plan[0] = pl;
+        s.shape.tile0 = t0;
+        if (!schedule_fits(g, s, precision)) continue;
+        const double t = time_of(s, mask);
+        if (st != LSHOM_OK) return st;
+        if (t < best_t) {
+          best_t = t;
+          bs = s;
+        }
+      }
+    }
+    cur.plan[0] = bs.plan[0];
+    cur.shape.tile0 = bs.shape.tile0;
+  }
+  // axis-1 passes (3-D)
+  if (g.d == 3) {
+    const unsigned mask = (1u << LSHOM_PASS_AXIS1_INVERSE) | (1u << LSHOM_PASS_AXIS1_FORWARD);
+    double best_t = 1e300;
+    Schedule bs = cur;
+    for (const FftPlan& pl : plan_candidates((int)g.N[1])) {
+      for (int t1 = 1; t1 <= 16; t1 *= 2) {
+        Schedule s = cur;
+        s.plan[1] = pl;
+        s.shape.tile1 = t1;
+        if (!schedule_fits(g, s, precision)) continue;
+        const double t = time_of(s, mask);
+        if (st != LSHOM_OK) return st;
+        if (t < best_t) {
+          best_t = t;
+          bs = s;
+        }
+      }
+    }
+    cur.plan[1] = bs.plan[1];
+    cur.shape.tile1 = bs.shape.tile1;
+  }
+  cur.ms_per_iter = time_of(cur, ~0u);
+  if (st != LSHOM_OK) return st;
+  *best = cur;
+  return LSHOM_OK;
 }
 
 }  // namespace lshom

@@ -11,6 +11,7 @@ namespace lshom {
 
 constexpr int kMaxDim = 3;
 constexpr int kUpdateBlocks = 512;   // grid of the elementwise kernels (one partial each)
+constexpr int kCondStride = 256;     // conductivity-table entries per problem
 
 // Device-resident CG scalars.
 //
@@ -61,6 +62,26 @@ struct Partials {
   __host__ __device__ double* region(int r) const { return base + (long long)r * stride; }
 };
 
+// Per-problem data of a batched launch (device memory).
+struct ProbEntry {
+  const uint8_t* phase;   // [nrows][n] phase image
+  double* e_out;          // FP64 field output d x |N| (may be null)
+  const double* x0;       // FP64 warm start d x |N| (may be null)
+  double l0;
+  double E[3];
+};
+
+// Problem dimension of a launch: block row blockIdx.y is problem p; its
+// vectors start p * vstride elements, its partial sums p * pstride doubles
+// and its state p entries after the launch's base pointers.  tab == nullptr
+// means a single problem whose data are the fields of the argument struct.
+struct Batch {
+  int nprob;
+  long long vstride;
+  long long pstride;
+  const ProbEntry* tab;
+};
+
 // Scalar steps of the single-block finalize kernel.
 enum FinMode : int {
   FZ_CHECK = 0,         // FP64: convergence / limit test on (r_m, r_m), m = iter_a
@@ -88,6 +109,7 @@ enum RowFlags : int {
   ROWF_CONST_E = 2,   // ROW_FWD: the input is the constant field E
   ROWF_ADD = 4,       // ROW_INV: add real_add to the output
   ROWF_LEFF = 8,      // ROW_INV: partial sums of <lambda out> into AUX
+  ROWF_TABLE_E = 16,  // batched: E of each problem from its table entry
 };
 
 template <typename T>
@@ -116,6 +138,7 @@ struct RowArgs {
   DevState* st;
   Partials parts;
   int gate;
+  Batch bt;
 };
 
 // ---------------------------------------------------------------------------
@@ -150,10 +173,12 @@ struct ColArgs {
   cx<T>* p_io;           // cg_step: p = r + beta p (written back)
   const cx<T>* r_in;
   int cg_step;           // this launch is the CG direction step (decides beta, stop)
-  // COL_FWD_PROJ: out = coef_base * base + coef_s * s
+  // COL_FWD_PROJ: out = coef_base * base + coef_s * [1 / l0 if s_inv_l0] * s
   cx<T>* out;
   const cx<T>* base;
   T coef_base, coef_s;
+  int s_inv_l0;
+  double l0;             // single problem (batched: the problem table)
   int dot;               // 0 none, 1 (base, out), 2 (out, out)
   int dot_region;        // partial region; PART_RR0 also sets nparts[0]
   FftPlan plan;
@@ -162,6 +187,7 @@ struct ColArgs {
   Partials parts;
   int gate;
   double inv_n;          // scales spectral sums to real-space inner products
+  Batch bt;
 };
 
 // ---------------------------------------------------------------------------
@@ -181,6 +207,7 @@ struct UpdArgs {
   int n_pq;              // partials of (p, q) to sum
   double inv_n;
   int gate;
+  Batch bt;
 };
 
 // Mixed precision: x64 += x32, x32 = 0 (accumulate); r32 = r64 and the
@@ -198,6 +225,7 @@ struct MixArgs {
   Partials parts;
   double inv_n;
   int gate;
+  Batch bt;
 };
 
 struct FinArgs {
@@ -208,6 +236,7 @@ struct FinArgs {
   int d;
   double inv_n;
   int gate;
+  Batch bt;
 };
 
 // Host launchers (passes.hip).
@@ -218,6 +247,8 @@ hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);
 hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);
+// copy nprob initial states from device memory src into st
+hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipStream_t s);
 template <typename T> hipError_t launch_fill_zero(cx<T>* p, long long n, hipStream_t s);
 hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipStream_t s);
 

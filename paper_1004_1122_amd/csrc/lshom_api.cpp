@@ -6,6 +6,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <string>
+#include <vector>
 
 #include "ctx.hpp"
 
@@ -28,9 +31,40 @@ lshom_status check_ready(lshom_ctx* c, int precision) {
   if (!c) return LSHOM_ERR_INVALID_ARG;
   if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
   if (!c->ws_ready) return fail(c, LSHOM_ERR_WORKSPACE, "no workspace attached for this problem");
-  if (precision == LSHOM_PRECISION_MIXED && !c->lay.has32)
+  if (precision == LSHOM_PRECISION_MIXED && !c->g.lay.has32)
     return fail(c, LSHOM_ERR_WORKSPACE, "workspace was sized for FP64 only");
   return LSHOM_OK;
+}
+
+// Initial device scalars of one problem.
+DevState initial_state(int d, long long nvox, const double* E, double tol, const lshom_solve_opts& o) {
+  DevState s{};
+  double e2 = 0.0;
+  for (int t = 0; t < d; ++t) e2 += E[t] * E[t];
+  s.b2 = e2 * (double)nvox;
+  s.tol2b2 = tol * tol * s.b2;
+  s.max_iter = o.max_iter;
+  if (o.precision == LSHOM_PRECISION_MIXED) {
+    s.refresh_every = o.refresh_every;
+    s.drop2 = o.refresh_drop * o.refresh_drop;
+  }
+  return s;
+}
+
+void fill_info(const DevState& hs, double l0, const lshom_solve_opts& o, int warm_used, lshom_solve_info* info) {
+  if (!info) return;
+  const bool mixed = o.precision == LSHOM_PRECISION_MIXED;
+  info->iterations = hs.iter_a;
+  info->applies_fp32 = mixed ? hs.iter_a : 0;
+  info->applies_fp64 = mixed ? hs.n_refresh : hs.iter_a;
+  info->status = hs.status;
+  info->warm_start_used = warm_used;
+  info->refreshes = mixed ? hs.n_refresh : 0;
+  const double rr = mixed ? hs.rr_true : hs.rr_log;
+  const double b2 = hs.b2 > 0.0 ? hs.b2 : 1.0;
+  info->rel_res = std::sqrt(rr / b2);
+  info->rel_res_true = o.true_residual ? std::sqrt(hs.rr_true / b2) : -1.0;
+  info->eta_r = l0 * std::sqrt(rr / b2);
 }
 
 hipError_t order_after_user(lshom_ctx* c) {
@@ -113,15 +147,12 @@ lshom_status lshom_create(lshom_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->host_state), sizeof(DevState), hipHostMallocDefault) !=
-          hipSuccess) {
+      hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
     if (c->ev) (void)hipEventDestroy(c->ev);
     delete c;
     return LSHOM_ERR_HIP;
   }
-  std::memset(c->host_state, 0, sizeof(DevState));
   *out = c;
   return LSHOM_OK;
 }
@@ -130,8 +161,7 @@ void lshom_destroy(lshom_ctx* c) {
   if (!c) return;
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
-  drop_graphs(c);
-  if (c->host_state) (void)hipHostFree(c->host_state);
+  drop_graphs(c->graphs);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -146,33 +176,22 @@ lshom_status lshom_set_microstructure(lshom_ctx* c, int d, const int64_t* N,
   if (!phase_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "phase_dev is NULL");
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
-  drop_graphs(c);
+  drop_graphs(c->graphs);
   c->ws_ready = false;
   c->have_problem = false;
-  c->d = d;
-  c->nvox = 1;
-  for (int a = 0; a < 3; ++a) c->N[a] = a < d ? N[a] : 1;
-  for (int a = 0; a < d; ++a) c->nvox *= N[a];
-  c->h = (int)(N[d - 1] / 2 + 1);
-  c->nrows = c->nvox / N[d - 1];
-  c->nhalf = c->nrows * c->h;
-  c->transposed = (d == 2);
-  c->phase = phase_dev;
+  c->g = Group{};
+  c->g.ctx = c;
+  c->g.graph_cache = &c->graphs;
+  if (group_setup(c->g, d, N, n_phases) != LSHOM_OK)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+  c->g.phase = phase_dev;
   c->cond.assign(cond_host, cond_host + n_phases);
   double lo = cond_host[0], hi = cond_host[0];
   for (int i = 1; i < n_phases; ++i) {
     lo = std::min(lo, cond_host[i]);
     hi = std::max(hi, cond_host[i]);
   }
-  c->l0 = 0.5 * (lo + hi);
-  for (int a = 0; a < d; ++a) c->plan[a] = default_plan((int)N[a]);
-  c->shape64 = default_shape(d, c->N, c->plan, (int)sizeof(cx<double>), kLdsBudget, kMinBlocks,
-                             c->transposed, n_phases);
-  c->shape32 = default_shape(d, c->N, c->plan, (int)sizeof(cx<float>), kLdsBudget, kMinBlocks,
-                             c->transposed, n_phases);
-  if (!shape_fits(d, c->N, c->plan, c->shape64, (int)sizeof(cx<double>), kLdsBudget, n_phases) ||
-      !shape_fits(d, c->N, c->plan, c->shape32, (int)sizeof(cx<float>), kLdsBudget, n_phases))
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+  c->g.l0 = 0.5 * (lo + hi);
   c->have_problem = true;
   c->err.clear();
   return LSHOM_OK;
@@ -184,8 +203,8 @@ lshom_status lshom_set_reference(lshom_ctx* c, double l0) {
   if (!std::isfinite(l0) || !(l0 > 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "l0 must be finite and > 0");
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
-  drop_graphs(c);  // l0 is baked into captured launches
-  c->l0 = l0;
+  drop_graphs(c->graphs);  // l0 is baked into captured launches
+  c->g.l0 = l0;
   return LSHOM_OK;
 }
 
@@ -194,7 +213,7 @@ lshom_status lshom_workspace_size(const lshom_ctx* c, int precision, size_t* byt
   if (!c->have_problem) return LSHOM_ERR_STATE;
   if (precision != LSHOM_PRECISION_FP64 && precision != LSHOM_PRECISION_MIXED)
     return LSHOM_ERR_INVALID_ARG;
-  *bytes = compute_layout(c, precision == LSHOM_PRECISION_MIXED).total;
+  *bytes = compute_layout(c->g, precision == LSHOM_PRECISION_MIXED).total;
   return LSHOM_OK;
 }
 
@@ -203,20 +222,20 @@ lshom_status lshom_set_workspace(lshom_ctx* c, void* dev, size_t bytes) {
   if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
   if (!dev || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
     return fail(c, LSHOM_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-  Layout l64 = compute_layout(c, false);
-  Layout lmx = compute_layout(c, true);
+  Layout l64 = compute_layout(c->g, false);
+  Layout lmx = compute_layout(c->g, true);
   Layout use;
   if (bytes >= lmx.total) use = lmx;
   else if (bytes >= l64.total) use = l64;
   else return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_workspace_size()");
   DeviceGuard g(c->device);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  drop_graphs(c);
+  drop_graphs(c->graphs);
   c->ws_ready = false;
-  c->ws = static_cast<char*>(dev);
+  c->g.ws = static_cast<char*>(dev);
   c->ws_bytes = bytes;
-  c->lay = use;
-  lshom_status s = prepare_workspace(c);
+  c->g.lay = use;
+  lshom_status s = prepare_workspace(c->g, c->cond, nullptr, {c->g.phase});
   if (s != LSHOM_OK) return s;
   c->ws_ready = true;
   c->err.clear();
@@ -235,28 +254,33 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
   if ((s = check_ready(c, o.precision)) != LSHOM_OK) return s;
   if (!E_host) return fail(c, LSHOM_ERR_INVALID_ARG, "E_host is NULL");
   if (!std::isfinite(tol) || tol < 0.0) return fail(c, LSHOM_ERR_INVALID_ARG, "tol must be finite and >= 0");
-  for (int a = 0; a < c->d; ++a)
+  for (int a = 0; a < c->g.d; ++a)
     if (!std::isfinite(E_host[a])) return fail(c, LSHOM_ERR_INVALID_ARG, "E must be finite");
   DeviceGuard g(c->device);
   HIP_TRY(c, order_after_user(c));
+  Group& gr = c->g;
   double e2 = 0.0;
-  for (int a = 0; a < c->d; ++a) e2 += E_host[a] * E_host[a];
+  for (int a = 0; a < gr.d; ++a) e2 += E_host[a] * E_host[a];
   if (e2 == 0.0) {
     // b = 0: the solution is e = 0 (Sec. 2.2, Eq. (15) is linear)
-    if (e_dev) HIP_TRY(c, hipMemsetAsync(e_dev, 0, sizeof(double) * c->d * c->nvox, c->stream));
+    if (e_dev) HIP_TRY(c, hipMemsetAsync(e_dev, 0, sizeof(double) * gr.d * gr.nvox, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (leff_host)
-      for (int a = 0; a < c->d; ++a) leff_host[a] = 0.0;
+      for (int a = 0; a < gr.d; ++a) leff_host[a] = 0.0;
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->rel_res_true = 0.0;
     }
     return LSHOM_OK;
   }
-  if (o.precision == LSHOM_PRECISION_FP64)
-    s = solve_fp64(c, E_host, tol, o, x0_dev, e_dev, leff_host, info);
-  else
-    s = solve_mixed(c, E_host, tol, o, x0_dev, e_dev, leff_host, info);
+  std::vector<DevState> init(1, initial_state(gr.d, gr.nvox, E_host, tol, o));
+  s = solve_group(gr, init, o, E_host, x0_dev, e_dev);
+  if (s != LSHOM_OK) return s;
+  const DevState& hs = gr.host_states[0];
+  if (leff_host)
+    for (int a = 0; a < gr.d; ++a) leff_host[a] = hs.leff[a];
+  fill_info(hs, gr.l0, o, gr.warm_used, info);
+  s = hs.status;
   if (s == LSHOM_OK) c->err.clear();
   else if (s == LSHOM_ERR_NOT_CONVERGED) c->err = "not converged within max_iter";
   else if (s == LSHOM_ERR_BREAKDOWN) c->err = "CG breakdown";
@@ -267,7 +291,7 @@ lshom_status lshom_homogenize(lshom_ctx* c, double tol, const lshom_solve_opts* 
                               double* leff_host, lshom_solve_info* infos) {
   if (!c || !leff_host) return LSHOM_ERR_INVALID_ARG;
   if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
-  const int d = c->d;
+  const int d = c->g.d;
   lshom_status worst = LSHOM_OK;
   for (int b = 0; b < d; ++b) {
     double E[3] = {0.0, 0.0, 0.0};
@@ -288,7 +312,7 @@ lshom_status lshom_apply(lshom_ctx* c, const double* p_dev, double* q_dev) {
   if (!p_dev || !q_dev || p_dev == q_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "p_dev/q_dev NULL or aliased");
   DeviceGuard g(c->device);
   HIP_TRY(c, order_after_user(c));
-  s = apply_real(c, p_dev, q_dev);
+  s = apply_real(c->g, p_dev, q_dev);
   if (s == LSHOM_OK) c->err.clear();
   return s;
 }
@@ -302,9 +326,419 @@ lshom_status lshom_time_passes(lshom_ctx* c, int precision, int reps, double* ms
   if (s != LSHOM_OK) return s;
   DeviceGuard g(c->device);
   HIP_TRY(c, order_after_user(c));
-  s = time_passes(c, precision, reps, ms_out, bytes_out);
+  s = time_passes(c->g, precision, reps, ms_out, bytes_out);
   if (s == LSHOM_OK) c->err.clear();
   return s;
+}
+
+// ---------------------------------------------------------------------------
+// Many problems: one group (same launches) per distinct grid
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchPlan {
+  std::vector<Group> groups;
+  std::vector<std::vector<int>> members;  // problem indices of each group
+  std::vector<size_t> offsets;            // workspace offset of each group
+  size_t total = 0;
+};
+
+lshom_status plan_batch(lshom_ctx* c, int n, const lshom_problem* probs, int precision, BatchPlan* bp) {
+  if (n < 1 || !probs) return fail(c, LSHOM_ERR_INVALID_ARG, "n must be >= 1 and probs non-NULL");
+  std::map<std::vector<int64_t>, int> by_grid;
+  for (int i = 0; i < n; ++i) {
+    const lshom_problem& p = probs[i];
+    lshom_status s = lshom_check_problem(p.d, p.N, p.n_phases, p.cond_host, p.l0 > 0 ? p.l0 : 0.0, p.E, p.tol);
+    if (s != LSHOM_OK) return fail(c, s, "problem " + std::to_string(i) + " is invalid");
+    if (!p.phase_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": phase_dev is NULL");
+    if (!(p.tol >= 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": tol < 0");
+    std::vector<int64_t> key(p.N, p.N + p.d);
+    key.insert(key.begin(), p.d);
+    auto it = by_grid.find(key);
+    if (it == by_grid.end()) {
+      it = by_grid.emplace(key, (int)bp->groups.size()).first;
+      bp->groups.emplace_back();
+      bp->members.emplace_back();
+    }
+    bp->members[it->second].push_back(i);
+  }
+  size_t off = 0;
+  for (size_t gi = 0; gi < bp->groups.size(); ++gi) {
+    Group& g = bp->groups[gi];
+    const lshom_problem& p0 = probs[bp->members[gi][0]];
+    int nph = 1;
+    for (int i : bp->members[gi]) nph = std::max(nph, probs[i].n_phases);
+    g.ctx = c;
+    if (group_setup(g, p0.d, p0.N, nph) != LSHOM_OK)
+      return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+    g.nprob = (int)bp->members[gi].size();
+    g.batched = true;
+    g.lay = compute_layout(g, precision == LSHOM_PRECISION_MIXED);
+    bp->offsets.push_back(off);
+    off += (g.lay.total + kAlign - 1) / kAlign * kAlign;
+  }
+  bp->total = off;
+  return LSHOM_OK;
+}
+
+// Carve group gi of a batch plan in the workspace and upload its tables.
+lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const lshom_problem* probs,
+                                 void* ws_dev, const lshom_solve_opts& o, std::vector<ProbEntry>* tab,
+                                 std::vector<DevState>* init) {
+  Group& g = bp.groups[gi];
+  const std::vector<int>& mem = bp.members[gi];
+  g.ws = static_cast<char*>(ws_dev) + bp.offsets[gi];
+  std::vector<double> cond((size_t)g.nprob * g.n_phases, 1.0);
+  tab->assign(g.nprob, ProbEntry{});
+  init->assign(g.nprob, DevState{});
+  std::vector<const uint8_t*> phases;
+  for (int j = 0; j < g.nprob; ++j) {
+    const lshom_problem& p = probs[mem[j]];
+    double lo = p.cond_host[0], hi = p.cond_host[0];
+    for (int i = 0; i < p.n_phases; ++i) {
+      cond[(size_t)j * g.n_phases + i] = p.cond_host[i];
+      lo = std::min(lo, p.cond_host[i]);
+      hi = std::max(hi, p.cond_host[i]);
+    }
+    ProbEntry& e = (*tab)[j];
+    e.phase = p.phase_dev;
+    e.e_out = p.e_dev;
+    e.x0 = nullptr;
+    e.l0 = p.l0 > 0.0 ? p.l0 : 0.5 * (lo + hi);
+    for (int t = 0; t < 3; ++t) e.E[t] = t < p.d ? p.E[t] : 0.0;
+    phases.push_back(p.phase_dev);
+    (*init)[j] = initial_state(p.d, g.nvox, p.E, p.tol, o);
+  }
+  lshom_status s = prepare_workspace(g, cond, tab, phases);
+  if (s != LSHOM_OK) return s;
+  // a phase index must be below the problem's own phase count: conductivities
+  // beyond it are never valid, so they are poisoned (the solve then breaks down)
+  for (int j = 0; j < g.nprob; ++j) {
+    const int np = probs[mem[j]].n_phases;
+    if (np >= g.n_phases) continue;
+    std::vector<double> bad((size_t)(g.n_phases - np), std::nan(""));
+    std::vector<float> badf(bad.size(), std::nanf(""));
+    HIP_TRY(c, hipMemcpy(g.ws + g.lay.off_cond64 + ((size_t)j * kCondStride + np) * sizeof(double),
+                         bad.data(), bad.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(g.ws + g.lay.off_cond32 + ((size_t)j * kCondStride + np) * sizeof(float),
+                         badf.data(), badf.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return LSHOM_OK;
+}
+
+void to_c_schedule(const Group& g, const Schedule& s, int precision, lshom_schedule* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->d = g.d;
+  for (int a = 0; a < 3; ++a) out->N[a] = g.N[a];
+  out->precision = precision;
+  out->rows_per_block = s.shape.rows_per_block;
+  out->tile0 = s.shape.tile0;
+  out->tile1 = s.shape.tile1;
+  for (int a = 0; a < g.d; ++a) {
+    out->nstages[a] = s.plan[a].nstages;
+    for (int k = 0; k < s.plan[a].nstages; ++k) out->radix[a][k] = s.plan[a].radix[k];
+  }
+  out->ms_per_iter = s.ms_per_iter;
+}
+
+lshom_status from_c_schedule(lshom_ctx* c, const lshom_schedule* in, Schedule* s) {
+  if (in->d != 2 && in->d != 3) return fail(c, LSHOM_ERR_INVALID_ARG, "schedule: d must be 2 or 3");
+  if (in->precision != LSHOM_PRECISION_FP64 && in->precision != LSHOM_PRECISION_MIXED)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "schedule: precision must be 0 or 1");
+  for (int a = 0; a < in->d; ++a) {
+    if (in->nstages[a] < 1 || in->nstages[a] > kMaxStages ||
+        !make_plan((int)in->N[a], in->radix[a], in->nstages[a], &s->plan[a]))
+      return fail(c, LSHOM_ERR_INVALID_ARG, "schedule: radices do not factor N");
+  }
+  s->shape.rows_per_block = in->rows_per_block;
+  s->shape.tile0 = in->tile0;
+  s->shape.tile1 = in->d == 3 ? in->tile1 : 1;
+  s->ms_per_iter = in->ms_per_iter;
+  return LSHOM_OK;
+}
+
+std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t colon = a.find(':');
+  return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+}  // namespace
+
+lshom_status lshom_batch_workspace_size(lshom_ctx* c, int32_t n, const lshom_problem* probs,
+                                        int precision, size_t* bytes) {
+  if (!c || !bytes) return LSHOM_ERR_INVALID_ARG;
+  if (precision != LSHOM_PRECISION_FP64 && precision != LSHOM_PRECISION_MIXED)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "precision must be FP64 (0) or MIXED (1)");
+  BatchPlan bp;
+  lshom_status s = plan_batch(c, n, probs, precision, &bp);
+  if (s != LSHOM_OK) return s;
+  *bytes = bp.total;
+  return LSHOM_OK;
+}
+
+lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* probs,
+                                 const lshom_solve_opts* opts, void* ws_dev, size_t ws_bytes,
+                                 double* leff_host, lshom_solve_info* infos) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  lshom_solve_opts o;
+  lshom_default_opts(&o);
+  if (opts) o = *opts;
+  lshom_status s = validate_opts(c, &o);
+  if (s != LSHOM_OK) return s;
+  BatchPlan bp;
+  if ((s = plan_batch(c, n, probs, o.precision, &bp)) != LSHOM_OK) return s;
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) != 0)
+    return fail(c, LSHOM_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+  if (ws_bytes < bp.total) return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_batch_workspace_size()");
+  DeviceGuard dg(c->device);
+  HIP_TRY(c, order_after_user(c));
+  lshom_status worst = LSHOM_OK;
+  for (size_t gi = 0; gi < bp.groups.size(); ++gi) {
+    Group& g = bp.groups[gi];
+    std::vector<ProbEntry> tab;
+    std::vector<DevState> init;
+    if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tab, &init)) != LSHOM_OK) return s;
+    if ((s = solve_group(g, init, o, nullptr, nullptr, nullptr)) != LSHOM_OK) return s;
+    const std::vector<int>& mem = bp.members[gi];
+    for (int j = 0; j < g.nprob; ++j) {
+      const DevState& hs = g.host_states[j];
+      const int i = mem[j];
+      if (leff_host)
+        for (int t = 0; t < 3; ++t) leff_host[(size_t)i * 3 + t] = t < g.d ? hs.leff[t] : 0.0;
+      if (infos) fill_info(hs, tab[j].l0, o, 0, &infos[i]);
+      if (hs.status != LSHOM_OK && worst == LSHOM_OK) worst = hs.status;
+    }
+  }
+  if (worst == LSHOM_OK) c->err.clear();
+  return worst;
+}
+
+lshom_status lshom_get_schedule(lshom_ctx* c, int precision, lshom_schedule* out) {
+  if (!c || !out) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
+  if (precision != LSHOM_PRECISION_FP64 && precision != LSHOM_PRECISION_MIXED)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "precision must be FP64 (0) or MIXED (1)");
+  Schedule s = current_schedule(c->g, precision);
+  auto it = c->schedules.find(SchedKey(c->g.d, c->g.N[0], c->g.N[1], c->g.N[2], precision));
+  if (it != c->schedules.end()) s.ms_per_iter = it->second.ms_per_iter;
+  to_c_schedule(c->g, s, precision, out);
+  return LSHOM_OK;
+}
+
+lshom_status lshom_set_schedule(lshom_ctx* c, const lshom_schedule* in) {
+  if (!c || !in) return LSHOM_ERR_INVALID_ARG;
+  Schedule s;
+  lshom_status st = from_c_schedule(c, in, &s);
+  if (st != LSHOM_OK) return st;
+  Group probe;
+  if (group_setup(probe, in->d, in->N, c->have_problem ? c->g.n_phases : 1) != LSHOM_OK)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+  if (!schedule_fits(probe, s, in->precision))
+    return fail(c, LSHOM_ERR_INVALID_ARG, "schedule exceeds the FFT batch or LDS limits");
+  c->schedules[SchedKey(in->d, probe.N[0], probe.N[1], probe.N[2], in->precision)] = s;
+  if (c->have_problem && c->g.d == in->d && c->g.N[0] == probe.N[0] && c->g.N[1] == probe.N[1] &&
+      c->g.N[2] == probe.N[2] && schedule_fits(c->g, s, in->precision)) {
+    DeviceGuard dg(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c->graphs);
+    apply_schedule(c->g, s, in->precision);
+  }
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_autotune(lshom_ctx* c, int precision, int reps, lshom_schedule* best) {
+  if (!c || reps < 1) return LSHOM_ERR_INVALID_ARG;
+  if (precision != LSHOM_PRECISION_FP64 && precision != LSHOM_PRECISION_MIXED)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "precision must be FP64 (0) or MIXED (1)");
+  lshom_status s = check_ready(c, precision);
+  if (s != LSHOM_OK) return s;
+  DeviceGuard dg(c->device);
+  HIP_TRY(c, order_after_user(c));
+  drop_graphs(c->graphs);
+  Schedule tuned;
+  if ((s = autotune_group(c->g, precision, reps, &tuned)) != LSHOM_OK) return s;
+  apply_schedule(c->g, tuned, precision);
+  c->schedules[SchedKey(c->g.d, c->g.N[0], c->g.N[1], c->g.N[2], precision)] = tuned;
+  if (best) to_c_schedule(c->g, tuned, precision, best);
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_autotune_batched(lshom_ctx* c, int32_t n, const lshom_problem* probs, int precision,
+                                    int reps, void* ws_dev, size_t ws_bytes, lshom_schedule* best,
+                                    int32_t* n_best) {
+  if (!c || reps < 1) return LSHOM_ERR_INVALID_ARG;
+  if (precision != LSHOM_PRECISION_FP64 && precision != LSHOM_PRECISION_MIXED)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "precision must be FP64 (0) or MIXED (1)");
+  BatchPlan bp;
+  lshom_status s = plan_batch(c, n, probs, precision, &bp);
+  if (s != LSHOM_OK) return s;
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) != 0)
+    return fail(c, LSHOM_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+  if (ws_bytes < bp.total) return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_batch_workspace_size()");
+  DeviceGuard dg(c->device);
+  HIP_TRY(c, order_after_user(c));
+  lshom_solve_opts o;
+  lshom_default_opts(&o);
+  o.precision = precision;
+  const int cap = n_best ? *n_best : 0;
+  for (size_t gi = 0; gi < bp.groups.size(); ++gi) {
+    Group& g = bp.groups[gi];
+    std::vector<ProbEntry> tab;
+    std::vector<DevState> init;
+    if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tab, &init)) != LSHOM_OK) return s;
+    // the timing needs meaningful vectors: one short solve fills them
+    lshom_solve_opts warm = o;
+    warm.max_iter = 2;
+    warm.graph_block = 0;
+    std::vector<DevState> short_init = init;
+    for (DevState& st : short_init) st.max_iter = 2;
+    if ((s = solve_group(g, short_init, warm, nullptr, nullptr, nullptr)) != LSHOM_OK) return s;
+    Schedule tuned;
+    if ((s = autotune_group(g, precision, reps, &tuned)) != LSHOM_OK) return s;
+    c->schedules[SchedKey(g.d, g.N[0], g.N[1], g.N[2], precision)] = tuned;
+    if (best && (int)gi < cap) to_c_schedule(g, tuned, precision, &best[gi]);
+  }
+  if (n_best) *n_best = (int32_t)bp.groups.size();
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_save_schedules(lshom_ctx* c, const char* path) {
+  if (!c || !path) return LSHOM_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(c, LSHOM_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  const std::string arch = arch_name(c->device);
+  for (const auto& kv : c->schedules) {
+    const int d = std::get<0>(kv.first);
+    const int prec = std::get<4>(kv.first);
+    const Schedule& s = kv.second;
+    std::fprintf(f, "{\"arch\": \"%s\", \"d\": %d, \"N\": [%lld, %lld, %lld], \"precision\": %d, "
+                    "\"rows_per_block\": %d, \"tile0\": %d, \"tile1\": %d, \"radix\": [",
+                 arch.c_str(), d, (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                 (long long)std::get<3>(kv.first), prec, s.shape.rows_per_block, s.shape.tile0, s.shape.tile1);
+    for (int a = 0; a < d; ++a) {
+      std::fprintf(f, "%s[", a ? ", " : "");
+      for (int k = 0; k < s.plan[a].nstages; ++k) std::fprintf(f, "%s%d", k ? ", " : "", s.plan[a].radix[k]);
+      std::fprintf(f, "]");
+    }
+    std::fprintf(f, "], \"ms_per_iter\": %.9g}\n", s.ms_per_iter);
+  }
+  std::fclose(f);
+  return LSHOM_OK;
+}
+
+// Integers in s after `key` up to the end of its value (a number or a
+// bracketed list, nested one level).
+static bool json_ints(const std::string& s, const char* key, std::vector<long long>* out) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = s.find(k);
+  if (p == std::string::npos) return false;
+  p = s.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  ++p;
+  while (p < s.size() && s[p] == ' ') ++p;
+  size_t end = p;
+  if (s[p] == '[') {
+    int depth = 0;
+    for (end = p; end < s.size(); ++end) {
+      if (s[end] == '[') ++depth;
+      if (s[end] == ']' && --depth == 0) break;
+    }
+  } else {
+    while (end < s.size() && s[end] != ',' && s[end] != '}') ++end;
+  }
+  out->clear();
+  long long v = 0;
+  bool in = false, neg = false;
+  for (size_t i = p; i <= end && i < s.size(); ++i) {
+    const char ch = s[i];
+    if (ch >= '0' && ch <= '9') {
+      v = v * 10 + (ch - '0');
+      in = true;
+    } else if (ch == '-' && !in) {
+      neg = true;
+    } else {
+      if (in) out->push_back(neg ? -v : v);
+      v = 0;
+      in = false;
+      neg = false;
+      if (ch == '.') return true;  // fractional part: keep the integer
+    }
+  }
+  if (in) out->push_back(neg ? -v : v);
+  return true;
+}
+
+lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
+  if (!c || !path) return LSHOM_ERR_INVALID_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(c, LSHOM_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  const std::string arch = arch_name(c->device);
+  char buf[4096];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string line(buf);
+    if (line.find('{') == std::string::npos) continue;
+    if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
+    std::vector<long long> d, N, prec, rows, t0, t1, radix;
+    if (!json_ints(line, "d", &d) || !json_ints(line, "N", &N) || !json_ints(line, "precision", &prec) ||
+        !json_ints(line, "rows_per_block", &rows) || !json_ints(line, "tile0", &t0) ||
+        !json_ints(line, "tile1", &t1) || d.size() != 1 || N.size() != 3) {
+      std::fclose(f);
+      return fail(c, LSHOM_ERR_INVALID_ARG, "schedule cache: malformed line");
+    }
+    lshom_schedule in;
+    std::memset(&in, 0, sizeof(in));
+    in.d = (int)d[0];
+    for (int a = 0; a < 3; ++a) in.N[a] = N[a];
+    in.precision = (int)prec[0];
+    in.rows_per_block = (int)rows[0];
+    in.tile0 = (int)t0[0];
+    in.tile1 = (int)t1[0];
+    // radix lists: split the bracketed value by inner brackets
+    const size_t rp = line.find("\"radix\"");
+    if (rp == std::string::npos) {
+      std::fclose(f);
+      return fail(c, LSHOM_ERR_INVALID_ARG, "schedule cache: missing radix");
+    }
+    size_t p = line.find('[', rp);
+    for (int a = 0; a < in.d; ++a) {
+      p = line.find('[', p + 1);
+      const size_t e = line.find(']', p);
+      if (p == std::string::npos || e == std::string::npos) {
+        std::fclose(f);
+        return fail(c, LSHOM_ERR_INVALID_ARG, "schedule cache: malformed radix list");
+      }
+      int k = 0;
+      long long v = 0;
+      bool inn = false;
+      for (size_t i = p + 1; i <= e; ++i) {
+        const char ch = line[i];
+        if (ch >= '0' && ch <= '9') {
+          v = v * 10 + (ch - '0');
+          inn = true;
+        } else if (inn) {
+          if (k < 16) in.radix[a][k++] = (int)v;
+          v = 0;
+          inn = false;
+        }
+      }
+      in.nstages[a] = k;
+      p = e;
+    }
+    lshom_status s = lshom_set_schedule(c, &in);
+    if (s != LSHOM_OK) {
+      std::fclose(f);
+      return s;
+    }
+  }
+  std::fclose(f);
+  return LSHOM_OK;
 }
 
 }  // extern "C"

@@ -112,7 +112,19 @@ __device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
 
 template <typename T, int NT, int RS>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
-  if (gated_out(a.st, a.gate)) return;
+  const int pb = blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
+  const long long vo = (long long)pb * a.bt.vstride;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  const uint8_t* phase = pe ? pe->phase : a.phase;
+  const T l0 = pe ? (T)pe->l0 : a.l0;
+  T Ev[kMaxDim];
+#pragma unroll
+  for (int c = 0; c < kMaxDim; ++c) Ev[c] = (pe && (a.flags & ROWF_TABLE_E)) ? (T)pe->E[c] : a.E[c];
+  const long long nvox = (long long)a.n * a.nrows;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, h = a.h, ss = a.ss, d = a.d, R = a.rows_per_block;
   const int half_rows = R / 2;
@@ -130,11 +142,11 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
   // stage twiddles, conductivities and phases (they overlap the data loads)
   copy_batched<cx<T>, NT>(tw, a.tw, n);
-  copy_batched<T, NT>(cond, a.cond, a.n_phases);
+  copy_batched<T, NT>(cond, a.cond + (long long)pb * kCondStride, a.n_phases);
   const bool need_phase = (a.mode == ROW_FUSED) || (a.mode == ROW_FWD && (a.flags & ROWF_DL)) ||
                           (a.mode == ROW_INV && (a.flags & ROWF_LEFF));
   if (need_phase) {
-    const uint8_t* src = a.phase + row0 * n;
+    const uint8_t* src = phase + row0 * n;
     const int nb = rows_here * n;
     // 4-byte loads where the row block is aligned
     if (((reinterpret_cast<uintptr_t>(src) & 3) == 0) && ((nb & 3) == 0))
@@ -159,8 +171,9 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       for (int u = 0; u < 2; ++u) {
         const int rl = ra + u;
         if (rl >= rows_here) continue;
-        T val = (a.flags & ROWF_CONST_E) ? pick3(a.E, c) : (T)pick3(a.real_in, c)[(row0 + rl) * n + x];
-        if (a.flags & ROWF_DL) val *= cond[ph[rl * n + x]] - a.l0;
+        const double* rin = pe ? (pe->x0 ? pe->x0 + c * nvox : nullptr) : pick3(a.real_in, c);
+        T val = (a.flags & ROWF_CONST_E) ? pick3(Ev, c) : (T)rin[(row0 + rl) * n + x];
+        if (a.flags & ROWF_DL) val *= cond[ph[rl * n + x]] - l0;
         v[u] = val;
       }
       Z[p * ss + x] = cx<T>{v[0], v[1]};
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           kk[u] = k;
           const int c = pair_comp(p);
           const int ra = pair_row(p);
-          const cx<T>* sp = pick3(a.spec, c);
+          const cx<T>* sp = pick3(a.spec, c) + vo;
           if (ra < rows_here) sa[u] = sp[(row0 + ra) * a.rs_row + k * a.rs_k];
           if (ra + 1 < rows_here) sb[u] = sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k];
         }
@@ -221,9 +234,9 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           const int rl = ra + u;
           if (rl >= rows_here) continue;
           const long long g = (row0 + rl) * n + x;
-          double val = (double)pick3(a.E, c) + (double)((u == 0 ? z.re : z.im) * a.inv_n);
+          double val = (double)pick3(Ev, c) + (double)((u == 0 ? z.re : z.im) * a.inv_n);
           if (a.flags & ROWF_ADD) val += pick3(a.real_add, c)[g];
-          double* out = pick3(a.real_out, c);
+          double* out = pe ? (pe->e_out ? pe->e_out + c * nvox : nullptr) : pick3(a.real_out, c);
           if (out) out[g] = val;
           if (a.flags & ROWF_LEFF) {
             const double jv = (double)cond[ph[rl * n + x]] * val;
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
         }
       }
       if (a.flags & ROWF_LEFF) {
-        double* dst = a.parts.region(PART_AUX) + (long long)blockIdx.x * 3;
+        double* dst = parts.region(PART_AUX) + (long long)blockIdx.x * 3;
         for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);
       }
       return;
@@ -248,9 +261,9 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       const int ra = pair_row(p);
       const cx<T> z = Z[p * ss + x];
       T t0 = T(0), t1 = T(0);
-      const T Ec = pick3(a.E, c);
-      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - a.l0) * (Ec + z.re * a.inv_n);
-      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - a.l0) * (Ec + z.im * a.inv_n);
+      const T Ec = pick3(Ev, c);
+      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - l0) * (Ec + z.re * a.inv_n);
+      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - l0) * (Ec + z.im * a.inv_n);
       Z[p * ss + x] = cx<T>{t0, t1};
     }
     __syncthreads();
@@ -274,7 +287,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     const cx<T> Y = Z[p * ss + k];
     const cx<T> Ym = Z[p * ss + (k == 0 ? 0 : n - k)];
     const T half = T(0.5);
-    cx<T>* sp = pick3(a.spec, c);
+    cx<T>* sp = pick3(a.spec, c) + vo;
     if (ra < rows_here)
       sp[(row0 + ra) * a.rs_row + k * a.rs_k] = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
     if (ra + 1 < rows_here)
@@ -288,7 +301,12 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
 template <typename T, int NT, int RS>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
-  if (gated_out(a.st, a.gate)) return;
+  const int pb = blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
   const int L = a.L, C = a.tile, ss = a.ss, d = a.d;
@@ -301,7 +319,8 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const long long i0 = (long long)(blockIdx.x - o * a.tiles_per_outer) * C;
   const long long rem = a.inner - i0;
   const int width = rem < C ? (int)rem : C;
-  const long long base_o = o * (long long)L * a.inner;
+  // every array of problem pb starts vstride elements after that of pb - 1
+  const long long base_o = (long long)pb * a.bt.vstride + o * (long long)L * a.inner;
   const cx<T> zero = {T(0), T(0)};
   // thread order over (l, c): c fastest in the natural layout, l fastest in
   // the transposed one, so that global accesses are contiguous
@@ -318,7 +337,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 
   if (a.mode == COL_INV_C) {
     double beta = 0.0;
-    if (a.cg_step && !cg_direction<NT>(a.st, a.parts, a.inv_n, &beta)) return;
+    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta)) return;
     const T tb = (T)beta;
     const int total = L * C;
     for (int base = 0; base < total; base += NT * kBatch) {
@@ -442,6 +461,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   double acc = 0.0;
   const int n_last = a.nd[a.dims - 1];
   const int total = L * C;
+  const T cs = a.coef_s * (a.s_inv_l0 ? (T)(1.0 / (pe ? pe->l0 : a.l0)) : T(1));
   for (int base = 0; base < total; base += NT * kBatch) {
     cx<T> bv[kBatch];
 #pragma unroll
@@ -476,7 +496,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
         }
       }
       // s = -i khat . tau_hat
-      cx<T> val = {a.coef_s * t.im, -a.coef_s * t.re};
+      cx<T> val = {cs * t.im, -cs * t.re};
       const cx<T> b = bv[u];
       val.re += a.coef_base * b.re;
       val.im += a.coef_base * b.im;
@@ -491,8 +511,8 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
     }
   }
   if (a.dot) {
-    store_partial<NT>(acc, a.parts.region(a.dot_region) + blockIdx.x);
-    if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) a.st->nparts[0] = (int)gridDim.x;
+    store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
+    if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
   }
 }
 
@@ -503,19 +523,28 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
-  if (gated_out(a.st, a.gate)) return;
-  const int k = a.st->iter_u;
-  const double rr = sum_partials<NT>(a.parts.region(k & 1), a.st->nparts[k & 1]) * a.inv_n;
-  const double pq = sum_partials<NT>(a.parts.region(PART_PQ), a.n_pq) * a.inv_n;
+  const int pb = blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  const long long vo = (long long)pb * a.bt.vstride;
+  const int k = st->iter_u;
+  const double rr = sum_partials<NT>(parts.region(k & 1), st->nparts[k & 1]) * a.inv_n;
+  const double pq = sum_partials<NT>(parts.region(PART_PQ), a.n_pq) * a.inv_n;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (lead) {
-      a.st->pq_log = pq;
-      a.st->status = -6;
-      a.st->done = 1;
+      st->pq_log = pq;
+      st->status = -6;
+      st->done = 1;
     }
     return;
   }
+  const cx<T>* __restrict__ P = a.p + vo;
+  const cx<T>* __restrict__ Q = a.q + vo;
+  cx<T>* __restrict__ X = a.x + vo;
+  cx<T>* __restrict__ Rv = a.r + vo;
   const double alpha = rr / pq;
   const T ta = (T)alpha;
   double acc = 0.0;
@@ -526,10 +555,10 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     for (int u = 0; u < kBatch; ++u) {
       const long long i = i0 + u * stride;
       if (i < a.n) {
-        p[u] = a.p[i];
-        q[u] = a.q[i];
-        x[u] = a.x[i];
-        r[u] = a.r[i];
+        p[u] = P[i];
+        q[u] = Q[i];
+        x[u] = X[i];
+        r[u] = Rv[i];
       }
     }
 #pragma unroll
@@ -540,19 +569,19 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
       x[u].im += ta * p[u].im;
       r[u].re -= ta * q[u].re;
       r[u].im -= ta * q[u].im;
-      a.x[i] = x[u];
-      a.r[i] = r[u];
+      X[i] = x[u];
+      Rv[i] = r[u];
       const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
       acc += w * ((double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im);
     }
   }
   const int nxt = (k + 1) & 1;
-  store_partial<NT>(acc, a.parts.region(nxt) + blockIdx.x);
+  store_partial<NT>(acc, parts.region(nxt) + blockIdx.x);
   if (lead) {
-    a.st->nparts[nxt] = (int)gridDim.x;
-    a.st->iter_a = k + 1;
-    a.st->alpha_log = alpha;
-    a.st->pq_log = pq;
+    st->nparts[nxt] = (int)gridDim.x;
+    st->iter_a = k + 1;
+    st->alpha_log = alpha;
+    st->pq_log = pq;
   }
 }
 
@@ -561,32 +590,39 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void mix_accumulate_kernel(MixArgs a) {
-  if (gated_out(a.st, a.gate)) return;
+  const int pb = blockIdx.y;
+  if (gated_out(a.st + pb, a.gate)) return;
+  const long long vo = (long long)pb * a.bt.vstride;
   const long long stride = (long long)gridDim.x * 256;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
-    const cx<float> y = a.x32[i];
-    cx<double> x = a.x64[i];
+    const cx<float> y = a.x32[vo + i];
+    cx<double> x = a.x64[vo + i];
     x.re += (double)y.re;
     x.im += (double)y.im;
-    a.x64[i] = x;
-    a.x32[i] = cx<float>{0.f, 0.f};
+    a.x64[vo + i] = x;
+    a.x32[vo + i] = cx<float>{0.f, 0.f};
   }
 }
 
 __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
-  if (gated_out(a.st, a.gate)) return;
-  const int k = a.st->iter_a;
+  const int pb = blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  const long long vo = (long long)pb * a.bt.vstride;
+  const int k = st->iter_a;
   double acc = 0.0;
   const long long stride = (long long)gridDim.x * 256;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
-    const cx<double> r = a.r64[i];
+    const cx<double> r = a.r64[vo + i];
     const cx<float> f = cx<float>{(float)r.re, (float)r.im};
-    a.r32[i] = f;
+    a.r32[vo + i] = f;
     const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
     acc += w * ((double)f.re * (double)f.re + (double)f.im * (double)f.im);
   }
-  store_partial<256>(acc, a.parts.region(k & 1) + blockIdx.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.st->nparts[k & 1] = (int)gridDim.x;
+  store_partial<256>(acc, parts.region(k & 1) + blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->nparts[k & 1] = (int)gridDim.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -595,13 +631,15 @@ __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   constexpr int NT = 256;
-  if (gated_out(a.st, a.gate)) return;
-  DevState* st = a.st;
+  DevState* st = a.st + blockIdx.y;
+  if (gated_out(st, a.gate)) return;
+  Partials parts = a.parts;
+  parts.base += (long long)blockIdx.y * a.bt.pstride;
   const bool lead = threadIdx.x == 0;
   switch (a.mode) {
     case FZ_CHECK: {
       const int m = st->iter_a;
-      const double rr = sum_partials<NT>(a.parts.region(m & 1), st->nparts[m & 1]) * a.inv_n;
+      const double rr = sum_partials<NT>(parts.region(m & 1), st->nparts[m & 1]) * a.inv_n;
       if (lead) {
         st->rr_log = rr;
         if (!isfinite(rr)) {
@@ -617,25 +655,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
       break;
     }
     case FZ_AUX: {
-      const double s = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      const double s = sum_partials<NT>(parts.region(PART_AUX), a.n) * a.inv_n;
       if (lead) st->dot_aux = s;
       break;
     }
     case FZ_RR_TRUE: {
-      const double s = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      const double s = sum_partials<NT>(parts.region(PART_AUX), a.n) * a.inv_n;
       if (lead) st->rr_true = s;
       break;
     }
     case FZ_LEFF: {
       for (int c = 0; c < a.d; ++c) {
-        const double s = sum_partials<NT>(a.parts.region(PART_AUX) + c, a.n, 3) * a.inv_n;
+        const double s = sum_partials<NT>(parts.region(PART_AUX) + c, a.n, 3) * a.inv_n;
         if (lead) st->leff[c] = s;
       }
       break;
     }
     case FZ_REFRESH:
     case FZ_REFRESH_INIT: {
-      const double rr = sum_partials<NT>(a.parts.region(PART_AUX), a.n) * a.inv_n;
+      const double rr = sum_partials<NT>(parts.region(PART_AUX), a.n) * a.inv_n;
       if (lead) {
         st->rr_true = rr;
         st->rr_ref = rr;
@@ -662,6 +700,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
 
 __global__ void state_init_kernel(DevState* st, DevState init) { *st = init; }
 
+__global__ __launch_bounds__(256) void state_copy_kernel(DevState* st, const DevState* src, int nprob) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < nprob) st[i] = src[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void fill_zero_kernel(cx<T>* p, long long n) {
   const long long stride = (long long)gridDim.x * 256;
@@ -674,6 +717,13 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(cx<T>* p, long long n) {
 // ---------------------------------------------------------------------------
 
 int lds_odd_stride(int n) { return (n & 1) ? n : n + 1; }
+
+static int nprob_of(const Batch& b) { return b.nprob > 1 ? b.nprob : 1; }
+
+hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipStream_t s) {
+  hipLaunchKernelGGL(state_copy_kernel, dim3((unsigned)((nprob + 255) / 256)), dim3(256), 0, s, st, src, nprob);
+  return hipGetLastError();
+}
 
 size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int n_phases, int* ss_out) {
   const int ss = lds_odd_stride(n);
@@ -728,17 +778,17 @@ hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipSt
 template <typename T, int RS>
 static void launch_row_rs(const RowArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
   if (nt == 128)
-    hipLaunchKernelGGL((row_kernel<T, 128, RS>), dim3((unsigned)nb), dim3(128), lds, s, a);
+    hipLaunchKernelGGL((row_kernel<T, 128, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(128), lds, s, a);
   else
-    hipLaunchKernelGGL((row_kernel<T, 256, RS>), dim3((unsigned)nb), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((row_kernel<T, 256, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(256), lds, s, a);
 }
 
 template <typename T, int RS>
 static void launch_col_rs(const ColArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
   if (nt == 128)
-    hipLaunchKernelGGL((col_kernel<T, 128, RS>), dim3((unsigned)nb), dim3(128), lds, s, a);
+    hipLaunchKernelGGL((col_kernel<T, 128, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(128), lds, s, a);
   else
-    hipLaunchKernelGGL((col_kernel<T, 256, RS>), dim3((unsigned)nb), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((col_kernel<T, 256, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(256), lds, s, a);
 }
 
 template <typename T>
@@ -769,22 +819,22 @@ hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(finalize_kernel, dim3(1, (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mix_accumulate_kernel, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(mix_accumulate_kernel, dim3((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mix_convert_kernel, dim3((unsigned)update_blocks(a.n)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(mix_convert_kernel, dim3((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

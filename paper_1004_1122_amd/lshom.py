@@ -65,6 +65,64 @@ class lshom_solve_info(Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class lshom_problem(Structure):
+    _fields_ = [
+        ("d", c_int32),
+        ("N", c_int64 * 3),
+        ("phase_dev", c_void_p),
+        ("n_phases", c_int32),
+        ("cond_host", POINTER(c_double)),
+        ("l0", c_double),
+        ("E", c_double * 3),
+        ("tol", c_double),
+        ("e_dev", c_void_p),
+    ]
+
+
+class lshom_schedule(Structure):
+    _fields_ = [
+        ("d", c_int32),
+        ("N", c_int64 * 3),
+        ("precision", c_int32),
+        ("rows_per_block", c_int32),
+        ("tile0", c_int32),
+        ("tile1", c_int32),
+        ("nstages", c_int32 * 3),
+        ("radix", (c_int32 * 16) * 3),
+        ("ms_per_iter", c_double),
+    ]
+
+    def as_dict(self):
+        d = int(self.d)
+        return {
+            "d": d,
+            "N": [int(self.N[a]) for a in range(d)],
+            "precision": int(self.precision),
+            "rows_per_block": int(self.rows_per_block),
+            "tile0": int(self.tile0),
+            "tile1": int(self.tile1),
+            "radix": [[int(self.radix[a][k]) for k in range(self.nstages[a])] for a in range(d)],
+            "ms_per_iter": float(self.ms_per_iter),
+        }
+
+    @classmethod
+    def from_dict(cls, s):
+        out = cls()
+        out.d = int(s["d"])
+        for a in range(3):
+            out.N[a] = int(s["N"][a]) if a < out.d else 1
+        out.precision = int(s["precision"])
+        out.rows_per_block = int(s["rows_per_block"])
+        out.tile0 = int(s["tile0"])
+        out.tile1 = int(s.get("tile1", 1))
+        for a, rad in enumerate(s["radix"]):
+            out.nstages[a] = len(rad)
+            for k, r in enumerate(rad):
+                out.radix[a][k] = int(r)
+        out.ms_per_iter = float(s.get("ms_per_iter", 0.0))
+        return out
+
+
 _lib = None
 
 
@@ -96,6 +154,16 @@ def load(path: str = LIB_PATH):
                                        POINTER(lshom_solve_info)]),
         "lshom_apply": (c_int32, [P, P, P]),
         "lshom_time_passes": (c_int32, [P, c_int, c_int, POINTER(c_double), POINTER(c_double)]),
+        "lshom_batch_workspace_size": (c_int32, [P, c_int32, POINTER(lshom_problem), c_int, POINTER(c_size_t)]),
+        "lshom_solve_batched": (c_int32, [P, c_int32, POINTER(lshom_problem), POINTER(lshom_solve_opts), P,
+                                          c_size_t, POINTER(c_double), POINTER(lshom_solve_info)]),
+        "lshom_get_schedule": (c_int32, [P, c_int, POINTER(lshom_schedule)]),
+        "lshom_set_schedule": (c_int32, [P, POINTER(lshom_schedule)]),
+        "lshom_autotune": (c_int32, [P, c_int, c_int, POINTER(lshom_schedule)]),
+        "lshom_autotune_batched": (c_int32, [P, c_int32, POINTER(lshom_problem), c_int, c_int, P, c_size_t,
+                                             POINTER(lshom_schedule), POINTER(c_int32)]),
+        "lshom_save_schedules": (c_int32, [P, c_char_p]),
+        "lshom_load_schedules": (c_int32, [P, c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -256,6 +324,27 @@ class Solver:
         _check(self.ctx, self.lib.lshom_time_passes(self.ctx, int(precision), int(reps), ms, by))
         return {n: (ms[i], by[i]) for i, n in enumerate(self.PASS_NAMES) if ms[i] > 0}
 
+    def get_schedule(self, precision=PRECISION_FP64):
+        s = lshom_schedule()
+        _check(self.ctx, self.lib.lshom_get_schedule(self.ctx, int(precision), ctypes.byref(s)))
+        return s.as_dict()
+
+    def set_schedule(self, sched):
+        s = lshom_schedule.from_dict(sched)
+        _check(self.ctx, self.lib.lshom_set_schedule(self.ctx, ctypes.byref(s)))
+
+    def autotune(self, precision=PRECISION_FP64, reps=20):
+        """Tune radix orders and pass shapes on this problem; returns the schedule."""
+        s = lshom_schedule()
+        _check(self.ctx, self.lib.lshom_autotune(self.ctx, int(precision), int(reps), ctypes.byref(s)))
+        return s.as_dict()
+
+    def save_schedules(self, path):
+        _check(self.ctx, self.lib.lshom_save_schedules(self.ctx, os.fsencode(path)))
+
+    def load_schedules(self, path):
+        _check(self.ctx, self.lib.lshom_load_schedules(self.ctx, os.fsencode(path)))
+
     def apply(self, p):
         """q = (I + B) p for an arbitrary real FP64 field p of shape (d, *N)."""
         torch = self.torch
@@ -263,3 +352,115 @@ class Solver:
         q = torch.empty_like(p)
         _check(self.ctx, self.lib.lshom_apply(self.ctx, c_void_p(p.data_ptr()), c_void_p(q.data_ptr())))
         return q
+
+
+# ---------------------------------------------------------------------------
+# Many problems in one call
+# ---------------------------------------------------------------------------
+
+class BatchSolver:
+    """Solves lists of problems with lshom_solve_batched on one device.
+
+    A problem is a dict with ``phase`` (uint8 array or tensor), ``cond``,
+    ``E``, ``tol`` and optionally ``l0`` (default (min + max) / 2) and
+    ``want_field`` (default False).  Workspace and device copies of the
+    phase images are owned by torch and kept until ``prepare`` is called with
+    other problems.
+    """
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("lshom.BatchSolver needs a GPU")
+        self.device = torch.device("cuda", device)
+        self.ctx = lshom_create(device, torch.cuda.current_stream(self.device).cuda_stream)
+        self._keep = []
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lshom_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def prepare(self, problems, precision=PRECISION_MIXED):
+        """Uploads phase images, allocates fields and the workspace."""
+        torch = self.torch
+        n = len(problems)
+        arr = (lshom_problem * n)()
+        keep, fields = [], []
+        for i, pr in enumerate(problems):
+            ph = pr["phase"]
+            if not isinstance(ph, torch.Tensor):
+                ph = torch.as_tensor(np.ascontiguousarray(ph, dtype=np.uint8))
+            ph = ph.to(device=self.device, dtype=torch.uint8).contiguous()
+            d = ph.dim()
+            cond = _dbl_array(pr["cond"])
+            e = None
+            if pr.get("want_field", False):
+                e = torch.empty((d,) + tuple(ph.shape), dtype=torch.float64, device=self.device)
+            keep += [ph, cond, e]
+            fields.append(e)
+            a = arr[i]
+            a.d = d
+            for t in range(3):
+                a.N[t] = int(ph.shape[t]) if t < d else 1
+                a.E[t] = float(pr["E"][t]) if t < d else 0.0
+            a.phase_dev = ph.data_ptr()
+            a.n_phases = len(pr["cond"])
+            a.cond_host = cond
+            a.l0 = float(pr.get("l0") or 0.0)
+            a.tol = float(pr["tol"])
+            a.e_dev = e.data_ptr() if e is not None else None
+        size = c_size_t()
+        _check(self.ctx, self.lib.lshom_batch_workspace_size(self.ctx, n, arr, int(precision), ctypes.byref(size)))
+        need = int(size.value)
+        if self._ws is None or self._ws.numel() < need + 256:
+            self._ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        self._arr, self._keep, self._fields, self._n, self._need = arr, keep, fields, n, need
+        self._precision = int(precision)
+        return need
+
+    def _ws_ptr(self):
+        return c_void_p(self._ws.data_ptr() + ((-self._ws.data_ptr()) % 256))
+
+    def autotune(self, precision=None, reps=10):
+        """Tune every grid of the prepared batch on the batch itself; returns the schedules."""
+        prec = self._precision if precision is None else int(precision)
+        cap = c_int32(self._n)
+        best = (lshom_schedule * self._n)()
+        _check(self.ctx, self.lib.lshom_autotune_batched(self.ctx, self._n, self._arr, prec, int(reps),
+                                                         self._ws_ptr(), self._need, best, ctypes.byref(cap)))
+        return [best[i].as_dict() for i in range(min(cap.value, self._n))]
+
+    def set_schedule(self, sched):
+        s = lshom_schedule.from_dict(sched)
+        _check(self.ctx, self.lib.lshom_set_schedule(self.ctx, ctypes.byref(s)))
+
+    def save_schedules(self, path):
+        _check(self.ctx, self.lib.lshom_save_schedules(self.ctx, os.fsencode(path)))
+
+    def load_schedules(self, path):
+        _check(self.ctx, self.lib.lshom_load_schedules(self.ctx, os.fsencode(path)))
+
+    def run(self, allow_fail=False, **opt_kw):
+        """Solve the prepared problems; returns (fields, leff [n, 3], infos)."""
+        o = lshom_default_opts()
+        for k, v in opt_kw.items():
+            setattr(o, k, v)
+        n = self._n
+        leff = (c_double * (3 * n))()
+        infos = (lshom_solve_info * n)()
+        st = self.lib.lshom_solve_batched(self.ctx, n, self._arr, ctypes.byref(o), self._ws_ptr(),
+                                          self._need, leff, infos)
+        allow = (LSHOM_ERR_NOT_CONVERGED, LSHOM_ERR_BREAKDOWN) if allow_fail else ()
+        _check(self.ctx, st, allow)
+        return self._fields, np.array(leff[:]).reshape(n, 3), [i.as_dict() for i in infos]
+
