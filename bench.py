@@ -1,25 +1,30 @@
 """Benchmark of the FFT-accelerated CG homogenisation solve on one MI355X.
 
-One step = the 729x729 contrast sweep: a 2-D cell with 40 random
-non-overlapping circles (RSA, radii U[0.02, 0.06], seed 2), contrast
-rho in {1e1, 1e2, 1e3, 1e4} on the circles and 1 in the matrix, l0 = (1 +
-rho) / 2, load cases E = (1, 0) and (0, 1), each solved to relative residual
-1e-6 by plain FP64 CG (8 solves per step).  Inputs (phase image, workspaces)
-are resident in HBM before the timed region.
+One step = the 729x729 contrast sweep in both forms of the solver: a 2-D cell
+with 40 random non-overlapping circles (RSA, radii U[0.02, 0.06], seed 2),
+contrast rho in {1e1, 1e2, 1e3, 1e4} on the circles and 1 in the matrix,
+l0 = (1 + rho) / 2, load cases E = (1, 0) and (0, 1), each solved to relative
+residual 1e-6 once by plain FP64 CG and once by FP32-apply / FP64-refinement
+CG (16 solves per step; the 8 solves of one form share every launch).
+Inputs (phase image, workspace, autotuned schedules) are resident in HBM
+before the timed region.
 
 Metric: GVoxel-CG-iters/s = sum over solves of |N| * (CG iterations) / wall
-time / 1e9, plus the time to a 1e-6 residual per solve.
+time / 1e9, plus the time to a 1e-6 residual of each single solve in each form.
 
 Printed: one JSON line with the metric, the roofline of the dominant pass
-kernel (algorithmic bytes / HIP-event duration vs 8 TB/s HBM peak) and the
-CPU oracle timed on a bounded sample of the same workload.
+kernel (algorithmic bytes / HIP-event durations of its launches inside real
+solves, against 8 TB/s HBM) and the CPU oracle timed on a bounded sample of
+the same workload.
 """
 
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -34,10 +39,28 @@ HBM_PEAK_GBS = 8000.0
 CONTRASTS = (1e1, 1e2, 1e3, 1e4)
 LOADS = ((1.0, 0.0), (0.0, 1.0))
 TOL = 1e-6
+FORMS = (("fp64", 0), ("mixed", 1))
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(pass_name, form):
+    """HBM bytes per launch from the committed counter summary of this kernel,
+    if it was taken on the current kernel sources (else None)."""
+    from paper_1004_1122_amd.profiling import kernel_source_hash
+    src = kernel_source_hash()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+        with open(path) as f:
+            for line in f:
+                m = re.match(r"^traffic-json:\s*(\{.*\})\s*$", line)
+                if not m:
+                    continue
+                rec = json.loads(m.group(1))
+                if rec.get("pass") == pass_name and rec.get("form") == form and rec.get("source_hash") == src:
+                    return rec
+    return None
 
 
 def cpu_baseline(phase, n_vox):
@@ -62,12 +85,42 @@ def cpu_baseline(phase, n_vox):
             "sample": f"729x729, E=(1,0), tol 1e-6, FP64 CG, {', '.join(sample)}; {dt:.1f} s"}
 
 
+def single_solve_times(lshom, phase_dev, reps=5, warm=2):
+    """Median wall time of each single solve to 1e-6 (the call returns after the
+    FP64 true residual has been confirmed on the device)."""
+    out = {}
+    for rho in CONTRASTS:
+        s = lshom.Solver(phase_dev, [1.0, rho], device=0)
+        for form, prec in FORMS:
+            s.autotune(precision=prec, reps=10)
+        for E in LOADS:
+            key = f"rho={rho:g},E=({E[0]:g},{E[1]:g})"
+            rec = {}
+            for form, prec in FORMS:
+                times = []
+                for k in range(warm + reps):
+                    t0 = time.perf_counter()
+                    _, _, info = s.solve(E, tol=TOL, want_field=False, precision=prec)
+                    dt = time.perf_counter() - t0
+                    if k >= warm:
+                        times.append(dt)
+                rec[form] = {"ms": 1e3 * statistics.median(times), "iterations": info["iterations"],
+                             "rel_res_true": info["rel_res_true"]}
+            rec["mixed_speedup"] = rec["fp64"]["ms"] / rec["mixed"]["ms"]
+            out[key] = rec
+        s.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single", action="store_true", help="skip the per-solve time-to-1e-6 runs")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the run, copy a device buffer of this size (the counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has "
@@ -82,49 +135,51 @@ def main():
     m = ms.circles_729(seed=2)
     n_vox = m.phase.size
     phase_dev = torch.from_numpy(m.phase).cuda()
-    solvers = {rho: lshom.Solver(phase_dev, [1.0, rho], device=0) for rho in CONTRASTS}
-    log(f"workload 729x729, vf={m.info['vf']:.4f}, {len(solvers)} contrasts")
+    probs = [dict(phase=phase_dev, cond=[1.0, rho], E=E, tol=TOL) for rho in CONTRASTS for E in LOADS]
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=lshom.PRECISION_MIXED)
+    sched = {form: bs.autotune(precision=prec, reps=10)[0] for form, prec in FORMS}
+    log(f"workload 729x729, vf={m.info['vf']:.4f}, {len(probs)} solves per form; schedules {sched}")
 
-    def step(record=None):
-        iters = 0
-        for rho, s in solvers.items():
-            for E in LOADS:
-                t0 = time.perf_counter()
-                _, _, info = s.solve(E, tol=TOL, want_field=False)
-                dt = time.perf_counter() - t0
-                iters += info["iterations"]
-                if record is not None:
-                    record.setdefault((rho, E), []).append((dt, info))
-        return iters
+    def step(acc):
+        for form, prec in FORMS:
+            t0 = time.perf_counter()
+            _, _, infos = bs.run(precision=prec)
+            acc[form]["s"] += time.perf_counter() - t0
+            acc[form]["iters"] += sum(i["iterations"] for i in infos)
+            acc[form]["per"] = [i["iterations"] for i in infos]
+
+    def fresh():
+        return {form: {"s": 0.0, "iters": 0, "per": None} for form, _ in FORMS}
 
     for _ in range(args.warmup):
-        step()
+        step(fresh())
     torch.cuda.synchronize()
-    rec = {}
+    acc = fresh()
     t0 = time.perf_counter()
-    total_iters = 0
     for k in range(args.steps):
-        total_iters += step(rec)
+        step(acc)
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    total_iters = sum(a["iters"] for a in acc.values())
     value = n_vox * total_iters / elapsed / 1e9
 
-    # kernel durations of one CG iteration (HIP events on the solver's stream)
-    s = solvers[1e4]
-    passes = s.time_passes(lshom.PRECISION_FP64, reps=50)
-    per_iter_ms = sum(ms_ for ms_, _ in passes.values())
-    dom_name, (dom_ms, dom_bytes) = max(passes.items(), key=lambda kv: kv[1][0])
+    # one more step with HIP events around every pass launch of the CG loops
+    timing = {}
+    for form, prec in FORMS:
+        bs.set_pass_timing(True)
+        bs.run(precision=prec)
+        timing[form] = bs.pass_timing()
+    bs.set_pass_timing(False)
+    (dom_form, dom_pass), (dom_ms, dom_bytes, dom_n) = max(
+        (((form, name), v) for form, t in timing.items() for name, v in t.items()), key=lambda kv: kv[1][0])
+    avg_ms = dom_ms / dom_n
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-
-    per_solve = {}
-    for (rho, E), lst in rec.items():
-        times = [t for t, _ in lst]
-        per_solve[f"rho={rho:g},E={E}"] = {
-            "iterations": lst[0][1]["iterations"],
-            "time_to_1e-6_ms": 1e3 * statistics.median(times),
-            "rel_res_true": lst[0][1]["rel_res_true"],
-        }
+    # counters taken on launches of known work give HBM bytes per algorithmic
+    # byte for this kernel; scaled to the launches timed here
+    traffic_rec = measured_traffic(dom_pass, dom_form)
+    traffic = traffic_rec["traffic_ratio"] * dom_bytes / dom_n if traffic_rec else None
 
     out = {
         "metric": METRIC,
@@ -137,34 +192,58 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64 (plain CG) + f32 apply/f64 dots (mixed CG)",
         "data": "synthetic",
         "config": {
             "workload": "2-D 729x729, 40 RSA circles r~U[0.02,0.06] seed 2, rho in {1e1,1e2,1e3,1e4}, "
-                        "E=(1,0),(0,1), plain FP64 CG to relative residual 1e-6",
-            "solves_per_step": len(CONTRASTS) * len(LOADS),
+                        "E=(1,0),(0,1), CG to relative residual 1e-6, plain FP64 and FP32-apply/FP64-refinement",
+            "solves_per_step": len(probs) * len(FORMS),
             "voxels": n_vox,
             "vf": m.info["vf"],
+            "schedules": sched,
+        },
+        "forms": {
+            form: {"GVoxel-CG-iters/s": n_vox * a["iters"] / a["s"] / 1e9,
+                   "ms_per_sweep": 1e3 * a["s"] / args.steps,
+                   "iterations_per_solve": a["per"]}
+            for form, a in acc.items()
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": dom_name,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel_ms": dom_ms,
-            "algorithmic_bytes": dom_bytes,
+            "traffic": traffic,
+            "kernel": f"{dom_pass} ({dom_form})",
+            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": dom_bytes / dom_n,
+            "launches": dom_n,
         },
-        "pass_ms": {k: v[0] for k, v in passes.items()},
-        "pass_GBs": {k: v[1] / (v[0] * 1e-3) / 1e9 for k, v in passes.items()},
-        "iteration_kernel_ms": per_iter_ms,
-        "per_solve": per_solve,
+        "pass_timing": {
+            form: {name: {"ms_total": v[0], "launches": v[2], "avg_ms": v[0] / v[2],
+                          "GB/s": v[1] / (v[0] * 1e-3) / 1e9}
+                   for name, v in t.items()}
+            for form, t in timing.items()
+        },
     }
+    if traffic_rec:
+        out["roofline"]["traffic_source"] = traffic_rec.get("summary")
+    if not args.no_single:
+        log("timing single solves to 1e-6")
+        out["time_to_1e-6"] = single_solve_times(lshom, phase_dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(m.phase, n_vox)
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        # an elementwise kernel that reads and writes nbytes once each
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
     print(json.dumps(out), flush=True)
 
 

@@ -269,6 +269,21 @@ lshom_status lshom_load_schedules(lshom_ctx* ctx, const char* path);
 lshom_status lshom_time_passes(lshom_ctx* ctx, int precision, int reps, double* ms_out,
                                double* bytes_out);
 
+/*
+ * Pass timing inside real solves.  While enabled, lshom_solve and
+ * lshom_solve_batched on this context queue their CG iterations without HIP
+ * graph capture and bracket every pass-kernel launch of the CG loop with a
+ * pair of HIP events on the context stream.  lshom_get_pass_timing returns,
+ * per pass class, the summed device milliseconds, the number of launches and
+ * the algorithmic HBM bytes of the work those launches did (the per-problem
+ * bytes of lshom_time_passes times the CG iterations the problems actually
+ * advanced; launches for problems that had already stopped count zero
+ * bytes).  Enabling (or disabling) resets the sums.  Arrays hold
+ * LSHOM_PASS_COUNT entries; any may be NULL.
+ */
+lshom_status lshom_set_pass_timing(lshom_ctx* ctx, int enable);
+lshom_status lshom_get_pass_timing(lshom_ctx* ctx, double* ms_out, double* bytes_out, int64_t* launches_out);
+
 #ifdef __cplusplus
 }
 #endif

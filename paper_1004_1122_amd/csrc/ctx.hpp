@@ -58,6 +58,21 @@ struct Schedule {
 
 using SchedKey = std::tuple<int, int64_t, int64_t, int64_t, int>;  // d, N0, N1, N2, precision
 
+// HIP-event timing of the CG-loop pass launches of real solves.
+struct PassTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // start/end event of pending launch i at 2i, 2i+1
+  std::vector<int> kinds;         // pass class of each pending launch
+  double ms[LSHOM_PASS_COUNT] = {};
+  double bytes[LSHOM_PASS_COUNT] = {};
+  long long launches[LSHOM_PASS_COUNT] = {};
+  double unit_bytes[LSHOM_PASS_COUNT] = {};  // per problem-iteration, current solve
+  void reset() {
+    kinds.clear();
+    for (int k = 0; k < LSHOM_PASS_COUNT; ++k) ms[k] = bytes[k] = 0.0, launches[k] = 0;
+  }
+};
+
 // Problems that share one grid (d, N) and are advanced by the same launches.
 struct Group {
   lshom_ctx* ctx = nullptr;     // errors and the context stream
@@ -81,6 +96,7 @@ struct Group {
   std::vector<DevState> host_states;
   int warm_used = 0;
   std::map<std::pair<int, int>, hipGraphExec_t>* graph_cache = nullptr;
+  bool in_cg = false;           // the CG-loop passes are being queued (timed when enabled)
 };
 
 // Fills the geometry, plans and shapes of g (from the context's schedule
@@ -107,6 +123,8 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
                          const double* E_single, const double* x0, double* e_single);
 lshom_status apply_real(Group& g, const double* p, double* q);
 lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out);
+// Algorithmic HBM bytes of each pass class for one problem and one CG iteration.
+void pass_model_bytes(const Group& g, int precision, double* out);
 
 lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg);
 void drop_graphs(std::map<std::pair<int, int>, hipGraphExec_t>& cache);
@@ -126,6 +144,7 @@ struct lshom_ctx {
   size_t ws_bytes = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   std::map<lshom::SchedKey, lshom::Schedule> schedules;  // autotuned or set by the caller
+  lshom::PassTimer timer;
 };
 
 #define HIP_TRY(ctx, expr)                                                                       \

@@ -179,6 +179,46 @@ Bufs<float> get_bufs<float>(Group& g) {
 
 hipStream_t stream_of(Group& g) { return g.ctx->stream; }
 
+// Launch f; inside the CG loop with pass timing on, between two events.
+template <typename F>
+hipError_t timed_launch(Group& g, int kind, F&& f) {
+  PassTimer& t = g.ctx->timer;
+  if (!t.on || !g.in_cg) return f();
+  const size_t i = t.kinds.size();
+  while (t.pool.size() < 2 * i + 2) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    t.pool.push_back(ev);
+  }
+  hipError_t e = hipEventRecord(t.pool[2 * i], stream_of(g));
+  if (e != hipSuccess) return e;
+  if ((e = f()) != hipSuccess) return e;
+  if ((e = hipEventRecord(t.pool[2 * i + 1], stream_of(g))) != hipSuccess) return e;
+  t.kinds.push_back(kind);
+  return hipSuccess;
+}
+
+// Fold the pending launch timings (after a stream synchronisation) and the
+// bytes of the problem-iterations advanced since `prev_iters`.
+hipError_t harvest_timing(Group& g, long long advanced) {
+  PassTimer& t = g.ctx->timer;
+  if (!t.on) return hipSuccess;
+  bool seen[LSHOM_PASS_COUNT] = {};
+  for (size_t i = 0; i < t.kinds.size(); ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, t.pool[2 * i], t.pool[2 * i + 1]);
+    if (e != hipSuccess) return e;
+    t.ms[t.kinds[i]] += ms;
+    t.launches[t.kinds[i]] += 1;
+    seen[t.kinds[i]] = true;
+  }
+  for (int k = 0; k < LSHOM_PASS_COUNT; ++k)
+    if (seen[k]) t.bytes[k] += (double)advanced * t.unit_bytes[k];
+  t.kinds.clear();
+  return hipSuccess;
+}
+
 // ---------------------------------------------------------------------------
 // Pass argument builders
 // ---------------------------------------------------------------------------
@@ -335,7 +375,8 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, -1);
     m.gate = gate;
-    if ((e = launch_col(m, stream_of(g))) != hipSuccess) return e;
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS1_FORWARD, [&] { return launch_col(m, stream_of(g)); })) != hipSuccess)
+      return e;
   }
   ColArgs<T> a = col0_args(g, b);
   a.mode = COL_FWD_PROJ;
@@ -347,7 +388,7 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
   a.dot = dot;
   a.dot_region = dot_region;
   a.gate = gate;
-  return launch_col(a, stream_of(g));
+  return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, stream_of(g)); });
 }
 
 // Inverse half: axis-0 inverse from the scalar c (or the CG direction step
@@ -363,11 +404,13 @@ hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<
   a.r_in = r_in;
   a.cg_step = p_io != nullptr;
   a.gate = gate;
-  if ((e = launch_col(a, stream_of(g))) != hipSuccess) return e;
+  if ((e = timed_launch(g, LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_col(a, stream_of(g)); })) != hipSuccess)
+    return e;
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, +1);
     m.gate = gate;
-    if ((e = launch_col(m, stream_of(g))) != hipSuccess) return e;
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_col(m, stream_of(g)); })) != hipSuccess)
+      return e;
   }
   return hipSuccess;
 }
@@ -382,9 +425,9 @@ hipError_t enq_apply_spec(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* 
   RowArgs<T> r = row_args(g, b);
   r.mode = ROW_FUSED;
   for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
-  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
+  if (!E) r.flags |= ROWF_STATE_E;
   r.gate = gate;
-  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row(r, stream_of(g)); })) != hipSuccess) return e;
   return enq_forward_project(g, b, out, base, coef_base, coef_s, 1, dot, dot_region, gate);
 }
 
@@ -398,12 +441,15 @@ hipError_t enq_cg_iteration(Group& g, const Bufs<T>& b, int gate) {
   cx<T>* p = b.v[2];
   cx<T>* q = b.v[3];
   static const double kZero[3] = {0.0, 0.0, 0.0};
-  if ((e = enq_apply_spec<T>(g, b, nullptr, p, r, kZero, q, p, T(1), T(1), 1, PART_PQ, gate)) !=
-      hipSuccess)
-    return e;
-  UpdArgs<T> u = upd_args(g, b);
-  u.gate = gate;
-  return launch_update(u, stream_of(g));
+  g.in_cg = true;
+  e = enq_apply_spec<T>(g, b, nullptr, p, r, kZero, q, p, T(1), T(1), 1, PART_PQ, gate);
+  if (e == hipSuccess) {
+    UpdArgs<T> u = upd_args(g, b);
+    u.gate = gate;
+    e = timed_launch(g, LSHOM_PASS_UPDATE, [&] { return launch_update(u, stream_of(g)); });
+  }
+  g.in_cg = false;
+  return e;
 }
 
 // Residual of the spectral iterate x for the load E:
@@ -422,7 +468,7 @@ hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>*
   r.mode = ROW_FWD;
   r.flags = ROWF_DL | ROWF_CONST_E;
   for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
-  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
+  if (!E) r.flags |= ROWF_STATE_E;
   r.gate = GATE_ALWAYS;
   if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
   return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS);
@@ -450,7 +496,7 @@ hipError_t enq_field_out(Group& g, const Bufs<double>& b, const cx<double>* x, c
   RowArgs<double> r = row_args(g, b);
   r.mode = ROW_INV;
   r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0);
-  if (!E && g.batched) r.flags |= ROWF_TABLE_E;
+  if (!E) r.flags |= ROWF_STATE_E;
   for (int t = 0; t < g.d; ++t) {
     r.E[t] = E ? E[t] : 0.0;
     r.real_out[t] = out ? out + (size_t)t * g.nvox : nullptr;
@@ -549,8 +595,15 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       st = fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
       break;
     }
+    long long before = 0;
+    for (const DevState& s : g.host_states) before += s.iter_a;
     hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue_block();
     if (e == hipSuccess) e = sync_states(g);
+    if (e == hipSuccess) {
+      long long after = 0;
+      for (const DevState& s : g.host_states) after += s.iter_a;
+      e = harvest_timing(g, after - before);
+    }
     if (e != hipSuccess) {
       st = fail(c, LSHOM_ERR_HIP, std::string("iteration block: ") + hipGetErrorString(e));
       break;
@@ -618,7 +671,10 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   Bufs<double> b64 = get_bufs<double>(g);
   const long long ncol = col0_block_count(g, b64);
   const long long nall = g.nhalf * g.nprob;
-  const double* E = g.batched ? nullptr : E_single;
+  // E of every problem is read from its device state: a captured graph then
+  // serves every load case
+  (void)E_single;
+  const double* E = nullptr;
   cx<double>* x64 = b64.v[0];
   cx<double>* r64 = b64.v[1];
   DevState* init_dev = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);  // staged, then reused
@@ -668,8 +724,12 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   HIP_TRY(c, sync_states(g));
   int max_iter = 0;
   for (const DevState& s : init) max_iter = std::max(max_iter, s.max_iter);
-  const int K = o.graph_block;
-  const int per = K > 0 ? K : 8;
+  // with pass timing on, the blocks are queued eagerly (events around each launch)
+  PassTimer& tm = c->timer;
+  const int K = tm.on ? 0 : o.graph_block;
+  const int per = o.graph_block > 0 ? o.graph_block : 8;
+  tm.kinds.clear();
+  pass_model_bytes(g, o.precision, tm.unit_bytes);
   lshom_status s;
   if (!mixed) {
     s = run_blocks(g, 0, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
@@ -709,8 +769,9 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
 lshom_status apply_real(Group& g, const double* p, double* q) {
   lshom_ctx* c = g.ctx;
   Bufs<double> b = get_bufs<double>(g);
+  static const double kNoE[3] = {0.0, 0.0, 0.0};
   HIP_TRY(c, enq_project_real(g, b, p, true, b.v[3]));
-  HIP_TRY(c, enq_field_out(g, b, b.v[3], nullptr, p, q, false));
+  HIP_TRY(c, enq_field_out(g, b, b.v[3], kNoE, p, q, false));
   HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
   return LSHOM_OK;
 }
@@ -718,6 +779,26 @@ lshom_status apply_real(Group& g, const double* p, double* q) {
 // ---------------------------------------------------------------------------
 // Per-kernel timing of one CG iteration's launches
 // ---------------------------------------------------------------------------
+
+void pass_model_bytes(const Group& g, int precision, double* out) {
+  const double cs = precision == LSHOM_PRECISION_FP64 ? (double)sizeof(cx<double>) : (double)sizeof(cx<float>);
+  const double nh = (double)g.nhalf;
+  const int d = g.d;
+  for (int k = 0; k < LSHOM_PASS_COUNT; ++k) out[k] = 0.0;
+  // axis-0 inverse with the direction step: reads r, p; writes p and the d pass components
+  out[LSHOM_PASS_AXIS0_INVERSE] = (3.0 + d) * nh * cs;
+  if (d == 3) {
+    // read and write the d components
+    out[LSHOM_PASS_AXIS1_INVERSE] = 2.0 * d * nh * cs;
+    out[LSHOM_PASS_AXIS1_FORWARD] = 2.0 * d * nh * cs;
+  }
+  // reads and writes the d components, reads one phase byte per voxel
+  out[LSHOM_PASS_ROW] = 2.0 * d * nh * cs + (double)g.nvox;
+  // reads the d components and p; writes q
+  out[LSHOM_PASS_AXIS0_FORWARD] = (d + 2.0) * nh * cs;
+  // reads x, r, p, q; writes x, r
+  out[LSHOM_PASS_UPDATE] = 6.0 * nh * cs;
+}
 
 namespace {
 
@@ -745,14 +826,14 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  const double cs = (double)sizeof(cx<T>);
-  const double nh = (double)g.nhalf;
   const int d = g.d;
+  double model[LSHOM_PASS_COUNT];
+  pass_model_bytes(g, sizeof(T) == sizeof(double) ? LSHOM_PRECISION_FP64 : LSHOM_PRECISION_MIXED, model);
   for (int k = 0; k < LSHOM_PASS_COUNT; ++k) {
     ms_out[k] = 0.0;
     if (bytes_out) bytes_out[k] = 0.0;
   }
-  auto timed = [&](int cls, double bytes, auto&& launch) -> hipError_t {
+  auto timed = [&](int cls, auto&& launch) -> hipError_t {
     if (!(mask & (1u << cls))) return hipSuccess;
     hipError_t e = launch();  // warm-up
     if (e != hipSuccess) return e;
@@ -764,7 +845,7 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
     float ms = 0.f;
     if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
     ms_out[cls] = (double)ms / reps;
-    if (bytes_out) bytes_out[cls] = bytes * g.nprob;
+    if (bytes_out) bytes_out[cls] = model[cls] * g.nprob;
     return hipSuccess;
   };
   hipError_t err;
@@ -775,25 +856,23 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
     a.r_in = r;
     a.cg_step = 1;
     a.gate = GATE_ALWAYS;
-    // reads r, p; writes p and the d pass components
-    err = timed(LSHOM_PASS_AXIS0_INVERSE, (3.0 + d) * nh * cs, [&] { return launch_col(a, sm); });
+    err = timed(LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_col(a, sm); });
   }
   if (err == hipSuccess && d == 3) {
     ColArgs<T> m = col1_args(g, b, +1);
     m.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_AXIS1_INVERSE, 2.0 * d * nh * cs, [&] { return launch_col(m, sm); });
+    err = timed(LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_col(m, sm); });
     if (err == hipSuccess) {
       ColArgs<T> f = col1_args(g, b, -1);
       f.gate = GATE_ALWAYS;
-      err = timed(LSHOM_PASS_AXIS1_FORWARD, 2.0 * d * nh * cs, [&] { return launch_col(f, sm); });
+      err = timed(LSHOM_PASS_AXIS1_FORWARD, [&] { return launch_col(f, sm); });
     }
   }
   if (err == hipSuccess) {
     RowArgs<T> rr = row_args(g, b);
     rr.mode = ROW_FUSED;
     rr.gate = GATE_ALWAYS;
-    // reads and writes the d components, reads one phase byte per voxel
-    err = timed(LSHOM_PASS_ROW, 2.0 * d * nh * cs + (double)g.nvox, [&] { return launch_row(rr, sm); });
+    err = timed(LSHOM_PASS_ROW, [&] { return launch_row(rr, sm); });
   }
   if (err == hipSuccess) {
     ColArgs<T> a = col0_args(g, b);
@@ -806,14 +885,12 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
     a.dot = 1;
     a.dot_region = PART_PQ;
     a.gate = GATE_ALWAYS;
-    // reads the d components and p; writes q
-    err = timed(LSHOM_PASS_AXIS0_FORWARD, (d + 2.0) * nh * cs, [&] { return launch_col(a, sm); });
+    err = timed(LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, sm); });
   }
   if (err == hipSuccess) {
     UpdArgs<T> u = upd_args(g, b);
     u.gate = GATE_ALWAYS;
-    // reads x, r, p, q; writes x, r
-    err = timed(LSHOM_PASS_UPDATE, 6.0 * nh * cs, [&] { return launch_update(u, sm); });
+    err = timed(LSHOM_PASS_UPDATE, [&] { return launch_update(u, sm); });
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

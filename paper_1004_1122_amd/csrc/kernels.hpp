@@ -32,6 +32,7 @@ struct DevState {
   double rr_ref;        // mixed: (r, r) at the last refresh
   double drop2;         // mixed: refresh when rr < drop2 * rr_ref
   double leff[3];       // <lambda e>
+  double E[3];          // macroscopic field of the solve (set with the initial state)
   int iter_a;           // iterations completed (written by the update kernel)
   int iter_u;           // iteration in progress (written by the direction kernel)
   int max_iter;
@@ -68,7 +69,6 @@ struct ProbEntry {
   double* e_out;          // FP64 field output d x |N| (may be null)
   const double* x0;       // FP64 warm start d x |N| (may be null)
   double l0;
-  double E[3];
 };
 
 // Problem dimension of a launch: block row blockIdx.y is problem p; its
@@ -109,7 +109,7 @@ enum RowFlags : int {
   ROWF_CONST_E = 2,   // ROW_FWD: the input is the constant field E
   ROWF_ADD = 4,       // ROW_INV: add real_add to the output
   ROWF_LEFF = 8,      // ROW_INV: partial sums of <lambda out> into AUX
-  ROWF_TABLE_E = 16,  // batched: E of each problem from its table entry
+  ROWF_STATE_E = 16,  // E of each problem from its device state (not the argument)
 };
 
 template <typename T>
@@ -151,6 +151,7 @@ enum ColMode : int {
   COL_INV_C = 0,    // scalar c -> i khat_a c (a < d) -> inverse FFT -> comp[a]
   COL_PLAIN = 1,    // comp[a] -> FFT (direction dir) -> comp[a]
   COL_FWD_PROJ = 2, // comp[a] -> forward FFT -> s = -i khat . tau_hat -> out
+  COL_PLAIN_FWD = 3, // kernel specialisation of COL_PLAIN with dir < 0 (launcher-internal)
 };
 
 template <typename T>

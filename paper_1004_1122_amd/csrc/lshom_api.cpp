@@ -42,6 +42,7 @@ DevState initial_state(int d, long long nvox, const double* E, double tol, const
   double e2 = 0.0;
   for (int t = 0; t < d; ++t) e2 += E[t] * E[t];
   s.b2 = e2 * (double)nvox;
+  for (int t = 0; t < 3; ++t) s.E[t] = t < d ? E[t] : 0.0;
   s.tol2b2 = tol * tol * s.b2;
   s.max_iter = o.max_iter;
   if (o.precision == LSHOM_PRECISION_MIXED) {
@@ -162,6 +163,7 @@ void lshom_destroy(lshom_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   drop_graphs(c->graphs);
+  for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -406,7 +408,6 @@ lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const l
     e.e_out = p.e_dev;
     e.x0 = nullptr;
     e.l0 = p.l0 > 0.0 ? p.l0 : 0.5 * (lo + hi);
-    for (int t = 0; t < 3; ++t) e.E[t] = t < p.d ? p.E[t] : 0.0;
     phases.push_back(p.phase_dev);
     (*init)[j] = initial_state(p.d, g.nvox, p.E, p.tol, o);
   }
@@ -606,6 +607,23 @@ lshom_status lshom_autotune_batched(lshom_ctx* c, int32_t n, const lshom_problem
   }
   if (n_best) *n_best = (int32_t)bp.groups.size();
   c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_set_pass_timing(lshom_ctx* c, int enable) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  c->timer.on = enable != 0;
+  c->timer.reset();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_get_pass_timing(lshom_ctx* c, double* ms_out, double* bytes_out, int64_t* launches_out) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  for (int k = 0; k < LSHOM_PASS_COUNT; ++k) {
+    if (ms_out) ms_out[k] = c->timer.ms[k];
+    if (bytes_out) bytes_out[k] = c->timer.bytes[k];
+    if (launches_out) launches_out[k] = c->timer.launches[k];
+  }
   return LSHOM_OK;
 }
 

@@ -110,7 +110,7 @@ __device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
 // Row pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT, int RS>
+template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int pb = blockIdx.y;
   DevState* st = a.st + pb;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const T l0 = pe ? (T)pe->l0 : a.l0;
   T Ev[kMaxDim];
 #pragma unroll
-  for (int c = 0; c < kMaxDim; ++c) Ev[c] = (pe && (a.flags & ROWF_TABLE_E)) ? (T)pe->E[c] : a.E[c];
+  for (int c = 0; c < kMaxDim; ++c) Ev[c] = (a.flags & ROWF_STATE_E) ? (T)st->E[c] : a.E[c];
   const long long nvox = (long long)a.n * a.nrows;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, h = a.h, ss = a.ss, d = a.d, R = a.rows_per_block;
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   // stage twiddles, conductivities and phases (they overlap the data loads)
   copy_batched<cx<T>, NT>(tw, a.tw, n);
   copy_batched<T, NT>(cond, a.cond + (long long)pb * kCondStride, a.n_phases);
-  const bool need_phase = (a.mode == ROW_FUSED) || (a.mode == ROW_FWD && (a.flags & ROWF_DL)) ||
-                          (a.mode == ROW_INV && (a.flags & ROWF_LEFF));
+  const bool need_phase = (MODE == ROW_FUSED) || (MODE == ROW_FWD && (a.flags & ROWF_DL)) ||
+                          (MODE == ROW_INV && (a.flags & ROWF_LEFF));
   if (need_phase) {
     const uint8_t* src = phase + row0 * n;
     const int nb = rows_here * n;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   auto pair_comp = [&](int p) -> int { return p / half_rows; };
   auto pair_row = [&](int p) -> int { return 2 * (p - (p / half_rows) * half_rows); };
 
-  if (a.mode == ROW_FWD) {
+  if constexpr (MODE == ROW_FWD) {
     __syncthreads();
     for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = idx / n;
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     __syncthreads();
     fft_lds<T, +1, NT, RS>(Z, npairs, ss, a.plan, tw, tid);
 
-    if (a.mode == ROW_INV) {
+    if constexpr (MODE == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
       for (int idx = tid; idx < npairs * n; idx += NT) {
         const int p = idx / n;
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 // Strided-axis pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT, int RS>
+template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int pb = blockIdx.y;
   DevState* st = a.st + pb;
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
     }
   };
 
-  if (a.mode == COL_INV_C) {
+  if constexpr (MODE == COL_INV_C) {
     double beta = 0.0;
     if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta)) return;
     const T tb = (T)beta;
@@ -405,57 +405,54 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   }
 
   {
+    // one component at a time, four loads in flight per thread (named
+    // registers: a register array indexed here ended up in scratch)
     const int total = L * C;
-    for (int base = 0; base < total; base += NT * kBatch) {
-      cx<T> v[kBatch][kMaxDim];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int idx = base + u * NT + tid;
-#pragma unroll
-        for (int al = 0; al < kMaxDim; ++al) v[u][al] = zero;
+    for (int al = 0; al < d; ++al) {
+      const cx<T>* __restrict__ src = pick3(a.comp, al);
+      auto ld = [&](int idx) -> cx<T> {
         if (idx < total) {
           int l, c;
           split(idx, l, c);
           if (c < width) {
-            const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-#pragma unroll
-            for (int al = 0; al < kMaxDim; ++al)
-              if (al < d) v[u][al] = a.comp[al][g];
+            const cx<T>* q = src + base_o + l * a.sl + (i0 + c) * a.sii;
+            return cx<T>{q->re, q->im};
           }
         }
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int idx = base + u * NT + tid;
-        if (idx >= total) continue;
-        int l, c;
-        split(idx, l, c);
-#pragma unroll
-        for (int al = 0; al < kMaxDim; ++al)
-          if (al < d) Z[(al * C + c) * ss + l] = v[u][al];
+        return zero;
+      };
+      auto st = [&](int idx, const cx<T>& v) {
+        if (idx < total) {
+          int l, c;
+          split(idx, l, c);
+          Z[(al * C + c) * ss + l] = v;
+        }
+      };
+      for (int base = tid; base < total; base += NT * 4) {
+        const cx<T> v0 = ld(base);
+        const cx<T> v1 = ld(base + NT);
+        const cx<T> v2 = ld(base + 2 * NT);
+        const cx<T> v3 = ld(base + 3 * NT);
+        st(base, v0);
+        st(base + NT, v1);
+        st(base + 2 * NT, v2);
+        st(base + 3 * NT, v3);
       }
     }
   }
   __syncthreads();
 
-  if (a.mode == COL_PLAIN) {
-    if (a.dir > 0)
-      fft_lds<T, +1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
-    else
-      fft_lds<T, -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
-    for (int idx = tid; idx < L * C; idx += NT) {
-      int l, c;
-      split(idx, l, c);
-      if (c < width) {
-        const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
-#pragma unroll
-        for (int al = 0; al < kMaxDim; ++al)
-          if (al < d) a.comp[al][g] = Z[(al * C + c) * ss + l];
+  if constexpr (MODE == COL_PLAIN || MODE == COL_PLAIN_FWD) {
+    fft_lds<T, MODE == COL_PLAIN ? +1 : -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
+    for (int al = 0; al < d; ++al) {
+      cx<T>* __restrict__ dst = pick3(a.comp, al);
+      for (int idx = tid; idx < L * C; idx += NT) {
+        int l, c;
+        split(idx, l, c);
+        if (c < width) dst[base_o + l * a.sl + (i0 + c) * a.sii] = Z[(al * C + c) * ss + l];
       }
     }
-    return;
-  }
-
+  } else {
   // COL_FWD_PROJ
   fft_lds<T, -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
   double acc = 0.0;
@@ -513,6 +510,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   if (a.dot) {
     store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
     if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
+  }
   }
 }
 
@@ -775,20 +773,39 @@ hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipSt
   return hipGetLastError();
 }
 
+// One kernel symbol per (precision, block size, radix set, pass mode): the
+// compiler specialises each mode, and profiles attribute time per pass.
+template <typename T, int RS, int MODE>
+static void launch_row_m(const RowArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
+  const dim3 grid((unsigned)nb, (unsigned)nprob_of(a.bt));
+  if (nt == 128)
+    hipLaunchKernelGGL((row_kernel<T, 128, RS, MODE>), grid, dim3(128), lds, s, a);
+  else
+    hipLaunchKernelGGL((row_kernel<T, 256, RS, MODE>), grid, dim3(256), lds, s, a);
+}
+
 template <typename T, int RS>
 static void launch_row_rs(const RowArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
+  if (a.mode == ROW_FUSED) launch_row_m<T, RS, ROW_FUSED>(a, lds, nb, nt, s);
+  else if (a.mode == ROW_INV) launch_row_m<T, RS, ROW_INV>(a, lds, nb, nt, s);
+  else launch_row_m<T, RS, ROW_FWD>(a, lds, nb, nt, s);
+}
+
+template <typename T, int RS, int MODE>
+static void launch_col_m(const ColArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
+  const dim3 grid((unsigned)nb, (unsigned)nprob_of(a.bt));
   if (nt == 128)
-    hipLaunchKernelGGL((row_kernel<T, 128, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(128), lds, s, a);
+    hipLaunchKernelGGL((col_kernel<T, 128, RS, MODE>), grid, dim3(128), lds, s, a);
   else
-    hipLaunchKernelGGL((row_kernel<T, 256, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((col_kernel<T, 256, RS, MODE>), grid, dim3(256), lds, s, a);
 }
 
 template <typename T, int RS>
 static void launch_col_rs(const ColArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
-  if (nt == 128)
-    hipLaunchKernelGGL((col_kernel<T, 128, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(128), lds, s, a);
-  else
-    hipLaunchKernelGGL((col_kernel<T, 256, RS>), dim3((unsigned)nb, (unsigned)nprob_of(a.bt)), dim3(256), lds, s, a);
+  if (a.mode == COL_INV_C) launch_col_m<T, RS, COL_INV_C>(a, lds, nb, nt, s);
+  else if (a.mode == COL_PLAIN && a.dir > 0) launch_col_m<T, RS, COL_PLAIN>(a, lds, nb, nt, s);
+  else if (a.mode == COL_PLAIN) launch_col_m<T, RS, COL_PLAIN_FWD>(a, lds, nb, nt, s);
+  else launch_col_m<T, RS, COL_FWD_PROJ>(a, lds, nb, nt, s);
 }
 
 template <typename T>

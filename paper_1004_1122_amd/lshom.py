@@ -162,6 +162,8 @@ def load(path: str = LIB_PATH):
         "lshom_autotune": (c_int32, [P, c_int, c_int, POINTER(lshom_schedule)]),
         "lshom_autotune_batched": (c_int32, [P, c_int32, POINTER(lshom_problem), c_int, c_int, P, c_size_t,
                                              POINTER(lshom_schedule), POINTER(c_int32)]),
+        "lshom_set_pass_timing": (c_int32, [P, c_int]),
+        "lshom_get_pass_timing": (c_int32, [P, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
         "lshom_save_schedules": (c_int32, [P, c_char_p]),
         "lshom_load_schedules": (c_int32, [P, c_char_p]),
     }
@@ -235,6 +237,22 @@ def lshom_destroy(ctx) -> None:
 # ---------------------------------------------------------------------------
 # High-level solver object (torch owns device memory)
 # ---------------------------------------------------------------------------
+
+PASS_NAMES = ["axis0_inverse", "axis1_inverse", "row", "axis1_forward", "axis0_forward", "update"]
+
+
+def lshom_set_pass_timing(ctx, enable: bool) -> None:
+    _check(ctx, load().lshom_set_pass_timing(ctx, int(bool(enable))))
+
+
+def lshom_get_pass_timing(ctx):
+    """{pass: (device ms, algorithmic bytes, launches)} summed over timed solves."""
+    ms = (c_double * 6)()
+    by = (c_double * 6)()
+    n = (c_int64 * 6)()
+    _check(ctx, load().lshom_get_pass_timing(ctx, ms, by, n))
+    return {name: (ms[i], by[i], int(n[i])) for i, name in enumerate(PASS_NAMES) if n[i] > 0}
+
 
 class Solver:
     """One microstructure on one device; owns a context and its workspace."""
@@ -315,7 +333,13 @@ class Solver:
         _check(self.ctx, self.lib.lshom_homogenize(self.ctx, float(tol), ctypes.byref(o), out, infos))
         return np.array(out[:]).reshape(self.d, self.d), [i.as_dict() for i in infos]
 
-    PASS_NAMES = ["axis0_inverse", "axis1_inverse", "row", "axis1_forward", "axis0_forward", "update"]
+    PASS_NAMES = PASS_NAMES
+
+    def set_pass_timing(self, enable=True):
+        lshom_set_pass_timing(self.ctx, enable)
+
+    def pass_timing(self):
+        return lshom_get_pass_timing(self.ctx)
 
     def time_passes(self, precision=PRECISION_FP64, reps=50):
         """Average device ms and algorithmic bytes per launch of each pass kernel."""
@@ -449,6 +473,12 @@ class BatchSolver:
 
     def load_schedules(self, path):
         _check(self.ctx, self.lib.lshom_load_schedules(self.ctx, os.fsencode(path)))
+
+    def set_pass_timing(self, enable=True):
+        lshom_set_pass_timing(self.ctx, enable)
+
+    def pass_timing(self):
+        return lshom_get_pass_timing(self.ctx)
 
     def run(self, allow_fail=False, **opt_kw):
         """Solve the prepared problems; returns (fields, leff [n, 3], infos)."""

@@ -1,0 +1,51 @@
+"""Launches of the pass kernels with known work, for hardware-counter runs.
+
+Builds the 729x729 circle cell (40 RSA circles, seed 2, contrast 1e4),
+applies the autotuned schedule of each precision, and launches every pass
+kernel of one CG iteration `--reps` times back to back (all blocks active, as
+in the middle of a solve).  Prints one JSON line with each pass's average
+launch time and algorithmic bytes.  With --copy-mib, finishes with an
+elementwise kernel that reads and writes that many MiB once (the counter
+calibration).
+
+  python -m paper_1004_1122_amd.pass_profile [--reps 20] [--copy-mib 256]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=0)
+    ap.add_argument("--rho", type=float, default=1e4)
+    args = ap.parse_args()
+    import torch
+    from . import lshom
+    from . import microstructure as ms
+
+    m = ms.circles_729(seed=2)
+    s = lshom.Solver(torch.from_numpy(m.phase).cuda(), [1.0, args.rho])
+    out = {"workload": "729x729 circles seed 2, rho %g" % args.rho, "reps": args.reps, "forms": {}}
+    for form, prec in (("fp64", lshom.PRECISION_FP64), ("mixed", lshom.PRECISION_MIXED)):
+        s.solve((1.0, 0.0), tol=1e-6, precision=prec, want_field=False)
+        sched = s.autotune(precision=prec, reps=10)
+        passes = s.time_passes(prec, reps=args.reps)
+        out["forms"][form] = {"schedule": sched,
+                              "passes": {k: {"ms": v[0], "algorithmic_bytes": v[1]} for k, v in passes.items()}}
+    if args.copy_mib > 0:
+        nbytes = args.copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        out["copy_bytes"] = nbytes
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+"""Summaries of rocprofv3 output for the pass kernels (text for the profile
+records kept with the sources).
+
+  python -m paper_1004_1122_amd.profiling stats --dir D --title T --command C --out F.md
+      kernel statistics table from D/*kernel_stats.csv (and launch shapes
+      from D/*kernel_trace.csv)
+
+  python -m paper_1004_1122_amd.profiling traffic --fetch D1 --write D2 --kernel REGEX
+      --pass NAME --form FORM --copy REGEX --copy-bytes N --command-fetch C1
+      --command-write C2 --alg-bytes B --out F.md
+      HBM bytes per launch of the kernels matching REGEX from two counter runs
+      (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
+      same counter reads for a copy kernel of N bytes read and N written, and
+      their ratio to the algorithmic bytes B of one such launch.
+"""
+
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("passes.hip", "fft_engine.hpp", "reduce.hpp", "kernels.hpp", "radix_consts.hpp")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(pattern):
+    out = []
+    for path in sorted(glob.glob(pattern, recursive=True)):
+        with open(path, newline="") as f:
+            out.extend(csv.DictReader(f))
+    return out
+
+
+def _col(row, *names):
+    for n in names:
+        for k in row:
+            if k.lower() == n.lower():
+                return row[k]
+    raise KeyError(names)
+
+
+def stats(args):
+    rows = _rows(os.path.join(args.dir, "**", "*kernel_stats.csv"))
+    trace = _rows(os.path.join(args.dir, "**", "*kernel_trace.csv"))
+    shapes = {}
+    for t in trace:
+        name = _col(t, "Kernel_Name")
+        try:
+            dur = int(_col(t, "End_Timestamp")) - int(_col(t, "Start_Timestamp"))
+        except KeyError:
+            dur = None
+        grid = tuple(int(_col(t, f"Grid_Size_{a}")) for a in "XYZ") if "Grid_Size_X" in t else None
+        wg = tuple(int(_col(t, f"Workgroup_Size_{a}")) for a in "XYZ") if "Workgroup_Size_X" in t else None
+        rec = shapes.setdefault(name, {"dur": [], "shapes": set()})
+        if dur is not None:
+            rec["dur"].append(dur)
+        if grid and wg:
+            rec["shapes"].add((tuple(g // w for g, w in zip(grid, wg)), wg[0]))
+    lines = [f"# {args.title}", "", "Command (GPU box, repository root in $R):", "", "```", args.command, "```", ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += ["| Kernel | Calls | Total ns | Average ns | Median ns | Min ns | Max ns | % | Blocks x threads |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = _col(r, "Name", "Kernel_Name")
+        med = ""
+        sh = ""
+        if name in shapes:
+            if shapes[name]["dur"]:
+                med = str(int(statistics.median(shapes[name]["dur"])))
+            sh = "; ".join(f"{'x'.join(map(str, b))} x {w}" for b, w in sorted(shapes[name]["shapes"])[:3])
+        lines.append(f"| `{name}` | {_col(r, 'Calls')} | {_col(r, 'TotalDurationNs')} | "
+                     f"{float(_col(r, 'AverageNs')):.0f} | {med} | {_col(r, 'MinNs')} | {_col(r, 'MaxNs')} | "
+                     f"{float(_col(r, 'Percentage')):.2f} | {sh} |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter_sums(pattern, counter):
+    per = {}
+    for r in _rows(pattern):
+        if _col(r, "Counter_Name") != counter:
+            continue
+        key = (_col(r, "Kernel_Name"), _col(r, "Dispatch_Id"))
+        per[key] = per.get(key, 0.0) + float(_col(r, "Counter_Value"))
+    return per
+
+
+def traffic(args):
+    fetch = _counter_sums(os.path.join(args.fetch, "**", "*counter_collection.csv"), "FETCH_SIZE")
+    write = _counter_sums(os.path.join(args.write, "**", "*counter_collection.csv"), "WRITE_SIZE")
+    kre, cre = re.compile(args.kernel), re.compile(args.copy)
+
+    def pick(per, rx):
+        vals = [v for (name, _), v in per.items() if rx.search(name)]
+        return vals
+
+    cf, cw = pick(fetch, cre), pick(write, cre)
+    kf, kw = pick(fetch, kre), pick(write, kre)
+    if not (cf and cw and kf and kw):
+        raise SystemExit(f"missing dispatches: copy {len(cf)}/{len(cw)}, kernel {len(kf)}/{len(kw)}")
+    copy_kib = args.copy_bytes / 1024.0
+    fetch_scale = copy_kib / max(cf)
+    write_scale = copy_kib / max(cw)
+    fetch_b = statistics.mean(kf) * fetch_scale * 1024.0
+    write_b = statistics.mean(kw) * write_scale * 1024.0
+    rec = {
+        "pass": args.pass_name, "form": args.form, "kernel_regex": args.kernel,
+        "launches": len(kf), "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b, "algorithmic_bytes_per_launch": args.alg_bytes,
+        "traffic_ratio": (fetch_b + write_b) / args.alg_bytes,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "copy_bytes": args.copy_bytes, "source_hash": kernel_source_hash(), "summary": os.path.basename(args.out),
+    }
+    lines = [
+        f"# HBM traffic of `{args.kernel}` ({args.pass_name}, {args.form})", "",
+        "Counter runs (GPU box, repository root in $R):", "", "```", args.command_fetch, args.command_write, "```", "",
+        f"Calibration: the copy kernel matching `{args.copy}` reads and writes {args.copy_bytes} bytes; "
+        f"FETCH_SIZE read {max(cf):.0f} KiB (scale {fetch_scale:.4f}), WRITE_SIZE {max(cw):.0f} KiB "
+        f"(scale {write_scale:.4f}).", "",
+        f"Kernel: {len(kf)} dispatches; mean FETCH_SIZE {statistics.mean(kf):.1f} KiB, "
+        f"WRITE_SIZE {statistics.mean(kw):.1f} KiB per dispatch; scaled: {fetch_b / 1e6:.3f} MB read + "
+        f"{write_b / 1e6:.3f} MB written = {(fetch_b + write_b) / 1e6:.3f} MB per launch, against "
+        f"{args.alg_bytes / 1e6:.3f} MB algorithmic (ratio {(fetch_b + write_b) / args.alg_bytes:.3f}).", "",
+        "traffic-json: " + json.dumps(rec), "",
+    ]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--dir", required=True)
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--note", default="")
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--pass", dest="pass_name", required=True)
+    t.add_argument("--form", required=True)
+    t.add_argument("--copy", default=r"neg")
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--alg-bytes", type=float, required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    stats(a) if a.cmd == "stats" else traffic(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,3 +109,31 @@ def test_batched_autotune_keeps_results():
         assert abs(inf1[i]["iterations"] - inf0[i]["iterations"]) <= 1
         assert _rel(f1[i].cpu().numpy(), f0[i].cpu().numpy()) < 1e-10
         assert np.allclose(leff1[i], leff0[i], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_pass_timing_inside_solves(precision):
+    """Eager solves with per-launch events give the graph solve's results bit for
+    bit; the timer's bytes are the per-pass model bytes times the iterations."""
+    from paper_1004_1122_amd import lshom
+    probs = []
+    for i, rho in enumerate([10.0, 1e3, 1e2]):
+        m = ms.grf_two_phase(81, 0.1, 0.4, rho, seed=500 + i)
+        probs.append(dict(phase=m.phase, cond=[1.0, rho], E=(1.0, 0.0), tol=1e-8, want_field=True))
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=1)
+    f0, leff0, inf0 = bs.run(precision=precision)
+    f0 = [f.clone() for f in f0]
+    bs.set_pass_timing(True)
+    f1, leff1, inf1 = bs.run(precision=precision)
+    t = bs.pass_timing()
+    bs.set_pass_timing(False)
+    for i in range(len(probs)):
+        assert torch.equal(f0[i], f1[i]) and inf0[i]["iterations"] == inf1[i]["iterations"]
+    assert set(t) == {"axis0_inverse", "row", "axis0_forward", "update"}
+    iters = sum(i["iterations"] for i in inf1)
+    s = lshom.Solver(probs[0]["phase"], probs[0]["cond"])
+    unit = {k: b for k, (_, b) in s.time_passes(precision, reps=1).items()}
+    for k, (ms_, by, n) in t.items():
+        assert ms_ > 0 and n >= max(i["iterations"] for i in inf1)
+        assert by == pytest.approx(iters * unit[k], rel=1e-12), k

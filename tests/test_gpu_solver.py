@@ -317,3 +317,24 @@ def test_mixed_reports_and_limits():
     homog = _solver(np.zeros((9, 9, 9), np.uint8), [3.0])
     e, leff, info = homog.solve([1.0, 1.0, 1.0], tol=1e-10, precision=1)
     assert info["iterations"] == 0 and np.allclose(leff, 3.0, rtol=1e-15)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solver_reuse_across_load_cases(precision):
+    """Solves with different E on one context (cached iteration graphs) equal
+    solves on fresh contexts bit for bit."""
+    from paper_1004_1122_amd import lshom
+    m = ms.grf_two_phase(81, 0.1, 0.4, 1e3, seed=77)
+    loads = [(1.0, 0.0), (0.0, 1.0), (0.6, -0.8), (1.0, 0.0)]
+    s = lshom.Solver(m.phase, m.cond)
+    for E in loads:
+        e1, l1, i1 = s.solve(E, tol=1e-8, precision=precision)
+        f = lshom.Solver(m.phase, m.cond)
+        e2, l2, i2 = f.solve(E, tol=1e-8, precision=precision)
+        assert i1["iterations"] == i2["iterations"] and i1["status"] == 0
+        assert torch.equal(e1, e2) and np.array_equal(l1, l2)
+    t, infos = s.homogenize(tol=1e-8, precision=precision)
+    for b in range(2):
+        E = (1.0, 0.0) if b == 0 else (0.0, 1.0)
+        _, l, _ = lshom.Solver(m.phase, m.cond).solve(E, tol=1e-8, precision=precision)
+        assert np.array_equal(t[:, b], l)
