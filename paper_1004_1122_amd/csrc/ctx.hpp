@@ -82,7 +82,7 @@ struct Group {
   int h = 0;
   bool transposed = false;      // 2-D spectral arrays stored [k1][k0]
   FftPlan plan64[3], plan32[3];
-  PassShape shape64{2, 1, 1}, shape32{2, 1, 1};
+  PassShape shape64{2, 1, 1, 0}, shape32{2, 1, 1, 0};
   int n_phases = 1;             // conductivity entries staged per problem
   // single problem (nprob == 1, batched == false)
   const uint8_t* phase = nullptr;
@@ -97,6 +97,7 @@ struct Group {
   int warm_used = 0;
   std::map<std::pair<int, int>, hipGraphExec_t>* graph_cache = nullptr;
   bool in_cg = false;           // the CG-loop passes are being queued (timed when enabled)
+  PassTimer* timer = nullptr;   // event timing of the CG-loop passes (null: off)
 };
 
 // Fills the geometry, plans and shapes of g (from the context's schedule

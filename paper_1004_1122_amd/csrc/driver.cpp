@@ -42,6 +42,8 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
   g.h = (int)(N[d - 1] / 2 + 1);
   g.nrows = g.nvox / N[d - 1];
   g.nhalf = g.nrows * g.h;
+  // in-kernel index arithmetic is 32-bit
+  if (g.nvox >= (1ll << 31)) return LSHOM_ERR_UNSUPPORTED;
   g.transposed = (d == 2);
   g.n_phases = n_phases;
   for (int a = 0; a < d; ++a) g.plan64[a] = g.plan32[a] = default_plan((int)N[a]);
@@ -101,7 +103,7 @@ Layout compute_layout(const Group& g, bool with32) {
   // any schedule can make (two rows per row-pass block, tiles of one)
   (void)with32;
   long long maxb = kUpdateBlocks;
-  maxb = std::max(maxb, ceil_div(g.nrows, 2));
+  maxb = std::max(maxb, (long long)g.d * ceil_div(g.nrows, 2));
   maxb = std::max(maxb, inner0_of(g));
   if (g.d == 3) maxb = std::max(maxb, g.N[0] * (long long)g.h);
   L.part_stride = 3 * maxb;
@@ -182,8 +184,8 @@ hipStream_t stream_of(Group& g) { return g.ctx->stream; }
 // Launch f; inside the CG loop with pass timing on, between two events.
 template <typename F>
 hipError_t timed_launch(Group& g, int kind, F&& f) {
-  PassTimer& t = g.ctx->timer;
-  if (!t.on || !g.in_cg) return f();
+  if (!g.timer || !g.timer->on || !g.in_cg) return f();
+  PassTimer& t = *g.timer;
   const size_t i = t.kinds.size();
   while (t.pool.size() < 2 * i + 2) {
     hipEvent_t ev;
@@ -202,8 +204,8 @@ hipError_t timed_launch(Group& g, int kind, F&& f) {
 // Fold the pending launch timings (after a stream synchronisation) and the
 // bytes of the problem-iterations advanced since `prev_iters`.
 hipError_t harvest_timing(Group& g, long long advanced) {
-  PassTimer& t = g.ctx->timer;
-  if (!t.on) return hipSuccess;
+  if (!g.timer || !g.timer->on) return hipSuccess;
+  PassTimer& t = *g.timer;
   bool seen[LSHOM_PASS_COUNT] = {};
   for (size_t i = 0; i < t.kinds.size(); ++i) {
     float ms = 0.f;
@@ -240,6 +242,9 @@ ColArgs<T> col0_args(Group& g, const Bufs<T>& b) {
   a.tiles_per_outer = (int)ceil_div(a.inner, a.tile);
   a.d = g.d;
   col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), &a.ss);
+  a.fd_L = make_fastdiv((uint32_t)a.L);
+  a.fd_C = make_fastdiv((uint32_t)a.tile);
+  a.fd_h = make_fastdiv((uint32_t)g.h);
   for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
@@ -269,6 +274,9 @@ ColArgs<T> col1_args(Group& g, const Bufs<T>& b, int dir) {
   a.tiles_per_outer = (int)ceil_div(a.inner, a.tile);
   a.d = g.d;
   col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), &a.ss);
+  a.fd_L = make_fastdiv((uint32_t)a.L);
+  a.fd_C = make_fastdiv((uint32_t)a.tile);
+  a.fd_h = make_fastdiv((uint32_t)g.h);
   for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
@@ -297,7 +305,13 @@ RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
   a.nrows = g.nrows;
   a.rows_per_block = b.shape.rows_per_block;
   a.d = g.d;
-  row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), g.n_phases, &a.ss);
+  a.split = b.shape.row_split;
+  const int comps = a.split ? 1 : a.d;
+  row_lds_bytes(a.n, a.rows_per_block, comps, (int)sizeof(cx<T>), g.n_phases, &a.ss);
+  a.fd_n = make_fastdiv((uint32_t)a.n);
+  a.fd_np = make_fastdiv((uint32_t)(comps * (a.rows_per_block / 2)));
+  a.fd_h = make_fastdiv((uint32_t)a.h);
+  a.fd_half = make_fastdiv((uint32_t)(a.rows_per_block / 2));
   if (g.transposed) {
     a.rs_row = 1;
     a.rs_k = g.nrows;
@@ -349,6 +363,8 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   u.h = g.h;
   u.n_last = (int)g.N[g.d - 1];
   u.klast_div = klast_div_of(g);
+  u.fd_kd = make_fastdiv((uint32_t)u.klast_div);
+  u.fd_h = make_fastdiv((uint32_t)g.h);
   u.x = b.v[0];
   u.r = b.v[1];
   u.p = b.v[2];
@@ -514,6 +530,8 @@ MixArgs mix_args(Group& g, const Bufs<double>& b64, const Bufs<float>& b32, int 
   m.h = g.h;
   m.n_last = (int)g.N[g.d - 1];
   m.klast_div = klast_div_of(g);
+  m.fd_kd = make_fastdiv((uint32_t)m.klast_div);
+  m.fd_h = make_fastdiv((uint32_t)g.h);
   m.x64 = b64.v[0];
   m.x32 = b32.v[0];
   m.r64 = b64.v[1];
@@ -726,6 +744,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   for (const DevState& s : init) max_iter = std::max(max_iter, s.max_iter);
   // with pass timing on, the blocks are queued eagerly (events around each launch)
   PassTimer& tm = c->timer;
+  g.timer = tm.on ? &tm : nullptr;
   const int K = tm.on ? 0 : o.graph_block;
   const int per = o.graph_block > 0 ? o.graph_block : 8;
   tm.kinds.clear();
@@ -805,17 +824,18 @@ namespace {
 template <typename T>
 lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out, double* bytes_out,
                            unsigned mask) {
+  // Real CG iterations (FP64 decisions, no stopping) from the residual of a
+  // unit load: every pass consumes the previous pass's output, so the data
+  // stay those of a solve; each launch is bracketed by a pair of events.
+  (void)mask;
   lshom_ctx* c = g.ctx;
   hipStream_t sm = stream_of(g);
-  cx<T>* r = b.v[1];
-  cx<T>* p = b.v[2];
-  cx<T>* q = b.v[3];
-  // a state in which the direction step proceeds (beta = 0) and the update
-  // uses alpha = 0, so repeated launches keep the vectors bounded
+  const long long nall = g.nhalf * g.nprob;
   DevState init{};
   init.max_iter = 1 << 30;
   init.tol2b2 = -1.0;
   init.b2 = 1.0;
+  init.E[0] = 1.0;
   {
     std::vector<DevState> all(g.nprob, init);
     DevState* staged = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);
@@ -823,78 +843,29 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
     HIP_TRY(c, launch_state_copy(dev_state(g), staged, g.nprob, sm));
     HIP_TRY(c, hipStreamSynchronize(sm));
   }
-  hipEvent_t e0, e1;
-  HIP_TRY(c, hipEventCreate(&e0));
-  HIP_TRY(c, hipEventCreate(&e1));
-  const int d = g.d;
+  HIP_TRY(c, launch_fill_zero(b.v[0], nall, sm));
+  HIP_TRY(c, launch_fill_zero(b.v[2], nall, sm));
+  static const double kUnit[3] = {1.0, 0.0, 0.0};
+  HIP_TRY(c, (enq_residual_of_E<T>(g, b, kUnit, b.v[1], PART_RR0)));
+  // one untimed iteration, then `reps` timed ones
+  HIP_TRY(c, (enq_cg_iteration<T>(g, b, GATE_ALWAYS)));
+  PassTimer local;
+  local.on = true;
+  PassTimer* saved = g.timer;
+  g.timer = &local;
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < reps && err == hipSuccess; ++i) err = enq_cg_iteration<T>(g, b, GATE_ALWAYS);
+  if (err == hipSuccess) err = hipStreamSynchronize(sm);
+  if (err == hipSuccess) err = harvest_timing(g, 0);
+  g.timer = saved;
+  if (err != hipSuccess) return fail(c, LSHOM_ERR_HIP, std::string("time_passes: ") + hipGetErrorString(err));
+  for (hipEvent_t ev : local.pool) (void)hipEventDestroy(ev);
   double model[LSHOM_PASS_COUNT];
   pass_model_bytes(g, sizeof(T) == sizeof(double) ? LSHOM_PRECISION_FP64 : LSHOM_PRECISION_MIXED, model);
   for (int k = 0; k < LSHOM_PASS_COUNT; ++k) {
-    ms_out[k] = 0.0;
-    if (bytes_out) bytes_out[k] = 0.0;
+    ms_out[k] = local.launches[k] ? local.ms[k] / (double)local.launches[k] : 0.0;
+    if (bytes_out) bytes_out[k] = local.launches[k] ? model[k] * g.nprob : 0.0;
   }
-  auto timed = [&](int cls, auto&& launch) -> hipError_t {
-    if (!(mask & (1u << cls))) return hipSuccess;
-    hipError_t e = launch();  // warm-up
-    if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(e0, sm)) != hipSuccess) return e;
-    for (int i = 0; i < reps; ++i)
-      if ((e = launch()) != hipSuccess) return e;
-    if ((e = hipEventRecord(e1, sm)) != hipSuccess) return e;
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
-    float ms = 0.f;
-    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
-    ms_out[cls] = (double)ms / reps;
-    if (bytes_out) bytes_out[cls] = model[cls] * g.nprob;
-    return hipSuccess;
-  };
-  hipError_t err;
-  {
-    ColArgs<T> a = col0_args(g, b);
-    a.mode = COL_INV_C;
-    a.p_io = p;
-    a.r_in = r;
-    a.cg_step = 1;
-    a.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_col(a, sm); });
-  }
-  if (err == hipSuccess && d == 3) {
-    ColArgs<T> m = col1_args(g, b, +1);
-    m.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_col(m, sm); });
-    if (err == hipSuccess) {
-      ColArgs<T> f = col1_args(g, b, -1);
-      f.gate = GATE_ALWAYS;
-      err = timed(LSHOM_PASS_AXIS1_FORWARD, [&] { return launch_col(f, sm); });
-    }
-  }
-  if (err == hipSuccess) {
-    RowArgs<T> rr = row_args(g, b);
-    rr.mode = ROW_FUSED;
-    rr.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_ROW, [&] { return launch_row(rr, sm); });
-  }
-  if (err == hipSuccess) {
-    ColArgs<T> a = col0_args(g, b);
-    a.mode = COL_FWD_PROJ;
-    a.out = q;
-    a.base = p;
-    a.coef_base = T(1);
-    a.coef_s = T(1);
-    a.s_inv_l0 = 1;
-    a.dot = 1;
-    a.dot_region = PART_PQ;
-    a.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, sm); });
-  }
-  if (err == hipSuccess) {
-    UpdArgs<T> u = upd_args(g, b);
-    u.gate = GATE_ALWAYS;
-    err = timed(LSHOM_PASS_UPDATE, [&] { return launch_update(u, sm); });
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (err != hipSuccess) return fail(c, LSHOM_ERR_HIP, std::string("time_passes: ") + hipGetErrorString(err));
   return LSHOM_OK;
 }
 
@@ -984,21 +955,25 @@ lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best) {
     double best_t = 1e300;
     Schedule bs = cur;
     for (const FftPlan& pl : plan_candidates((int)g.N[last])) {
-      for (int r = 2; r <= 16; r += 2) {
-        Schedule s = cur;
-        s.plan[last] = pl;
-        s.shape.rows_per_block = r;
-        if (!schedule_fits(g, s, precision)) continue;
-        const double t = time_of(s, mask);
-        if (st != LSHOM_OK) return st;
-        if (t < best_t) {
-          best_t = t;
-          bs = s;
+      for (int split = 0; split <= 1; ++split) {
+        for (int r = 2; r <= 32; r += 2) {
+          Schedule s = cur;
+          s.plan[last] = pl;
+          s.shape.rows_per_block = r;
+          s.shape.row_split = split;
+          if (!schedule_fits(g, s, precision)) continue;
+          const double t = time_of(s, mask);
+          if (st != LSHOM_OK) return st;
+          if (t < best_t) {
+            best_t = t;
+            bs = s;
+          }
         }
       }
     }
     cur.plan[last] = bs.plan[last];
     cur.shape.rows_per_block = bs.shape.rows_per_block;
+    cur.shape.row_split = bs.shape.row_split;
   }
   // axis-0 passes (inverse with the direction step, forward with the projection)
   if (last != 0) {

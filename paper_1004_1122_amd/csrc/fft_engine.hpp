@@ -143,11 +143,39 @@ __device__ __forceinline__ void dft(cx<T>* x) {
 
 constexpr int kMaxStages = 16;
 
-// Radix schedule of one axis; the product of radix[0..nstages) is n.
+// Unsigned division by a runtime constant d >= 1, for 0 <= x < 2^31, as a
+// multiply-high and a shift: with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1, floor(x / d) = (mulhi(x, m) + x) >> s
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, the round-up multiplier; x < 2^31 keeps the sum
+// within 32 bits).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+
+__host__ inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 1u, 0u};
+  if (d <= 1) return f;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.s = s;
+  f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << s) - d)) / d + 1);
+  return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t x, const FastDiv& f) {
+  return (__umulhi(x, f.m) + x) >> f.s;
+}
+
+// Radix schedule of one axis; the product of radix[0..nstages) is n.  nr[st]
+// and ns[st] divide by n / radix[st] and by the product of the radices before
+// stage st (filled by the host planner).
 struct FftPlan {
   int n;
   int nstages;
   int radix[kMaxStages];
+  FastDiv nr[kMaxStages];
+  FastDiv ns[kMaxStages];
 };
 
 // Butterflies held per thread across the stage barrier, per radix.  The host
@@ -172,23 +200,24 @@ __host__ __device__ inline int plan_batch_cap(const FftPlan& p, int threads) {
 // exp(-2 pi i m / n) (conjugated for the inverse direction, S = +1).
 template <typename T, int R, int S, int NT>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, int Ns,
-                                          const cx<T>* __restrict__ tw, int tid) {
+                                          const cx<T>* __restrict__ tw, int tid, const FastDiv& fnr,
+                                          const FastDiv& fns) {
   constexpr int JM = jobs_per_thread(R);
-  const int NR = n / R;
+  const int NR = (int)fnr.d;
   const int jobs = nseq * NR;
-  const int step = n / (Ns * R);
+  const int step = NR / Ns;  // n / (Ns R)
   cx<T> v[JM][R];
 #pragma unroll
   for (int q = 0; q < JM; ++q) {
     const int job = tid + q * NT;
     if (job < jobs) {
-      const int s = job / NR;
+      const int s = (int)fdiv((uint32_t)job, fnr);
       const int j = job - s * NR;
       const cx<T>* b = buf + s * ss + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = b[r * NR];
       if (Ns > 1) {
-        const int k = j % Ns;
+        const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> w = tw[r * k * step];
@@ -204,9 +233,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
   for (int q = 0; q < JM; ++q) {
     const int job = tid + q * NT;
     if (job < jobs) {
-      const int s = job / NR;
+      const int s = (int)fdiv((uint32_t)job, fnr);
       const int j = job - s * NR;
-      const int k = j % Ns;
+      const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
       cx<T>* b = buf + s * ss + (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) b[r * Ns] = v[q][r];
@@ -236,22 +265,22 @@ __device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
   for (int st = 0; st < plan.nstages; ++st) {
     const int R = plan.radix[st];
     if constexpr (RS == RADIX_POW3) {
-      if (R == 9) fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
-      else fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+      if (R == 9) fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+      else fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
     } else if constexpr (RS == RADIX_POW2) {
-      if (R == 8) fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
-      else if (R == 4) fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
-      else fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid);
+      if (R == 8) fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+      else if (R == 4) fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+      else fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
     } else {
       switch (R) {
-        case 2: fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 3: fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 4: fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 5: fft_stage<T, 5, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 6: fft_stage<T, 6, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
-        case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid); break;
+        case 2: fft_stage<T, 2, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 3: fft_stage<T, 3, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 4: fft_stage<T, 4, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 5: fft_stage<T, 5, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 6: fft_stage<T, 6, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
+        case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
         default: break;
       }
     }

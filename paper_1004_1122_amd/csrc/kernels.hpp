@@ -94,8 +94,10 @@ enum FinMode : int {
 
 // ---------------------------------------------------------------------------
 // Row pass: FFTs along the contiguous (last) real-space axis.  A block owns
-// rows_per_block consecutive rows (an even number) and pairs row 2j with row
-// 2j+1 of the same component into one complex transform.
+// rows_per_block consecutive rows (an even number) of every component, or of
+// one component (split: block b handles component b % d of row block b / d),
+// and pairs row 2j with row 2j+1 of the same component into one complex
+// transform.
 // Spectral element (row, k) of a component lives at row * rs_row + k * rs_k:
 // natural layout rs_row = h, rs_k = 1; transposed (2-D) rs_row = 1, rs_k = nrows.
 // ---------------------------------------------------------------------------
@@ -119,6 +121,7 @@ struct RowArgs {
   long long nrows;       // product of the other axes
   int rows_per_block;    // even
   int d;
+  int split;             // one component per block
   int mode, flags;
   int ss;                // LDS stride between sequences (odd, >= n)
   long long rs_row, rs_k;
@@ -139,6 +142,7 @@ struct RowArgs {
   Partials parts;
   int gate;
   Batch bt;
+  FastDiv fd_n, fd_np, fd_h, fd_half;  // n, pairs per block, h, rows_per_block / 2
 };
 
 // ---------------------------------------------------------------------------
@@ -189,6 +193,7 @@ struct ColArgs {
   int gate;
   double inv_n;          // scales spectral sums to real-space inner products
   Batch bt;
+  FastDiv fd_L, fd_C, fd_h;  // L, tile, h
 };
 
 // ---------------------------------------------------------------------------
@@ -209,6 +214,7 @@ struct UpdArgs {
   double inv_n;
   int gate;
   Batch bt;
+  FastDiv fd_kd, fd_h;   // klast_div, h (n < 2^31)
 };
 
 // Mixed precision: x64 += x32, x32 = 0 (accumulate); r32 = r64 and the
@@ -227,6 +233,7 @@ struct MixArgs {
   double inv_n;
   int gate;
   Batch bt;
+  FastDiv fd_kd, fd_h;
 };
 
 struct FinArgs {
@@ -258,7 +265,8 @@ template <typename T> long long col_blocks(const ColArgs<T>& a);
 long long update_blocks(long long n);
 
 // Dynamic LDS of a launch (sequence data + twiddles + phase bytes).
-size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int n_phases, int* ss_out);
+// comps: components per row-pass block (1 when split, else d)
+size_t row_lds_bytes(int n, int rows_per_block, int comps, int elem_bytes, int n_phases, int* ss_out);
 size_t col_lds_bytes(int L, int tile, int d, int elem_bytes, int* ss_out);
 int lds_odd_stride(int n);
 

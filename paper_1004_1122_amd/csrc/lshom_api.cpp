@@ -436,6 +436,7 @@ void to_c_schedule(const Group& g, const Schedule& s, int precision, lshom_sched
   out->rows_per_block = s.shape.rows_per_block;
   out->tile0 = s.shape.tile0;
   out->tile1 = s.shape.tile1;
+  out->row_split = s.shape.row_split;
   for (int a = 0; a < g.d; ++a) {
     out->nstages[a] = s.plan[a].nstages;
     for (int k = 0; k < s.plan[a].nstages; ++k) out->radix[a][k] = s.plan[a].radix[k];
@@ -455,6 +456,7 @@ lshom_status from_c_schedule(lshom_ctx* c, const lshom_schedule* in, Schedule* s
   s->shape.rows_per_block = in->rows_per_block;
   s->shape.tile0 = in->tile0;
   s->shape.tile1 = in->d == 3 ? in->tile1 : 1;
+  s->shape.row_split = in->row_split;
   s->ms_per_iter = in->ms_per_iter;
   return LSHOM_OK;
 }
@@ -637,9 +639,10 @@ lshom_status lshom_save_schedules(lshom_ctx* c, const char* path) {
     const int prec = std::get<4>(kv.first);
     const Schedule& s = kv.second;
     std::fprintf(f, "{\"arch\": \"%s\", \"d\": %d, \"N\": [%lld, %lld, %lld], \"precision\": %d, "
-                    "\"rows_per_block\": %d, \"tile0\": %d, \"tile1\": %d, \"radix\": [",
+                    "\"rows_per_block\": %d, \"row_split\": %d, \"tile0\": %d, \"tile1\": %d, \"radix\": [",
                  arch.c_str(), d, (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
-                 (long long)std::get<3>(kv.first), prec, s.shape.rows_per_block, s.shape.tile0, s.shape.tile1);
+                 (long long)std::get<3>(kv.first), prec, s.shape.rows_per_block, s.shape.row_split, s.shape.tile0,
+                 s.shape.tile1);
     for (int a = 0; a < d; ++a) {
       std::fprintf(f, "%s[", a ? ", " : "");
       for (int k = 0; k < s.plan[a].nstages; ++k) std::fprintf(f, "%s%d", k ? ", " : "", s.plan[a].radix[k]);
@@ -703,7 +706,7 @@ lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
     std::string line(buf);
     if (line.find('{') == std::string::npos) continue;
     if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
-    std::vector<long long> d, N, prec, rows, t0, t1, radix;
+    std::vector<long long> d, N, prec, rows, t0, t1, radix, split;
     if (!json_ints(line, "d", &d) || !json_ints(line, "N", &N) || !json_ints(line, "precision", &prec) ||
         !json_ints(line, "rows_per_block", &rows) || !json_ints(line, "tile0", &t0) ||
         !json_ints(line, "tile1", &t1) || d.size() != 1 || N.size() != 3) {
@@ -718,6 +721,7 @@ lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
     in.rows_per_block = (int)rows[0];
     in.tile0 = (int)t0[0];
     in.tile1 = (int)t1[0];
+    in.row_split = (json_ints(line, "row_split", &split) && split.size() == 1) ? (int)split[0] : 0;
     // radix lists: split the bracketed value by inner brackets
     const size_t rp = line.find("\"radix\"");
     if (rp == std::string::npos) {

@@ -40,7 +40,7 @@ __device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long
   if (a.dims == 2) {
     idx[1] = (int)ii;
   } else {
-    idx[1] = (int)(ii / a.h);
+    idx[1] = (int)fdiv((uint32_t)ii, a.fd_h);
     idx[2] = (int)(ii - (long long)idx[1] * a.h);
   }
   if (a.dims == 2) idx[2] = 0;
@@ -128,7 +128,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n = a.n, h = a.h, ss = a.ss, d = a.d, R = a.rows_per_block;
   const int half_rows = R / 2;
-  const int npairs = d * half_rows;
+  // split: this block holds one component (c_fix) of row block rb
+  const long long rb = a.split ? (long long)(blockIdx.x / d) : (long long)blockIdx.x;
+  const int c_fix = a.split ? (int)(blockIdx.x - rb * d) : 0;
+  const int npairs = (a.split ? 1 : d) * half_rows;
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   size_t off = align16((size_t)npairs * ss * sizeof(cx<T>));
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + off);
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   off = align16(off + (size_t)a.n_phases * sizeof(T));
   uint8_t* ph = smem_raw + off;  // [R][n] phase bytes of this block's rows
   const int tid = threadIdx.x;
-  const long long row0 = (long long)blockIdx.x * R;
+  const long long row0 = rb * R;
   const int rows_here = (int)((a.nrows - row0) < R ? (a.nrows - row0) : R);
 
   // stage twiddles, conductivities and phases (they overlap the data loads)
@@ -156,13 +159,16 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   }
 
   // pair p: component c = p / half_rows, rows 2j and 2j+1 with j = p % half_rows
-  auto pair_comp = [&](int p) -> int { return p / half_rows; };
-  auto pair_row = [&](int p) -> int { return 2 * (p - (p / half_rows) * half_rows); };
+  // (split: component c_fix, rows 2p and 2p + 1)
+  auto pair_comp = [&](int p) -> int { return a.split ? c_fix : (int)fdiv((uint32_t)p, a.fd_half); };
+  auto pair_row = [&](int p) -> int {
+    return a.split ? 2 * p : 2 * (p - (int)fdiv((uint32_t)p, a.fd_half) * half_rows);
+  };
 
   if constexpr (MODE == ROW_FWD) {
     __syncthreads();
     for (int idx = tid; idx < npairs * n; idx += NT) {
-      const int p = idx / n;
+      const int p = (int)fdiv((uint32_t)idx, a.fd_n);
       const int x = idx - p * n;
       const int c = pair_comp(p);
       const int ra = pair_row(p);
@@ -195,10 +201,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
         if (idx < total) {
           int p, k;
           if (a.row_fast) {
-            k = idx / npairs;
+            k = (int)fdiv((uint32_t)idx, a.fd_np);
             p = idx - k * npairs;
           } else {
-            p = idx / h;
+            p = (int)fdiv((uint32_t)idx, a.fd_h);
             k = idx - p * h;
           }
           pk[u] = p;
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     if constexpr (MODE == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
       for (int idx = tid; idx < npairs * n; idx += NT) {
-        const int p = idx / n;
+        const int p = (int)fdiv((uint32_t)idx, a.fd_n);
         const int x = idx - p * n;
         const int c = pair_comp(p);
         const int ra = pair_row(p);
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
     // ROW_FUSED: polarisation dL (E + u) at the nodes (Sec. 2.2, Eq. (17))
     for (int idx = tid; idx < npairs * n; idx += NT) {
-      const int p = idx / n;
+      const int p = (int)fdiv((uint32_t)idx, a.fd_n);
       const int x = idx - p * n;
       const int c = pair_comp(p);
       const int ra = pair_row(p);
@@ -276,10 +282,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   for (int idx = tid; idx < total; idx += NT) {
     int p, k;
     if (a.row_fast) {
-      k = idx / npairs;
+      k = (int)fdiv((uint32_t)idx, a.fd_np);
       p = idx - k * npairs;
     } else {
-      p = idx / h;
+      p = (int)fdiv((uint32_t)idx, a.fd_h);
       k = idx - p * h;
     }
     const int c = pair_comp(p);
@@ -327,10 +333,10 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const bool l_fast = a.sl == 1;
   auto split = [&](int idx, int& l, int& c) {
     if (l_fast) {
-      c = idx / L;
+      c = (int)fdiv((uint32_t)idx, a.fd_L);
       l = idx - c * L;
     } else {
-      l = idx / C;
+      l = (int)fdiv((uint32_t)idx, a.fd_C);
       c = idx - l * C;
     }
   };
@@ -499,7 +505,8 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       val.im += a.coef_base * b.im;
       a.out[g] = val;
       if (a.dot) {
-        const double w = half_weight((i0 + c) % a.h, n_last);
+        const uint32_t kl = (uint32_t)(i0 + c);
+        const double w = half_weight(kl - fdiv(kl, a.fd_h) * (uint32_t)a.h, n_last);
         if (a.dot == 1)
           acc += w * ((double)b.re * (double)val.re + (double)b.im * (double)val.im);
         else
@@ -569,7 +576,8 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
       r[u].im -= ta * q[u].im;
       X[i] = x[u];
       Rv[i] = r[u];
-      const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
+      const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
+      const double w = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
       acc += w * ((double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im);
     }
   }
@@ -616,7 +624,8 @@ __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
     const cx<double> r = a.r64[vo + i];
     const cx<float> f = cx<float>{(float)r.re, (float)r.im};
     a.r32[vo + i] = f;
-    const double w = half_weight((i / a.klast_div) % a.h, a.n_last);
+    const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
+    const double w = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
     acc += w * ((double)f.re * (double)f.re + (double)f.im * (double)f.im);
   }
   store_partial<256>(acc, parts.region(k & 1) + blockIdx.x);
@@ -723,10 +732,10 @@ hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipSt
   return hipGetLastError();
 }
 
-size_t row_lds_bytes(int n, int rows_per_block, int d, int elem_bytes, int n_phases, int* ss_out) {
+size_t row_lds_bytes(int n, int rows_per_block, int comps, int elem_bytes, int n_phases, int* ss_out) {
   const int ss = lds_odd_stride(n);
   if (ss_out) *ss_out = ss;
-  const int npairs = d * (rows_per_block / 2);
+  const int npairs = comps * (rows_per_block / 2);
   size_t off = align16((size_t)npairs * ss * elem_bytes);
   off = align16(off + (size_t)n * elem_bytes);
   off = align16(off + (size_t)n_phases * (size_t)(elem_bytes / 2));
@@ -741,7 +750,7 @@ size_t col_lds_bytes(int L, int tile, int d, int elem_bytes, int* ss_out) {
 
 template <typename T>
 long long row_blocks(const RowArgs<T>& a) {
-  return (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
+  return (a.split ? a.d : 1) * ((a.nrows + a.rows_per_block - 1) / a.rows_per_block);
 }
 
 template <typename T>
@@ -810,9 +819,10 @@ static void launch_col_rs(const ColArgs<T>& a, size_t lds, long long nb, int nt,
 
 template <typename T>
 hipError_t launch_row(const RowArgs<T>& a, hipStream_t s) {
-  const size_t lds = row_lds_bytes(a.n, a.rows_per_block, a.d, (int)sizeof(cx<T>), a.n_phases, nullptr);
+  const int comps = a.split ? 1 : a.d;
+  const size_t lds = row_lds_bytes(a.n, a.rows_per_block, comps, (int)sizeof(cx<T>), a.n_phases, nullptr);
   const long long nb = row_blocks(a);
-  const int nt = pick_threads(a.d * (a.rows_per_block / 2) * a.n, a.plan);
+  const int nt = pick_threads(comps * (a.rows_per_block / 2) * a.n, a.plan);
   switch (plan_radix_set(a.plan)) {
     case RADIX_POW3: launch_row_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
     case RADIX_POW2: launch_row_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;

@@ -11,6 +11,22 @@ bool fft_size_ok(int64_t n) {
   return n == 1;
 }
 
+// Per-stage divisors of the stage loop: n / radix and the product of the
+// radices already applied.
+static void finish_plan(FftPlan* p) {
+  int ns = 1;
+  for (int st = 0; st < kMaxStages; ++st) {
+    if (st < p->nstages && p->radix[st] >= 1) {
+      p->nr[st] = make_fastdiv((uint32_t)(p->n / p->radix[st]));
+      p->ns[st] = make_fastdiv((uint32_t)ns);
+      ns *= p->radix[st];
+    } else {
+      p->nr[st] = make_fastdiv(1);
+      p->ns[st] = make_fastdiv(1);
+    }
+  }
+}
+
 FftPlan default_plan(int n) {
   FftPlan p{};
   p.n = n;
@@ -29,6 +45,7 @@ FftPlan default_plan(int n) {
   if (p.nstages == 0) {  // n == 1
     p.radix[0] = 1;
   }
+  finish_plan(&p);
   return p;
 }
 
@@ -41,9 +58,11 @@ bool make_plan(int n, const int* radices, int nstages, FftPlan* plan) {
     prod *= r;
   }
   if (prod != n) return false;
+  *plan = FftPlan{};
   plan->n = n;
   plan->nstages = nstages;
   for (int i = 0; i < nstages; ++i) plan->radix[i] = radices[i];
+  finish_plan(plan);
   return true;
 }
 
@@ -65,7 +84,7 @@ constexpr int kMaxThreads = 256;
 
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
                         size_t lds_budget, long long min_blocks, bool transposed, int n_phases) {
-  PassShape s{2, 1, 1};
+  PassShape s{2, 1, 1, 0};
   const int last = d - 1;
   const int n_last = (int)N[last];
   const long long h = n_last / 2 + 1;
@@ -73,16 +92,19 @@ PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_
   for (int a = 0; a < last; ++a) nrows *= N[a];
 
   // row pass: even row counts; in the transposed layout each global access
-  // covers rows_per_block contiguous elements, so aim for 64-byte segments
+  // covers rows_per_block contiguous elements, so aim for 128-byte segments
+  // (whole cache lines) with one component per block
   {
     const int cap = plan_batch_cap(plans[last], kMaxThreads);
-    const int target = transposed ? (64 / elem_bytes < 2 ? 2 : 64 / elem_bytes) : 64;
+    s.row_split = transposed ? 1 : 0;
+    const int comps = s.row_split ? 1 : d;
+    const int target = transposed ? (128 / elem_bytes < 2 ? 2 : 128 / elem_bytes) : 64;
     int best = 2;
     for (int r = 2; r <= target; r += 2) {
-      if ((long long)d * (r / 2) * n_last > cap) break;
-      if (row_lds_bytes(n_last, r, d, elem_bytes, n_phases, nullptr) > lds_budget) break;
+      if ((long long)comps * (r / 2) * n_last > cap) break;
+      if (row_lds_bytes(n_last, r, comps, elem_bytes, n_phases, nullptr) > lds_budget) break;
       best = r;
-      if (!transposed && (long long)d * (r / 2) * n_last >= 2048) break;
+      if (!transposed && (long long)comps * (r / 2) * n_last >= 2048) break;
     }
     while (best > 2 && ceil_div(nrows, best) < min_blocks) best -= 2;
     s.rows_per_block = best;
@@ -116,10 +138,13 @@ bool shape_fits(int d, const int64_t* N, const FftPlan* plans, const PassShape& 
   const int n_last = (int)N[last];
   if (s.rows_per_block < 2 || (s.rows_per_block & 1)) return false;
   if (s.tile0 < 1 || s.tile1 < 1) return false;
+  if (s.row_split != 0 && s.row_split != 1) return false;
   {
-    const int npairs = d * (s.rows_per_block / 2);
+    const int comps = s.row_split ? 1 : d;
+    const int npairs = comps * (s.rows_per_block / 2);
     if ((long long)npairs * n_last > plan_batch_cap(plans[last], kMaxThreads)) return false;
-    if (row_lds_bytes(n_last, s.rows_per_block, d, elem_bytes, n_phases, nullptr) > lds_budget) return false;
+    if (row_lds_bytes(n_last, s.rows_per_block, comps, elem_bytes, n_phases, nullptr) > lds_budget)
+      return false;
   }
   if ((long long)d * s.tile0 * N[0] > plan_batch_cap(plans[0], kMaxThreads)) return false;
   if (col_lds_bytes((int)N[0], s.tile0, d, elem_bytes, nullptr) > lds_budget) return false;

@@ -27,6 +27,7 @@ struct PassShape {
   int rows_per_block;    // row pass (even)
   int tile0;             // axis-0 pass tile
   int tile1;             // axis-1 pass tile (3-D)
+  int row_split;         // row pass: one component per block
 };
 
 // Default shapes within the FFT batch limit (256 threads) and lds_budget

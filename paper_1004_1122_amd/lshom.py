@@ -87,6 +87,7 @@ class lshom_schedule(Structure):
         ("rows_per_block", c_int32),
         ("tile0", c_int32),
         ("tile1", c_int32),
+        ("row_split", c_int32),
         ("nstages", c_int32 * 3),
         ("radix", (c_int32 * 16) * 3),
         ("ms_per_iter", c_double),
@@ -101,6 +102,7 @@ class lshom_schedule(Structure):
             "rows_per_block": int(self.rows_per_block),
             "tile0": int(self.tile0),
             "tile1": int(self.tile1),
+            "row_split": int(self.row_split),
             "radix": [[int(self.radix[a][k]) for k in range(self.nstages[a])] for a in range(d)],
             "ms_per_iter": float(self.ms_per_iter),
         }
@@ -115,6 +117,7 @@ class lshom_schedule(Structure):
         out.rows_per_block = int(s["rows_per_block"])
         out.tile0 = int(s["tile0"])
         out.tile1 = int(s.get("tile1", 1))
+        out.row_split = int(s.get("row_split", 0))
         for a, rad in enumerate(s["radix"]):
             out.nstages[a] = len(rad)
             for k, r in enumerate(rad):
