@@ -25,6 +25,8 @@ SOURCES = [
     "plan.cpp",
     "driver.cpp",
     "lshom_api.cpp",
+    "cnn_kernels.hip",
+    "cnn.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

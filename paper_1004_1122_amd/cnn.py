@@ -1,0 +1,225 @@
+"""Python binding of include/lshom_cnn.h (the warm-start network).
+
+Argument marshalling only: parameters, activations and the optimiser state
+live in torch-owned device buffers handed to the library; every step runs in
+the HIP kernels of liblshom.so.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+from . import lshom as _ls
+
+_sig_done = False
+
+
+def _lib():
+    global _sig_done
+    lib = _ls.load()
+    if not _sig_done:
+        P = c_void_p
+        sig = {
+            "lshom_cnn_create": (c_int, [POINTER(c_void_p), c_int, P, c_int]),
+            "lshom_cnn_destroy": (None, [P]),
+            "lshom_cnn_last_error": (c_char_p, [P]),
+            "lshom_cnn_param_size": (c_int, [P, POINTER(c_int64), POINTER(c_size_t)]),
+            "lshom_cnn_set_param_buffer": (c_int, [P, P, c_size_t]),
+            "lshom_cnn_set_params": (c_int, [P, POINTER(c_float), c_int64]),
+            "lshom_cnn_get_params": (c_int, [P, POINTER(c_float), c_int64]),
+            "lshom_cnn_get_grads": (c_int, [P, POINTER(c_float), c_int64]),
+            "lshom_cnn_workspace_size": (c_int, [P, c_int, c_int, c_int, POINTER(c_size_t)]),
+            "lshom_cnn_set_workspace": (c_int, [P, P, c_size_t, c_int, c_int, c_int]),
+            "lshom_cnn_forward": (c_int, [P, P, P, c_int, c_int, c_int, P, P]),
+            "lshom_cnn_train_step": (c_int, [P, P, P, P, c_int, c_int, c_float, c_int, POINTER(c_double)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _sig_done = True
+    return lib
+
+
+class CnnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} ({status})")
+        self.status = status
+
+
+def layer_shapes(c0: int = 32):
+    """(name, weight shape, bias length) in the compact parameter order."""
+    c = [c0, 2 * c0, 4 * c0, 8 * c0]
+    s = [("enc0a", (3, 3, 2, c[0])), ("enc0b", (3, 3, c[0], c[0])), ("down0", (3, 3, c[0], c[1])),
+         ("enc1a", (3, 3, c[1], c[1])), ("enc1b", (3, 3, c[1], c[1])), ("down1", (3, 3, c[1], c[2])),
+         ("enc2a", (3, 3, c[2], c[2])), ("enc2b", (3, 3, c[2], c[2])), ("down2", (3, 3, c[2], c[3])),
+         ("bot_a", (3, 3, c[3], c[3])), ("bot_b", (3, 3, c[3], c[3]))]
+    for lev in (2, 1, 0):
+        s += [(f"up{lev}", (3, 3, c[lev + 1], c[lev])), (f"dec{lev}a", (3, 3, 2 * c[lev], c[lev])),
+              (f"dec{lev}b", (3, 3, c[lev], c[lev]))]
+    s.append(("head", (c[0], 2)))
+    return [(n, shp, shp[-1]) for n, shp in s]
+
+
+def he_init(c0: int = 32, seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, in the compact order (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for _, shp, nb in layer_shapes(c0):
+        fan_in = int(np.prod(shp[:-1]))
+        gain = 1.0 if len(shp) == 2 else 2.0
+        parts.append((rng.standard_normal(shp) * np.sqrt(gain / fan_in)).ravel())
+        parts.append(np.zeros(nb))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def pack(params: dict, c0: int = 32) -> np.ndarray:
+    """{name: [w, b]} (the oracle's layout) -> compact float32 vector."""
+    parts = []
+    for name, shp, nb in layer_shapes(c0):
+        w, b = params[name]
+        assert tuple(w.shape) == shp and len(b) == nb, name
+        parts += [np.asarray(w, np.float64).ravel(), np.asarray(b, np.float64)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unpack(vec: np.ndarray, c0: int = 32) -> dict:
+    out, k = {}, 0
+    for name, shp, nb in layer_shapes(c0):
+        n = int(np.prod(shp))
+        out[name] = [np.asarray(vec[k:k + n], np.float64).reshape(shp), np.asarray(vec[k + n:k + n + nb], np.float64)]
+        k += n + nb
+    return out
+
+
+class WarmStartNet:
+    """The U-Net of include/lshom_cnn.h on one device."""
+
+    def __init__(self, base_channels: int = 32, device: int = 0, params=None, seed: int = 0):
+        import torch
+        self.torch = torch
+        self.lib = _lib()
+        if not torch.cuda.is_available():
+            raise RuntimeError("WarmStartNet needs a GPU")
+        self.c0 = base_channels
+        self.device = torch.device("cuda", device)
+        h = c_void_p()
+        st = self.lib.lshom_cnn_create(ctypes.byref(h), device, c_void_p(torch.cuda.current_stream(self.device).cuda_stream),
+                                       base_channels)
+        if st != 0:
+            raise CnnError(st, "lshom_cnn_create failed")
+        self.h = h
+        n = c_int64()
+        nb = c_size_t()
+        self._check(self.lib.lshom_cnn_param_size(self.h, ctypes.byref(n), ctypes.byref(nb)))
+        self.n_params = int(n.value)
+        self._pbuf = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        self._check(self.lib.lshom_cnn_set_param_buffer(self.h, self._aligned(self._pbuf), int(nb.value)))
+        self._ws = None
+        self._ws_key = None
+        self.set_params(he_init(base_channels, seed) if params is None else params)
+
+    @staticmethod
+    def _aligned(t):
+        return c_void_p(t.data_ptr() + ((-t.data_ptr()) % 256))
+
+    def _check(self, st):
+        if st != 0:
+            msg = self.lib.lshom_cnn_last_error(self.h)
+            raise CnnError(st, msg.decode() if msg else "lshom_cnn error")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lshom_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # parameters ---------------------------------------------------------
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        self._check(self.lib.lshom_cnn_set_params(self.h, v.ctypes.data_as(POINTER(c_float)), v.size))
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(self.n_params, np.float32)
+        self._check(self.lib.lshom_cnn_get_params(self.h, v.ctypes.data_as(POINTER(c_float)), v.size))
+        return v
+
+    def get_grads(self) -> np.ndarray:
+        v = np.empty(self.n_params, np.float32)
+        self._check(self.lib.lshom_cnn_get_grads(self.h, v.ctypes.data_as(POINTER(c_float)), v.size))
+        return v
+
+    def save(self, path):
+        np.savez(path, params=self.get_params(), base_channels=self.c0)
+
+    @classmethod
+    def load(cls, path, device: int = 0):
+        with np.load(path, allow_pickle=False) as f:
+            return cls(int(f["base_channels"]), device, params=f["params"])
+
+    # workspace ----------------------------------------------------------
+    def _ensure_ws(self, B, N, training):
+        key = (B, N, bool(training))
+        if self._ws_key == key:
+            return
+        if self._ws_key is not None and self._ws_key[:2] == (B, N) and self._ws_key[2] and not training:
+            return  # a training workspace serves inference too
+        sz = c_size_t()
+        self._check(self.lib.lshom_cnn_workspace_size(self.h, B, N, int(training), ctypes.byref(sz)))
+        self._ws = None
+        self._ws = self.torch.empty(int(sz.value) + 256, dtype=self.torch.uint8, device=self.device)
+        self._check(self.lib.lshom_cnn_set_workspace(self.h, self._aligned(self._ws), int(sz.value), B, N, int(training)))
+        self._ws_key = key
+
+    def _inputs(self, phase, log10_rho):
+        torch = self.torch
+        ph = phase if isinstance(phase, torch.Tensor) else torch.as_tensor(np.ascontiguousarray(phase, np.uint8))
+        ph = ph.to(device=self.device, dtype=torch.uint8).contiguous()
+        if ph.dim() == 2:
+            ph = ph[None]
+        lr = torch.as_tensor(np.atleast_1d(np.asarray(log10_rho, np.float32)) if not isinstance(log10_rho, torch.Tensor)
+                             else log10_rho).to(device=self.device, dtype=torch.float32).contiguous()
+        if lr.numel() == 1 and ph.shape[0] > 1:
+            lr = lr.expand(ph.shape[0]).contiguous()
+        return ph, lr
+
+    def forward(self, phase, log10_rho, load_axis: int = 0, want_raw: bool = False):
+        """Predicted fields [B, 2, N, N] (float64, E + prediction) and
+        optionally the raw output [B, N, N, 2] (float32)."""
+        torch = self.torch
+        ph, lr = self._inputs(phase, log10_rho)
+        B, N = ph.shape[0], ph.shape[1]
+        self._ensure_ws(B, N, False)
+        e = torch.empty((B, 2, N, N), dtype=torch.float64, device=self.device)
+        raw = torch.empty((B, N, N, 2), dtype=torch.float32, device=self.device) if want_raw else None
+        self._check(self.lib.lshom_cnn_forward(self.h, c_void_p(ph.data_ptr()), c_void_p(lr.data_ptr()), B, N,
+                                               int(load_axis), c_void_p(e.data_ptr()),
+                                               c_void_p(raw.data_ptr()) if raw is not None else None))
+        return (e, raw) if want_raw else e
+
+    def train_step(self, phase, log10_rho, e_target, lr: float = 1e-3, update: bool = True) -> float:
+        """One step on a batch; e_target: FP64 [B, 2, N, N] solutions for E = e1."""
+        torch = self.torch
+        ph, lrho = self._inputs(phase, log10_rho)
+        B, N = ph.shape[0], ph.shape[1]
+        self._ensure_ws(B, N, True)
+        e = e_target.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(e.shape) != (B, 2, N, N):
+            raise ValueError(f"e_target must have shape {(B, 2, N, N)}, got {tuple(e.shape)}")
+        loss = c_double()
+        self._check(self.lib.lshom_cnn_train_step(self.h, c_void_p(ph.data_ptr()), c_void_p(lrho.data_ptr()),
+                                                  c_void_p(e.data_ptr()), B, N, float(lr), int(bool(update)),
+                                                  ctypes.byref(loss)))
+        return float(loss.value)
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_unet32.npz")

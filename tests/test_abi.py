@@ -15,8 +15,14 @@ def lib():
 
 
 def test_every_header_symbol_is_exported(lib):
-    names = lshom.header_symbols()
+    import glob
+    import os
+    names = []
+    inc = os.path.join(os.path.dirname(lshom.HEADER_PATH), "*.h")
+    for path in sorted(glob.glob(inc)):
+        names += lshom.header_symbols(path)
     assert "lshom_solve" in names and "lshom_set_microstructure" in names
+    assert "lshom_cnn_forward" in names and "lshom_cnn_train_step" in names
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
@@ -76,4 +82,17 @@ def test_create_without_gpu_fails_cleanly(lib):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert lib.lshom_create(ctypes.byref(h), 0, None) == lshom.LSHOM_ERR_HIP
+    assert not h.value
+
+
+def test_cnn_create_without_gpu_fails_cleanly(lib):
+    import ctypes
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1004_1122_amd import cnn
+    lib = cnn._lib()
+    h = ctypes.c_void_p()
+    assert lib.lshom_cnn_create(ctypes.byref(h), 0, None, 32) == lshom.LSHOM_ERR_HIP
+    assert lib.lshom_cnn_create(ctypes.byref(h), 0, None, 12) == lshom.LSHOM_ERR_INVALID_ARG
     assert not h.value
