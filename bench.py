@@ -112,6 +112,27 @@ def single_solve_times(lshom, phase_dev, reps=5, warm=2):
     return out
 
 
+def warm_start_leg(n243=8, n729=4):
+    """Time to 1e-6 from e = E and from the learned initial guess (network
+    inference included) on held-out two-phase random-field problems, plain FP64."""
+    from paper_1004_1122_amd import cnn, warmstart
+    from paper_1004_1122_amd import microstructure as ms
+    if not os.path.exists(cnn.DEFAULT_WEIGHTS):
+        return None
+    log("timing the learned warm start")
+    net = cnn.WarmStartNet.load(cnn.DEFAULT_WEIGHTS)
+    out = {"weights": os.path.relpath(cnn.DEFAULT_WEIGHTS, ROOT)}
+    for n, cnt, scale in ((243, n243, 1), (729, n729, 3)):
+        items = []
+        for i in range(cnt):
+            m = ms.warmstart_eval_problem(i, n)
+            items.append((m.phase, m.info["log10_rho"], m.cond))
+        rows = warmstart.evaluate(net, items, scale=scale, reps=3)
+        out[f"{n}x{n}"] = dict(warmstart.summarize(rows), network_grid=n // scale)
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +253,9 @@ def main():
     if not args.no_single:
         log("timing single solves to 1e-6")
         out["time_to_1e-6"] = single_solve_times(lshom, phase_dev)
+        ws = warm_start_leg()
+        if ws is not None:
+            out["warm_start"] = ws
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(m.phase, n_vox)

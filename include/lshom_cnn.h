@@ -66,12 +66,16 @@ lshom_status lshom_cnn_set_workspace(lshom_cnn* net, void* dev, size_t bytes, in
 /*
  * Prediction for batch images (phase_dev: uint8 [batch][n][n], nonzero =
  * the inclusion phase; log10_rho_dev: float [batch] contrasts).  load_axis 0
- * predicts the field of E = e1, 1 that of E = e2.  e_dev (may be NULL):
- * FP64 [batch][2][n][n], E + prediction (usable as x0_dev of lshom_solve).
- * raw_dev (may be NULL): FP32 [batch][n][n][2], the network output.
+ * predicts the field of E = e1, 1 that of E = e2.  scale 1 runs the network
+ * on the n x n image; scale 3 runs it on the n/3 x n/3 image whose pixels
+ * are the majority phase of 3 x 3 blocks and spreads each prediction over
+ * its block (the workspace is then set for n/3).  e_dev (may be NULL): FP64
+ * [batch][2][n][n], E + prediction (usable as x0_dev of lshom_solve).
+ * raw_dev (may be NULL): FP32 [batch][n/scale][n/scale][2], the network
+ * output.
  */
 lshom_status lshom_cnn_forward(lshom_cnn* net, const uint8_t* phase_dev, const float* log10_rho_dev, int batch,
-                               int n, int load_axis, double* e_dev, float* raw_dev);
+                               int n, int load_axis, int scale, double* e_dev, float* raw_dev);
 
 /*
  * One training step on a batch: target fields e_dev FP64 [batch][2][n][n]

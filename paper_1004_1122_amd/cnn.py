@@ -34,7 +34,7 @@ def _lib():
             "lshom_cnn_get_grads": (c_int, [P, POINTER(c_float), c_int64]),
             "lshom_cnn_workspace_size": (c_int, [P, c_int, c_int, c_int, POINTER(c_size_t)]),
             "lshom_cnn_set_workspace": (c_int, [P, P, c_size_t, c_int, c_int, c_int]),
-            "lshom_cnn_forward": (c_int, [P, P, P, c_int, c_int, c_int, P, P]),
+            "lshom_cnn_forward": (c_int, [P, P, P, c_int, c_int, c_int, c_int, P, P]),
             "lshom_cnn_train_step": (c_int, [P, P, P, P, c_int, c_int, c_float, c_int, POINTER(c_double)]),
         }
         for name, (res, args) in sig.items():
@@ -119,7 +119,7 @@ class WarmStartNet:
         self.n_params = int(n.value)
         self._pbuf = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
         self._check(self.lib.lshom_cnn_set_param_buffer(self.h, self._aligned(self._pbuf), int(nb.value)))
-        self._ws = None
+        self._ws_cache = {}
         self._ws_key = None
         self.set_params(he_init(base_channels, seed) if params is None else params)
 
@@ -168,17 +168,25 @@ class WarmStartNet:
 
     # workspace ----------------------------------------------------------
     def _ensure_ws(self, B, N, training):
+        """Workspaces are kept per (batch, N, training) shape; switching
+        between shapes only re-points the library."""
         key = (B, N, bool(training))
         if self._ws_key == key:
             return
-        if self._ws_key is not None and self._ws_key[:2] == (B, N) and self._ws_key[2] and not training:
-            return  # a training workspace serves inference too
-        sz = c_size_t()
-        self._check(self.lib.lshom_cnn_workspace_size(self.h, B, N, int(training), ctypes.byref(sz)))
-        self._ws = None
-        self._ws = self.torch.empty(int(sz.value) + 256, dtype=self.torch.uint8, device=self.device)
-        self._check(self.lib.lshom_cnn_set_workspace(self.h, self._aligned(self._ws), int(sz.value), B, N, int(training)))
+        if not training and (B, N, True) in self._ws_cache:
+            key = (B, N, True)  # a training workspace serves inference too
+        if key not in self._ws_cache:
+            sz = c_size_t()
+            self._check(self.lib.lshom_cnn_workspace_size(self.h, B, N, int(key[2]), ctypes.byref(sz)))
+            self._ws_cache[key] = (self.torch.empty(int(sz.value) + 256, dtype=self.torch.uint8, device=self.device),
+                                   int(sz.value))
+        buf, size = self._ws_cache[key]
+        self._check(self.lib.lshom_cnn_set_workspace(self.h, self._aligned(buf), size, B, N, int(key[2])))
         self._ws_key = key
+
+    def drop_workspaces(self):
+        self._ws_cache.clear()
+        self._ws_key = None
 
     def _inputs(self, phase, log10_rho):
         torch = self.torch
@@ -192,17 +200,18 @@ class WarmStartNet:
             lr = lr.expand(ph.shape[0]).contiguous()
         return ph, lr
 
-    def forward(self, phase, log10_rho, load_axis: int = 0, want_raw: bool = False):
+    def forward(self, phase, log10_rho, load_axis: int = 0, want_raw: bool = False, scale: int = 1):
         """Predicted fields [B, 2, N, N] (float64, E + prediction) and
-        optionally the raw output [B, N, N, 2] (float32)."""
+        optionally the raw output [B, N/scale, N/scale, 2] (float32)."""
         torch = self.torch
         ph, lr = self._inputs(phase, log10_rho)
         B, N = ph.shape[0], ph.shape[1]
-        self._ensure_ws(B, N, False)
+        nc = N // scale
+        self._ensure_ws(B, nc, False)
         e = torch.empty((B, 2, N, N), dtype=torch.float64, device=self.device)
-        raw = torch.empty((B, N, N, 2), dtype=torch.float32, device=self.device) if want_raw else None
+        raw = torch.empty((B, nc, nc, 2), dtype=torch.float32, device=self.device) if want_raw else None
         self._check(self.lib.lshom_cnn_forward(self.h, c_void_p(ph.data_ptr()), c_void_p(lr.data_ptr()), B, N,
-                                               int(load_axis), c_void_p(e.data_ptr()),
+                                               int(load_axis), int(scale), c_void_p(e.data_ptr()),
                                                c_void_p(raw.data_ptr()) if raw is not None else None))
         return (e, raw) if want_raw else e
 

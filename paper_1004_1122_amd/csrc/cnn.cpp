@@ -342,14 +342,15 @@ hipError_t cast_all(lshom_cnn* c) {
 
 // --- forward and backward ----------------------------------------------------
 
-hipError_t forward(lshom_cnn* c, const Plan& p, int B, const uint8_t* phase, const float* lr, int transpose) {
+hipError_t forward(lshom_cnn* c, const Plan& p, int B, const uint8_t* phase, const float* lr, int transpose,
+                   int scale) {
   const int c0 = c->c0;
   const int* Nl = p.Nl;
   hipError_t e;
   bf16_t* x = at<bf16_t>(c, p.x);
 #define FWD(expr)                          \
   if ((e = (expr)) != hipSuccess) return e
-  FWD(launch_make_input(B, Nl[0], phase, lr, transpose, x, c->stream));
+  FWD(launch_make_input(B, Nl[0], phase, lr, transpose, scale, x, c->stream));
   bf16_t* cat0 = at<bf16_t>(c, p.cat0);
   bf16_t* cat1 = at<bf16_t>(c, p.cat1);
   bf16_t* cat2 = at<bf16_t>(c, p.cat2);
@@ -655,19 +656,21 @@ lshom_status lshom_cnn_set_workspace(lshom_cnn* c, void* dev, size_t bytes, int 
 }
 
 lshom_status lshom_cnn_forward(lshom_cnn* c, const uint8_t* phase_dev, const float* log10_rho_dev, int batch, int n,
-                               int load_axis, double* e_dev, float* raw_dev) {
+                               int load_axis, int scale, double* e_dev, float* raw_dev) {
   if (!c || !phase_dev || !log10_rho_dev) return LSHOM_ERR_INVALID_ARG;
   if (load_axis != 0 && load_axis != 1) return fail(c, LSHOM_ERR_INVALID_ARG, "load_axis must be 0 or 1");
-  lshom_status s = check_ws(c, batch, n, false);
+  if ((scale != 1 && scale != 3) || n % scale != 0) return fail(c, LSHOM_ERR_INVALID_ARG, "scale must be 1 or 3 and divide n");
+  const int nc = n / scale;
+  lshom_status s = check_ws(c, batch, nc, false);
   if (s != LSHOM_OK) return s;
-  const Plan p = make_plan(c, batch, n, c->ws_train);
+  const Plan p = make_plan(c, batch, nc, c->ws_train);
   DeviceGuard g(c->device);
   CNN_TRY(c, order_after_user(c));
-  CNN_TRY(c, forward(c, p, batch, phase_dev, log10_rho_dev, load_axis));
+  CNN_TRY(c, forward(c, p, batch, phase_dev, log10_rho_dev, load_axis, scale));
   const float* out = at<float>(c, p.out);
-  if (e_dev) CNN_TRY(c, launch_make_field(batch, n, out, load_axis, e_dev, c->stream));
+  if (e_dev) CNN_TRY(c, launch_make_field(batch, nc, out, load_axis, scale, e_dev, c->stream));
   if (raw_dev)
-    CNN_TRY(c, hipMemcpyAsync(raw_dev, out, (size_t)batch * n * n * 2 * sizeof(float), hipMemcpyDeviceToDevice,
+    CNN_TRY(c, hipMemcpyAsync(raw_dev, out, (size_t)batch * nc * nc * 2 * sizeof(float), hipMemcpyDeviceToDevice,
                               c->stream));
   CNN_TRY(c, hipStreamSynchronize(c->stream));
   c->err.clear();
@@ -683,7 +686,7 @@ lshom_status lshom_cnn_train_step(lshom_cnn* c, const uint8_t* phase_dev, const 
   const Plan p = make_plan(c, batch, n, 1);
   DeviceGuard g(c->device);
   CNN_TRY(c, order_after_user(c));
-  CNN_TRY(c, forward(c, p, batch, phase_dev, log10_rho_dev, 0));
+  CNN_TRY(c, forward(c, p, batch, phase_dev, log10_rho_dev, 0, 1));
   double* part = at<double>(c, p.part);
   double* loss = at<double>(c, p.loss);
   CNN_TRY(c, launch_rel_mse(batch, n, at<float>(c, p.out), e_dev, part, loss, at<float>(c, p.gout), c->stream));

@@ -66,8 +66,9 @@ hipError_t launch_grad_prep(long long P, int C, int Cp, const float* g0, int ld0
 // coarse[b, I, J, c] (+)= sum over the 3 x 3 fine pixels of fine[b, 3I+p, 3J+q, c]
 hipError_t launch_pool3_sum(int B, int Hc, int Wc, int C, const float* fine, float* coarse, hipStream_t s);
 // Network input [B, N, N, 8]: phase indicator (phase != 0), log10(rho) / 4, zeros.
-// transpose: read the image transposed (load case E = e2).
-hipError_t launch_make_input(int B, int N, const uint8_t* phase, const float* log10_rho, int transpose,
+// transpose: read the image transposed (load case E = e2).  scale 3: the
+// image is 3N x 3N and pixel (i, j) is the majority of block (3i.., 3j..).
+hipError_t launch_make_input(int B, int N, const uint8_t* phase, const float* log10_rho, int transpose, int scale,
                              bf16_t* x, hipStream_t s);
 // Relative MSE of pred [B, N, N, 2] (FP32, pixel stride 2) against the
 // fluctuation of FP64 planar fields e [B][2][N][N] for E = e1; writes the
@@ -77,7 +78,8 @@ hipError_t launch_rel_mse(int B, int N, const float* pred, const double* e, doub
                           float* grad, hipStream_t s);
 // Predicted field (FP64 planar [B][2][N][N]): E + prediction; transpose maps
 // the prediction for the transposed image to the load case E = e2.
-hipError_t launch_make_field(int B, int N, const float* pred, int transpose, double* e, hipStream_t s);
+// scale 3: the field is 3N x 3N, pixel (i, j) takes prediction (i / 3, j / 3).
+hipError_t launch_make_field(int B, int N, const float* pred, int transpose, int scale, double* e, hipStream_t s);
 // Weight copies: w16[k][n] = bf16(w[k][n]); wt16 for the input gradient:
 // conv3 flips the taps (tap 8 - t) and transposes, down3 and 1x1 transpose.
 hipError_t launch_cast_weights(const float* w, int taps, int cin, int np, int flip, bf16_t* w16, bf16_t* wt16,

@@ -277,16 +277,24 @@ __global__ void pool3_sum_kernel(int B, int Hc, int Wc, int C, const float* fine
   }
 }
 
-__global__ void make_input_kernel(int B, int N, const uint8_t* phase, const float* lr, int transpose, bf16_t* x) {
+__global__ void make_input_kernel(int B, int N, const uint8_t* phase, const float* lr, int transpose, int scale,
+                                  bf16_t* x) {
   const long long n = (long long)B * N * N;
+  const int NF = N * scale;  // side of the stored image
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(e % N);
     const long long t = e / N;
     const int i = (int)(t % N);
     const int b = (int)(t / N);
-    const long long src = transpose ? ((long long)b * N + j) * N + i : e;
+    int cnt = 0;
+    for (int p = 0; p < scale; ++p)
+      for (int q = 0; q < scale; ++q) {
+        const int fi = scale * i + p, fj = scale * j + q;
+        const long long src = transpose ? ((long long)b * NF + fj) * NF + fi : ((long long)b * NF + fi) * NF + fj;
+        cnt += phase[src] != 0;
+      }
     uint4 v0 = {0u, 0u, 0u, 0u};
-    const uint32_t ph = phase[src] != 0 ? 0x3F80u : 0u;
+    const uint32_t ph = 2 * cnt > scale * scale ? 0x3F80u : 0u;
     const uint32_t rr = f2bf(lr[b] * 0.25f);
     v0.x = ph | (rr << 16);
     *reinterpret_cast<uint4*>(x + e * 8) = v0;
@@ -352,23 +360,25 @@ __global__ void mse_loss_kernel(int B, int nb, const double* part, double* loss)
   *loss = l / B;
 }
 
-__global__ void make_field_kernel(int B, int N, const float* pred, int transpose, double* e) {
-  const long long nn = (long long)N * N;
-  const long long n = (long long)B * nn;
+__global__ void make_field_kernel(int B, int N, const float* pred, int transpose, int scale, double* e) {
+  const int NF = N * scale;
+  const long long nn = (long long)N * N, nnf = (long long)NF * NF;
+  const long long n = (long long)B * nnf;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-    const int b = (int)(q / nn);
-    const long long p = q - (long long)b * nn;
-    const int i = (int)(p / N), j = (int)(p - (p / N) * N);
+    const int b = (int)(q / nnf);
+    const long long pf = q - (long long)b * nnf;
+    const int fi = (int)(pf / NF), fj = (int)(pf - (pf / NF) * NF);
+    const int i = fi / scale, j = fj / scale;
     for (int c = 0; c < 2; ++c) {
       double v;
       if (!transpose) {
-        v = (c == 0 ? 1.0 : 0.0) + (double)pred[((long long)b * nn + p) * 2 + c];
+        v = (c == 0 ? 1.0 : 0.0) + (double)pred[((long long)b * nn + (long long)i * N + j) * 2 + c];
       } else {
         // field of the load case e2 from the prediction for the transposed image
         const long long pt = (long long)j * N + i;
         v = (c == 1 ? 1.0 : 0.0) + (double)pred[((long long)b * nn + pt) * 2 + (1 - c)];
       }
-      e[((long long)b * 2 + c) * nn + p] = v;
+      e[((long long)b * 2 + c) * nnf + pf] = v;
     }
   }
 }
@@ -447,10 +457,10 @@ hipError_t launch_pool3_sum(int B, int Hc, int Wc, int C, const float* fine, flo
   return hipGetLastError();
 }
 
-hipError_t launch_make_input(int B, int N, const uint8_t* phase, const float* log10_rho, int transpose, bf16_t* x,
-                             hipStream_t s) {
+hipError_t launch_make_input(int B, int N, const uint8_t* phase, const float* log10_rho, int transpose, int scale,
+                             bf16_t* x, hipStream_t s) {
   hipLaunchKernelGGL(make_input_kernel, dim3(grid_for((long long)B * N * N)), dim3(256), 0, s, B, N, phase, log10_rho,
-                     transpose, x);
+                     transpose, scale, x);
   return hipGetLastError();
 }
 
@@ -468,9 +478,9 @@ hipError_t launch_rel_mse(int B, int N, const float* pred, const double* e, doub
   return hipGetLastError();
 }
 
-hipError_t launch_make_field(int B, int N, const float* pred, int transpose, double* e, hipStream_t s) {
-  hipLaunchKernelGGL(make_field_kernel, dim3(grid_for((long long)B * N * N)), dim3(256), 0, s, B, N, pred, transpose,
-                     e);
+hipError_t launch_make_field(int B, int N, const float* pred, int transpose, int scale, double* e, hipStream_t s) {
+  hipLaunchKernelGGL(make_field_kernel, dim3(grid_for((long long)B * N * N * scale * scale)), dim3(256), 0, s, B, N,
+                     pred, transpose, scale, e);
   return hipGetLastError();
 }
 

@@ -135,28 +135,17 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   size_t off = align16((size_t)npairs * ss * sizeof(cx<T>));
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + off);
-  off = align16(off + (size_t)n * sizeof(cx<T>));
+  off = align16(off + (size_t)twiddle_entries(n) * sizeof(cx<T>));
   T* cond = reinterpret_cast<T*>(smem_raw + off);
-  off = align16(off + (size_t)a.n_phases * sizeof(T));
-  uint8_t* ph = smem_raw + off;  // [R][n] phase bytes of this block's rows
   const int tid = threadIdx.x;
   const long long row0 = rb * R;
   const int rows_here = (int)((a.nrows - row0) < R ? (a.nrows - row0) : R);
+  // phase bytes of this block's rows, read where used (each once, coalesced)
+  const uint8_t* ph = phase + row0 * n;
 
   // stage twiddles, conductivities and phases (they overlap the data loads)
-  copy_batched<cx<T>, NT>(tw, a.tw, n);
+  copy_batched<cx<T>, NT>(tw, a.tw, twiddle_entries(n));
   copy_batched<T, NT>(cond, a.cond + (long long)pb * kCondStride, a.n_phases);
-  const bool need_phase = (MODE == ROW_FUSED) || (MODE == ROW_FWD && (a.flags & ROWF_DL)) ||
-                          (MODE == ROW_INV && (a.flags & ROWF_LEFF));
-  if (need_phase) {
-    const uint8_t* src = phase + row0 * n;
-    const int nb = rows_here * n;
-    // 4-byte loads where the row block is aligned
-    if (((reinterpret_cast<uintptr_t>(src) & 3) == 0) && ((nb & 3) == 0))
-      copy_batched<uint32_t, NT>(reinterpret_cast<uint32_t*>(ph), reinterpret_cast<const uint32_t*>(src), nb / 4);
-    else
-      copy_batched<uint8_t, NT>(ph, src, nb);
-  }
 
   // pair p: component c = p / half_rows, rows 2j and 2j+1 with j = p % half_rows
   // (split: component c_fix, rows 2p and 2p + 1)
@@ -319,7 +308,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int nseq = d * C;
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + align16((size_t)nseq * ss * sizeof(cx<T>)));
-  copy_batched<cx<T>, NT>(tw, a.tw, L);
+  copy_batched<cx<T>, NT>(tw, a.tw, twiddle_entries(L));
 
   const long long o = blockIdx.x / a.tiles_per_outer;
   const long long i0 = (long long)(blockIdx.x - o * a.tiles_per_outer) * C;
@@ -737,15 +726,14 @@ size_t row_lds_bytes(int n, int rows_per_block, int comps, int elem_bytes, int n
   if (ss_out) *ss_out = ss;
   const int npairs = comps * (rows_per_block / 2);
   size_t off = align16((size_t)npairs * ss * elem_bytes);
-  off = align16(off + (size_t)n * elem_bytes);
-  off = align16(off + (size_t)n_phases * (size_t)(elem_bytes / 2));
-  return off + (size_t)rows_per_block * n + 16;
+  off = align16(off + (size_t)twiddle_entries(n) * elem_bytes);
+  return off + (size_t)n_phases * (size_t)(elem_bytes / 2);
 }
 
 size_t col_lds_bytes(int L, int tile, int d, int elem_bytes, int* ss_out) {
   const int ss = lds_odd_stride(L);
   if (ss_out) *ss_out = ss;
-  return align16((size_t)d * tile * ss * elem_bytes) + (size_t)L * elem_bytes;
+  return align16((size_t)d * tile * ss * elem_bytes) + (size_t)twiddle_entries(L) * elem_bytes;
 }
 
 template <typename T>
