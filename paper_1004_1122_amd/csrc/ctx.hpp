@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -128,7 +129,11 @@ lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, doub
 void pass_model_bytes(const Group& g, int precision, double* out);
 
 lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg);
+// Serialises graph captures against host-staged uploads and events on the
+// caller's stream across contexts (concurrent solves on several threads).
+std::mutex& setup_mutex();
 void drop_graphs(std::map<std::pair<int, int>, hipGraphExec_t>& cache);
+void drop_batch_graphs(lshom_ctx* c);
 
 }  // namespace lshom
 
@@ -144,6 +149,9 @@ struct lshom_ctx {
   lshom::Group g;               // the single problem of set_microstructure
   size_t ws_bytes = 0;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  // iteration graphs of batched groups, per (workspace address, grid, problem
+  // count, phase count, layout); valid while the schedules stay unchanged
+  std::map<std::vector<long long>, std::map<std::pair<int, int>, hipGraphExec_t>> batch_graphs;
   std::map<lshom::SchedKey, lshom::Schedule> schedules;  // autotuned or set by the caller
   lshom::PassTimer timer;
 };

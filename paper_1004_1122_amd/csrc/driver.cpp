@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <mutex>
+
 #include "ctx.hpp"
 
 namespace lshom {
@@ -19,6 +21,11 @@ lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg) {
 void drop_graphs(std::map<std::pair<int, int>, hipGraphExec_t>& cache) {
   for (auto& kv : cache) (void)hipGraphExecDestroy(kv.second);
   cache.clear();
+}
+
+void drop_batch_graphs(lshom_ctx* c) {
+  for (auto& kv : c->batch_graphs) drop_graphs(kv.second);
+  c->batch_graphs.clear();
 }
 
 namespace {
@@ -126,6 +133,14 @@ Layout compute_layout(const Group& g, bool with32) {
   }
   L.total = off;
   return L;
+}
+
+// Work that must not overlap another context's stream capture (host-staged
+// uploads, events on the caller's stream) and the captures themselves are
+// serialised process-wide.
+std::mutex& setup_mutex() {
+  static std::mutex m;
+  return m;
 }
 
 namespace {
@@ -587,6 +602,7 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       if (it != g.graph_cache->end()) ex = it->second;
     }
     if (!ex) {
+      std::lock_guard<std::mutex> lock(setup_mutex());
       hipGraph_t gr = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(stream_of(g), hipStreamCaptureModeThreadLocal));
       hipError_t e = enqueue_block();
@@ -641,7 +657,19 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
                                const std::vector<const uint8_t*>& phases) {
   lshom_ctx* c = g.ctx;
   const Layout& use = g.lay;
+  // uploads are ordered on the group's stream (no legacy-stream copies that
+  // could disturb a graph capture of another context); the host staging
+  // vectors below outlive them: the guard synchronises on every return path
+  std::lock_guard<std::mutex> lock(setup_mutex());
+  struct SyncOnExit {
+    hipStream_t s;
+    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+  };
+  std::vector<std::vector<double>> tw64(g.d);
+  std::vector<std::vector<float>> tw32(g.d);
   const int np = g.nprob;
+  std::vector<DevState> zero(np);
+  unsigned host_max = 0;
   std::vector<double> c64((size_t)kCondStride * np, 0.0);
   std::vector<float> c32((size_t)kCondStride * np, 0.0f);
   for (int p = 0; p < np; ++p)
@@ -649,29 +677,30 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
       c64[(size_t)p * kCondStride + i] = cond[(size_t)p * g.n_phases + i];
       c32[(size_t)p * kCondStride + i] = (float)cond[(size_t)p * g.n_phases + i];
     }
-  HIP_TRY(c, hipMemcpy(g.ws + use.off_cond64, c64.data(), c64.size() * sizeof(double), hipMemcpyHostToDevice));
-  HIP_TRY(c, hipMemcpy(g.ws + use.off_cond32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_cond64, c64.data(), c64.size() * sizeof(double), hipMemcpyHostToDevice, stream_of(g)));
+  HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_cond32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice, stream_of(g)));
   for (int a = 0; a < g.d; ++a) {
-    std::vector<double> tw;
-    twiddles((int)g.N[a], &tw);
-    std::vector<float> tw32(tw.size());
-    for (size_t i = 0; i < tw.size(); ++i) tw32[i] = (float)tw[i];
-    HIP_TRY(c, hipMemcpy(g.ws + use.off_tw64[a], tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(g.ws + use.off_tw32[a], tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    twiddles((int)g.N[a], &tw64[a]);
+    tw32[a].resize(tw64[a].size());
+    for (size_t i = 0; i < tw64[a].size(); ++i) tw32[a][i] = (float)tw64[a][i];
+    HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_tw64[a], tw64[a].data(), tw64[a].size() * sizeof(double),
+                              hipMemcpyHostToDevice, stream_of(g)));
+    HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_tw32[a], tw32[a].data(), tw32[a].size() * sizeof(float),
+                              hipMemcpyHostToDevice, stream_of(g)));
   }
   if (tab)
-    HIP_TRY(c, hipMemcpy(g.ws + use.off_tab, tab->data(), tab->size() * sizeof(ProbEntry), hipMemcpyHostToDevice));
-  std::vector<DevState> zero(np);
-  HIP_TRY(c, hipMemcpy(g.ws + use.off_state, zero.data(), sizeof(DevState) * np, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_tab, tab->data(), tab->size() * sizeof(ProbEntry), hipMemcpyHostToDevice, stream_of(g)));
+  SyncOnExit sync_guard{stream_of(g)};
+  HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_state, zero.data(), sizeof(DevState) * np, hipMemcpyHostToDevice,
+                            stream_of(g)));
   g.host_states.assign(np, DevState{});
   // every phase index must name a conductivity
   unsigned* mx = reinterpret_cast<unsigned*>(g.ws + use.off_scratch);
   for (const uint8_t* ph : phases) {
-    unsigned host_max = 0;
-    HIP_TRY(c, hipMemcpy(mx, &host_max, sizeof(unsigned), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemsetAsync(mx, 0, sizeof(unsigned), stream_of(g)));
     HIP_TRY(c, launch_max_phase(ph, g.nvox, mx, stream_of(g)));
+    HIP_TRY(c, hipMemcpyAsync(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost, stream_of(g)));
     HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
-    HIP_TRY(c, hipMemcpy(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (host_max >= (unsigned)g.n_phases)
       return fail(c, LSHOM_ERR_INVALID_ARG, "phase image holds an index >= n_phases");
   }

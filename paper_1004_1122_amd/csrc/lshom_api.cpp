@@ -69,6 +69,7 @@ void fill_info(const DevState& hs, double l0, const lshom_solve_opts& o, int war
 }
 
 hipError_t order_after_user(lshom_ctx* c) {
+  std::lock_guard<std::mutex> lock(setup_mutex());
   hipError_t e = hipEventRecord(c->ev, c->user_stream);
   if (e != hipSuccess) return e;
   return hipStreamWaitEvent(c->stream, c->ev, 0);
@@ -163,6 +164,7 @@ void lshom_destroy(lshom_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   drop_graphs(c->graphs);
+  drop_batch_graphs(c);
   for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
   if (c->ev) (void)hipEventDestroy(c->ev);
   if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -179,6 +181,7 @@ lshom_status lshom_set_microstructure(lshom_ctx* c, int d, const int64_t* N,
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   drop_graphs(c->graphs);
+  drop_batch_graphs(c);
   c->ws_ready = false;
   c->have_problem = false;
   c->g = Group{};
@@ -205,7 +208,8 @@ lshom_status lshom_set_reference(lshom_ctx* c, double l0) {
   if (!std::isfinite(l0) || !(l0 > 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "l0 must be finite and > 0");
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
-  drop_graphs(c->graphs);  // l0 is baked into captured launches
+  drop_graphs(c->graphs);
+  drop_batch_graphs(c);  // l0 is baked into captured launches
   c->g.l0 = l0;
   return LSHOM_OK;
 }
@@ -233,6 +237,7 @@ lshom_status lshom_set_workspace(lshom_ctx* c, void* dev, size_t bytes) {
   DeviceGuard g(c->device);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   drop_graphs(c->graphs);
+  drop_batch_graphs(c);
   c->ws_ready = false;
   c->g.ws = static_cast<char*>(dev);
   c->ws_bytes = bytes;
@@ -420,10 +425,11 @@ lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const l
     if (np >= g.n_phases) continue;
     std::vector<double> bad((size_t)(g.n_phases - np), std::nan(""));
     std::vector<float> badf(bad.size(), std::nanf(""));
-    HIP_TRY(c, hipMemcpy(g.ws + g.lay.off_cond64 + ((size_t)j * kCondStride + np) * sizeof(double),
-                         bad.data(), bad.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(g.ws + g.lay.off_cond32 + ((size_t)j * kCondStride + np) * sizeof(float),
-                         badf.data(), badf.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpyAsync(g.ws + g.lay.off_cond64 + ((size_t)j * kCondStride + np) * sizeof(double),
+                              bad.data(), bad.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(g.ws + g.lay.off_cond32 + ((size_t)j * kCondStride + np) * sizeof(float),
+                              badf.data(), badf.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   return LSHOM_OK;
 }
@@ -505,6 +511,11 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
     std::vector<ProbEntry> tab;
     std::vector<DevState> init;
     if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tab, &init)) != LSHOM_OK) return s;
+    if (c->batch_graphs.size() > 64) drop_batch_graphs(c);
+    const std::vector<long long> tag = {(long long)reinterpret_cast<uintptr_t>(g.ws), g.d, (long long)g.N[0],
+                                        (long long)g.N[1], (long long)g.N[2], g.nprob, g.n_phases,
+                                        (long long)g.lay.total, g.lay.has32 ? 1 : 0};
+    g.graph_cache = &c->batch_graphs[tag];
     if ((s = solve_group(g, init, o, nullptr, nullptr, nullptr)) != LSHOM_OK) return s;
     const std::vector<int>& mem = bp.members[gi];
     for (int j = 0; j < g.nprob; ++j) {
@@ -548,6 +559,7 @@ lshom_status lshom_set_schedule(lshom_ctx* c, const lshom_schedule* in) {
     DeviceGuard dg(c->device);
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c->graphs);
+  drop_batch_graphs(c);
     apply_schedule(c->g, s, in->precision);
   }
   c->err.clear();
@@ -563,6 +575,7 @@ lshom_status lshom_autotune(lshom_ctx* c, int precision, int reps, lshom_schedul
   DeviceGuard dg(c->device);
   HIP_TRY(c, order_after_user(c));
   drop_graphs(c->graphs);
+  drop_batch_graphs(c);
   Schedule tuned;
   if ((s = autotune_group(c->g, precision, reps, &tuned)) != LSHOM_OK) return s;
   apply_schedule(c->g, tuned, precision);
@@ -607,6 +620,7 @@ lshom_status lshom_autotune_batched(lshom_ctx* c, int32_t n, const lshom_problem
     c->schedules[SchedKey(g.d, g.N[0], g.N[1], g.N[2], precision)] = tuned;
     if (best && (int)gi < cap) to_c_schedule(g, tuned, precision, &best[gi]);
   }
+  drop_batch_graphs(c);  // captured with the previous schedules
   if (n_best) *n_best = (int32_t)bp.groups.size();
   c->err.clear();
   return LSHOM_OK;
