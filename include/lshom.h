@@ -196,7 +196,8 @@ lshom_status lshom_solve_batched(lshom_ctx* ctx, int32_t n, const lshom_problem*
  * axis's FFT (product = N[a]; radices 2..9) and the pass shapes (rows of the
  * last axis per row-pass block, an even number; whether a row-pass block
  * holds one component (row_split = 1) or all d; column tiles of the axis-0
- * and axis-1 passes).  Results do not depend on the schedule beyond
+ * and axis-1 passes; block sizes of the row and axis passes, 128 or 256
+ * threads, 0 for the smallest that holds the batch).  Results do not depend on the schedule beyond
  * floating-point rounding.
  */
 typedef struct lshom_schedule {
@@ -207,6 +208,8 @@ typedef struct lshom_schedule {
   int32_t tile0;
   int32_t tile1;
   int32_t row_split;
+  int32_t threads_row;
+  int32_t threads_col;
   int32_t nstages[3];
   int32_t radix[3][16];
   double ms_per_iter;  /* autotuned device time of one CG iteration's passes (0: not measured) */

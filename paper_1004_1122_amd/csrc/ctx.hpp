@@ -83,7 +83,7 @@ struct Group {
   int h = 0;
   bool transposed = false;      // 2-D spectral arrays stored [k1][k0]
   FftPlan plan64[3], plan32[3];
-  PassShape shape64{2, 1, 1, 0}, shape32{2, 1, 1, 0};
+  PassShape shape64{2, 1, 1, 0, 0, 0}, shape32{2, 1, 1, 0, 0, 0};
   int n_phases = 1;             // conductivity entries staged per problem
   // single problem (nprob == 1, batched == false)
   const uint8_t* phase = nullptr;

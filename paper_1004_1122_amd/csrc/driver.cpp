@@ -260,6 +260,7 @@ ColArgs<T> col0_args(Group& g, const Bufs<T>& b) {
   a.fd_L = make_fastdiv((uint32_t)a.L);
   a.fd_C = make_fastdiv((uint32_t)a.tile);
   a.fd_h = make_fastdiv((uint32_t)g.h);
+  a.nt = b.shape.threads_col;
   for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
@@ -292,6 +293,7 @@ ColArgs<T> col1_args(Group& g, const Bufs<T>& b, int dir) {
   a.fd_L = make_fastdiv((uint32_t)a.L);
   a.fd_C = make_fastdiv((uint32_t)a.tile);
   a.fd_h = make_fastdiv((uint32_t)g.h);
+  a.nt = b.shape.threads_col;
   for (int t = 0; t < g.d; ++t) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
@@ -321,6 +323,7 @@ RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
   a.rows_per_block = b.shape.rows_per_block;
   a.d = g.d;
   a.split = b.shape.row_split;
+  a.nt = b.shape.threads_row;
   const int comps = a.split ? 1 : a.d;
   row_lds_bytes(a.n, a.rows_per_block, comps, (int)sizeof(cx<T>), g.n_phases, &a.ss);
   a.fd_n = make_fastdiv((uint32_t)a.n);
@@ -986,10 +989,40 @@ lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best) {
     for (const FftPlan& pl : plan_candidates((int)g.N[last])) {
       for (int split = 0; split <= 1; ++split) {
         for (int r = 2; r <= 32; r += 2) {
+         for (int nt : {0, 256}) {
           Schedule s = cur;
           s.plan[last] = pl;
           s.shape.rows_per_block = r;
           s.shape.row_split = split;
+          s.shape.threads_row = nt;
+          if (!schedule_fits(g, s, precision)) continue;
+          const double t = time_of(s, mask);
+          if (st != LSHOM_OK) return st;
+          if (t < best_t) {
+            best_t = t;
+            bs = s;
+          }
+         }
+        }
+      }
+    }
+    cur.plan[last] = bs.plan[last];
+    cur.shape.rows_per_block = bs.shape.rows_per_block;
+    cur.shape.row_split = bs.shape.row_split;
+    cur.shape.threads_row = bs.shape.threads_row;
+  }
+  // axis-0 passes (inverse with the direction step, forward with the projection)
+  if (last != 0) {
+    const unsigned mask = (1u << LSHOM_PASS_AXIS0_INVERSE) | (1u << LSHOM_PASS_AXIS0_FORWARD);
+    double best_t = 1e300;
+    Schedule bs = cur;
+    for (const FftPlan& pl : plan_candidates((int)g.N[0])) {
+      for (int t0 = 1; t0 <= 16; t0 *= 2) {
+        for (int nt : {0, 256}) {
+          Schedule s = cur;
+          s.plan[0] = pl;
+          s.shape.tile0 = t0;
+          s.shape.threads_col = nt;
           if (!schedule_fits(g, s, precision)) continue;
           const double t = time_of(s, mask);
           if (st != LSHOM_OK) return st;
@@ -1000,31 +1033,9 @@ lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best) {
         }
       }
     }
-    cur.plan[last] = bs.plan[last];
-    cur.shape.rows_per_block = bs.shape.rows_per_block;
-    cur.shape.row_split = bs.shape.row_split;
-  }
-  // axis-0 passes (inverse with the direction step, forward with the projection)
-  if (last != 0) {
-    const unsigned mask = (1u << LSHOM_PASS_AXIS0_INVERSE) | (1u << LSHOM_PASS_AXIS0_FORWARD);
-    double best_t = 1e300;
-    Schedule bs = cur;
-    for (const FftPlan& pl : plan_candidates((int)g.N[0])) {
-      for (int t0 = 1; t0 <= 16; t0 *= 2) {
-        Schedule s = cur;
-        s.plan[0] = pl;
-        s.shape.tile0 = t0;
-        if (!schedule_fits(g, s, precision)) continue;
-        const double t = time_of(s, mask);
-        if (st != LSHOM_OK) return st;
-        if (t < best_t) {
-          best_t = t;
-          bs = s;
-        }
-      }
-    }
     cur.plan[0] = bs.plan[0];
     cur.shape.tile0 = bs.shape.tile0;
+    cur.shape.threads_col = bs.shape.threads_col;
   }
   // axis-1 passes (3-D)
   if (g.d == 3) {

@@ -122,6 +122,7 @@ struct RowArgs {
   int rows_per_block;    // even
   int d;
   int split;             // one component per block
+  int nt;                // block size (0: chosen by the launcher)
   int mode, flags;
   int ss;                // LDS stride between sequences (odd, >= n)
   long long rs_row, rs_k;
@@ -166,6 +167,7 @@ struct ColArgs {
   long long sl, sii;
   int tile;
   int tiles_per_outer;
+  int nt;                // block size (0: chosen by the launcher)
   int d;
   int mode, dir;
   int ss;

@@ -443,6 +443,8 @@ void to_c_schedule(const Group& g, const Schedule& s, int precision, lshom_sched
   out->tile0 = s.shape.tile0;
   out->tile1 = s.shape.tile1;
   out->row_split = s.shape.row_split;
+  out->threads_row = s.shape.threads_row;
+  out->threads_col = s.shape.threads_col;
   for (int a = 0; a < g.d; ++a) {
     out->nstages[a] = s.plan[a].nstages;
     for (int k = 0; k < s.plan[a].nstages; ++k) out->radix[a][k] = s.plan[a].radix[k];
@@ -463,6 +465,8 @@ lshom_status from_c_schedule(lshom_ctx* c, const lshom_schedule* in, Schedule* s
   s->shape.tile0 = in->tile0;
   s->shape.tile1 = in->d == 3 ? in->tile1 : 1;
   s->shape.row_split = in->row_split;
+  s->shape.threads_row = in->threads_row;
+  s->shape.threads_col = in->threads_col;
   s->ms_per_iter = in->ms_per_iter;
   return LSHOM_OK;
 }
@@ -653,10 +657,11 @@ lshom_status lshom_save_schedules(lshom_ctx* c, const char* path) {
     const int prec = std::get<4>(kv.first);
     const Schedule& s = kv.second;
     std::fprintf(f, "{\"arch\": \"%s\", \"d\": %d, \"N\": [%lld, %lld, %lld], \"precision\": %d, "
-                    "\"rows_per_block\": %d, \"row_split\": %d, \"tile0\": %d, \"tile1\": %d, \"radix\": [",
+                    "\"rows_per_block\": %d, \"row_split\": %d, \"threads_row\": %d, \"threads_col\": %d, "
+                    "\"tile0\": %d, \"tile1\": %d, \"radix\": [",
                  arch.c_str(), d, (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
-                 (long long)std::get<3>(kv.first), prec, s.shape.rows_per_block, s.shape.row_split, s.shape.tile0,
-                 s.shape.tile1);
+                 (long long)std::get<3>(kv.first), prec, s.shape.rows_per_block, s.shape.row_split,
+                 s.shape.threads_row, s.shape.threads_col, s.shape.tile0, s.shape.tile1);
     for (int a = 0; a < d; ++a) {
       std::fprintf(f, "%s[", a ? ", " : "");
       for (int k = 0; k < s.plan[a].nstages; ++k) std::fprintf(f, "%s%d", k ? ", " : "", s.plan[a].radix[k]);
@@ -720,7 +725,7 @@ lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
     std::string line(buf);
     if (line.find('{') == std::string::npos) continue;
     if (line.find("\"arch\": \"" + arch + "\"") == std::string::npos) continue;
-    std::vector<long long> d, N, prec, rows, t0, t1, radix, split;
+    std::vector<long long> d, N, prec, rows, t0, t1, radix, split, ntr, ntc;
     if (!json_ints(line, "d", &d) || !json_ints(line, "N", &N) || !json_ints(line, "precision", &prec) ||
         !json_ints(line, "rows_per_block", &rows) || !json_ints(line, "tile0", &t0) ||
         !json_ints(line, "tile1", &t1) || d.size() != 1 || N.size() != 3) {
@@ -736,6 +741,8 @@ lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
     in.tile0 = (int)t0[0];
     in.tile1 = (int)t1[0];
     in.row_split = (json_ints(line, "row_split", &split) && split.size() == 1) ? (int)split[0] : 0;
+    in.threads_row = (json_ints(line, "threads_row", &ntr) && ntr.size() == 1) ? (int)ntr[0] : 0;
+    in.threads_col = (json_ints(line, "threads_col", &ntc) && ntc.size() == 1) ? (int)ntc[0] : 0;
     // radix lists: split the bracketed value by inner brackets
     const size_t rp = line.find("\"radix\"");
     if (rp == std::string::npos) {

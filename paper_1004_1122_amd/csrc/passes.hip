@@ -810,7 +810,7 @@ hipError_t launch_row(const RowArgs<T>& a, hipStream_t s) {
   const int comps = a.split ? 1 : a.d;
   const size_t lds = row_lds_bytes(a.n, a.rows_per_block, comps, (int)sizeof(cx<T>), a.n_phases, nullptr);
   const long long nb = row_blocks(a);
-  const int nt = pick_threads(comps * (a.rows_per_block / 2) * a.n, a.plan);
+  const int nt = a.nt ? a.nt : pick_threads(comps * (a.rows_per_block / 2) * a.n, a.plan);
   switch (plan_radix_set(a.plan)) {
     case RADIX_POW3: launch_row_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
     case RADIX_POW2: launch_row_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;
@@ -823,7 +823,7 @@ template <typename T>
 hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
   const size_t lds = col_lds_bytes(a.L, a.tile, a.d, (int)sizeof(cx<T>), nullptr);
   const long long nb = col_blocks(a);
-  const int nt = pick_threads(a.d * a.tile * a.L, a.plan);
+  const int nt = a.nt ? a.nt : pick_threads(a.d * a.tile * a.L, a.plan);
   switch (plan_radix_set(a.plan)) {
     case RADIX_POW3: launch_col_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
     case RADIX_POW2: launch_col_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;

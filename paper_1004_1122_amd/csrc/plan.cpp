@@ -84,7 +84,7 @@ constexpr int kMaxThreads = 256;
 
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
                         size_t lds_budget, long long min_blocks, bool transposed, int n_phases) {
-  PassShape s{2, 1, 1, 0};
+  PassShape s{2, 1, 1, 0, 0, 0};
   const int last = d - 1;
   const int n_last = (int)N[last];
   const long long h = n_last / 2 + 1;
@@ -139,6 +139,13 @@ bool shape_fits(int d, const int64_t* N, const FftPlan* plans, const PassShape& 
   if (s.rows_per_block < 2 || (s.rows_per_block & 1)) return false;
   if (s.tile0 < 1 || s.tile1 < 1) return false;
   if (s.row_split != 0 && s.row_split != 1) return false;
+  auto nt_ok = [](int t) { return t == 0 || t == 128 || t == kMaxThreads; };
+  if (!nt_ok(s.threads_row) || !nt_ok(s.threads_col)) return false;
+  // a forced 128-thread block must still hold its batch
+  auto cap_ok = [&](int t, long long points, const FftPlan& pl) { return t != 128 || points <= plan_batch_cap(pl, 128); };
+  if (!cap_ok(s.threads_row, (long long)(s.row_split ? 1 : d) * (s.rows_per_block / 2) * n_last, plans[last])) return false;
+  if (!cap_ok(s.threads_col, (long long)d * s.tile0 * N[0], plans[0])) return false;
+  if (d == 3 && !cap_ok(s.threads_col, (long long)d * s.tile1 * N[1], plans[1])) return false;
   {
     const int comps = s.row_split ? 1 : d;
     const int npairs = comps * (s.rows_per_block / 2);

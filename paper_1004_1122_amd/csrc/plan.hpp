@@ -28,6 +28,8 @@ struct PassShape {
   int tile0;             // axis-0 pass tile
   int tile1;             // axis-1 pass tile (3-D)
   int row_split;         // row pass: one component per block
+  int threads_row;       // block size of the row pass (0: smallest that holds the batch)
+  int threads_col;       // block size of the axis passes (0: as above)
 };
 
 // Default shapes within the FFT batch limit (256 threads) and lds_budget

@@ -88,6 +88,8 @@ class lshom_schedule(Structure):
         ("tile0", c_int32),
         ("tile1", c_int32),
         ("row_split", c_int32),
+        ("threads_row", c_int32),
+        ("threads_col", c_int32),
         ("nstages", c_int32 * 3),
         ("radix", (c_int32 * 16) * 3),
         ("ms_per_iter", c_double),
@@ -103,6 +105,8 @@ class lshom_schedule(Structure):
             "tile0": int(self.tile0),
             "tile1": int(self.tile1),
             "row_split": int(self.row_split),
+            "threads_row": int(self.threads_row),
+            "threads_col": int(self.threads_col),
             "radix": [[int(self.radix[a][k]) for k in range(self.nstages[a])] for a in range(d)],
             "ms_per_iter": float(self.ms_per_iter),
         }
@@ -118,6 +122,8 @@ class lshom_schedule(Structure):
         out.tile0 = int(s["tile0"])
         out.tile1 = int(s.get("tile1", 1))
         out.row_split = int(s.get("row_split", 0))
+        out.threads_row = int(s.get("threads_row", 0))
+        out.threads_col = int(s.get("threads_col", 0))
         for a, rad in enumerate(s["radix"]):
             out.nstages[a] = len(rad)
             for k, r in enumerate(rad):

@@ -66,6 +66,14 @@ def test_set_schedule_rejects_invalid():
         s.set_schedule(dict(good, rows_per_block=4096))
     with pytest.raises(lshom.LshomError):
         s.set_schedule(dict(good, radix=[[27], good["radix"][1]]))  # radix above 9
+    with pytest.raises(lshom.LshomError):
+        s.set_schedule(dict(good, threads_row=64))
+    # forced 256-thread blocks are accepted and give the same field up to rounding
+    e0, _, _ = s.solve((1.0, 0.0), tol=1e-10)
+    s.set_schedule(dict(good, threads_row=256, threads_col=256))
+    assert s.get_schedule(0)["threads_row"] == 256
+    e1, _, _ = s.solve((1.0, 0.0), tol=1e-10)
+    assert float((e1 - e0).norm() / e0.norm()) < 1e-12
     # a valid reordering is accepted and applied
     s.set_schedule(dict(good, radix=[[3, 9], [9, 3]], rows_per_block=6))
     now = s.get_schedule(0)
