@@ -114,7 +114,8 @@ template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int pb = blockIdx.y;
   DevState* st = a.st + pb;
-  if (gated_out(st, a.gate)) return;
+  // the flags a row pass gates on are written only by earlier launches
+  if (gated_out_stable(st, a.gate)) return;
   const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
   const long long vo = (long long)pb * a.bt.vstride;
   Partials parts = a.parts;
@@ -143,9 +144,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   // phase bytes of this block's rows, read where used (each once, coalesced)
   const uint8_t* ph = phase + row0 * n;
 
-  // stage twiddles, conductivities and phases (they overlap the data loads)
-  copy_batched<cx<T>, NT>(tw, a.tw, twiddle_entries(n));
-  copy_batched<T, NT>(cond, a.cond + (long long)pb * kCondStride, a.n_phases);
+  const int ntw = twiddle_entries(n);
+  const T* csrc = a.cond + (long long)pb * kCondStride;
 
   // pair p: component c = p / half_rows, rows 2j and 2j+1 with j = p % half_rows
   // (split: component c_fix, rows 2p and 2p + 1)
@@ -155,6 +155,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   };
 
   if constexpr (MODE == ROW_FWD) {
+    copy_batched<cx<T>, NT>(tw, a.tw, ntw);
+    copy_batched<T, NT>(cond, csrc, a.n_phases);
     __syncthreads();
     for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = (int)fdiv((uint32_t)idx, a.fd_n);
@@ -204,6 +206,25 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           if (ra < rows_here) sa[u] = sp[(row0 + ra) * a.rs_row + k * a.rs_k];
           if (ra + 1 < rows_here) sb[u] = sp[(row0 + ra + 1) * a.rs_row + k * a.rs_k];
         }
+      }
+      if (base == 0) {
+        // twiddles and conductivities, requested while the first data chunk
+        // is in flight
+        auto ldtw = [&](int i) -> cx<T> {
+          if (i < ntw) {
+            const cx<T>* q = a.tw + i;
+            return cx<T>{q->re, q->im};
+          }
+          return cx<T>{T(0), T(0)};
+        };
+        const cx<T> tw0 = ldtw(tid);
+        const cx<T> tw1 = ldtw(tid + NT);
+        const T cd0 = tid < a.n_phases ? csrc[tid] : T(0);
+        if (tid < ntw) tw[tid] = tw0;
+        if (tid + NT < ntw) tw[tid + NT] = tw1;
+        for (int i = tid + 2 * NT; i < ntw; i += NT) tw[i] = a.tw[i];
+        if (tid < a.n_phases) cond[tid] = cd0;
+        for (int i = tid + NT; i < a.n_phases; i += NT) cond[i] = csrc[i];
       }
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
@@ -298,7 +319,11 @@ template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int pb = blockIdx.y;
   DevState* st = a.st + pb;
-  if (gated_out(st, a.gate)) return;
+  // the direction step of the inverse pass reads its gate with the (r, r)
+  // sums (block 0 of the same launch may set the flags); the other modes
+  // see flags that only earlier launches write
+  constexpr bool kDirGate = MODE == COL_INV_C;
+  if (!(kDirGate && a.cg_step) && gated_out_stable(st, a.gate)) return;
   const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
@@ -332,7 +357,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 
   if constexpr (MODE == COL_INV_C) {
     double beta = 0.0;
-    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta)) return;
+    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate)) return;
     const T tb = (T)beta;
     const int total = L * C;
     for (int base = 0; base < total; base += NT * kBatch) {
@@ -519,13 +544,18 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
   const int pb = blockIdx.y;
   DevState* st = a.st + pb;
-  if (gated_out(st, a.gate)) return;
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
   const long long vo = (long long)pb * a.bt.vstride;
+  // gate, iteration index and both sums in one reduction (block 0 of this
+  // launch sets the done flag on a breakdown)
+  const int skip0 = gate_flags(st, a.gate);
   const int k = st->iter_u;
-  const double rr = sum_partials<NT>(parts.region(k & 1), st->nparts[k & 1]) * a.inv_n;
-  const double pq = sum_partials<NT>(parts.region(PART_PQ), a.n_pq) * a.inv_n;
+  double sums[2] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
+                    partial_share<NT>(parts.region(PART_PQ), a.n_pq)};
+  if (block_sums_gated<NT, 2>(sums, skip0)) return;
+  const double rr = sums[0] * a.inv_n;
+  const double pq = sums[1] * a.inv_n;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (lead) {

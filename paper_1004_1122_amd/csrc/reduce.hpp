@@ -67,17 +67,86 @@ __device__ __forceinline__ bool gated_out(const DevState* st, int gate) {
   return skip != 0;
 }
 
+// Gate of a pass whose flags only earlier launches write (the row pass and the
+// forward axis-0 pass): every wave reads the same values, so each decides on
+// its own and no block barrier delays the first loads.
+__device__ __forceinline__ bool gated_out_stable(const DevState* st, int gate) {
+  if (gate == GATE_ALWAYS) return false;
+  const int done = st->done;
+  const int refresh = st->refresh;
+  if (gate == GATE_ACTIVE) return done != 0;
+  if (gate == GATE_REFRESH) return done != 0 || refresh == 0;
+  return done != 0 || refresh != 0;  // GATE_NO_REFRESH
+}
+
+// Thread 0's reading of the entry flags (nonzero: skip the kernel).
+__device__ __forceinline__ int gate_flags(const DevState* st, int gate) {
+  if (gate == GATE_ALWAYS || threadIdx.x != 0) return 0;
+  const int done = st->done;
+  const int refresh = st->refresh;
+  if (gate == GATE_ACTIVE) return done != 0;
+  if (gate == GATE_REFRESH) return done != 0 || refresh == 0;
+  return done != 0 || refresh != 0;  // GATE_NO_REFRESH
+}
+
+// This thread's share of the sum of p[0..n).
+template <int NT>
+__device__ __forceinline__ double partial_share(const double* p, int n) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) acc += p[i];
+  return acc;
+}
+
+// Block sums of NS values together with thread 0's gate decision: one pass of
+// barriers, and every wave leaves with the same sums and the same decision.
+// Returns true when the block must skip the kernel.
+template <int NT, int NS>
+__device__ __forceinline__ bool block_sums_gated(double (&v)[NS], int skip0) {
+  __shared__ double red[NS][NT / 64];
+  __shared__ double total[NS];
+  __shared__ int skip;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[s] += __shfl_down(v[s], off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) red[s][threadIdx.x >> 6] = v[s];
+  }
+  if (threadIdx.x == 0) skip = skip0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT / 64; ++i) t += red[s][i];
+      total[s] = t;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NS; ++s) v[s] = total[s];
+  return skip != 0;
+}
+
 // The CG direction step (start of iteration k = iter_a): convergence test on
 // (r_k, r_k), iteration limit, and beta = (r_k, r_k) / (r_{k-1}, r_{k-1}).
 // Mixed precision requests an FP64 refresh instead of stopping.  Returns
 // false when the block must not compute the iteration.  Identical decision
 // in every block; block 0 records it.
+// The entry gate is read with the sums: a block it sends back returns false
+// without touching the state.
 template <int NT>
-__device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, double* beta_out) {
+__device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, double* beta_out, int gate) {
+  const int skip0 = gate_flags(st, gate);
   const int k = st->iter_a;
-  const double rr = sum_partials<NT>(parts.region(k & 1), st->nparts[k & 1]) * inv_n;
-  double rr_prev = 0.0;
-  if (k > 0) rr_prev = sum_partials<NT>(parts.region((k + 1) & 1), st->nparts[(k + 1) & 1]) * inv_n;
+  double v[2] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
+                 k > 0 ? partial_share<NT>(parts.region((k + 1) & 1), st->nparts[(k + 1) & 1]) : 0.0};
+  if (block_sums_gated<NT, 2>(v, skip0)) return false;
+  const double rr = v[0] * inv_n;
+  const double rr_prev = v[1] * inv_n;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   bool stop = false;
   if (st->refresh_every > 0) {
