@@ -30,7 +30,7 @@ constexpr long long kMinBlocks = 128;
 struct Layout {
   size_t total = 0;
   size_t off_state = 0, off_partials = 0, off_cond64 = 0, off_cond32 = 0, off_scratch = 0;
-  size_t off_tab = 0;
+  size_t off_tab = 0, off_live = 0;
   size_t off_tw64[3] = {0, 0, 0}, off_tw32[3] = {0, 0, 0};
   size_t off_v64[4] = {0, 0, 0, 0}, off_w64[3] = {0, 0, 0};
   size_t off_v32[4] = {0, 0, 0, 0}, off_w32[3] = {0, 0, 0};
@@ -91,6 +91,9 @@ struct Group {
   // batch
   int nprob = 1;
   bool batched = false;         // per-problem data come from the device table
+  // grid rows of the iteration launches once finished problems are dropped
+  // (0: one row per problem, no indirection)
+  int live_rows = 0;
   // device memory
   char* ws = nullptr;
   Layout lay;

@@ -106,6 +106,7 @@ Layout compute_layout(const Group& g, bool with32) {
   L.off_state = take(sizeof(DevState) * np);
   L.off_scratch = take(256);
   L.off_tab = take(sizeof(ProbEntry) * np);
+  L.off_live = take(sizeof(int) * np);
   // partial sums: one slot (three in AUX) per block of the widest launch
   // any schedule can make (two rows per row-pass block, tiles of one)
   (void)with32;
@@ -156,10 +157,11 @@ Partials dev_parts(Group& g) {
 
 Batch batch_of(Group& g) {
   Batch b{};
-  b.nprob = g.nprob;
+  b.nprob = g.live_rows > 0 ? g.live_rows : g.nprob;
   b.vstride = g.nhalf;
   b.pstride = g.lay.pstride;
   b.tab = g.batched ? reinterpret_cast<const ProbEntry*>(g.ws + g.lay.off_tab) : nullptr;
+  b.live = g.live_rows > 0 ? reinterpret_cast<const int*>(g.ws + g.lay.off_live) : nullptr;
   return b;
 }
 
@@ -589,26 +591,60 @@ bool all_done(const Group& g) {
   return true;
 }
 
+// Grid rows for n_live unfinished problems out of nprob: the smallest entry
+// >= n_live of the ladder nprob, 3/4 nprob, 9/16 nprob, ..., 1.  The ladder
+// bounds the number of distinct launch shapes (and captured graphs) by
+// about 2.4 log2(nprob); a shape holds at most a third more rows than
+// problems left.
+int ladder_rows(int nprob, int n_live) {
+  int r = nprob;
+  for (;;) {
+    const int next = std::max(1, (r * 3) / 4);
+    if (next >= r || next < n_live) return r;
+    r = next;
+  }
+}
+
 // Run blocks of work until the device reports every problem done.  A block is
 // captured once into a HIP graph and replayed (cached per key when the group
-// has a cache); with K == 0 it is queued eagerly.
+// has a cache); with K == 0 it is queued eagerly.  In a batch, the launches
+// cover only the unfinished problems once enough have finished: a block then
+// starts by listing them on the device, and its graph is cached per row count.
 template <typename F>
 lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqueue_block) {
   lshom_ctx* c = g.ctx;
   HIP_TRY(c, sync_states(g));
+  struct ResetRows {
+    Group& g;
+    ~ResetRows() { g.live_rows = 0; }
+  } reset_rows{g};
+  g.live_rows = 0;
+  int* live_dev = reinterpret_cast<int*>(g.ws + g.lay.off_live);
+  auto enqueue = [&]() -> hipError_t {
+    if (g.live_rows > 0) {
+      hipError_t e = launch_compact_live(dev_state(g), g.nprob, g.live_rows, live_dev, stream_of(g));
+      if (e != hipSuccess) return e;
+    }
+    return enqueue_block();
+  };
   hipGraphExec_t ex = nullptr;
   bool owned = false;
-  if (K > 0) {
-    auto gk = std::make_pair(key, K);
+  auto get_graph = [&]() -> lshom_status {
+    if (K <= 0) return LSHOM_OK;
+    const int rows = g.live_rows > 0 ? g.live_rows : g.nprob;
+    auto gk = std::make_pair(key + 4 * rows, K);
     if (g.graph_cache) {
       auto it = g.graph_cache->find(gk);
-      if (it != g.graph_cache->end()) ex = it->second;
+      if (it != g.graph_cache->end()) {
+        ex = it->second;
+        return LSHOM_OK;
+      }
     }
-    if (!ex) {
+    {
       std::lock_guard<std::mutex> lock(setup_mutex());
       hipGraph_t gr = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(stream_of(g), hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue_block();
+      hipError_t e = enqueue();
       hipError_t e2 = hipStreamEndCapture(stream_of(g), &gr);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (gr) (void)hipGraphDestroy(gr);
@@ -622,8 +658,10 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       if (g.graph_cache) g.graph_cache->emplace(gk, ex);
       else owned = true;
     }
-  }
-  lshom_status st = LSHOM_OK;
+    return LSHOM_OK;
+  };
+  lshom_status st = get_graph();
+  if (st != LSHOM_OK) return st;
   // the device sets `done` at the latest after max_iter iterations; the
   // block bound only guards against a state that stopped advancing
   for (long long blocks = 0;; ++blocks) {
@@ -632,9 +670,23 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       st = fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
       break;
     }
+    if (g.nprob > 1) {
+      int n_live = 0;
+      for (const DevState& s : g.host_states) n_live += s.done == 0;
+      const int rows = ladder_rows(g.nprob, n_live);
+      const int cur = g.live_rows > 0 ? g.live_rows : g.nprob;
+      if (rows < cur) {
+        if (owned) (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+        owned = false;
+        g.live_rows = rows;
+        st = get_graph();
+        if (st != LSHOM_OK) return st;
+      }
+    }
     long long before = 0;
     for (const DevState& s : g.host_states) before += s.iter_a;
-    hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue_block();
+    hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue();
     if (e == hipSuccess) e = sync_states(g);
     if (e == hipSuccess) {
       long long after = 0;

@@ -76,11 +76,17 @@ struct ProbEntry {
 // and its state p entries after the launch's base pointers.  tab == nullptr
 // means a single problem whose data are the fields of the argument struct.
 struct Batch {
-  int nprob;
+  int nprob;              // grid rows of the launch
   long long vstride;
   long long pstride;
   const ProbEntry* tab;
+  const int* live;        // grid row -> problem; null: row y is problem y
 };
+
+// Problem of this block (see Batch::live).
+__device__ __forceinline__ int batch_prob(const Batch& b) {
+  return b.live ? b.live[blockIdx.y] : (int)blockIdx.y;
+}
 
 // Scalar steps of the single-block finalize kernel.
 enum FinMode : int {
@@ -259,6 +265,9 @@ hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);
 hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);
 // copy nprob initial states from device memory src into st
 hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipStream_t s);
+// live[0..rows): the problems whose state is not done, in index order, then
+// done problems to fill the rows (the host picks rows >= the count not done).
+hipError_t launch_compact_live(const DevState* st, int nprob, int rows, int* live, hipStream_t s);
 template <typename T> hipError_t launch_fill_zero(cx<T>* p, long long n, hipStream_t s);
 hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipStream_t s);
 

@@ -112,7 +112,7 @@ __device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
 
 template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
-  const int pb = blockIdx.y;
+  const int pb = batch_prob(a.bt);
   DevState* st = a.st + pb;
   // the flags a row pass gates on are written only by earlier launches
   if (gated_out_stable(st, a.gate)) return;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
 template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
-  const int pb = blockIdx.y;
+  const int pb = batch_prob(a.bt);
   DevState* st = a.st + pb;
   // the direction step of the inverse pass reads its gate with the (r, r)
   // sums (block 0 of the same launch may set the flags); the other modes
@@ -542,7 +542,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 template <typename T>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
-  const int pb = blockIdx.y;
+  const int pb = batch_prob(a.bt);
   DevState* st = a.st + pb;
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void mix_accumulate_kernel(MixArgs a) {
-  const int pb = blockIdx.y;
+  const int pb = batch_prob(a.bt);
   if (gated_out(a.st + pb, a.gate)) return;
   const long long vo = (long long)pb * a.bt.vstride;
   const long long stride = (long long)gridDim.x * 256;
@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void mix_accumulate_kernel(MixArgs a) {
 }
 
 __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
-  const int pb = blockIdx.y;
+  const int pb = batch_prob(a.bt);
   DevState* st = a.st + pb;
   if (gated_out(st, a.gate)) return;
   Partials parts = a.parts;
@@ -657,10 +657,11 @@ __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
   constexpr int NT = 256;
-  DevState* st = a.st + blockIdx.y;
+  const int pb = batch_prob(a.bt);
+  DevState* st = a.st + pb;
   if (gated_out(st, a.gate)) return;
   Partials parts = a.parts;
-  parts.base += (long long)blockIdx.y * a.bt.pstride;
+  parts.base += (long long)pb * a.bt.pstride;
   const bool lead = threadIdx.x == 0;
   switch (a.mode) {
     case FZ_CHECK: {
@@ -726,6 +727,50 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
 
 __global__ void state_init_kernel(DevState* st, DevState init) { *st = init; }
 
+// One block: a running count over chunks of 256 problems (ballots per wave,
+// wave totals in LDS), so the list keeps index order.
+__global__ __launch_bounds__(256) void compact_live_kernel(const DevState* st, int nprob, int rows, int* live) {
+  __shared__ int wsum[2][4];
+  __shared__ int first_done;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) first_done = nprob;
+  __syncthreads();
+  int base_live = 0, base_done = 0;
+  for (int c0 = 0; c0 < nprob; c0 += 256) {
+    const int i = c0 + tid;
+    const bool in = i < nprob;
+    const bool act = in && st[i].done == 0;
+    const bool dn = in && !act;
+    const unsigned long long ba = __ballot(act), bd = __ballot(dn);
+    const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (lane == 0) {
+      wsum[0][w] = __popcll(ba);
+      wsum[1][w] = __popcll(bd);
+    }
+    __syncthreads();
+    int off_a = base_live, off_d = base_done, tot_a = 0, tot_d = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (k < w) {
+        off_a += wsum[0][k];
+        off_d += wsum[1][k];
+      }
+      tot_a += wsum[0][k];
+      tot_d += wsum[1][k];
+    }
+    if (act) {
+      const int pos = off_a + __popcll(ba & below);
+      if (pos < rows) live[pos] = i;
+    }
+    if (dn && off_d + __popcll(bd & below) == 0) first_done = i;
+    base_live += tot_a;
+    base_done += tot_d;
+    __syncthreads();
+  }
+  // fill the remaining rows with a done problem (its blocks return at entry)
+  const int fill = first_done < nprob ? first_done : 0;
+  for (int r = base_live + tid; r < rows; r += 256) live[r] = fill;
+}
+
 __global__ __launch_bounds__(256) void state_copy_kernel(DevState* st, const DevState* src, int nprob) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i < nprob) st[i] = src[i];
@@ -745,6 +790,11 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(cx<T>* p, long long n) {
 int lds_odd_stride(int n) { return (n & 1) ? n : n + 1; }
 
 static int nprob_of(const Batch& b) { return b.nprob > 1 ? b.nprob : 1; }
+
+hipError_t launch_compact_live(const DevState* st, int nprob, int rows, int* live, hipStream_t s) {
+  hipLaunchKernelGGL(compact_live_kernel, dim3(1), dim3(256), 0, s, st, nprob, rows, live);
+  return hipGetLastError();
+}
 
 hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipStream_t s) {
   hipLaunchKernelGGL(state_copy_kernel, dim3((unsigned)((nprob + 255) / 256)), dim3(256), 0, s, st, src, nprob);

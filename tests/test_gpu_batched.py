@@ -83,3 +83,28 @@ def test_batched_rejects_bad_phase():
     bs.prepare(probs, precision=0)
     with pytest.raises(lshom.LshomError):
         bs.run(precision=0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_with_uneven_convergence_equals_single(precision):
+    """Eight problems of one grid whose iteration counts spread over an order
+    of magnitude: as problems finish, the launches shrink to the unfinished
+    ones (rows 8, 6, 4, 3, 2, 1), which must not change any result."""
+    from paper_1004_1122_amd import lshom
+    probs = []
+    for i, rho in enumerate(np.geomspace(2.0, 3e4, 8)):
+        m = ms.grf_two_phase(27, 0.15, 0.4, float(rho), seed=700 + i)
+        probs.append(dict(phase=m.phase, cond=[1.0, float(rho)], E=(1.0, 0.5) if i % 2 else (0.0, 1.0),
+                          tol=1e-9, want_field=True))
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=1)
+    fields, leff, infos = bs.run(precision=precision, graph_block=4)
+    iters = [inf["iterations"] for inf in infos]
+    assert max(iters) > 4 * min(iters), iters
+    for i, pr in enumerate(probs):
+        s = lshom.Solver(pr["phase"], pr["cond"])
+        e, l1, info = s.solve(pr["E"], tol=pr["tol"], precision=precision, graph_block=4)
+        assert infos[i]["status"] == 0
+        assert infos[i]["iterations"] == info["iterations"], i
+        assert torch.equal(fields[i], e), i
+        assert np.array_equal(leff[i][:2], l1), i
