@@ -64,6 +64,7 @@ __all__ = [
     "homogenize",
     "eta_r",
     "eta_e",
+    "eta_e_from_residual",
     "project_gradient",
     "optimal_reference",
     "reference_omega",
@@ -210,7 +211,7 @@ def reference_omega(omega: float, rho: float) -> float:
 # ---------------------------------------------------------------------------
 
 def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
-       history=False, apply=None):
+       history=False, apply=None, norm="r", eta_history=False):
     """Solve ``(I + B) e = e0`` by Hestenes-Stiefel CG.
 
     Follows the CG method the paper applies to the collocation system
@@ -225,10 +226,17 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     ``n_iter`` forces exactly that many iterations (used to compare with the
     GPU at an equal iteration count).  ``x0`` defaults to ``b``.
 
+    ``norm="eta_e"`` replaces the test by the equilibrium criterion of
+    Sec. 3, Eq. (21), ``eta_e(x_m) <= tol``, evaluated from its definition on
+    the current iterate.  ``eta_history`` records ``(eta_r, eta_e)`` of every
+    iterate ``x_0 .. x_m`` (``eta_r`` of Eq. (22) from the recursive residual).
+
     Returns a dict with the field ``e``, ``iterations``, ``rel_res`` (the
     recursive residual), ``converged``, ``breakdown`` and optionally the
-    residual ``history``.
+    residual ``history`` and ``eta_history``.
     """
+    if norm not in ("r", "eta_e"):
+        raise ValueError("norm must be 'r' or 'eta_e'")
     lam = np.asarray(lam, dtype=np.float64)
     shape = lam.shape
     A = apply if apply is not None else (lambda v: apply_A(v, lam, l0))
@@ -243,12 +251,23 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     p = r.copy()
     rr = _dot(r, r)
     hist = [math.sqrt(rr) / bnorm]
+    etas = []
+
+    def stop_test():
+        eta_e_x = eta_e(lam, x) if (norm == "eta_e" or eta_history) else None
+        if eta_history:
+            etas.append((l0 * math.sqrt(rr) / bnorm, eta_e_x))
+        if norm == "eta_e":
+            return eta_e_x <= tol
+        return math.sqrt(rr) <= tol * bnorm
+
     m = 0
     limit = max_iter if n_iter is None else n_iter
     converged = False
     breakdown = False
     while True:
-        if n_iter is None and math.sqrt(rr) <= tol * bnorm:
+        ok = stop_test()
+        if n_iter is None and ok:
             converged = True
             break
         if m >= limit:
@@ -268,11 +287,13 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
         m += 1
         hist.append(math.sqrt(rr) / bnorm)
     if n_iter is not None:
-        converged = math.sqrt(rr) <= tol * bnorm
+        converged = ok
     out = dict(e=x, iterations=m, rel_res=math.sqrt(rr) / bnorm,
                converged=converged, breakdown=breakdown, r=r)
     if history:
         out["history"] = hist
+    if eta_history:
+        out["eta_history"] = etas
     return out
 
 
@@ -288,23 +309,40 @@ def true_residual(lam, l0, E, e) -> float:
 # The basic Moulinec-Suquet scheme (Sec. 2.3, Eq. (18))
 # ---------------------------------------------------------------------------
 
-def ffth(lam, l0, E, tol=1e-8, max_iter=100000):
+def ffth(lam, l0, E, tol=1e-8, max_iter=100000, norm="r", eta_history=False):
     """Neumann-series iterate ``e^(m) = sum_{j<=m} (-B)^j e0``.
 
-    Sec. 2.3, Eq. (18), evaluated as ``e^(m+1) = e0 - B e^(m)``.  Stops when
-    ``||e^(m+1) - e^(m)|| <= tol ||e0||`` (``eta_r / l0`` of Eq. (22)).
+    Sec. 2.3, Eq. (18), evaluated as ``e^(m+1) = e0 - B e^(m)``.  Stops after
+    the apply in which the test on ``e^(m)`` holds and returns ``e^(m+1)``:
+    ``||e^(m+1) - e^(m)|| <= tol ||e0||`` (``eta_r / l0`` of Eq. (22)), or with
+    ``norm="eta_e"`` ``eta_e(e^(m)) <= tol`` (Eq. (21)).  ``eta_history``
+    records ``(eta_r, eta_e)`` of ``e^(0) .. e^(m)``, where the residual of
+    ``e^(m)`` is the step ``e^(m+1) - e^(m)``.
     """
+    if norm not in ("r", "eta_e"):
+        raise ValueError("norm must be 'r' or 'eta_e'")
     lam = np.asarray(lam, dtype=np.float64)
     b = _rhs(E, lam.shape)
     bnorm = math.sqrt(_dot(b, b))
     e = b.copy()
+    etas = []
     for m in range(1, max_iter + 1):
         e_new = b - apply_B(e, lam, l0)
         diff = e_new - e
+        step = math.sqrt(_dot(diff, diff))
+        eta_e_m = eta_e(lam, e) if (norm == "eta_e" or eta_history) else None
+        if eta_history:
+            etas.append((l0 * step / bnorm, eta_e_m))
         e = e_new
-        if math.sqrt(_dot(diff, diff)) <= tol * bnorm:
-            return dict(e=e, iterations=m, converged=True)
-    return dict(e=e, iterations=max_iter, converged=False)
+        ok = eta_e_m <= tol if norm == "eta_e" else step <= tol * bnorm
+        if ok:
+            out = dict(e=e, iterations=m, converged=True)
+            break
+    else:
+        out = dict(e=e, iterations=max_iter, converged=False)
+    if eta_history:
+        out["eta_history"] = etas
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -427,6 +465,30 @@ def eta_e(lam, e) -> float:
     zero = (0,) * d
     den = float(sum(abs(j_hat[a][zero]) ** 2 for a in range(d)))
     return math.sqrt(num / den)
+
+
+def eta_e_from_residual(lam, l0, E, e) -> float:
+    """``eta_e`` through the residual of an admissible field ``e``.
+
+    With ``r = e0 - (I + B) e`` and ``j = lambda e``: for ``k != 0``,
+    ``k . j_hat = k . tau_hat + l0 k . e_hat`` (``tau = (lambda - l0) e``) and
+    ``k . r_hat = -k . e_hat - k . tau_hat / l0`` (Sec. 2.2, Eqs. (15)-(17)),
+    so ``k . j_hat = -l0 k . r_hat``; ``r_hat(k)`` is parallel to ``k`` for
+    the gradient fields of Sec. 2.1, hence ``|k . r_hat| = |k| |r_hat|``.
+    Valid for odd grids (no Nyquist modes, where the Green operator is zero).
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    d = lam.ndim
+    axes = tuple(range(1, d + 1))
+    r = _rhs(E, lam.shape) - apply_A(e, lam, l0)
+    r_hat = _fftn(r, axes)
+    ks = grid_frequencies(lam.shape)
+    k2 = sum(ks[a].astype(np.float64) ** 2 for a in range(d))
+    num = float(np.sum(k2 * sum(np.abs(r_hat[a]) ** 2 for a in range(d))))
+    j_hat = _fftn(lam[None, ...] * e, axes)
+    zero = (0,) * d
+    den = float(sum(abs(j_hat[a][zero]) ** 2 for a in range(d)))
+    return l0 * math.sqrt(num / den)
 
 
 def project_gradient(v: np.ndarray) -> np.ndarray:

@@ -337,3 +337,73 @@ def test_cg_grows_like_sqrt_rho_ffth_like_rho():
     assert its_cg[1] / its_cg[0] < 5.0
     assert its_ff[1] / its_ff[0] > 5.0
     assert its_cg[1] < its_ff[1]
+
+
+# ---------------------------------------------------------------------------
+# Termination norms (Sec. 3, Eqs. (21)-(22)) and the FFTH rate (Eq. (23))
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(15, 21), (7, 9, 5)])
+def test_eta_e_residual_identity(shape):
+    """eta_e from its definition (FFT of j = lambda e) equals l0 || |k| r_hat ||
+    / |j_hat(0)| on admissible iterates (the form a solver can evaluate from
+    its residual without transforming j)."""
+    lam = _rand_lam(shape, 21, 1.0, 50.0)
+    d = len(shape)
+    E = np.arange(1.0, d + 1.0)
+    l0 = o.optimal_reference(lam)
+    for m in (0, 1, 4, 9):
+        e = o.cg(lam, l0, E, n_iter=m)["e"]
+        a = o.eta_e(lam, e)
+        b = o.eta_e_from_residual(lam, l0, E, e)
+        assert abs(a - b) <= 1e-10 * a, (m, a, b)
+    # and it is l0-invariant on a fixed field (both sides are fields' norms)
+    e = o.cg(lam, l0, E, n_iter=3)["e"]
+    assert abs(o.eta_e_from_residual(lam, 2.0 * l0, E, e) - o.eta_e(lam, e)) <= 1e-10 * o.eta_e(lam, e)
+
+
+def test_cg_eta_e_termination_is_first_crossing():
+    lam = ms.square_inclusion(rho=100.0).lam()
+    l0 = o.optimal_reference(lam)
+    tol = 1e-4
+    res = o.cg(lam, l0, [1.0, 0.0], tol=tol, norm="eta_e", eta_history=True)
+    m = res["iterations"]
+    assert res["converged"] and m > 2
+    assert o.eta_e(lam, res["e"]) <= tol
+    prev = o.cg(lam, l0, [1.0, 0.0], n_iter=m - 1)["e"]
+    assert o.eta_e(lam, prev) > tol
+    etas = res["eta_history"]
+    assert len(etas) == m + 1
+    assert all(h[1] > tol for h in etas[:-1]) and etas[-1][1] <= tol
+    # eta_r of the history is l0 ||r|| / ||e0|| of the recursive residual
+    plain = o.cg(lam, l0, [1.0, 0.0], n_iter=m, history=True)["history"]
+    np.testing.assert_allclose([h[0] for h in etas], l0 * np.array(plain), rtol=1e-14)
+
+
+@pytest.mark.parametrize("rho", [10.0, 1000.0])
+def test_ffth_contracts_at_the_eyre_milton_rate(rho):
+    """With l0 = (min + max) / 2 each FFTH step is -B applied to the previous
+    step; B = Gamma0 l0 (dL / l0) is an orthogonal projection times a
+    multiplication bounded by (rho - 1) / (rho + 1), so every eta_r step
+    contracts at least at that rate (Eq. (23))."""
+    lam = ms.square_inclusion(rho=rho).lam()
+    l0 = o.optimal_reference(lam)
+    gamma = (rho - 1.0) / (rho + 1.0)
+    res = o.ffth(lam, l0, [1.0, 0.0], tol=1e-5, max_iter=400, eta_history=True)
+    r = [h[0] for h in res["eta_history"]]
+    assert len(r) > 5
+    for a, b in zip(r, r[1:]):
+        assert b <= gamma * a * (1.0 + 1e-12)
+
+
+def test_ffth_eta_e_termination():
+    lam = ms.square_inclusion(rho=50.0).lam()
+    l0 = o.optimal_reference(lam)
+    tol = 1e-4
+    res = o.ffth(lam, l0, [1.0, 0.0], tol=tol, norm="eta_e", eta_history=True)
+    etas = res["eta_history"]
+    assert res["converged"] and len(etas) == res["iterations"]
+    assert etas[-1][1] <= tol and all(h[1] > tol for h in etas[:-1])
+    # the returned field is the next iterate e0 - B e^(m)
+    cg_sol = o.cg(lam, l0, [1.0, 0.0], tol=1e-12)["e"]
+    assert np.linalg.norm(res["e"] - cg_sol) / np.linalg.norm(cg_sol) < 1e-3
