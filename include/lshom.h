@@ -50,6 +50,12 @@ typedef int32_t lshom_status;
 #define LSHOM_PRECISION_FP64 0  /* every step in FP64 */
 #define LSHOM_PRECISION_MIXED 1 /* FP32 operator and vectors, FP64 dots and refresh */
 
+#define LSHOM_METHOD_CG 0       /* conjugate gradients on Eq. (15) (Sec. 2.3, Sec. 3) */
+#define LSHOM_METHOD_FFTH 1     /* the basic scheme: Neumann series of Sec. 2.3, Eq. (18) */
+
+#define LSHOM_NORM_RESIDUAL 0    /* stop when ||r|| <= tol ||e0|| (eta_r / l0, Eq. (22)) */
+#define LSHOM_NORM_EQUILIBRIUM 1 /* stop when eta_e <= tol (Sec. 3, Eq. (21)) */
+
 typedef struct lshom_ctx lshom_ctx;
 
 /* Solver options; lshom_default_opts() fills the defaults shown. */
@@ -59,7 +65,19 @@ typedef struct lshom_solve_opts {
   int32_t refresh_every; /* 50: mixed only, FP64 refresh at least this often */
   double refresh_drop;   /* 0.1: mixed only, refresh when ||r|| fell by this factor */
   int32_t graph_block;   /* 16: iterations per captured HIP graph launch (0: no graph) */
-  int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop */
+  int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop (and eta_e, odd N) */
+  int32_t method;        /* LSHOM_METHOD_CG; LSHOM_METHOD_FFTH: FP64 only, no x0 */
+  int32_t norm;          /* LSHOM_NORM_RESIDUAL; EQUILIBRIUM: FP64 and odd N only */
+  /*
+   * NULL, or (single solves, FP64, odd N) a caller-owned device buffer of
+   * 2 * history_len doubles receiving (eta_r, eta_e) of iterate m at
+   * [2m], [2m + 1] for m < history_len.  CG: iterates x_0 .. x_iterations
+   * (eta_r from the recursive residual); FFTH: e^0 .. e^(iterations - 1),
+   * whose residual is the step to the next iterate.  Entries past the last
+   * iterate are left untouched.
+   */
+  double* history_dev;
+  int32_t history_len;   /* 0 */
 } lshom_solve_opts;
 
 /* Per-solve report. */
@@ -73,6 +91,8 @@ typedef struct lshom_solve_info {
   double rel_res;         /* ||r|| / ||b|| of the recursive residual */
   double rel_res_true;    /* ||b - A x|| / ||b|| in FP64 (if computed, else -1) */
   double eta_r;           /* l0 ||r|| / ||b||, the residual norm of Sec. 3, Eq. (22) */
+  double eta_e;           /* equilibrium norm of Sec. 3, Eq. (21) of the returned field
+                             (computed with the FP64 true residual, odd N; else -1) */
 } lshom_solve_info;
 
 /* Fixed-size message for a status code (static storage). */
@@ -125,8 +145,13 @@ lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* b
 lshom_status lshom_set_workspace(lshom_ctx* ctx, void* dev, size_t bytes);
 
 /*
- * Solve (I + B) e = e0 with e0 = E at every node (Sec. 2.2, Eq. (15)) by CG.
- * Stops when ||r|| <= tol ||e0|| (recursive residual), or after max_iter.
+ * Solve (I + B) e = e0 with e0 = E at every node (Sec. 2.2, Eq. (15)) by CG,
+ * or with opts->method = LSHOM_METHOD_FFTH by the basic scheme
+ * e^(m+1) = e0 - B e^(m) (Eq. (18)).  Stops when ||r|| <= tol ||e0||
+ * (recursive residual; for the basic scheme the step e^(m+1) - e^(m)), or
+ * with LSHOM_NORM_EQUILIBRIUM when eta_e <= tol, or after max_iter.  The
+ * basic scheme tests iterate m in the apply that forms m + 1 and returns
+ * e^(m+1).
  * x0_dev: NULL starts from e = E; otherwise a d x |N| FP64 field whose
  * admissible part E + P(x0) is used (P: projection on zero-mean curl-free
  * fields); it is rejected (start from E) if its residual is not finite or not
@@ -180,7 +205,9 @@ lshom_status lshom_batch_workspace_size(lshom_ctx* ctx, int32_t n, const lshom_p
                                         int precision, size_t* bytes);
 
 /*
- * Solve n problems (warm starts are not taken here).  ws_dev: caller-owned
+ * Solve n problems (warm starts are not taken here; opts->method and
+ * opts->norm apply to every problem, opts->history_dev must be NULL).
+ * ws_dev: caller-owned
  * device workspace of at least lshom_batch_workspace_size bytes, 256-byte
  * aligned (it is not kept after the call).  leff_host: n x 3 (row i is
  * <lambda e> of problem i, zero-padded); infos: n reports; both may be NULL.

@@ -101,6 +101,7 @@ struct Group {
   int warm_used = 0;
   std::map<std::pair<int, int>, hipGraphExec_t>* graph_cache = nullptr;
   bool in_cg = false;           // the CG-loop passes are being queued (timed when enabled)
+  bool eq = false;              // the iteration loop forms the equilibrium norm (FP64)
   PassTimer* timer = nullptr;   // event timing of the CG-loop passes (null: off)
 };
 

@@ -115,7 +115,7 @@ Layout compute_layout(const Group& g, bool with32) {
   maxb = std::max(maxb, inner0_of(g));
   if (g.d == 3) maxb = std::max(maxb, g.N[0] * (long long)g.h);
   L.part_stride = 3 * maxb;
-  L.pstride = 4 * L.part_stride;
+  L.pstride = kPartRegions * L.part_stride;
   L.off_partials = take((size_t)L.pstride * np * sizeof(double));
   L.off_cond64 = take((size_t)kCondStride * np * sizeof(double));
   L.off_cond32 = take((size_t)kCondStride * np * sizeof(float));
@@ -363,8 +363,9 @@ long long col0_block_count(Group& g, const Bufs<T>& b) {
   return col_blocks(col0_args(g, b));
 }
 
-hipError_t enq_finalize(Group& g, int mode, long long n, int gate) {
+hipError_t enq_finalize(Group& g, int mode, long long n, int gate, int eq = 0) {
   FinArgs f{};
+  f.eq = eq;
   f.st = dev_state(g);
   f.parts = dev_parts(g);
   f.mode = mode;
@@ -395,6 +396,10 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   u.inv_n = 1.0 / (double)g.nvox;
   u.gate = GATE_ACTIVE;
   u.bt = batch_of(g);
+  u.eq = g.eq ? 1 : 0;
+  u.dims = g.d;
+  for (int t = 0; t < 3; ++t) u.nd[t] = (int)g.N[t];
+  u.fd_n1 = make_fastdiv((uint32_t)g.N[1]);
   return u;
 }
 
@@ -406,7 +411,8 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
 // out = coef_base * base + coef_s * [1 / l0] * (-i khat) . tau_hat
 template <typename T>
 hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<T>* base,
-                               T coef_base, T coef_s, int s_inv_l0, int dot, int dot_region, int gate) {
+                               T coef_base, T coef_s, int s_inv_l0, int dot, int dot_region, int gate,
+                               int eq = 0) {
   hipError_t e;
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, -1);
@@ -423,6 +429,8 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
   a.s_inv_l0 = s_inv_l0;
   a.dot = dot;
   a.dot_region = dot_region;
+  a.eq = eq;
+  a.eq_region = PART_EQ0;
   a.gate = gate;
   return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, stream_of(g)); });
 }
@@ -431,7 +439,7 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
 // p = r + beta p), [3-D axis-1 inverse].
 template <typename T>
 hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
-                              const cx<T>* r_in, int gate) {
+                              const cx<T>* r_in, int gate, int eq = 0) {
   hipError_t e;
   ColArgs<T> a = col0_args(g, b);
   a.mode = COL_INV_C;
@@ -439,6 +447,7 @@ hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<
   a.p_io = p_io;
   a.r_in = r_in;
   a.cg_step = p_io != nullptr;
+  a.eq = eq;
   a.gate = gate;
   if ((e = timed_launch(g, LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_col(a, stream_of(g)); })) != hipSuccess)
     return e;
@@ -455,16 +464,16 @@ hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<
 template <typename T>
 hipError_t enq_apply_spec(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
                           const cx<T>* r_in, const double* E, cx<T>* out, const cx<T>* base,
-                          T coef_base, T coef_s, int dot, int dot_region, int gate) {
+                          T coef_base, T coef_s, int dot, int dot_region, int gate, int eq = 0) {
   hipError_t e;
-  if ((e = enq_inverse_from_c(g, b, c_in, p_io, r_in, gate)) != hipSuccess) return e;
+  if ((e = enq_inverse_from_c(g, b, c_in, p_io, r_in, gate, eq)) != hipSuccess) return e;
   RowArgs<T> r = row_args(g, b);
   r.mode = ROW_FUSED;
   for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
   if (!E) r.flags |= ROWF_STATE_E;
   r.gate = gate;
   if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row(r, stream_of(g)); })) != hipSuccess) return e;
-  return enq_forward_project(g, b, out, base, coef_base, coef_s, 1, dot, dot_region, gate);
+  return enq_forward_project(g, b, out, base, coef_base, coef_s, 1, dot, dot_region, gate, eq);
 }
 
 // One CG iteration in the spectral coordinate:
@@ -478,7 +487,7 @@ hipError_t enq_cg_iteration(Group& g, const Bufs<T>& b, int gate) {
   cx<T>* q = b.v[3];
   static const double kZero[3] = {0.0, 0.0, 0.0};
   g.in_cg = true;
-  e = enq_apply_spec<T>(g, b, nullptr, p, r, kZero, q, p, T(1), T(1), 1, PART_PQ, gate);
+  e = enq_apply_spec<T>(g, b, nullptr, p, r, kZero, q, p, T(1), T(1), 1, PART_PQ, gate, g.eq ? 1 : 0);
   if (e == hipSuccess) {
     UpdArgs<T> u = upd_args(g, b);
     u.gate = gate;
@@ -492,13 +501,28 @@ hipError_t enq_cg_iteration(Group& g, const Bufs<T>& b, int gate) {
 // r = -(x + (1/l0) P dL (E + u(x))).
 template <typename T>
 hipError_t enq_true_residual(Group& g, const Bufs<T>& b, const cx<T>* x, const double* E,
-                             cx<T>* out, int dot_region, int gate) {
-  return enq_apply_spec<T>(g, b, x, nullptr, nullptr, E, out, x, T(-1), T(-1), 2, dot_region, gate);
+                             cx<T>* out, int dot_region, int gate, int eq = 0) {
+  return enq_apply_spec<T>(g, b, x, nullptr, nullptr, E, out, x, T(-1), T(-1), 2, dot_region, gate, eq);
+}
+
+// One step of the basic scheme (Sec. 2.3, Eq. (18)) in the spectral
+// coordinate: x <- -(1/l0) P dL (E + u(x)), i.e. e^(m+1) = e0 - B e^(m); the
+// step x_new - x (the residual of e^(m)) is reduced for the tests.
+hipError_t enq_ffth_iteration(Group& g, const Bufs<double>& b, int gate) {
+  hipError_t e;
+  cx<double>* x = b.v[0];
+  g.in_cg = true;
+  e = enq_apply_spec<double>(g, b, x, nullptr, nullptr, nullptr, x, x, 0.0, -1.0, 3, PART_RR0, gate,
+                             g.eq ? 1 : 0);
+  g.in_cg = false;
+  if (e != hipSuccess) return e;
+  return enq_finalize(g, FZ_FFTH, col0_block_count(g, b), gate, g.eq ? 1 : 0);
 }
 
 // r0 for x0 = E: r0 = -(1/l0) P dL E.
 template <typename T>
-hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>* out, int dot_region) {
+hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>* out, int dot_region,
+                             int eq = 0) {
   hipError_t e;
   RowArgs<T> r = row_args(g, b);
   r.mode = ROW_FWD;
@@ -507,7 +531,7 @@ hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>*
   if (!E) r.flags |= ROWF_STATE_E;
   r.gate = GATE_ALWAYS;
   if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
-  return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS);
+  return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS, eq);
 }
 
 // Real FP64 field v (d x |N|) -> spectral coordinate of P v (of P dL v / l0).
@@ -632,7 +656,7 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
   auto get_graph = [&]() -> lshom_status {
     if (K <= 0) return LSHOM_OK;
     const int rows = g.live_rows > 0 ? g.live_rows : g.nprob;
-    auto gk = std::make_pair(key + 4 * rows, K);
+    auto gk = std::make_pair(key + 8 * rows, K);
     if (g.graph_cache) {
       auto it = g.graph_cache->find(gk);
       if (it != g.graph_cache->end()) {
@@ -770,6 +794,18 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
                          const double* E_single, const double* x0, double* e_single) {
   lshom_ctx* c = g.ctx;
   const bool mixed = o.precision == LSHOM_PRECISION_MIXED;
+  const bool ffth = o.method == LSHOM_METHOD_FFTH;
+  // the equilibrium sums ride along the loop when the norm or a history needs
+  // them (FP64, odd grids: checked by the caller)
+  struct EqReset {
+    Group& g;
+    ~EqReset() { g.eq = false; }
+  } eq_reset{g};
+  g.eq = !mixed && (o.norm == LSHOM_NORM_EQUILIBRIUM || o.history_dev != nullptr);
+  bool odd = true;
+  for (int a = 0; a < g.d; ++a) odd = odd && (g.N[a] & 1);
+  const int eq_final = odd ? 1 : 0;
+  const int eq_loop = g.eq ? 1 : 0;
   Bufs<double> b64 = get_bufs<double>(g);
   const long long ncol = col0_block_count(g, b64);
   const long long nall = g.nhalf * g.nprob;
@@ -802,8 +838,8 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, PART_AUX)));
     HIP_TRY(c, enq_finalize(g, FZ_AUX, ncol, GATE_ALWAYS));
     HIP_TRY(c, enq_project_real(g, b64, x0, false, x64));
-    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS));
+    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS, eq_loop)));
+    HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS, eq_loop));
     HIP_TRY(c, sync_states(g));
     const DevState& hs = g.host_states[0];
     const double rr = mixed ? hs.rr_true : hs.rr_log;
@@ -819,8 +855,11 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     HIP_TRY(c, hipMemcpyAsync(init_dev, init.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice,
                               stream_of(g)));
     HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, g.nprob, stream_of(g)));
-    HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, init_region)));
-    HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS));
+    // the basic scheme tests each iterate inside its own step
+    if (!ffth) {
+      HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, init_region, eq_loop)));
+      HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS, eq_loop));
+    }
   }
   if (mixed) HIP_TRY(c, launch_mix_convert(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
   HIP_TRY(c, sync_states(g));
@@ -834,13 +873,21 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   tm.kinds.clear();
   pass_model_bytes(g, o.precision, tm.unit_bytes);
   lshom_status s;
-  if (!mixed) {
-    s = run_blocks(g, 0, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+  if (ffth) {
+    s = run_blocks(g, 3 + eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+      for (int k = 0; k < per; ++k) {
+        hipError_t e = enq_ffth_iteration(g, b64, GATE_ACTIVE);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    });
+  } else if (!mixed) {
+    s = run_blocks(g, 2 * eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
       for (int k = 0; k < per; ++k) {
         hipError_t e = enq_cg_iteration<double>(g, b64, GATE_ACTIVE);
         if (e != hipSuccess) return e;
       }
-      return enq_finalize(g, FZ_CHECK, 0, GATE_ACTIVE);
+      return enq_finalize(g, FZ_CHECK, 0, GATE_ACTIVE, eq_loop);
     });
   } else {
     // a refresh may cut a block short: at least one iteration per block is certain
@@ -856,8 +903,8 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   // fold what a breakdown left in the FP32 correction (no-op after a refresh)
   if (mixed) HIP_TRY(c, launch_mix_accumulate(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
   if (o.true_residual) {
-    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, b64.v[3], PART_AUX, GATE_ALWAYS)));
-    HIP_TRY(c, enq_finalize(g, FZ_RR_TRUE, ncol, GATE_ALWAYS));
+    HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, b64.v[3], PART_AUX, GATE_ALWAYS, eq_final)));
+    HIP_TRY(c, enq_finalize(g, FZ_RR_TRUE, ncol, GATE_ALWAYS, eq_final));
   }
   HIP_TRY(c, enq_field_out(g, b64, x64, E, nullptr, e_single, true));
   HIP_TRY(c, sync_states(g));

@@ -19,8 +19,9 @@ constexpr int kCondStride = 256;     // conductivity-table entries per problem
 // producing kernel stores one partial sum, and the consuming kernel (which
 // starts after the producer has finished) sums the partials in block order in
 // each of its blocks, so all blocks obtain the same value.  Each field below
-// is written by block 0 of exactly one kernel kind and never read by that
-// kernel kind, so blocks of one kernel do not race on it.
+// is written by one thread of a launch (block 0's first thread, or for jx and
+// taup the thread that holds the k = 0 mode) and read only by later launches
+// or by that same thread, so blocks of one kernel do not race on it.
 struct DevState {
   double tol2b2;        // (tol * ||b||)^2
   double b2;            // ||b||^2 = |E|^2 |N|
@@ -33,6 +34,16 @@ struct DevState {
   double drop2;         // mixed: refresh when rr < drop2 * rr_ref
   double leff[3];       // <lambda e>
   double E[3];          // macroscopic field of the solve (set with the initial state)
+  double l0;            // reference conductivity (the norms of Sec. 3, Eqs. (21)-(22))
+  double nvox;          // |N|
+  double tol2;          // tol^2 (equilibrium test)
+  double jx[3];         // DFT at k = 0 of dL (E + u(x)) for the iterate being tested
+  double taup[3];       // DFT at k = 0 of dL u(p) for the last CG direction
+  double eta_e_log;     // eta_e of the last test (-1: not formed)
+  double eta_e_true;    // eta_e of the final field (-1: not formed)
+  double* hist;         // (eta_r, eta_e) of iterate m at [2m], [2m + 1], m < hist_len (or null)
+  int hist_len;
+  int norm;             // 0: ||r|| <= tol ||b||; 1: eta_e <= tol
   int iter_a;           // iterations completed (written by the update kernel)
   int iter_u;           // iteration in progress (written by the direction kernel)
   int max_iter;
@@ -54,8 +65,11 @@ enum Gate : int {
   GATE_NO_REFRESH = 3,  // mixed FP32 kernels: skip when done or a refresh is due
 };
 
-// Regions of the partial-sum array (each `stride` doubles; AUX holds 3 per block).
-enum PartRegion : int { PART_RR0 = 0, PART_RR1 = 1, PART_PQ = 2, PART_AUX = 3 };
+// Regions of the partial-sum array (each `stride` doubles; AUX holds 3 per
+// block).  EQ0 / EQ1 hold the |k|^2-weighted residual sums of the
+// equilibrium norm beside RR0 / RR1 (same producer, same count).
+enum PartRegion : int { PART_RR0 = 0, PART_RR1 = 1, PART_PQ = 2, PART_AUX = 3, PART_EQ0 = 4, PART_EQ1 = 5 };
+constexpr int kPartRegions = 6;
 
 struct Partials {
   double* base;
@@ -96,6 +110,7 @@ enum FinMode : int {
   FZ_LEFF = 3,          // leff[c] = sum(AUX[3 b + c]) / |N|
   FZ_REFRESH = 4,       // mixed: rr_true = sum(AUX); new reference; done tests
   FZ_REFRESH_INIT = 5,  // mixed: as FZ_REFRESH without counting a refresh
+  FZ_FFTH = 6,          // basic scheme: norms of the step sum(RR0), sum(EQ0); count; done tests
 };
 
 // ---------------------------------------------------------------------------
@@ -192,8 +207,13 @@ struct ColArgs {
   T coef_base, coef_s;
   int s_inv_l0;
   double l0;             // single problem (batched: the problem table)
-  int dot;               // 0 none, 1 (base, out), 2 (out, out)
+  int dot;               // 0 none, 1 (base, out), 2 (out, out), 3 (out - base, out - base)
   int dot_region;        // partial region; PART_RR0 also sets nparts[0]
+  // equilibrium norm: record the DFT at k = 0 of the transformed field (taup
+  // for dot 1, jx otherwise); dots 2 and 3 also store the |k|^2-weighted sum
+  // into eq_region.  COL_INV_C with cg_step: the direction step reads it.
+  int eq;
+  int eq_region;
   FftPlan plan;
   const cx<T>* tw;
   DevState* st;
@@ -223,6 +243,11 @@ struct UpdArgs {
   int gate;
   Batch bt;
   FastDiv fd_kd, fd_h;   // klast_div, h (n < 2^31)
+  // equilibrium norm: |k|^2-weighted (r, r) beside (r, r), jx += alpha taup
+  int eq;
+  int dims;
+  int nd[kMaxDim];
+  FastDiv fd_n1;         // nd[1] (3-D index split)
 };
 
 // Mixed precision: x64 += x32, x32 = 0 (accumulate); r32 = r64 and the
@@ -253,6 +278,7 @@ struct FinArgs {
   double inv_n;
   int gate;
   Batch bt;
+  int eq;                // the equilibrium sums beside the (r, r) sums are present
 };
 
 // Host launchers (passes.hip).

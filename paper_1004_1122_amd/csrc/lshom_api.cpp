@@ -37,13 +37,24 @@ lshom_status check_ready(lshom_ctx* c, int precision) {
 }
 
 // Initial device scalars of one problem.
-DevState initial_state(int d, long long nvox, const double* E, double tol, const lshom_solve_opts& o) {
+DevState initial_state(int d, long long nvox, const double* E, double tol, double l0, const lshom_solve_opts& o,
+                       bool with_history) {
   DevState s{};
   double e2 = 0.0;
   for (int t = 0; t < d; ++t) e2 += E[t] * E[t];
   s.b2 = e2 * (double)nvox;
   for (int t = 0; t < 3; ++t) s.E[t] = t < d ? E[t] : 0.0;
   s.tol2b2 = tol * tol * s.b2;
+  s.tol2 = tol * tol;
+  s.l0 = l0;
+  s.nvox = (double)nvox;
+  s.norm = o.norm;
+  s.eta_e_log = -1.0;
+  s.eta_e_true = -1.0;
+  if (with_history) {
+    s.hist = o.history_dev;
+    s.hist_len = o.history_len;
+  }
   s.max_iter = o.max_iter;
   if (o.precision == LSHOM_PRECISION_MIXED) {
     s.refresh_every = o.refresh_every;
@@ -66,6 +77,7 @@ void fill_info(const DevState& hs, double l0, const lshom_solve_opts& o, int war
   info->rel_res = std::sqrt(rr / b2);
   info->rel_res_true = o.true_residual ? std::sqrt(hs.rr_true / b2) : -1.0;
   info->eta_r = l0 * std::sqrt(rr / b2);
+  info->eta_e = o.true_residual ? hs.eta_e_true : -1.0;
 }
 
 hipError_t order_after_user(lshom_ctx* c) {
@@ -86,6 +98,26 @@ lshom_status validate_opts(lshom_ctx* c, const lshom_solve_opts* o) {
     if (!(o->refresh_drop > 0.0 && o->refresh_drop < 1.0))
       return fail(c, LSHOM_ERR_INVALID_ARG, "refresh_drop must be in (0, 1)");
   }
+  if (o->method != LSHOM_METHOD_CG && o->method != LSHOM_METHOD_FFTH)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "method must be CG (0) or FFTH (1)");
+  if (o->norm != LSHOM_NORM_RESIDUAL && o->norm != LSHOM_NORM_EQUILIBRIUM)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "norm must be RESIDUAL (0) or EQUILIBRIUM (1)");
+  if (o->history_len < 0) return fail(c, LSHOM_ERR_INVALID_ARG, "history_len must be >= 0");
+  const bool mixed = o->precision == LSHOM_PRECISION_MIXED;
+  if (mixed && o->method == LSHOM_METHOD_FFTH)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme runs in FP64 only");
+  if (mixed && (o->norm == LSHOM_NORM_EQUILIBRIUM || o->history_dev))
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the equilibrium norm and the history are FP64 only");
+  return LSHOM_OK;
+}
+
+// The equilibrium norm is formed from the residual (no transform of the
+// current), which needs grids without Nyquist modes.
+lshom_status check_equilibrium_grid(lshom_ctx* c, const lshom_solve_opts& o, const int64_t* N, int d) {
+  if (o.norm != LSHOM_NORM_EQUILIBRIUM && !o.history_dev) return LSHOM_OK;
+  for (int a = 0; a < d; ++a)
+    if ((N[a] & 1) == 0)
+      return fail(c, LSHOM_ERR_UNSUPPORTED, "the equilibrium norm and the history need odd N");
   return LSHOM_OK;
 }
 
@@ -117,6 +149,10 @@ void lshom_default_opts(lshom_solve_opts* o) {
   o->refresh_drop = 0.1;
   o->graph_block = 16;
   o->true_residual = 1;
+  o->method = LSHOM_METHOD_CG;
+  o->norm = LSHOM_NORM_RESIDUAL;
+  o->history_dev = nullptr;
+  o->history_len = 0;
 }
 
 lshom_status lshom_check_problem(int d, const int64_t* N, int n_phases, const double* cond,
@@ -263,6 +299,9 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
   if (!std::isfinite(tol) || tol < 0.0) return fail(c, LSHOM_ERR_INVALID_ARG, "tol must be finite and >= 0");
   for (int a = 0; a < c->g.d; ++a)
     if (!std::isfinite(E_host[a])) return fail(c, LSHOM_ERR_INVALID_ARG, "E must be finite");
+  if ((s = check_equilibrium_grid(c, o, c->g.N, c->g.d)) != LSHOM_OK) return s;
+  if (o.method == LSHOM_METHOD_FFTH && x0_dev)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme starts from e = E (no x0)");
   DeviceGuard g(c->device);
   HIP_TRY(c, order_after_user(c));
   Group& gr = c->g;
@@ -280,7 +319,7 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
     }
     return LSHOM_OK;
   }
-  std::vector<DevState> init(1, initial_state(gr.d, gr.nvox, E_host, tol, o));
+  std::vector<DevState> init(1, initial_state(gr.d, gr.nvox, E_host, tol, gr.l0, o, true));
   s = solve_group(gr, init, o, E_host, x0_dev, e_dev);
   if (s != LSHOM_OK) return s;
   const DevState& hs = gr.host_states[0];
@@ -414,7 +453,7 @@ lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const l
     e.x0 = nullptr;
     e.l0 = p.l0 > 0.0 ? p.l0 : 0.5 * (lo + hi);
     phases.push_back(p.phase_dev);
-    (*init)[j] = initial_state(p.d, g.nvox, p.E, p.tol, o);
+    (*init)[j] = initial_state(p.d, g.nvox, p.E, p.tol, e.l0, o, false);
   }
   lshom_status s = prepare_workspace(g, cond, tab, phases);
   if (s != LSHOM_OK) return s;
@@ -502,8 +541,11 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
   if (opts) o = *opts;
   lshom_status s = validate_opts(c, &o);
   if (s != LSHOM_OK) return s;
+  if (o.history_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "history_dev must be NULL for batched solves");
   BatchPlan bp;
   if ((s = plan_batch(c, n, probs, o.precision, &bp)) != LSHOM_OK) return s;
+  for (int32_t i = 0; i < n; ++i)
+    if ((s = check_equilibrium_grid(c, o, probs[i].N, probs[i].d)) != LSHOM_OK) return s;
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) != 0)
     return fail(c, LSHOM_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
   if (ws_bytes < bp.total) return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_batch_workspace_size()");

@@ -34,7 +34,8 @@ __device__ __forceinline__ int freq_of(int m, int n) { return (m <= n / 2) ? m :
 // false where the Green operator vanishes: k = 0, and for even N any
 // k_a = N_a / 2.
 template <typename T>
-__device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long ii, double* kh) {
+__device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long ii, double* kh,
+                                           double* k2_out = nullptr) {
   int idx[kMaxDim];
   idx[0] = l;
   if (a.dims == 2) {
@@ -59,6 +60,7 @@ __device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long
     }
   }
   if (k2 == 0.0) return false;
+  if (k2_out) *k2_out = k2;
   const double inv = 1.0 / sqrt(k2);
 #pragma unroll
   for (int t = 0; t < kMaxDim; ++t) kh[t] = kf[t] * inv;
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 
   if constexpr (MODE == COL_INV_C) {
     double beta = 0.0;
-    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate)) return;
+    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq)) return;
     const T tb = (T)beta;
     const int total = L * C;
     for (int base = 0; base < total; base += NT * kBatch) {
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   } else {
   // COL_FWD_PROJ
   fft_lds<T, -1, NT, RS>(Z, nseq, ss, a.plan, tw, tid);
-  double acc = 0.0;
+  double acc = 0.0, acc_eq = 0.0;
   const int n_last = a.nd[a.dims - 1];
   const int total = L * C;
   const T cs = a.coef_s * (a.s_inv_l0 ? (T)(1.0 / (pe ? pe->l0 : a.l0)) : T(1));
@@ -500,7 +502,14 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       if (c >= width) continue;
       const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
       double kh[kMaxDim];
-      const bool nz = khat_axis0(a, l, i0 + c, kh);
+      double k2 = 0.0;
+      const bool nz = khat_axis0(a, l, i0 + c, kh, &k2);
+      if (a.eq && l == 0 && i0 + c == 0) {
+        // k = 0: the cell sum of the transformed field (dL (E + u) or dL u)
+        double* dst = a.dot == 1 ? st->taup : st->jx;
+#pragma unroll
+        for (int al = 0; al < kMaxDim; ++al) dst[al] = al < d ? (double)Z[(al * C + c) * ss + l].re : 0.0;
+      }
       cx<T> t = zero;
       if (nz) {
 #pragma unroll
@@ -521,18 +530,52 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       if (a.dot) {
         const uint32_t kl = (uint32_t)(i0 + c);
         const double w = half_weight(kl - fdiv(kl, a.fd_h) * (uint32_t)a.h, n_last);
-        if (a.dot == 1)
+        if (a.dot == 1) {
           acc += w * ((double)b.re * (double)val.re + (double)b.im * (double)val.im);
-        else
-          acc += w * ((double)val.re * (double)val.re + (double)val.im * (double)val.im);
+        } else {
+          // dot 2: |out|^2; dot 3: the step |out - base|^2 of the basic scheme
+          const double dr = a.dot == 3 ? (double)val.re - (double)b.re : (double)val.re;
+          const double di = a.dot == 3 ? (double)val.im - (double)b.im : (double)val.im;
+          const double m2 = dr * dr + di * di;
+          acc += w * m2;
+          if (a.eq) acc_eq += w * k2 * m2;
+        }
       }
     }
   }
   if (a.dot) {
-    store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
+    if (a.eq && a.dot != 1) {
+      double v[2] = {acc, acc_eq};
+      (void)block_sums_gated<NT, 2>(v, 0);
+      if (tid == 0) {
+        parts.region(a.dot_region)[blockIdx.x] = v[0];
+        parts.region(a.eq_region)[blockIdx.x] = v[1];
+      }
+    } else {
+      store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
+    }
     if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
   }
   }
+}
+
+// |k|^2 (integer frequencies) of half-spectrum entry i: 2-D arrays are
+// stored [k1][k0] (kq = i / N0 is k1), 3-D arrays [k0][k1][k2] (kq = i).
+template <typename T>
+__device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, uint32_t kq, uint32_t k_last) {
+  int k0, k1;
+  if (a.dims == 2) {
+    k0 = (int)(i - kq * (uint32_t)a.nd[0]);
+    k1 = 0;
+  } else {
+    const uint32_t rest = fdiv(kq, a.fd_h);
+    const uint32_t i0 = fdiv(rest, a.fd_n1);
+    k1 = freq_of((int)(rest - i0 * (uint32_t)a.nd[1]), a.nd[1]);
+    k0 = (int)i0;
+  }
+  k0 = freq_of(k0, a.nd[0]);
+  const double kl = (double)k_last;
+  return (double)k0 * k0 + (double)k1 * k1 + kl * kl;
 }
 
 // ---------------------------------------------------------------------------
@@ -571,7 +614,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   cx<T>* __restrict__ Rv = a.r + vo;
   const double alpha = rr / pq;
   const T ta = (T)alpha;
-  double acc = 0.0;
+  double acc = 0.0, acc_eq = 0.0;
   const long long stride = (long long)gridDim.x * NT;
   for (long long i0 = (long long)blockIdx.x * NT + threadIdx.x; i0 < a.n; i0 += stride * kBatch) {
     cx<T> p[kBatch], q[kBatch], x[kBatch], r[kBatch];
@@ -596,17 +639,32 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
       X[i] = x[u];
       Rv[i] = r[u];
       const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
-      const double w = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
-      acc += w * ((double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im);
+      const uint32_t k_last = kq - fdiv(kq, a.fd_h) * (uint32_t)a.h;
+      const double w = half_weight(k_last, a.n_last);
+      const double m2 = (double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im;
+      acc += w * m2;
+      if (a.eq) acc_eq += w * spectral_k2(a, (uint32_t)i, kq, k_last) * m2;
     }
   }
   const int nxt = (k + 1) & 1;
-  store_partial<NT>(acc, parts.region(nxt) + blockIdx.x);
+  if (a.eq) {
+    double v[2] = {acc, acc_eq};
+    (void)block_sums_gated<NT, 2>(v, 0);
+    if (threadIdx.x == 0) {
+      parts.region(nxt)[blockIdx.x] = v[0];
+      parts.region(PART_EQ0 + nxt)[blockIdx.x] = v[1];
+    }
+  } else {
+    store_partial<NT>(acc, parts.region(nxt) + blockIdx.x);
+  }
   if (lead) {
     st->nparts[nxt] = (int)gridDim.x;
     st->iter_a = k + 1;
     st->alpha_log = alpha;
     st->pq_log = pq;
+    // cell sum of dL (E + u(x)) follows x += alpha p linearly
+    if (a.eq)
+      for (int c = 0; c < kMaxDim; ++c) st->jx[c] += alpha * st->taup[c];
   }
 }
 
@@ -667,12 +725,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     case FZ_CHECK: {
       const int m = st->iter_a;
       const double rr = sum_partials<NT>(parts.region(m & 1), st->nparts[m & 1]) * a.inv_n;
+      bool conv = rr <= st->tol2b2;
+      if (a.eq) {
+        const double eqs = sum_partials<NT>(parts.region(PART_EQ0 + (m & 1)), st->nparts[m & 1]);
+        const bool eq_ok = equilibrium_test(st, m, rr, eqs, lead);
+        if (st->norm == 1) conv = eq_ok;
+      }
       if (lead) {
         st->rr_log = rr;
         if (!isfinite(rr)) {
           st->status = -6;
           st->done = 1;
-        } else if (rr <= st->tol2b2) {
+        } else if (conv) {
           st->done = 1;
         } else if (m >= st->max_iter) {
           st->status = -5;
@@ -688,7 +752,33 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
     case FZ_RR_TRUE: {
       const double s = sum_partials<NT>(parts.region(PART_AUX), a.n) * a.inv_n;
+      if (a.eq) (void)equilibrium_test(st, -1, s, sum_partials<NT>(parts.region(PART_EQ0), a.n), lead);
       if (lead) st->rr_true = s;
+      break;
+    }
+    case FZ_FFTH: {
+      // iterate m was transformed into m + 1; the step is its residual
+      const int m = st->iter_a;
+      const double rr = sum_partials<NT>(parts.region(PART_RR0), a.n) * a.inv_n;
+      bool conv = rr <= st->tol2b2;
+      if (a.eq) {
+        const bool eq_ok = equilibrium_test(st, m, rr, sum_partials<NT>(parts.region(PART_EQ0), a.n), lead);
+        if (st->norm == 1) conv = eq_ok;
+      }
+      if (lead) {
+        st->rr_log = rr;
+        st->iter_a = m + 1;
+        st->iter_u = m;
+        if (!isfinite(rr)) {
+          st->status = -6;
+          st->done = 1;
+        } else if (conv) {
+          st->done = 1;
+        } else if (m + 1 >= st->max_iter) {
+          st->status = -5;
+          st->done = 1;
+        }
+      }
       break;
     }
     case FZ_LEFF: {

@@ -131,6 +131,36 @@ __device__ __forceinline__ bool block_sums_gated(double (&v)[NS], int skip0) {
   return skip != 0;
 }
 
+// The two termination norms of Sec. 3 for iterate m: eta_r = l0 ||r|| / ||e0||
+// (Eq. (22)) from the real-space (r, r), and eta_e (Eq. (21)) from the
+// |k|^2-weighted spectral residual sum eq: for an admissible field the
+// divergence of the current in Fourier space is k . j_hat = -l0 k . r_hat and
+// r_hat is parallel to k, so eta_e = l0 sqrt(eq) / |j_hat(0)| with
+// j_hat(0) = jx + l0 |N| E.  The lead thread records eta_e and, for m >= 0,
+// history entry m.  Returns whether eta_e <= tol.
+__device__ inline bool equilibrium_test(DevState* st, int m, double rr, double eq, bool lead) {
+  const double l0 = st->l0;
+  double j2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double jc = st->jx[c] + l0 * st->nvox * st->E[c];
+    j2 += jc * jc;
+  }
+  const double eta_e = l0 * sqrt(eq / j2);
+  if (lead) {
+    if (m >= 0) {
+      st->eta_e_log = eta_e;
+      if (st->hist && m < st->hist_len) {
+        st->hist[2 * m] = l0 * sqrt(rr / st->b2);
+        st->hist[2 * m + 1] = eta_e;
+      }
+    } else {
+      st->eta_e_true = eta_e;
+    }
+  }
+  return eta_e * eta_e <= st->tol2;
+}
+
 // The CG direction step (start of iteration k = iter_a): convergence test on
 // (r_k, r_k), iteration limit, and beta = (r_k, r_k) / (r_{k-1}, r_{k-1}).
 // Mixed precision requests an FP64 refresh instead of stopping.  Returns
@@ -138,13 +168,17 @@ __device__ __forceinline__ bool block_sums_gated(double (&v)[NS], int skip0) {
 // in every block; block 0 records it.
 // The entry gate is read with the sums: a block it sends back returns false
 // without touching the state.
+// With eq (plain FP64 CG only) the equilibrium sums of the same producer are
+// summed too and the test follows the state's norm.
 template <int NT>
-__device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, double* beta_out, int gate) {
+__device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, double* beta_out, int gate,
+                             int eq) {
   const int skip0 = gate_flags(st, gate);
   const int k = st->iter_a;
-  double v[2] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
-                 k > 0 ? partial_share<NT>(parts.region((k + 1) & 1), st->nparts[(k + 1) & 1]) : 0.0};
-  if (block_sums_gated<NT, 2>(v, skip0)) return false;
+  double v[3] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
+                 k > 0 ? partial_share<NT>(parts.region((k + 1) & 1), st->nparts[(k + 1) & 1]) : 0.0,
+                 eq ? partial_share<NT>(parts.region(PART_EQ0 + (k & 1)), st->nparts[k & 1]) : 0.0};
+  if (block_sums_gated<NT, 3>(v, skip0)) return false;
   const double rr = v[0] * inv_n;
   const double rr_prev = v[1] * inv_n;
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -163,10 +197,11 @@ __device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, 
       stop = true;
     }
   } else {
+    const bool eq_ok = eq && equilibrium_test(st, k, rr, v[2], lead);
     if (!isfinite(rr)) {
       if (lead) st->status = -6;
       stop = true;
-    } else if (rr <= st->tol2b2) {
+    } else if ((eq && st->norm == 1) ? eq_ok : rr <= st->tol2b2) {
       stop = true;
     } else if (k >= st->max_iter) {
       if (lead) st->status = -5;

@@ -36,6 +36,12 @@ LSHOM_ERR_UNSUPPORTED = -7
 PRECISION_FP64 = 0
 PRECISION_MIXED = 1
 
+METHOD_CG = 0
+METHOD_FFTH = 1
+
+NORM_RESIDUAL = 0
+NORM_EQUILIBRIUM = 1
+
 
 class lshom_solve_opts(Structure):
     _fields_ = [
@@ -45,6 +51,10 @@ class lshom_solve_opts(Structure):
         ("refresh_drop", c_double),
         ("graph_block", c_int32),
         ("true_residual", c_int32),
+        ("method", c_int32),
+        ("norm", c_int32),
+        ("history_dev", c_void_p),
+        ("history_len", c_int32),
     ]
 
 
@@ -59,6 +69,7 @@ class lshom_solve_info(Structure):
         ("rel_res", c_double),
         ("rel_res_true", c_double),
         ("eta_r", c_double),
+        ("eta_e", c_double),
     ]
 
     def as_dict(self):
@@ -316,10 +327,20 @@ class Solver:
             setattr(o, k, v)
         return o
 
-    def solve(self, E, tol=1e-8, x0=None, want_field=True, allow_fail=False, **opt_kw):
-        """Returns (e [d, *N] float64 device tensor or None, leff ndarray, info dict)."""
+    def solve(self, E, tol=1e-8, x0=None, want_field=True, allow_fail=False, history=0, **opt_kw):
+        """Returns (e [d, *N] float64 device tensor or None, leff ndarray, info dict).
+
+        ``method`` / ``norm`` select the basic scheme and the equilibrium test
+        (METHOD_*, NORM_*); ``history=n`` records (eta_r, eta_e) of the first
+        n iterates into ``info["history"]`` (an [m, 2] array, m the iterates
+        the solve produced, at most n)."""
         torch = self.torch
         o = self.opts(**opt_kw)
+        hist = None
+        if history:
+            hist = torch.full((int(history), 2), float("nan"), dtype=torch.float64, device=self.device)
+            o.history_dev = hist.data_ptr()
+            o.history_len = int(history)
         e = torch.empty((self.d,) + self.shape, dtype=torch.float64, device=self.device) if want_field else None
         leff = (c_double * self.d)()
         info = lshom_solve_info()
@@ -333,7 +354,11 @@ class Solver:
                                   ctypes.byref(info))
         allow = (LSHOM_ERR_NOT_CONVERGED, LSHOM_ERR_BREAKDOWN) if allow_fail else ()
         _check(self.ctx, st, allow)
-        return e, np.array(leff[:]), info.as_dict()
+        out = info.as_dict()
+        if hist is not None:
+            m = info.iterations + (1 if o.method == METHOD_CG else 0)
+            out["history"] = hist[:min(m, int(history))].cpu().numpy()
+        return e, np.array(leff[:]), out
 
     def homogenize(self, tol=1e-8, **opt_kw):
         o = self.opts(**opt_kw)

@@ -1,0 +1,177 @@
+"""The basic scheme (Sec. 2.3, Eq. (18)) and the two termination norms of
+Sec. 3 (Eqs. (21)-(22)) on the GPU, through the C ABI, against the CPU oracle.
+
+FP64 bars: fields within 1e-10 (relative L2) at an equal iteration count;
+equal iteration counts for both norms; eta_r / eta_e histories within 1e-8
+relative (plus an absolute floor of 1e-12 of the first value, where the
+recursive and the true residual part ways at rounding level).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import lshom_oracle as o
+from paper_1004_1122_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _cases():
+    sq = ms.square_inclusion(rho=10.0)
+    grf = ms.grf_two_phase(45, 0.15, 0.4, 50.0, seed=11)
+    rng = np.random.default_rng(5)
+    cube = (rng.random((15, 15, 15)) < 0.3).astype(np.uint8)
+    return [("square63_rho10", sq.phase, [1.0, 10.0], (1.0, 0.0)),
+            ("grf45_rho50", grf.phase, [1.0, 50.0], (0.6, -0.8)),
+            ("cube15_rho20", cube, [1.0, 20.0], (0.0, 1.0, 0.5))]
+
+
+CASES = _cases()
+
+
+def _solver(phase, cond):
+    from paper_1004_1122_amd import lshom
+    return lshom.Solver(np.ascontiguousarray(phase, dtype=np.uint8), cond)
+
+
+def _close_hist(gpu, ref, rtol=1e-8):
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape, (gpu.shape, ref.shape)
+    floor = 1e-12 * np.abs(ref[0])
+    err = np.abs(gpu - ref)
+    assert np.all(err <= rtol * np.abs(ref) + floor), float((err / (np.abs(ref) + floor)).max())
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_ffth_matches_oracle(case):
+    from paper_1004_1122_amd import lshom
+    _, phase, cond, E = case
+    lam = ms.lam_field(phase, cond)
+    l0 = o.optimal_reference(lam)
+    s = _solver(phase, cond)
+    e, leff, info = s.solve(E, tol=1e-6, method=lshom.METHOD_FFTH, history=4000)
+    ref = o.ffth(lam, l0, E, tol=1e-6, eta_history=True)
+    assert info["status"] == 0
+    assert info["iterations"] == ref["iterations"]
+    assert _rel(e.cpu().numpy(), ref["e"]) < 1e-10
+    lref = o.leff(lam, ref["e"])
+    np.testing.assert_allclose(leff, lref, rtol=1e-10, atol=1e-12 * np.abs(lref).max())
+    _close_hist(info["history"], ref["eta_history"])
+    # the reported eta_e is that of the returned field (from its definition)
+    assert abs(info["eta_e"] - o.eta_e(lam, e.cpu().numpy())) <= 1e-8 * o.eta_e(lam, e.cpu().numpy())
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_ffth_equilibrium_termination(case):
+    from paper_1004_1122_amd import lshom
+    _, phase, cond, E = case
+    lam = ms.lam_field(phase, cond)
+    l0 = o.optimal_reference(lam)
+    s = _solver(phase, cond)
+    e, _, info = s.solve(E, tol=1e-4, method=lshom.METHOD_FFTH, norm=lshom.NORM_EQUILIBRIUM)
+    ref = o.ffth(lam, l0, E, tol=1e-4, norm="eta_e")
+    assert info["iterations"] == ref["iterations"]
+    assert _rel(e.cpu().numpy(), ref["e"]) < 1e-10
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_cg_history_and_equilibrium_termination(case):
+    from paper_1004_1122_amd import lshom
+    _, phase, cond, E = case
+    lam = ms.lam_field(phase, cond)
+    l0 = o.optimal_reference(lam)
+    s = _solver(phase, cond)
+    e, _, info = s.solve(E, tol=1e-8, history=500)
+    ref = o.cg(lam, l0, E, tol=1e-8, eta_history=True)
+    assert info["iterations"] == ref["iterations"]
+    _close_hist(info["history"], ref["eta_history"])
+    # equilibrium test: same stopping iterate, same field
+    e, _, info = s.solve(E, tol=1e-5, norm=lshom.NORM_EQUILIBRIUM)
+    ref = o.cg(lam, l0, E, tol=1e-5, norm="eta_e")
+    assert info["iterations"] == ref["iterations"]
+    assert _rel(e.cpu().numpy(), ref["e"]) < 1e-10
+    eta = o.eta_e(lam, e.cpu().numpy())
+    assert eta <= 1e-5 and abs(info["eta_e"] - eta) <= 1e-8 * eta
+
+
+def test_plain_cg_reports_eta_e():
+    phase, cond, E = CASES[1][1], CASES[1][2], CASES[1][3]
+    lam = ms.lam_field(phase, cond)
+    s = _solver(phase, cond)
+    e, _, info = s.solve(E, tol=1e-7)
+    eta = o.eta_e(lam, e.cpu().numpy())
+    assert abs(info["eta_e"] - eta) <= 1e-8 * eta
+    # mixed precision reports it too (from its final FP64 check)
+    e, _, info = s.solve(E, tol=1e-7, precision=1)
+    eta = o.eta_e(lam, e.cpu().numpy())
+    assert abs(info["eta_e"] - eta) <= 1e-8 * eta
+
+
+def test_cg_beats_ffth_more_at_higher_contrast():
+    """The paper's central comparison on a circle array: CG needs a fraction
+    of the basic scheme's iterations, and that fraction shrinks with the
+    contrast (Sec. 3; iterations ~ sqrt(rho) against ~ rho, Eq. (23))."""
+    from paper_1004_1122_amd import lshom
+    ratios = []
+    for rho in (10.0, 1000.0):
+        m = ms.circle_array(n=63, vf=0.5, rho=rho)
+        s = _solver(m.phase, [1.0, rho])
+        _, _, icg = s.solve((1.0, 0.0), tol=1e-4)
+        _, _, iff = s.solve((1.0, 0.0), tol=1e-4, method=lshom.METHOD_FFTH, max_iter=20000)
+        assert icg["status"] == 0 and iff["status"] == 0
+        ratios.append(icg["iterations"] / iff["iterations"])
+    assert ratios[0] < 0.6 and ratios[1] < ratios[0] / 3
+
+
+def test_option_errors():
+    from paper_1004_1122_amd import lshom
+    even = np.zeros((16, 12), np.uint8)
+    even[4:8, 3:6] = 1
+    s = _solver(even, [1.0, 5.0])
+    with pytest.raises(lshom.LshomError) as ex:
+        s.solve((1.0, 0.0), norm=lshom.NORM_EQUILIBRIUM)
+    assert ex.value.status == lshom.LSHOM_ERR_UNSUPPORTED
+    # the basic scheme on an even grid with the residual norm is fine
+    _, _, info = s.solve((1.0, 0.0), tol=1e-6, method=lshom.METHOD_FFTH)
+    assert info["status"] == 0 and info["eta_e"] == -1.0
+    odd = _solver(CASES[0][1], CASES[0][2])
+    with pytest.raises(lshom.LshomError) as ex:
+        odd.solve((1.0, 0.0), method=lshom.METHOD_FFTH, precision=1)
+    assert ex.value.status == lshom.LSHOM_ERR_UNSUPPORTED
+    with pytest.raises(lshom.LshomError) as ex:
+        odd.solve((1.0, 0.0), method=lshom.METHOD_FFTH, x0=torch.zeros((2, 63, 63), dtype=torch.float64))
+    assert ex.value.status == lshom.LSHOM_ERR_UNSUPPORTED
+    with pytest.raises(lshom.LshomError) as ex:
+        odd.solve((1.0, 0.0), method=7)
+    assert ex.value.status == lshom.LSHOM_ERR_INVALID_ARG
+
+
+def test_batched_ffth_equals_single():
+    from paper_1004_1122_amd import lshom
+    probs = []
+    for i, rho in enumerate((3.0, 30.0, 300.0)):
+        m = ms.grf_two_phase(27, 0.2, 0.4, rho, seed=40 + i)
+        probs.append(dict(phase=m.phase, cond=[1.0, rho], E=(1.0, 0.0), tol=1e-7, want_field=True))
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=0)
+    fields, leff, infos = bs.run(method=lshom.METHOD_FFTH, norm=lshom.NORM_EQUILIBRIUM, max_iter=50000)
+    for i, pr in enumerate(probs):
+        s = _solver(pr["phase"], pr["cond"])
+        e, l1, info = s.solve(pr["E"], tol=pr["tol"], method=lshom.METHOD_FFTH, norm=lshom.NORM_EQUILIBRIUM,
+                              max_iter=50000)
+        assert infos[i]["status"] == 0
+        assert infos[i]["iterations"] == info["iterations"], i
+        assert torch.equal(fields[i], e), i
+        assert np.array_equal(leff[i][:2], l1), i
