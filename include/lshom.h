@@ -105,7 +105,7 @@ void lshom_default_opts(lshom_solve_opts* opts);
 
 /*
  * Host-only validation of a problem statement (no device is touched):
- * d in {2, 3}; 3 <= N[a] <= 4096 with prime factors in {2, 3, 5, 7};
+ * d in {2, 3}; 3 <= N[a] <= 4096 with prime factors in {2, 3, 5, 7, 11, 13, 17};
  * 1 <= n_phases <= 256 with finite cond > 0; l0 finite > 0, or exactly 0 to
  * mean "the default (min + max) / 2" of Sec. 2.3, Eq. (19); E (d values, may
  * be NULL) finite; tol finite >= 0 (tol < 0 skips the check).

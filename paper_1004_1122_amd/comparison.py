@@ -1,0 +1,174 @@
+"""The numerical study of Sec. 3 of the paper, rerun on the GPU solver.
+
+Workload (Sec. 3): transverse conduction in a square array of circular
+particles at volume fraction 0.5, one particle per cell on N = 255 x 255
+nodes, matrix conductivity 1, particle conductivity rho, E = (1, 0), reference
+medium l0(omega) = 1 - omega + rho omega (Eq. (20)).  Both methods run in
+FP64 through the C ABI:
+
+* ``omega``: iterations of CG relative to the basic scheme against omega for
+  both termination norms at eps = 1e-4 (the relative iteration counts of the
+  paper's first figure), and eta_r / eta_e at convergence under the eta_r
+  test (its companion panel);
+* ``contrast``: total iterations against rho at omega = 0.5 (eta_r test) with
+  the fitted growth exponents (about 1/2 for CG, 1 for the basic scheme,
+  following the rates of Eq. (23));
+* ``time``: device time per iteration of each method (the paper's CPU-time
+  comparison);
+* ``progress``: (eta_r, eta_e) of every iterate for rho = 10 and 1e3, with
+  the observed mean contraction beside the bounds of Eq. (23).
+
+The eta_r test of Eq. (22) is l0 ||r|| / ||e0|| <= eps, i.e. the solver's
+relative residual test with tol = eps / l0.
+
+  python -m paper_1004_1122_amd.comparison --out comparison.json
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import microstructure as ms
+
+EPS = 1e-4
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _solve(lshom, s, l0, method, norm, max_iter, history=0):
+    s.set_reference(l0)
+    tol = EPS / l0 if norm == lshom.NORM_RESIDUAL else EPS
+    _, _, info = s.solve((1.0, 0.0), tol=tol, method=method, norm=norm, max_iter=max_iter, want_field=False,
+                         allow_fail=True, history=history)
+    return info
+
+
+def omega_sweep(lshom, n, rhos, omegas, max_iter):
+    rows = []
+    for rho in rhos:
+        m = ms.circle_array(n=n, vf=0.5, rho=rho)
+        s = lshom.Solver(m.phase, [1.0, rho])
+        for om in omegas:
+            l0 = 1.0 - om + rho * om
+            rec = {"rho": rho, "omega": om, "l0": l0}
+            for nname, norm in (("eta_r", lshom.NORM_RESIDUAL), ("eta_e", lshom.NORM_EQUILIBRIUM)):
+                cg = _solve(lshom, s, l0, lshom.METHOD_CG, norm, max_iter)
+                ff = _solve(lshom, s, l0, lshom.METHOD_FFTH, norm, max_iter)
+                rec[nname] = {"cg": cg["iterations"], "ffth": ff["iterations"],
+                              "cg_status": cg["status"], "ffth_status": ff["status"],
+                              "ratio": (cg["iterations"] / ff["iterations"]
+                                        if ff["status"] == 0 and cg["status"] == 0 else None)}
+                if nname == "eta_r":
+                    # eta_r / eta_e at convergence (both of the returned field)
+                    rec["cg_eta_r_over_eta_e"] = cg["eta_r"] / cg["eta_e"] if cg["eta_e"] > 0 else None
+                    rec["ffth_eta_r_over_eta_e"] = ff["eta_r"] / ff["eta_e"] if ff["eta_e"] > 0 else None
+            rows.append(rec)
+            log(f"omega rho={rho:g} omega={om:g}: {json.dumps({k: rec[k] for k in ('eta_r', 'eta_e')})}")
+        s.close()
+    return rows
+
+
+def contrast_sweep(lshom, n, rhos, max_iter):
+    rows = []
+    for rho in rhos:
+        m = ms.circle_array(n=n, vf=0.5, rho=rho)
+        s = lshom.Solver(m.phase, [1.0, rho])
+        l0 = 0.5 * (1.0 + rho)
+        cg = _solve(lshom, s, l0, lshom.METHOD_CG, lshom.NORM_RESIDUAL, max_iter)
+        ff = _solve(lshom, s, l0, lshom.METHOD_FFTH, lshom.NORM_RESIDUAL, max_iter)
+        rows.append({"rho": rho, "cg": cg["iterations"], "ffth": ff["iterations"],
+                     "cg_status": cg["status"], "ffth_status": ff["status"]})
+        log(f"contrast rho={rho:g}: cg {cg['iterations']} ffth {ff['iterations']}")
+        s.close()
+    ok = [r for r in rows if r["cg_status"] == 0 and r["ffth_status"] == 0]
+    lr = np.log10([r["rho"] for r in ok])
+    fit = {}
+    for key in ("cg", "ffth"):
+        if len(ok) >= 2:
+            fit[key + "_exponent"] = float(np.polyfit(lr, np.log10([r[key] for r in ok]), 1)[0])
+    return {"rows": rows, "fit": fit}
+
+
+def time_per_iteration(lshom, n, rho, reps=3):
+    import torch
+    m = ms.circle_array(n=n, vf=0.5, rho=rho)
+    s = lshom.Solver(m.phase, [1.0, rho])
+    l0 = 0.5 * (1.0 + rho)
+    out = {}
+    for name, method in (("cg", lshom.METHOD_CG), ("ffth", lshom.METHOD_FFTH)):
+        _solve(lshom, s, l0, method, lshom.NORM_RESIDUAL, 200000)  # graphs, plans
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = _solve(lshom, s, l0, method, lshom.NORM_RESIDUAL, 200000)
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        out[name] = {"iterations": info["iterations"], "ms_total": best * 1e3,
+                     "us_per_iteration": best * 1e6 / max(info["iterations"], 1)}
+    out["cg_over_ffth_per_iteration"] = out["cg"]["us_per_iteration"] / out["ffth"]["us_per_iteration"]
+    out["cg_over_ffth_total"] = out["cg"]["ms_total"] / out["ffth"]["ms_total"]
+    s.close()
+    return out
+
+
+def progress(lshom, n, rho, max_iter):
+    m = ms.circle_array(n=n, vf=0.5, rho=rho)
+    s = lshom.Solver(m.phase, [1.0, rho])
+    l0 = 0.5 * (1.0 + rho)
+    out = {"rho": rho}
+    bounds = {"cg": (math.sqrt(rho) - 1) / (math.sqrt(rho) + 1), "ffth": (rho - 1) / (rho + 1)}
+    for name, method in (("cg", lshom.METHOD_CG), ("ffth", lshom.METHOD_FFTH)):
+        info = _solve(lshom, s, l0, method, lshom.NORM_RESIDUAL, max_iter, history=max_iter + 1)
+        h = info["history"]
+        k = len(h) - 1
+        rate = (h[-1, 0] / h[0, 0]) ** (1.0 / k) if k > 0 else None
+        out[name] = {"iterations": info["iterations"], "eta_r": h[:, 0].tolist(), "eta_e": h[:, 1].tolist(),
+                     "mean_rate_eta_r": rate, "rate_bound": bounds[name]}
+        log(f"progress rho={rho:g} {name}: {info['iterations']} iterations, mean eta_r rate {rate:.4f} "
+            f"(bound {bounds[name]:.4f})")
+    s.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--max-iter", type=int, default=200000)
+    ap.add_argument("--quick", action="store_true", help="fewer cases (a smoke run)")
+    args = ap.parse_args()
+    from . import lshom
+    n = args.n
+    if args.quick:
+        omegas, rhos_om, rhos_c = [0.5, 1.0], [10.0], [10.0, 100.0]
+    else:
+        omegas = [0.5, 0.6, 0.75, 1.0, 1.25, 1.5]
+        rhos_om = [10.0, 100.0, 1000.0]
+        rhos_c = [1e1, 1e2, 1e3, 1e4]
+    t0 = time.perf_counter()
+    report = {"workload": f"circle array vf 0.5, {n}x{n}, E=(1,0), eps={EPS:g}, FP64",
+              "omega": omega_sweep(lshom, n, rhos_om, omegas, args.max_iter),
+              "contrast": contrast_sweep(lshom, n, rhos_c, args.max_iter),
+              "time": time_per_iteration(lshom, n, 10.0),
+              "progress": [progress(lshom, n, rho, 20000) for rho in (10.0, 1000.0)]}
+    report["seconds"] = time.perf_counter() - t0
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(report, f)
+    summary = {"contrast": report["contrast"], "time": report["time"],
+               "omega_ratios": [(r["rho"], r["omega"], r["eta_r"]["ratio"], r["eta_e"]["ratio"],
+                                 r["cg_eta_r_over_eta_e"]) for r in report["omega"]]}
+    print(json.dumps(summary), flush=True)
+
+
+if __name__ == "__main__":
+    main()

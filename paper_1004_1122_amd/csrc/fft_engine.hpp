@@ -122,7 +122,7 @@ __device__ __forceinline__ void dft(cx<T>* x) {
     const cx<T> a = x[0], b = x[1];
     x[0] = cadd(a, b);
     x[1] = csub(a, b);
-  } else if constexpr (R == 3 || R == 5 || R == 7) {
+  } else if constexpr (R == 3 || R == 5 || R == 7 || R == 11 || R == 13 || R == 17) {
     dft_prime<T, R, S>(x);
   } else if constexpr (R == 4) {
     dft_ct<T, 2, 2, S>(x);
@@ -133,7 +133,7 @@ __device__ __forceinline__ void dft(cx<T>* x) {
   } else if constexpr (R == 9) {
     dft_ct<T, 3, 3, S>(x);
   } else {
-    static_assert(R <= 9, "unsupported radix");
+    static_assert(R <= 9 || R == 11 || R == 13 || R == 17, "unsupported radix");
   }
 }
 
@@ -181,7 +181,7 @@ struct FftPlan {
 // Butterflies held per thread across the stage barrier, per radix.  The host
 // sizes every batch so that nseq * n / R <= jobs_per_thread(R) * threads.
 __host__ __device__ constexpr int jobs_per_thread(int R) {
-  return R <= 3 ? 4 : (R <= 5 ? 3 : 2);
+  return R <= 3 ? 4 : (R <= 5 ? 3 : (R <= 9 ? 2 : 1));
 }
 
 // Largest number of points (nseq * n) one batch may hold for a plan.
@@ -258,20 +258,24 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
 
 // Radix sets a kernel is compiled for: the register footprint of a kernel is
 // that of its largest butterfly, so grids whose lengths are powers of 3 (or
-// of 2) get kernels without the radix-5/7 code.
-enum RadixSet : int { RADIX_POW3 = 0, RADIX_POW2 = 1, RADIX_ALL = 2 };
+// of 2) get kernels without the radix-5/7 code, and only grids with a prime
+// factor 11, 13 or 17 get the kernels that carry those butterflies.
+enum RadixSet : int { RADIX_POW3 = 0, RADIX_POW2 = 1, RADIX_ALL = 2, RADIX_WIDE = 3 };
+
+__host__ __device__ constexpr bool is_wide_prime(int R) { return R == 11 || R == 13 || R == 17; }
 
 __host__ __device__ inline bool radix_in_set(int R, int set) {
   if (set == RADIX_POW3) return R == 3 || R == 9;
   if (set == RADIX_POW2) return R == 2 || R == 4 || R == 8;
-  return R >= 2 && R <= 9;
+  if (set == RADIX_ALL) return R >= 2 && R <= 9;
+  return (R >= 2 && R <= 9) || is_wide_prime(R);
 }
 
 // Transform nseq sequences of length plan.n in LDS.  Callers synchronise
 // before (data written) and may read the result right after.  Every radix of
 // the plan must belong to RS.
 template <typename T, int S, int NT, int RS>
-__device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
+__device__ __forceinline__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
                         const cx<T>* __restrict__ tw, int tid) {
   int Ns = 1;
   for (int st = 0; st < plan.nstages; ++st) {
@@ -293,7 +297,13 @@ __device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
         case 7: fft_stage<T, 7, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
         case 8: fft_stage<T, 8, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
         case 9: fft_stage<T, 9, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]); break;
-        default: break;
+        default:
+          if constexpr (RS == RADIX_WIDE) {
+            if (R == 11) fft_stage<T, 11, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+            else if (R == 13) fft_stage<T, 13, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+            else if (R == 17) fft_stage<T, 17, S, NT>(buf, nseq, ss, plan.n, Ns, tw, tid, plan.nr[st], plan.ns[st]);
+          }
+          break;
       }
     }
     Ns *= R;
@@ -301,12 +311,13 @@ __device__ void fft_lds(cx<T>* buf, int nseq, int ss, const FftPlan& plan,
 }
 
 __host__ __device__ inline int plan_radix_set(const FftPlan& p) {
-  bool p3 = true, p2 = true;
+  bool p3 = true, p2 = true, wide = false;
   for (int s = 0; s < p.nstages; ++s) {
     p3 = p3 && radix_in_set(p.radix[s], RADIX_POW3);
     p2 = p2 && radix_in_set(p.radix[s], RADIX_POW2);
+    wide = wide || is_wide_prime(p.radix[s]);
   }
-  return p3 ? RADIX_POW3 : (p2 ? RADIX_POW2 : RADIX_ALL);
+  return p3 ? RADIX_POW3 : (p2 ? RADIX_POW2 : (wide ? RADIX_WIDE : RADIX_ALL));
 }
 
 }  // namespace lshom

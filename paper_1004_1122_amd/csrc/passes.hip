@@ -984,6 +984,7 @@ hipError_t launch_row(const RowArgs<T>& a, hipStream_t s) {
   switch (plan_radix_set(a.plan)) {
     case RADIX_POW3: launch_row_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
     case RADIX_POW2: launch_row_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;
+    case RADIX_WIDE: launch_row_rs<T, RADIX_WIDE>(a, lds, nb, nt, s); break;
     default: launch_row_rs<T, RADIX_ALL>(a, lds, nb, nt, s); break;
   }
   return hipGetLastError();
@@ -997,6 +998,7 @@ hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
   switch (plan_radix_set(a.plan)) {
     case RADIX_POW3: launch_col_rs<T, RADIX_POW3>(a, lds, nb, nt, s); break;
     case RADIX_POW2: launch_col_rs<T, RADIX_POW2>(a, lds, nb, nt, s); break;
+    case RADIX_WIDE: launch_col_rs<T, RADIX_WIDE>(a, lds, nb, nt, s); break;
     default: launch_col_rs<T, RADIX_ALL>(a, lds, nb, nt, s); break;
   }
   return hipGetLastError();

@@ -6,7 +6,7 @@ namespace lshom {
 
 bool fft_size_ok(int64_t n) {
   if (n < 1) return false;
-  for (int p : {2, 3, 5, 7})
+  for (int p : {2, 3, 5, 7, 11, 13, 17})
     while (n % p == 0) n /= p;
   return n == 1;
 }
@@ -32,7 +32,7 @@ FftPlan default_plan(int n) {
   p.n = n;
   p.nstages = 0;
   int rest = n;
-  const int order[] = {9, 8, 7, 5, 6, 4, 3, 2};
+  const int order[] = {9, 8, 7, 5, 6, 4, 3, 2, 17, 13, 11};
   while (rest > 1 && p.nstages < kMaxStages) {
     for (int r : order) {
       if (rest % r == 0) {
@@ -54,7 +54,7 @@ bool make_plan(int n, const int* radices, int nstages, FftPlan* plan) {
   long long prod = 1;
   for (int i = 0; i < nstages; ++i) {
     const int r = radices[i];
-    if (r < 2 || r > 9) return false;
+    if (r < 2 || (r > 9 && !is_wide_prime(r))) return false;
     prod *= r;
   }
   if (prod != n) return false;

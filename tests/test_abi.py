@@ -46,7 +46,8 @@ def test_default_opts():
     (1, (63,), [1.0], 1.0, None, 1e-6, -1),                   # d not in {2,3}
     (4, (3, 3, 3, 3), [1.0], 1.0, None, 1e-6, -1),
     (2, (2, 63), [1.0], 1.0, None, 1e-6, -1),                 # N < 3
-    (2, (11, 63), [1.0], 1.0, None, 1e-6, -7),                # prime factor 11
+    (2, (19, 63), [1.0], 1.0, None, 1e-6, -7),                # prime factor 19
+    (2, (255, 39), [1.0], 1.0, None, 1e-6, 0),                # prime factors 17 and 13
     (2, (8192, 3), [1.0], 1.0, None, 1e-6, -7),               # too long
     (2, (9, 9), [1.0, 0.0], 1.0, None, 1e-6, -1),             # cond <= 0
     (2, (9, 9), [1.0, math.inf], 1.0, None, 1e-6, -1),        # cond not finite

@@ -44,7 +44,9 @@ def _random_phases(shape, n_phases, seed, lo=1.0, hi=50.0):
 # ---------------------------------------------------------------------------
 
 APPLY_SHAPES = [(63, 63), (81, 81), (45, 27), (27, 45), (7, 5), (16, 12), (10, 14), (729, 729),
-                (15, 15, 15), (9, 15, 21), (8, 6, 10), (27, 27, 27), (5, 7, 3)]
+                (15, 15, 15), (9, 15, 21), (8, 6, 10), (27, 27, 27), (5, 7, 3),
+                # prime factors 11, 13, 17 (the paper's 255 = 3 5 17 grid)
+                (255, 255), (33, 39), (17, 26), (13, 11, 17), (34, 22, 12)]
 
 
 @pytest.mark.parametrize("shape", APPLY_SHAPES, ids=lambda s: "x".join(map(str, s)))
@@ -124,6 +126,21 @@ def test_3d(shape, rho):
         phase = (rng.random(shape) < 0.3).astype(np.uint8)
     m = ms.Microstructure(phase, np.array([1.0, rho]))
     s, lam, l0, e, leff, info, ref = _parity_case(m, [0.3, -1.0, 0.5], 1e-7)
+    _assert_parity(e, leff, info, ref, lam)
+
+
+@pytest.mark.parametrize("rho", [10.0, 1e3])
+def test_paper_circle_array_255(rho):
+    """The workload of Sec. 3 at its own grid (255 = 3 5 17: radix-17 stages)."""
+    m = ms.circle_array(n=255, vf=0.5, rho=rho)
+    s, lam, l0, e, leff, info, ref = _parity_case(m, [1.0, 0.0], 1e-8)
+    _assert_parity(e, leff, info, ref, lam)
+
+
+def test_wide_prime_grids_3d():
+    phase, cond = _random_phases((13, 11, 17), 3, seed=17)
+    m = ms.Microstructure(phase, cond)
+    s, lam, l0, e, leff, info, ref = _parity_case(m, [0.2, 1.0, -0.4], 1e-9)
     _assert_parity(e, leff, info, ref, lam)
 
 
