@@ -56,7 +56,10 @@ __all__ = [
     "green_hat",
     "apply_B",
     "apply_A",
+    "apply_BT",
+    "apply_AT",
     "cg",
+    "bicg",
     "ffth",
     "dense_operator",
     "dense_solve",
@@ -184,6 +187,27 @@ def apply_A(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
     return p + apply_B(p, lam, l0)
 
 
+def apply_BT(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+    """``B^T p = dL F^{-1} Gamma0_hat F p``: the factors of Eq. (16) in the
+    other order (``dL`` is diagonal and ``F^{-1} Gamma0_hat F`` is a real
+    symmetric matrix), the product BiCG needs besides ``B`` (Sec. 2.3)."""
+    shape = lam.shape
+    d = len(shape)
+    axes = tuple(range(1, d + 1))
+    p_hat = _fftn(np.asarray(p, dtype=np.float64), axes)
+    ks, inv = _green_factors(shape, l0)
+    w_hat = np.zeros_like(p_hat)
+    for a in range(d):
+        for b in range(d):
+            w_hat[a] += (ks[a] * ks[b] * inv) * p_hat[b]
+    return (lam - l0)[None, ...] * _ifftn(w_hat, axes).real
+
+
+def apply_AT(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+    """``(I + B)^T p``."""
+    return p + apply_BT(p, lam, l0)
+
+
 def _dot(u, v) -> float:
     return float(np.dot(u.ravel(), v.ravel()))
 
@@ -295,6 +319,60 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     if eta_history:
         out["eta_history"] = etas
     return out
+
+
+def bicg(lam, l0, E, tol=1e-8, max_iter=10000, n_iter=None):
+    """Solve ``(I + B) e = e0`` by the biconjugate gradient method.
+
+    Sec. 2.3 proposes it beside CG and Sec. 3 names Saad's Algorithm 7.3:
+    ``r0 = b - A x0``, shadow residual ``r0* = r0``, ``p0 = r0``,
+    ``p0* = r0*``; per iteration ``alpha = (r, r*) / (A p, p*)``,
+    ``x += alpha p``, ``r -= alpha A p``, ``r* -= alpha A^T p*``,
+    ``beta = (r_new, r*_new) / (r, r*)``, ``p = r + beta p``,
+    ``p* = r* + beta p*``.  The test ``||r|| <= tol ||b||`` precedes each
+    iteration (as in ``cg``); ``n_iter`` forces that many iterations.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    shape = lam.shape
+    b = _rhs(E, shape)
+    bnorm = math.sqrt(_dot(b, b))
+    x = b.copy()
+    if bnorm == 0.0:
+        return dict(e=np.zeros_like(b), iterations=0, rel_res=0.0, converged=True, breakdown=False)
+    r = b - apply_A(x, lam, l0)
+    rs = r.copy()
+    p = r.copy()
+    ps = rs.copy()
+    rho = _dot(r, rs)
+    m = 0
+    limit = max_iter if n_iter is None else n_iter
+    converged = breakdown = False
+    while True:
+        rn = math.sqrt(_dot(r, r))
+        if n_iter is None and rn <= tol * bnorm:
+            converged = True
+            break
+        if m >= limit:
+            break
+        ap = apply_A(p, lam, l0)
+        sigma = _dot(ap, ps)
+        if sigma == 0.0 or not math.isfinite(sigma):
+            breakdown = True
+            break
+        alpha = rho / sigma
+        x += alpha * p
+        r -= alpha * ap
+        rs -= alpha * apply_AT(ps, lam, l0)
+        rho_new = _dot(r, rs)
+        beta = rho_new / rho
+        p = r + beta * p
+        ps = rs + beta * ps
+        rho = rho_new
+        m += 1
+    rel = math.sqrt(_dot(r, r)) / bnorm
+    if n_iter is not None:
+        converged = rel <= tol
+    return dict(e=x, iterations=m, rel_res=rel, converged=converged, breakdown=breakdown)
 
 
 def true_residual(lam, l0, E, e) -> float:

@@ -72,6 +72,27 @@ def test_apply_matches_dense_matrix(shape):
     assert nn == flat.size
 
 
+@pytest.mark.parametrize("shape", [(5, 5), (3, 7), (5, 3, 4)])
+def test_transposed_apply_matches_dense_transpose(shape):
+    """B^T of BiCG (Sec. 2.3) against the transpose of the explicit matrix."""
+    lam = _rand_lam(shape, 12)
+    l0 = 9.0
+    d = len(shape)
+    rng = np.random.default_rng(13)
+    p = rng.standard_normal((d,) + shape)
+    M, flat = o.dense_operator(lam, l0)
+    vec = np.concatenate([p[a].ravel()[flat] for a in range(d)])
+    ref = (M.T @ vec).real
+    got = o.apply_AT(p, lam, l0)
+    got_vec = np.concatenate([got[a].ravel()[flat] for a in range(d)])
+    np.testing.assert_allclose(got_vec, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # and the pair is adjoint for the Euclidean product
+    q = rng.standard_normal((d,) + shape)
+    lhs = float(np.vdot(o.apply_A(p, lam, l0), q))
+    rhs = float(np.vdot(p, o.apply_AT(q, lam, l0)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
 def test_dense_matrix_is_nonsymmetric():
     """Sec. 2.2: B is non-symmetric on the full space."""
     lam = _rand_lam((5, 5), 4)
@@ -407,3 +428,39 @@ def test_ffth_eta_e_termination():
     # the returned field is the next iterate e0 - B e^(m)
     cg_sol = o.cg(lam, l0, [1.0, 0.0], tol=1e-12)["e"]
     assert np.linalg.norm(res["e"] - cg_sol) / np.linalg.norm(cg_sol) < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# BiCG (Sec. 2.3; Sec. 3: Saad, Algorithm 7.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,rho", [((7, 7), 30.0), ((5, 5, 3), 10.0)])
+def test_bicg_matches_dense_solve(shape, rho):
+    rng = np.random.default_rng(31)
+    lam = np.where(rng.random(shape) < 0.4, rho, 1.0)
+    l0 = o.optimal_reference(lam)
+    E = np.arange(1.0, len(shape) + 1.0)
+    res = o.bicg(lam, l0, E, tol=1e-13)
+    ref, imag = o.dense_solve(lam, l0, E)
+    assert imag < 1e-10
+    assert res["converged"]
+    assert np.linalg.norm(res["e"] - ref) / np.linalg.norm(ref) < 1e-11
+
+
+@pytest.mark.parametrize("rho", [10.0, 1000.0])
+def test_bicg_iterates_equal_cg(rho):
+    """Sec. 3 reports that CG and BiCG generate the same iterates on this
+    system (with the shadow residual r0* = r0); the differences are rounding."""
+    lam = ms.square_inclusion(rho=rho).lam()
+    l0 = o.optimal_reference(lam)
+    for k in (1, 4, 12):
+        a = o.cg(lam, l0, [1.0, 0.0], n_iter=k)["e"]
+        b = o.bicg(lam, l0, [1.0, 0.0], n_iter=k)["e"]
+        assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-12
+    a = o.cg(lam, l0, [1.0, 0.0], tol=1e-8)
+    b = o.bicg(lam, l0, [1.0, 0.0], tol=1e-8)
+    # over ~100 iterations at high contrast rounding moves the stopping
+    # iterate by a few (the paper sees the same at rho = 1e4)
+    assert abs(a["iterations"] - b["iterations"]) <= (0 if rho < 100 else 0.06 * a["iterations"])
+    # both meet the residual test; the fields agree to the conditioning times tol
+    assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(a["e"]) < 1e-5
