@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--streams", type=int, default=1,
                     help="batches per form (all batches run concurrently; the box has 4 hardware queues)")
     ap.add_argument("--no-single", action="store_true", help="skip the per-solve time-to-1e-6 runs")
+    ap.add_argument("--save-schedules", default=None,
+                    help="write the autotuned schedules of the timed batches to this file prefix (.fp64 / .mixed)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the run, copy a device buffer of this size (the counter calibration kernel)")
     args = ap.parse_args()
@@ -172,6 +174,8 @@ def main():
             bs = lshom.BatchSolver()
             bs.prepare(part, precision=prec)
             sc = bs.autotune(precision=prec, reps=10)[0]
+            if args.save_schedules and form not in sched:
+                bs.save_schedules(f"{args.save_schedules}.{form}")
             sched.setdefault(form, sc)
             solvers[(form, j)] = bs
     log(f"workload 729x729, vf={m.info['vf']:.4f}, {len(probs)} solves per form in {args.streams} batches; "

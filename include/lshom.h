@@ -52,6 +52,7 @@ typedef int32_t lshom_status;
 
 #define LSHOM_METHOD_CG 0       /* conjugate gradients on Eq. (15) (Sec. 2.3, Sec. 3) */
 #define LSHOM_METHOD_FFTH 1     /* the basic scheme: Neumann series of Sec. 2.3, Eq. (18) */
+#define LSHOM_METHOD_BICG 2     /* biconjugate gradients on the nodal system (Sec. 2.3; Sec. 3) */
 
 #define LSHOM_NORM_RESIDUAL 0    /* stop when ||r|| <= tol ||e0|| (eta_r / l0, Eq. (22)) */
 #define LSHOM_NORM_EQUILIBRIUM 1 /* stop when eta_e <= tol (Sec. 3, Eq. (21)) */
@@ -66,7 +67,8 @@ typedef struct lshom_solve_opts {
   double refresh_drop;   /* 0.1: mixed only, refresh when ||r|| fell by this factor */
   int32_t graph_block;   /* 16: iterations per captured HIP graph launch (0: no graph) */
   int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop (and eta_e, odd N) */
-  int32_t method;        /* LSHOM_METHOD_CG; LSHOM_METHOD_FFTH: FP64 only, no x0 */
+  int32_t method;        /* LSHOM_METHOD_CG; FFTH and BICG: FP64 only, no x0; BICG: single
+                            solves, residual norm, workspace from lshom_workspace_size_for */
   int32_t norm;          /* LSHOM_NORM_RESIDUAL; EQUILIBRIUM: FP64 and odd N only */
   /*
    * NULL, or (single solves, FP64, odd N) a caller-owned device buffer of
@@ -141,7 +143,15 @@ lshom_status lshom_set_reference(lshom_ctx* ctx, double l0);
 /* Bytes of device workspace the current problem needs (both precisions). */
 lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* bytes);
 
-/* Attach caller-owned device workspace (256-byte aligned, >= the size above). */
+/*
+ * Bytes of device workspace a solve with these options needs (opts NULL =
+ * defaults).  BiCG iterates on d-component nodal fields and needs seven of
+ * them (x, r, r*, p, p*, A p, A^T p*) on top of the CG workspace.
+ */
+lshom_status lshom_workspace_size_for(const lshom_ctx* ctx, const lshom_solve_opts* opts, size_t* bytes);
+
+/* Attach caller-owned device workspace (256-byte aligned, >= the size above;
+ * the largest of the layouts above that fits is used). */
 lshom_status lshom_set_workspace(lshom_ctx* ctx, void* dev, size_t bytes);
 
 /*
@@ -149,6 +159,8 @@ lshom_status lshom_set_workspace(lshom_ctx* ctx, void* dev, size_t bytes);
  * or with opts->method = LSHOM_METHOD_FFTH by the basic scheme
  * e^(m+1) = e0 - B e^(m) (Eq. (18)).  Stops when ||r|| <= tol ||e0||
  * (recursive residual; for the basic scheme the step e^(m+1) - e^(m)), or
+ * with LSHOM_METHOD_BICG by BiCG on the nodal fields (shadow residual
+ * r0* = r0; info->applies_fp64 counts both products per iteration), or
  * with LSHOM_NORM_EQUILIBRIUM when eta_e <= tol, or after max_iter.  The
  * basic scheme tests iterate m in the apply that forms m + 1 and returns
  * e^(m+1).

@@ -34,9 +34,12 @@ struct Layout {
   size_t off_tw64[3] = {0, 0, 0}, off_tw32[3] = {0, 0, 0};
   size_t off_v64[4] = {0, 0, 0, 0}, off_w64[3] = {0, 0, 0};
   size_t off_v32[4] = {0, 0, 0, 0}, off_w32[3] = {0, 0, 0};
+  // BiCG: real d x |N| FP64 fields x, r, r*, p, p*, A p, A^T p* (single problems)
+  size_t off_bicg[7] = {0, 0, 0, 0, 0, 0, 0};
   long long part_stride = 0;  // doubles per partial region
-  long long pstride = 0;      // doubles per problem (4 regions)
+  long long pstride = 0;      // doubles per problem (all regions)
   bool has32 = false;
+  bool has_bicg = false;
 };
 
 template <typename T>
@@ -116,7 +119,7 @@ Schedule current_schedule(const Group& g, int precision);
 // Times the passes of one CG iteration for candidate schedules on the group's
 // current data and returns the fastest (per pass, independently).
 lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best);
-Layout compute_layout(const Group& g, bool with32);
+Layout compute_layout(const Group& g, bool with32, bool with_bicg = false);
 
 // Uploads twiddles, conductivity tables (cond[p * n_phases + i]) and the
 // problem table; checks every phase index.
@@ -128,6 +131,8 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
 lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lshom_solve_opts& o,
                          const double* E_single, const double* x0, double* e_single);
 lshom_status apply_real(Group& g, const double* p, double* q);
+// BiCG (single problem, FP64, workspace with the BiCG fields): e_out may be null.
+lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out);
 lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out);
 // Algorithmic HBM bytes of each pass class for one problem and one CG iteration.
 void pass_model_bytes(const Group& g, int precision, double* out);

@@ -94,7 +94,7 @@ Schedule current_schedule(const Group& g, int precision) {
   return s;
 }
 
-Layout compute_layout(const Group& g, bool with32) {
+Layout compute_layout(const Group& g, bool with32, bool with_bicg) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -132,6 +132,9 @@ Layout compute_layout(const Group& g, bool with32) {
     for (int i = 0; i < 4; ++i) L.off_v32[i] = take(v32);
     for (int a = 0; a < g.d; ++a) L.off_w32[a] = take(v32);
   }
+  L.has_bicg = with_bicg;
+  if (with_bicg)
+    for (int i = 0; i < 7; ++i) L.off_bicg[i] = take((size_t)g.d * g.nvox * np * sizeof(double));
   L.total = off;
   return L;
 }
@@ -536,36 +539,54 @@ hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>*
 
 // Real FP64 field v (d x |N|) -> spectral coordinate of P v (of P dL v / l0).
 hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bool with_dl,
-                            cx<double>* out) {
+                            cx<double>* out, int gate = GATE_ALWAYS) {
   hipError_t e;
   RowArgs<double> r = row_args(g, b);
   r.mode = ROW_FWD;
   r.flags = with_dl ? ROWF_DL : 0;
   for (int t = 0; t < g.d; ++t) r.real_in[t] = v + (size_t)t * g.nvox;
-  r.gate = GATE_ALWAYS;
+  r.gate = gate;
   if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
-  return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, with_dl ? 1 : 0, 0, PART_AUX,
-                                     GATE_ALWAYS);
+  return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, with_dl ? 1 : 0, 0, PART_AUX, gate);
 }
 
 // Real field out = add + E + u(x); with leff, <lambda out> into state.leff.
+// dl_scale: out = add + (lambda - l0) / l0 (E + u(x)).
 hipError_t enq_field_out(Group& g, const Bufs<double>& b, const cx<double>* x, const double* E,
-                         const double* add, double* out, bool leff) {
+                         const double* add, double* out, bool leff, bool dl_scale = false,
+                         int gate = GATE_ALWAYS) {
   hipError_t e;
-  if ((e = enq_inverse_from_c<double>(g, b, x, nullptr, nullptr, GATE_ALWAYS)) != hipSuccess) return e;
+  if ((e = enq_inverse_from_c<double>(g, b, x, nullptr, nullptr, gate)) != hipSuccess) return e;
   RowArgs<double> r = row_args(g, b);
   r.mode = ROW_INV;
-  r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0);
+  r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0) | (dl_scale ? ROWF_DL_SCALE : 0);
   if (!E) r.flags |= ROWF_STATE_E;
   for (int t = 0; t < g.d; ++t) {
     r.E[t] = E ? E[t] : 0.0;
     r.real_out[t] = out ? out + (size_t)t * g.nvox : nullptr;
     r.real_add[t] = add ? add + (size_t)t * g.nvox : nullptr;
   }
-  r.gate = GATE_ALWAYS;
+  r.gate = gate;
   if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
-  if (leff) return enq_finalize(g, FZ_LEFF, row_blocks(r), GATE_ALWAYS);
+  if (leff) return enq_finalize(g, FZ_LEFF, row_blocks(r), gate);
   return hipSuccess;
+}
+
+const double kNoE[3] = {0.0, 0.0, 0.0};
+
+// q = (I + B) v = v + Gamma0 dL v on real nodal fields (Sec. 2.2, Eq. (16)).
+hipError_t enq_apply_A_real(Group& g, const Bufs<double>& b, const double* v, double* q, int gate) {
+  hipError_t e = enq_project_real(g, b, v, true, b.v[3], gate);
+  if (e != hipSuccess) return e;
+  return enq_field_out(g, b, b.v[3], kNoE, v, q, false, false, gate);
+}
+
+// q = (I + B)^T v = v + dL Gamma0 v = v + (dL / l0) P v: the same passes in
+// the other order (projection first, polarisation at the nodes last).
+hipError_t enq_apply_AT_real(Group& g, const Bufs<double>& b, const double* v, double* q, int gate) {
+  hipError_t e = enq_project_real(g, b, v, false, b.v[3], gate);
+  if (e != hipSuccess) return e;
+  return enq_field_out(g, b, b.v[3], kNoE, v, q, false, true, gate);
 }
 
 MixArgs mix_args(Group& g, const Bufs<double>& b64, const Bufs<float>& b32, int gate) {
@@ -919,10 +940,103 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
 lshom_status apply_real(Group& g, const double* p, double* q) {
   lshom_ctx* c = g.ctx;
   Bufs<double> b = get_bufs<double>(g);
-  static const double kNoE[3] = {0.0, 0.0, 0.0};
   HIP_TRY(c, enq_project_real(g, b, p, true, b.v[3]));
   HIP_TRY(c, enq_field_out(g, b, b.v[3], kNoE, p, q, false));
   HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  return LSHOM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// BiCG on the nodal system (Sec. 2.3; Saad's Algorithm 7.3 as cited in Sec. 3)
+// ---------------------------------------------------------------------------
+
+lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out) {
+  lshom_ctx* c = g.ctx;
+  Bufs<double> b = get_bufs<double>(g);
+  auto field = [&](int i) { return reinterpret_cast<double*>(g.ws + g.lay.off_bicg[i]); };
+  double* x = field(0);
+  double* r = field(1);
+  double* rs = field(2);
+  double* p = field(3);
+  double* ps = field(4);
+  double* ap = field(5);
+  double* atp = field(6);
+  BicgArgs v{};
+  v.n = g.nvox;
+  v.d = g.d;
+  v.x = x;
+  v.r = r;
+  v.rs = rs;
+  v.p = p;
+  v.ps = ps;
+  v.ap = ap;
+  v.atp = atp;
+  v.phase = g.phase;
+  v.cond = b.cond;
+  v.st = dev_state(g);
+  v.parts = dev_parts(g);
+  v.fd_n = make_fastdiv((uint32_t)g.nvox);
+  const long long nb = bicg_blocks(v);
+  auto vec = [&](int mode, int gate) {
+    BicgArgs a = v;
+    a.mode = mode;
+    a.gate = gate;
+    return launch_bicg(a, stream_of(g));
+  };
+  // scalar steps over real-field sums (no spectral 1 / |N| factor)
+  auto fin = [&](int mode, long long n, int gate, double inv_n) {
+    FinArgs f{};
+    f.st = dev_state(g);
+    f.parts = dev_parts(g);
+    f.mode = mode;
+    f.n = (int)n;
+    f.d = g.d;
+    f.inv_n = inv_n;
+    f.gate = gate;
+    f.bt = batch_of(g);
+    return launch_finalize(f, stream_of(g));
+  };
+  DevState* init_dev = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);
+  HIP_TRY(c, hipMemcpyAsync(init_dev, &init, sizeof(DevState), hipMemcpyHostToDevice, stream_of(g)));
+  HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, 1, stream_of(g)));
+  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  // x0 = E, r0 = b - A x0, r0* = r0 = p0 = p0*
+  HIP_TRY(c, vec(BV_FILL_E, GATE_ALWAYS));
+  HIP_TRY(c, enq_apply_A_real(g, b, x, ap, GATE_ALWAYS));
+  HIP_TRY(c, vec(BV_START, GATE_ALWAYS));
+  HIP_TRY(c, fin(FZ_BICG_START, nb, GATE_ALWAYS, 1.0));
+  HIP_TRY(c, sync_states(g));
+  PassTimer& tm = c->timer;
+  g.timer = tm.on ? &tm : nullptr;
+  const int K = tm.on ? 0 : o.graph_block;
+  const int per = o.graph_block > 0 ? o.graph_block : 8;
+  tm.kinds.clear();
+  pass_model_bytes(g, LSHOM_PRECISION_FP64, tm.unit_bytes);
+  lshom_status s = run_blocks(g, 5, K, (long long)o.max_iter / per + 4, [&]() -> hipError_t {
+    for (int k = 0; k < per; ++k) {
+      hipError_t e;
+      if ((e = enq_apply_A_real(g, b, p, ap, GATE_ACTIVE)) != hipSuccess) return e;
+      if ((e = enq_apply_AT_real(g, b, ps, atp, GATE_ACTIVE)) != hipSuccess) return e;
+      if ((e = vec(BV_DOT_APP, GATE_ACTIVE)) != hipSuccess) return e;
+      if ((e = fin(FZ_BICG_ALPHA, nb, GATE_ACTIVE, 1.0)) != hipSuccess) return e;
+      if ((e = vec(BV_UPDATE, GATE_ACTIVE)) != hipSuccess) return e;
+      if ((e = fin(FZ_BICG_STEP, nb, GATE_ACTIVE, 1.0)) != hipSuccess) return e;
+      if ((e = vec(BV_DIRECTION, GATE_ACTIVE)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  });
+  if (s != LSHOM_OK) return s;
+  // FP64 true residual of the returned field and <lambda e>
+  if (o.true_residual) {
+    HIP_TRY(c, enq_apply_A_real(g, b, x, ap, GATE_ALWAYS));
+    HIP_TRY(c, vec(BV_RESID, GATE_ALWAYS));
+    HIP_TRY(c, fin(FZ_RR_TRUE, nb, GATE_ALWAYS, 1.0));
+  }
+  HIP_TRY(c, vec(BV_LEFF, GATE_ALWAYS));
+  HIP_TRY(c, fin(FZ_LEFF, nb, GATE_ALWAYS, 1.0 / (double)g.nvox));
+  if (e_out)
+    HIP_TRY(c, hipMemcpyAsync(e_out, x, sizeof(double) * g.d * g.nvox, hipMemcpyDeviceToDevice, stream_of(g)));
+  HIP_TRY(c, sync_states(g));
   return LSHOM_OK;
 }
 

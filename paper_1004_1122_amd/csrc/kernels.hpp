@@ -41,6 +41,9 @@ struct DevState {
   double taup[3];       // DFT at k = 0 of dL u(p) for the last CG direction
   double eta_e_log;     // eta_e of the last test (-1: not formed)
   double eta_e_true;    // eta_e of the final field (-1: not formed)
+  double bicg_rho;      // BiCG: (r, r*) of the current iterate
+  double bicg_alpha;    // BiCG: step of the current iteration
+  double bicg_beta;     // BiCG: direction update of the current iteration
   double* hist;         // (eta_r, eta_e) of iterate m at [2m], [2m + 1], m < hist_len (or null)
   int hist_len;
   int norm;             // 0: ||r|| <= tol ||b||; 1: eta_e <= tol
@@ -111,6 +114,9 @@ enum FinMode : int {
   FZ_REFRESH = 4,       // mixed: rr_true = sum(AUX); new reference; done tests
   FZ_REFRESH_INIT = 5,  // mixed: as FZ_REFRESH without counting a refresh
   FZ_FFTH = 6,          // basic scheme: norms of the step sum(RR0), sum(EQ0); count; done tests
+  FZ_BICG_START = 7,    // BiCG: rho = sum(AUX[3b]), (r, r) = sum(AUX[3b + 1]); done tests
+  FZ_BICG_ALPHA = 8,    // BiCG: alpha = rho / sum(PQ) (breakdown when zero or not finite)
+  FZ_BICG_STEP = 9,     // BiCG: rho' and (r, r) of the new iterate; beta; count; done tests
 };
 
 // ---------------------------------------------------------------------------
@@ -133,6 +139,7 @@ enum RowFlags : int {
   ROWF_ADD = 4,       // ROW_INV: add real_add to the output
   ROWF_LEFF = 8,      // ROW_INV: partial sums of <lambda out> into AUX
   ROWF_STATE_E = 16,  // E of each problem from its device state (not the argument)
+  ROWF_DL_SCALE = 32, // ROW_INV: multiply E + u by (lambda - l0) / l0 before adding real_add
 };
 
 template <typename T>
@@ -250,6 +257,37 @@ struct UpdArgs {
   FastDiv fd_n1;         // nd[1] (3-D index split)
 };
 
+// BiCG on real d-component nodal fields ([d][n] FP64, components contiguous):
+// the elementwise steps around the two operator applies of an iteration.
+enum BicgMode : int {
+  BV_FILL_E = 0,     // x = E
+  BV_START = 1,      // r = E - ap, r* = p = p* = r; AUX: (r, r*), (r, r)
+  BV_DOT_APP = 2,    // PQ: (A p, p*)
+  BV_UPDATE = 3,     // x += alpha p, r -= alpha A p, r* -= alpha A^T p*; AUX: (r, r*), (r, r)
+  BV_DIRECTION = 4,  // p = r + beta p, p* = r* + beta p*
+  BV_LEFF = 5,       // AUX[3b + c]: sum of lambda x_c
+  BV_RESID = 6,      // AUX[b]: sum of (E - ap)^2
+};
+
+struct BicgArgs {
+  long long n;           // nodes per component
+  int d;
+  int mode;
+  double* x;
+  double* r;
+  double* rs;
+  double* p;
+  double* ps;
+  const double* ap;
+  const double* atp;
+  const uint8_t* phase;  // BV_LEFF
+  const double* cond;
+  DevState* st;
+  Partials parts;
+  int gate;
+  FastDiv fd_n;
+};
+
 // Mixed precision: x64 += x32, x32 = 0 (accumulate); r32 = r64 and the
 // partials of (r32, r32) into the (r, r) buffer of the current iteration
 // (convert).
@@ -288,6 +326,8 @@ template <typename T> hipError_t launch_update(const UpdArgs<T>& a, hipStream_t 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);
+hipError_t launch_bicg(const BicgArgs& a, hipStream_t s);
+long long bicg_blocks(const BicgArgs& a);
 hipError_t launch_state_init(DevState* st, const DevState& init, hipStream_t s);
 // copy nprob initial states from device memory src into st
 hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipStream_t s);

@@ -78,6 +78,10 @@ void fill_info(const DevState& hs, double l0, const lshom_solve_opts& o, int war
   info->rel_res_true = o.true_residual ? std::sqrt(hs.rr_true / b2) : -1.0;
   info->eta_r = l0 * std::sqrt(rr / b2);
   info->eta_e = o.true_residual ? hs.eta_e_true : -1.0;
+  if (o.method == LSHOM_METHOD_BICG) {
+    info->applies_fp64 = 2 * hs.iter_a;
+    info->eta_e = -1.0;
+  }
 }
 
 hipError_t order_after_user(lshom_ctx* c) {
@@ -98,14 +102,16 @@ lshom_status validate_opts(lshom_ctx* c, const lshom_solve_opts* o) {
     if (!(o->refresh_drop > 0.0 && o->refresh_drop < 1.0))
       return fail(c, LSHOM_ERR_INVALID_ARG, "refresh_drop must be in (0, 1)");
   }
-  if (o->method != LSHOM_METHOD_CG && o->method != LSHOM_METHOD_FFTH)
-    return fail(c, LSHOM_ERR_INVALID_ARG, "method must be CG (0) or FFTH (1)");
+  if (o->method != LSHOM_METHOD_CG && o->method != LSHOM_METHOD_FFTH && o->method != LSHOM_METHOD_BICG)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "method must be CG (0), FFTH (1) or BICG (2)");
   if (o->norm != LSHOM_NORM_RESIDUAL && o->norm != LSHOM_NORM_EQUILIBRIUM)
     return fail(c, LSHOM_ERR_INVALID_ARG, "norm must be RESIDUAL (0) or EQUILIBRIUM (1)");
   if (o->history_len < 0) return fail(c, LSHOM_ERR_INVALID_ARG, "history_len must be >= 0");
   const bool mixed = o->precision == LSHOM_PRECISION_MIXED;
-  if (mixed && o->method == LSHOM_METHOD_FFTH)
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme runs in FP64 only");
+  if (mixed && o->method != LSHOM_METHOD_CG)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme and BiCG run in FP64 only");
+  if (o->method == LSHOM_METHOD_BICG && (o->norm != LSHOM_NORM_RESIDUAL || o->history_dev))
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG stops on the residual norm and keeps no history");
   if (mixed && (o->norm == LSHOM_NORM_EQUILIBRIUM || o->history_dev))
     return fail(c, LSHOM_ERR_UNSUPPORTED, "the equilibrium norm and the history are FP64 only");
   return LSHOM_OK;
@@ -259,17 +265,33 @@ lshom_status lshom_workspace_size(const lshom_ctx* c, int precision, size_t* byt
   return LSHOM_OK;
 }
 
+lshom_status lshom_workspace_size_for(const lshom_ctx* c, const lshom_solve_opts* opts, size_t* bytes) {
+  if (!c || !bytes) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return LSHOM_ERR_STATE;
+  lshom_solve_opts o;
+  lshom_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.precision != LSHOM_PRECISION_FP64 && o.precision != LSHOM_PRECISION_MIXED) return LSHOM_ERR_INVALID_ARG;
+  *bytes = compute_layout(c->g, o.precision == LSHOM_PRECISION_MIXED, o.method == LSHOM_METHOD_BICG).total;
+  return LSHOM_OK;
+}
+
 lshom_status lshom_set_workspace(lshom_ctx* c, void* dev, size_t bytes) {
   if (!c) return LSHOM_ERR_INVALID_ARG;
   if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
   if (!dev || (reinterpret_cast<uintptr_t>(dev) % kAlign) != 0)
     return fail(c, LSHOM_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
-  Layout l64 = compute_layout(c->g, false);
-  Layout lmx = compute_layout(c->g, true);
+  // the largest layout that fits: [FP32 part] [BiCG fields]
   Layout use;
-  if (bytes >= lmx.total) use = lmx;
-  else if (bytes >= l64.total) use = l64;
-  else return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_workspace_size()");
+  bool found = false;
+  for (int k = 3; k >= 0 && !found; --k) {
+    const Layout l = compute_layout(c->g, (k & 1) != 0, (k & 2) != 0);
+    if (bytes >= l.total) {
+      use = l;
+      found = true;
+    }
+  }
+  if (!found) return fail(c, LSHOM_ERR_WORKSPACE, "workspace smaller than lshom_workspace_size()");
   DeviceGuard g(c->device);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   drop_graphs(c->graphs);
@@ -300,8 +322,14 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
   for (int a = 0; a < c->g.d; ++a)
     if (!std::isfinite(E_host[a])) return fail(c, LSHOM_ERR_INVALID_ARG, "E must be finite");
   if ((s = check_equilibrium_grid(c, o, c->g.N, c->g.d)) != LSHOM_OK) return s;
-  if (o.method == LSHOM_METHOD_FFTH && x0_dev)
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme starts from e = E (no x0)");
+  if (o.method != LSHOM_METHOD_CG && x0_dev)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme and BiCG start from e = E (no x0)");
+  if (o.method == LSHOM_METHOD_BICG) {
+    if (!c->g.lay.has_bicg)
+      return fail(c, LSHOM_ERR_WORKSPACE, "workspace has no BiCG fields (size it with lshom_workspace_size_for)");
+    if ((long long)c->g.d * c->g.nvox >= (1ll << 31))
+      return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG fields above 2^31 values");
+  }
   DeviceGuard g(c->device);
   HIP_TRY(c, order_after_user(c));
   Group& gr = c->g;
@@ -320,7 +348,10 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
     return LSHOM_OK;
   }
   std::vector<DevState> init(1, initial_state(gr.d, gr.nvox, E_host, tol, gr.l0, o, true));
-  s = solve_group(gr, init, o, E_host, x0_dev, e_dev);
+  if (o.method == LSHOM_METHOD_BICG)
+    s = solve_bicg(gr, init[0], o, e_dev);
+  else
+    s = solve_group(gr, init, o, E_host, x0_dev, e_dev);
   if (s != LSHOM_OK) return s;
   const DevState& hs = gr.host_states[0];
   if (leff_host)
@@ -542,6 +573,7 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
   lshom_status s = validate_opts(c, &o);
   if (s != LSHOM_OK) return s;
   if (o.history_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "history_dev must be NULL for batched solves");
+  if (o.method == LSHOM_METHOD_BICG) return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG runs single solves only");
   BatchPlan bp;
   if ((s = plan_batch(c, n, probs, o.precision, &bp)) != LSHOM_OK) return s;
   for (int32_t i = 0; i < n; ++i)
@@ -605,7 +637,7 @@ lshom_status lshom_set_schedule(lshom_ctx* c, const lshom_schedule* in) {
     DeviceGuard dg(c->device);
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c->graphs);
-  drop_batch_graphs(c);
+    drop_batch_graphs(c);
     apply_schedule(c->g, s, in->precision);
   }
   c->err.clear();

@@ -114,7 +114,22 @@ __device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
 
 template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
-  const int pb = batch_prob(a.bt);
+  // The dispatcher deals blocks to the 8 XCDs (each with its own L2) in
+  // linear order, one each in turn.  Neighbouring row blocks share the cache
+  // lines at their edges in the transposed layout, so the linear id is
+  // re-mapped to give each XCD one contiguous run of (problem, row block)
+  // pairs: the shared lines are then fetched once into one L2.
+  unsigned bx, by;
+  {
+    const unsigned gx = gridDim.x, total = gx * gridDim.y;
+    const unsigned lin = blockIdx.y * gx + blockIdx.x;
+    const unsigned xcd = lin & 7u, slot = lin >> 3;
+    const unsigned q = total >> 3, rem = total & 7u;
+    const unsigned lin2 = xcd * q + (xcd < rem ? xcd : rem) + slot;
+    by = lin2 / gx;
+    bx = lin2 - by * gx;
+  }
+  const int pb = a.bt.live ? a.bt.live[by] : (int)by;
   DevState* st = a.st + pb;
   // the flags a row pass gates on are written only by earlier launches
   if (gated_out_stable(st, a.gate)) return;
@@ -132,8 +147,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   const int n = a.n, h = a.h, ss = a.ss, d = a.d, R = a.rows_per_block;
   const int half_rows = R / 2;
   // split: this block holds one component (c_fix) of row block rb
-  const long long rb = a.split ? (long long)(blockIdx.x / d) : (long long)blockIdx.x;
-  const int c_fix = a.split ? (int)(blockIdx.x - rb * d) : 0;
+  const long long rb = a.split ? (long long)(bx / d) : (long long)bx;
+  const int c_fix = a.split ? (int)(bx - rb * d) : 0;
   const int npairs = (a.split ? 1 : d) * half_rows;
   cx<T>* Z = reinterpret_cast<cx<T>*>(smem_raw);
   size_t off = align16((size_t)npairs * ss * sizeof(cx<T>));
@@ -253,6 +268,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           if (rl >= rows_here) continue;
           const long long g = (row0 + rl) * n + x;
           double val = (double)pick3(Ev, c) + (double)((u == 0 ? z.re : z.im) * a.inv_n);
+          if (a.flags & ROWF_DL_SCALE) val *= ((double)cond[ph[rl * n + x]] - (double)l0) / (double)l0;
           if (a.flags & ROWF_ADD) val += pick3(a.real_add, c)[g];
           double* out = pe ? (pe->e_out ? pe->e_out + c * nvox : nullptr) : pick3(a.real_out, c);
           if (out) out[g] = val;
@@ -265,7 +281,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
         }
       }
       if (a.flags & ROWF_LEFF) {
-        double* dst = parts.region(PART_AUX) + (long long)blockIdx.x * 3;
+        double* dst = parts.region(PART_AUX) + (long long)bx * 3;
         for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);
       }
       return;
@@ -710,6 +726,92 @@ __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// BiCG elementwise steps (one partial per block, fixed-order sums)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void bicg_kernel(BicgArgs a) {
+  constexpr int NT = 256;
+  DevState* st = a.st;
+  if (gated_out(st, a.gate)) return;
+  const long long total = a.n * a.d;
+  const long long stride = (long long)gridDim.x * NT;
+  const long long i0 = (long long)blockIdx.x * NT + threadIdx.x;
+  if (a.mode == BV_LEFF) {
+    double acc[kMaxDim] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < a.d; ++c) {
+      const double* xc = a.x + (long long)c * a.n;
+      double s = 0.0;
+      for (long long j = i0; j < a.n; j += stride) s += a.cond[a.phase[j]] * xc[j];
+      acc[c] = s;
+    }
+    double* dst = a.parts.region(PART_AUX) + (long long)blockIdx.x * 3;
+    for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);
+    return;
+  }
+  double s0 = 0.0, s1 = 0.0;
+  const double alpha = a.mode == BV_UPDATE ? st->bicg_alpha : 0.0;
+  const double beta = a.mode == BV_DIRECTION ? st->bicg_beta : 0.0;
+  for (long long i = i0; i < total; i += stride) {
+    switch (a.mode) {
+      case BV_FILL_E: {
+        const int c = (int)fdiv((uint32_t)i, a.fd_n);
+        a.x[i] = st->E[c];
+        break;
+      }
+      case BV_START: {
+        const int c = (int)fdiv((uint32_t)i, a.fd_n);
+        const double r = st->E[c] - a.ap[i];
+        a.r[i] = r;
+        a.rs[i] = r;
+        a.p[i] = r;
+        a.ps[i] = r;
+        s0 += r * r;
+        s1 += r * r;
+        break;
+      }
+      case BV_DOT_APP:
+        s0 += a.ap[i] * a.ps[i];
+        break;
+      case BV_UPDATE: {
+        a.x[i] += alpha * a.p[i];
+        const double r = a.r[i] - alpha * a.ap[i];
+        const double rs = a.rs[i] - alpha * a.atp[i];
+        a.r[i] = r;
+        a.rs[i] = rs;
+        s0 += r * rs;
+        s1 += r * r;
+        break;
+      }
+      case BV_DIRECTION:
+        a.p[i] = a.r[i] + beta * a.p[i];
+        a.ps[i] = a.rs[i] + beta * a.ps[i];
+        break;
+      case BV_RESID: {
+        const int c = (int)fdiv((uint32_t)i, a.fd_n);
+        const double r = st->E[c] - a.ap[i];
+        s0 += r * r;
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  if (a.mode == BV_START || a.mode == BV_UPDATE) {
+    double v[2] = {s0, s1};
+    (void)block_sums_gated<NT, 2>(v, 0);
+    if (threadIdx.x == 0) {
+      double* dst = a.parts.region(PART_AUX) + (long long)blockIdx.x * 3;
+      dst[0] = v[0];
+      dst[1] = v[1];
+    }
+  } else if (a.mode == BV_DOT_APP) {
+    store_partial<NT>(s0, a.parts.region(PART_PQ) + blockIdx.x);
+  } else if (a.mode == BV_RESID) {
+    store_partial<NT>(s0, a.parts.region(PART_AUX) + blockIdx.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Single-block scalar steps
 // ---------------------------------------------------------------------------
 
@@ -754,6 +856,43 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
       const double s = sum_partials<NT>(parts.region(PART_AUX), a.n) * a.inv_n;
       if (a.eq) (void)equilibrium_test(st, -1, s, sum_partials<NT>(parts.region(PART_EQ0), a.n), lead);
       if (lead) st->rr_true = s;
+      break;
+    }
+    case FZ_BICG_START:
+    case FZ_BICG_STEP: {
+      const double rho = sum_partials<NT>(parts.region(PART_AUX), a.n, 3);
+      const double rr = sum_partials<NT>(parts.region(PART_AUX) + 1, a.n, 3);
+      if (lead) {
+        const int m = st->iter_a + (a.mode == FZ_BICG_STEP ? 1 : 0);
+        st->iter_a = m;
+        st->rr_log = rr;
+        if (a.mode == FZ_BICG_STEP) st->bicg_beta = rho / st->bicg_rho;
+        st->bicg_rho = rho;
+        if (!isfinite(rr) || !isfinite(rho)) {
+          st->status = -6;
+          st->done = 1;
+        } else if (rr <= st->tol2b2) {
+          st->done = 1;
+        } else if (m >= st->max_iter) {
+          st->status = -5;
+          st->done = 1;
+        } else if (rho == 0.0) {
+          st->status = -6;
+          st->done = 1;
+        }
+      }
+      break;
+    }
+    case FZ_BICG_ALPHA: {
+      const double sigma = sum_partials<NT>(parts.region(PART_PQ), a.n);
+      if (lead) {
+        if (!(sigma != 0.0) || !isfinite(sigma)) {
+          st->status = -6;
+          st->done = 1;
+        } else {
+          st->bicg_alpha = st->bicg_rho / sigma;
+        }
+      }
       break;
     }
     case FZ_FFTH: {
@@ -883,6 +1022,13 @@ static int nprob_of(const Batch& b) { return b.nprob > 1 ? b.nprob : 1; }
 
 hipError_t launch_compact_live(const DevState* st, int nprob, int rows, int* live, hipStream_t s) {
   hipLaunchKernelGGL(compact_live_kernel, dim3(1), dim3(256), 0, s, st, nprob, rows, live);
+  return hipGetLastError();
+}
+
+long long bicg_blocks(const BicgArgs& a) { return update_blocks(a.n * a.d); }
+
+hipError_t launch_bicg(const BicgArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(bicg_kernel, dim3((unsigned)bicg_blocks(a)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

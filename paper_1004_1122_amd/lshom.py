@@ -38,6 +38,7 @@ PRECISION_MIXED = 1
 
 METHOD_CG = 0
 METHOD_FFTH = 1
+METHOD_BICG = 2
 
 NORM_RESIDUAL = 0
 NORM_EQUILIBRIUM = 1
@@ -167,6 +168,7 @@ def load(path: str = LIB_PATH):
         "lshom_set_microstructure": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
         "lshom_set_reference": (c_int32, [P, c_double]),
         "lshom_workspace_size": (c_int32, [P, c_int, POINTER(c_size_t)]),
+        "lshom_workspace_size_for": (c_int32, [P, POINTER(lshom_solve_opts), POINTER(c_size_t)]),
         "lshom_set_workspace": (c_int32, [P, P, c_size_t]),
         "lshom_solve": (c_int32, [P, POINTER(c_double), c_double, POINTER(lshom_solve_opts), P, P,
                                   POINTER(c_double), POINTER(lshom_solve_info)]),
@@ -300,12 +302,32 @@ class Solver:
                                                            len(self.cond), _dbl_array(self.cond)))
         size = c_size_t()
         _check(self.ctx, self.lib.lshom_workspace_size(self.ctx, int(precision), ctypes.byref(size)))
-        self.ws_bytes = int(size.value)
-        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self._attach_workspace(int(size.value))
+
+    def _attach_workspace(self, nbytes):
+        torch = self.torch
+        self.ws_bytes = nbytes
+        self._ws_raw = None
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         off = (-raw.data_ptr()) % 256
         self._ws_raw = raw
         self.ws_ptr = raw.data_ptr() + off
         _check(self.ctx, self.lib.lshom_set_workspace(self.ctx, c_void_p(self.ws_ptr), self.ws_bytes))
+
+    def _ensure_workspace(self, o):
+        """Grows the workspace when the options need more (BiCG fields)."""
+        size = c_size_t()
+        _check(self.ctx, self.lib.lshom_workspace_size_for(self.ctx, ctypes.byref(o), ctypes.byref(size)))
+        need = int(size.value)
+        if o.method == METHOD_BICG:
+            # keep the FP32 part as well, so that mixed solves still fit
+            mixed = lshom_default_opts()
+            mixed.precision = PRECISION_MIXED
+            mixed.method = METHOD_BICG
+            _check(self.ctx, self.lib.lshom_workspace_size_for(self.ctx, ctypes.byref(mixed), ctypes.byref(size)))
+            need = max(need, int(size.value))
+        if need > self.ws_bytes:
+            self._attach_workspace(need)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -336,6 +358,7 @@ class Solver:
         the solve produced, at most n)."""
         torch = self.torch
         o = self.opts(**opt_kw)
+        self._ensure_workspace(o)
         hist = None
         if history:
             hist = torch.full((int(history), 2), float("nan"), dtype=torch.float64, device=self.device)

@@ -1,14 +1,19 @@
 """Launches of the pass kernels with known work, for hardware-counter runs.
 
 Builds the 729x729 circle cell (40 RSA circles, seed 2, contrast 1e4),
-applies the autotuned schedule of each precision, and launches every pass
-kernel of one CG iteration `--reps` times back to back (all blocks active, as
-in the middle of a solve).  Prints one JSON line with each pass's average
-launch time and algorithmic bytes.  With --copy-mib, finishes with an
-elementwise kernel that reads and writes that many MiB once (the counter
-calibration).
+applies the autotuned schedule of each precision (or, with --schedules, the
+schedules another run saved, e.g. bench.py --save-schedules), and launches
+every pass kernel of one CG iteration `--reps` times back to back (all blocks
+active, as in the middle of a solve).  Prints one JSON line with each pass's
+average launch time and algorithmic bytes.
 
-  python -m paper_1004_1122_amd.pass_profile [--reps 20] [--copy-mib 256]
+The timed launches of form k (1: FP64, 2: mixed) are bracketed by the k-th
+pair of dispatches of a small elementwise |x| kernel, so that counter records
+can be cut to exactly those launches (profiling.py traffic --window k).  With
+--copy-mib, finishes with an elementwise kernel that reads and writes that
+many MiB once (the counter calibration).
+
+  python -m paper_1004_1122_amd.pass_profile [--reps 20] [--copy-mib 256] [--schedules F ...]
 """
 
 from __future__ import annotations
@@ -22,6 +27,8 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--rho", type=float, default=1e4)
+    ap.add_argument("--schedules", nargs="*", default=None,
+                    help="schedule files (lshom_save_schedules format) to load instead of autotuning")
     args = ap.parse_args()
     import torch
     from . import lshom
@@ -30,10 +37,18 @@ def main():
     m = ms.circles_729(seed=2)
     s = lshom.Solver(torch.from_numpy(m.phase).cuda(), [1.0, args.rho])
     out = {"workload": "729x729 circles seed 2, rho %g" % args.rho, "reps": args.reps, "forms": {}}
+    marker = torch.ones(64, device="cuda")
+    if args.schedules:
+        for path in args.schedules:
+            s.load_schedules(path)
     for form, prec in (("fp64", lshom.PRECISION_FP64), ("mixed", lshom.PRECISION_MIXED)):
         s.solve((1.0, 0.0), tol=1e-6, precision=prec, want_field=False)
-        sched = s.autotune(precision=prec, reps=10)
+        sched = s.get_schedule(prec) if args.schedules else s.autotune(precision=prec, reps=10)
+        torch.cuda.synchronize()
+        torch.abs(marker)
         passes = s.time_passes(prec, reps=args.reps)
+        torch.abs(marker)
+        torch.cuda.synchronize()
         out["forms"][form] = {"schedule": sched,
                               "passes": {k: {"ms": v[0], "algorithmic_bytes": v[1]} for k, v in passes.items()}}
     if args.copy_mib > 0:

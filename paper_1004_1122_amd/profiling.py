@@ -11,7 +11,9 @@ records kept with the sources).
       HBM bytes per launch of the kernels matching REGEX from two counter runs
       (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the
       same counter reads for a copy kernel of N bytes read and N written, and
-      their ratio to the algorithmic bytes B of one such launch.
+      their ratio to the algorithmic bytes B of one such launch.  --window K
+      keeps only dispatches between the (2K-1)-th and 2K-th dispatch of the
+      marker kernel (--marker REGEX, default the |x| kernel of torch.abs).
 """
 
 from __future__ import annotations
@@ -96,9 +98,18 @@ def _counter_sums(pattern, counter):
     for r in _rows(pattern):
         if _col(r, "Counter_Name") != counter:
             continue
-        key = (_col(r, "Kernel_Name"), _col(r, "Dispatch_Id"))
+        key = (_col(r, "Kernel_Name"), int(_col(r, "Dispatch_Id")))
         per[key] = per.get(key, 0.0) + float(_col(r, "Counter_Value"))
     return per
+
+
+def _window(per, marker_rx, k):
+    """Entries between the (2k-1)-th and 2k-th dispatch of the marker kernel."""
+    ids = sorted(d for (name, d) in per if marker_rx.search(name))
+    if len(ids) < 2 * k:
+        raise SystemExit(f"only {len(ids)} marker dispatches, window {k} needs {2 * k}")
+    lo, hi = ids[2 * k - 2], ids[2 * k - 1]
+    return {key: v for key, v in per.items() if lo < key[1] < hi}
 
 
 def traffic(args):
@@ -111,6 +122,9 @@ def traffic(args):
         return vals
 
     cf, cw = pick(fetch, cre), pick(write, cre)
+    if args.window:
+        mre = re.compile(args.marker)
+        fetch, write = _window(fetch, mre, args.window), _window(write, mre, args.window)
     kf, kw = pick(fetch, kre), pick(write, kre)
     if not (cf and cw and kf and kw):
         raise SystemExit(f"missing dispatches: copy {len(cf)}/{len(cw)}, kernel {len(kf)}/{len(kw)}")
@@ -164,6 +178,8 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     t.add_argument("--alg-bytes", type=float, required=True)
+    t.add_argument("--window", type=int, default=0)
+    t.add_argument("--marker", default=r"AbsFunctor")
     t.add_argument("--out", required=True)
     a = ap.parse_args()
     stats(a) if a.cmd == "stats" else traffic(a)
