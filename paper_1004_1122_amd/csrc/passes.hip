@@ -131,8 +131,11 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   }
   const int pb = a.bt.live ? a.bt.live[by] : (int)by;
   DevState* st = a.st + pb;
-  // the flags a row pass gates on are written only by earlier launches
-  if (gated_out_stable(st, a.gate)) return;
+  // the flags a row pass gates on are written only by earlier launches; the
+  // spectral passes read them with their first data chunk (below)
+  if constexpr (MODE == ROW_FWD) {
+    if (gated_out_stable(st, a.gate)) return;
+  }
   const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
   const long long vo = (long long)pb * a.bt.vstride;
   Partials parts = a.parts;
@@ -154,11 +157,13 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   size_t off = align16((size_t)npairs * ss * sizeof(cx<T>));
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + off);
   off = align16(off + (size_t)twiddle_entries(n) * sizeof(cx<T>));
+  uint8_t* phs = smem_raw + off;  // phase bytes of the block's rows (fused pass)
+  off = align16(off + (size_t)R * n);
   T* cond = reinterpret_cast<T*>(smem_raw + off);
   const int tid = threadIdx.x;
   const long long row0 = rb * R;
   const int rows_here = (int)((a.nrows - row0) < R ? (a.nrows - row0) : R);
-  // phase bytes of this block's rows, read where used (each once, coalesced)
+  // phase bytes of this block's rows (each read once, coalesced)
   const uint8_t* ph = phase + row0 * n;
 
   const int ntw = twiddle_entries(n);
@@ -225,8 +230,20 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
         }
       }
       if (base == 0) {
-        // twiddles and conductivities, requested while the first data chunk
-        // is in flight
+        // the gate, the twiddles, the conductivities and (fused pass) the
+        // phase bytes, requested while the first data chunk is in flight
+        if (gated_out_stable(st, a.gate)) return;
+        if constexpr (MODE == ROW_FUSED) {
+          const int nph = rows_here * n;
+          for (int i0 = tid; i0 < nph; i0 += 8 * NT) {
+            uint8_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = i0 + u * NT < nph ? ph[i0 + u * NT] : (uint8_t)0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (i0 + u * NT < nph) phs[i0 + u * NT] = v[u];
+          }
+        }
         auto ldtw = [&](int i) -> cx<T> {
           if (i < ntw) {
             const cx<T>* q = a.tw + i;
@@ -296,8 +313,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       const cx<T> z = Z[p * ss + x];
       T t0 = T(0), t1 = T(0);
       const T Ec = pick3(Ev, c);
-      if (ra < rows_here) t0 = (cond[ph[ra * n + x]] - l0) * (Ec + z.re * a.inv_n);
-      if (ra + 1 < rows_here) t1 = (cond[ph[(ra + 1) * n + x]] - l0) * (Ec + z.im * a.inv_n);
+      if (ra < rows_here) t0 = (cond[phs[ra * n + x]] - l0) * (Ec + z.re * a.inv_n);
+      if (ra + 1 < rows_here) t1 = (cond[phs[(ra + 1) * n + x]] - l0) * (Ec + z.im * a.inv_n);
       Z[p * ss + x] = cx<T>{t0, t1};
     }
     __syncthreads();
@@ -1043,6 +1060,7 @@ size_t row_lds_bytes(int n, int rows_per_block, int comps, int elem_bytes, int n
   const int npairs = comps * (rows_per_block / 2);
   size_t off = align16((size_t)npairs * ss * elem_bytes);
   off = align16(off + (size_t)twiddle_entries(n) * elem_bytes);
+  off = align16(off + (size_t)rows_per_block * n);  // phase bytes
   return off + (size_t)n_phases * (size_t)(elem_bytes / 2);
 }
 
