@@ -169,14 +169,23 @@ def main():
     parts = [[p for k, p in enumerate(probs) if k % args.streams == j] for j in range(args.streams)]
     solvers = {}
     sched = {}
+    # every batch's schedules (the grid's and its tail's) are kept in a file
+    # so that the later single-form runs use exactly the same ones
+    import tempfile
+    sched_dir = tempfile.mkdtemp(prefix="lshom_sched_")
+    sched_file = {}
     for form, prec in FORMS:
         for j, part in enumerate(parts):
             bs = lshom.BatchSolver()
             bs.prepare(part, precision=prec)
-            sc = bs.autotune(precision=prec, reps=10)[0]
-            if args.save_schedules and form not in sched:
-                bs.save_schedules(f"{args.save_schedules}.{form}")
-            sched.setdefault(form, sc)
+            sc = bs.autotune(precision=prec, reps=10)
+            if form not in sched:
+                sched_file[form] = os.path.join(sched_dir, f"{form}.jsonl")
+                bs.save_schedules(sched_file[form])
+                if args.save_schedules:
+                    bs.save_schedules(f"{args.save_schedules}.{form}")
+            sched.setdefault(form, sc[0])
+            sched.setdefault(form + "_tail", sc[1] if len(sc) > 1 else None)
             solvers[(form, j)] = bs
     log(f"workload 729x729, vf={m.info['vf']:.4f}, {len(probs)} solves per form in {args.streams} batches; "
         f"schedules {sched}")
@@ -226,7 +235,7 @@ def main():
     for form, prec in FORMS:
         one = lshom.BatchSolver()
         one.prepare(probs, precision=prec)
-        one.set_schedule(sched[form])
+        one.load_schedules(sched_file[form])
         one.run(precision=prec)
         t0 = time.perf_counter()
         _, _, infos = one.run(precision=prec)

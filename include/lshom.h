@@ -252,6 +252,8 @@ typedef struct lshom_schedule {
   int32_t nstages[3];
   int32_t radix[3][16];
   double ms_per_iter;  /* autotuned device time of one CG iteration's passes (0: not measured) */
+  int32_t tail_rows;   /* 0: the schedule of the grid; > 0: used instead by batched launches that
+                          cover at most this many unfinished problems (the tail of a batch) */
 } lshom_schedule;
 
 /* Schedule the current problem uses at `precision`. */

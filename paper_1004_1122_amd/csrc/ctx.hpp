@@ -58,6 +58,7 @@ struct Schedule {
   FftPlan plan[3];
   PassShape shape;
   double ms_per_iter = 0.0;   // autotuned cost of one CG iteration's passes
+  int tail_rows = 0;          // > 0: for batched launches of at most this many unfinished problems
 };
 
 using SchedKey = std::tuple<int, int64_t, int64_t, int64_t, int>;  // d, N0, N1, N2, precision
@@ -97,6 +98,10 @@ struct Group {
   // grid rows of the iteration launches once finished problems are dropped
   // (0: one row per problem, no indirection)
   int live_rows = 0;
+  // schedules for launches of at most tail_rows unfinished problems (per precision)
+  Schedule tail_sched[2];
+  bool has_tail[2] = {false, false};
+  int tail_rows = 0;
   // device memory
   char* ws = nullptr;
   Layout lay;
@@ -119,6 +124,10 @@ Schedule current_schedule(const Group& g, int precision);
 // Times the passes of one CG iteration for candidate schedules on the group's
 // current data and returns the fastest (per pass, independently).
 lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best);
+// The same with the launches restricted to the first `rows` problems of the
+// group (the tail of a batch); best->tail_rows = rows.
+constexpr int kTailRows = 2;
+lshom_status autotune_tail(Group& g, int precision, int reps, int rows, Schedule* best);
 Layout compute_layout(const Group& g, bool with32, bool with_bicg = false);
 
 // Uploads twiddles, conductivity tables (cond[p * n_phases + i]) and the

@@ -65,6 +65,13 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
     for (int prec = 0; prec < 2; ++prec) {
       auto it = g.ctx->schedules.find(SchedKey(d, g.N[0], g.N[1], g.N[2], prec));
       if (it != g.ctx->schedules.end() && schedule_fits(g, it->second, prec)) apply_schedule(g, it->second, prec);
+      // tail schedules are kept under precision + 2
+      auto tt = g.ctx->schedules.find(SchedKey(d, g.N[0], g.N[1], g.N[2], prec + 2));
+      if (tt != g.ctx->schedules.end() && schedule_fits(g, tt->second, prec) && tt->second.tail_rows > 0) {
+        g.tail_sched[prec] = tt->second;
+        g.has_tail[prec] = true;
+        g.tail_rows = std::max(g.tail_rows, tt->second.tail_rows);
+      }
     }
   }
   return LSHOM_OK;
@@ -659,11 +666,25 @@ template <typename F>
 lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqueue_block) {
   lshom_ctx* c = g.ctx;
   HIP_TRY(c, sync_states(g));
+  // the tail of a batch (few unfinished problems) may run with its own
+  // schedules; the group's own ones come back on every exit
+  const Schedule main_sched[2] = {current_schedule(g, LSHOM_PRECISION_FP64),
+                                  current_schedule(g, LSHOM_PRECISION_MIXED)};
   struct ResetRows {
     Group& g;
-    ~ResetRows() { g.live_rows = 0; }
-  } reset_rows{g};
+    const Schedule* main;
+    ~ResetRows() {
+      g.live_rows = 0;
+      for (int p = 0; p < 2; ++p)
+        if (g.has_tail[p]) apply_schedule(g, main[p], p);
+    }
+  } reset_rows{g, main_sched};
   g.live_rows = 0;
+  auto use_schedules_for = [&](int rows) {
+    const bool tail = g.tail_rows > 0 && rows <= g.tail_rows;
+    for (int p = 0; p < 2; ++p)
+      if (g.has_tail[p]) apply_schedule(g, tail ? g.tail_sched[p] : main_sched[p], p);
+  };
   int* live_dev = reinterpret_cast<int*>(g.ws + g.lay.off_live);
   auto enqueue = [&]() -> hipError_t {
     if (g.live_rows > 0) {
@@ -725,6 +746,7 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
         ex = nullptr;
         owned = false;
         g.live_rows = rows;
+        use_schedules_for(rows);
         st = get_graph();
         if (st != LSHOM_OK) return st;
       }
@@ -894,18 +916,22 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   tm.kinds.clear();
   pass_model_bytes(g, o.precision, tm.unit_bytes);
   lshom_status s;
+  // the blocks take the buffers (and launch shapes) current when they are
+  // queued: the tail of a batch may switch schedules
   if (ffth) {
     s = run_blocks(g, 3 + eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+      const Bufs<double> f64 = get_bufs<double>(g);
       for (int k = 0; k < per; ++k) {
-        hipError_t e = enq_ffth_iteration(g, b64, GATE_ACTIVE);
+        hipError_t e = enq_ffth_iteration(g, f64, GATE_ACTIVE);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     });
   } else if (!mixed) {
     s = run_blocks(g, 2 * eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+      const Bufs<double> f64 = get_bufs<double>(g);
       for (int k = 0; k < per; ++k) {
-        hipError_t e = enq_cg_iteration<double>(g, b64, GATE_ACTIVE);
+        hipError_t e = enq_cg_iteration<double>(g, f64, GATE_ACTIVE);
         if (e != hipSuccess) return e;
       }
       return enq_finalize(g, FZ_CHECK, 0, GATE_ACTIVE, eq_loop);
@@ -913,11 +939,13 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   } else {
     // a refresh may cut a block short: at least one iteration per block is certain
     s = run_blocks(g, 1, K, (long long)max_iter + 4, [&]() -> hipError_t {
+      const Bufs<double> f64 = get_bufs<double>(g);
+      const Bufs<float> f32 = get_bufs<float>(g);
       for (int k = 0; k < per; ++k) {
-        hipError_t e = enq_cg_iteration<float>(g, b32, GATE_NO_REFRESH);
+        hipError_t e = enq_cg_iteration<float>(g, f32, GATE_NO_REFRESH);
         if (e != hipSuccess) return e;
       }
-      return enq_mix_refresh(g, b64, b32, E, GATE_REFRESH);
+      return enq_mix_refresh(g, f64, f32, E, GATE_REFRESH);
     });
   }
   if (s != LSHOM_OK) return s;
@@ -1184,6 +1212,24 @@ double time_mask(Group& g, int precision, int reps, unsigned mask, lshom_status*
 }
 
 }  // namespace
+
+lshom_status autotune_tail(Group& g, int precision, int reps, int rows, Schedule* best) {
+  lshom_ctx* c = g.ctx;
+  if (rows < 1 || rows > g.nprob) return fail(c, LSHOM_ERR_INVALID_ARG, "tail rows out of range");
+  std::vector<int> live(rows);
+  for (int i = 0; i < rows; ++i) live[i] = i;
+  {
+    std::lock_guard<std::mutex> lock(setup_mutex());
+    HIP_TRY(c, hipMemcpyAsync(g.ws + g.lay.off_live, live.data(), sizeof(int) * rows, hipMemcpyHostToDevice,
+                              stream_of(g)));
+    HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  }
+  g.live_rows = rows;
+  lshom_status s = autotune_group(g, precision, reps, best);
+  g.live_rows = 0;
+  best->tail_rows = rows;
+  return s;
+}
 
 lshom_status autotune_group(Group& g, int precision, int reps, Schedule* best) {
   const bool f64 = precision == LSHOM_PRECISION_FP64;

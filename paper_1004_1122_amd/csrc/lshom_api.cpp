@@ -520,6 +520,7 @@ void to_c_schedule(const Group& g, const Schedule& s, int precision, lshom_sched
     for (int k = 0; k < s.plan[a].nstages; ++k) out->radix[a][k] = s.plan[a].radix[k];
   }
   out->ms_per_iter = s.ms_per_iter;
+  out->tail_rows = s.tail_rows;
 }
 
 lshom_status from_c_schedule(lshom_ctx* c, const lshom_schedule* in, Schedule* s) {
@@ -538,6 +539,8 @@ lshom_status from_c_schedule(lshom_ctx* c, const lshom_schedule* in, Schedule* s
   s->shape.threads_row = in->threads_row;
   s->shape.threads_col = in->threads_col;
   s->ms_per_iter = in->ms_per_iter;
+  if (in->tail_rows < 0) return fail(c, LSHOM_ERR_INVALID_ARG, "schedule: tail_rows must be >= 0");
+  s->tail_rows = in->tail_rows;
   return LSHOM_OK;
 }
 
@@ -631,6 +634,13 @@ lshom_status lshom_set_schedule(lshom_ctx* c, const lshom_schedule* in) {
     return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
   if (!schedule_fits(probe, s, in->precision))
     return fail(c, LSHOM_ERR_INVALID_ARG, "schedule exceeds the FFT batch or LDS limits");
+  if (s.tail_rows > 0) {
+    // a tail schedule serves batched launches only (kept under precision + 2)
+    c->schedules[SchedKey(in->d, probe.N[0], probe.N[1], probe.N[2], in->precision + 2)] = s;
+    drop_batch_graphs(c);
+    c->err.clear();
+    return LSHOM_OK;
+  }
   c->schedules[SchedKey(in->d, probe.N[0], probe.N[1], probe.N[2], in->precision)] = s;
   if (c->have_problem && c->g.d == in->d && c->g.N[0] == probe.N[0] && c->g.N[1] == probe.N[1] &&
       c->g.N[2] == probe.N[2] && schedule_fits(c->g, s, in->precision)) {
@@ -681,6 +691,7 @@ lshom_status lshom_autotune_batched(lshom_ctx* c, int32_t n, const lshom_problem
   lshom_default_opts(&o);
   o.precision = precision;
   const int cap = n_best ? *n_best : 0;
+  int n_tail = 0;
   for (size_t gi = 0; gi < bp.groups.size(); ++gi) {
     Group& g = bp.groups[gi];
     std::vector<ProbEntry> tab;
@@ -697,9 +708,20 @@ lshom_status lshom_autotune_batched(lshom_ctx* c, int32_t n, const lshom_problem
     if ((s = autotune_group(g, precision, reps, &tuned)) != LSHOM_OK) return s;
     c->schedules[SchedKey(g.d, g.N[0], g.N[1], g.N[2], precision)] = tuned;
     if (best && (int)gi < cap) to_c_schedule(g, tuned, precision, &best[gi]);
+    // the tail of the batch: launches that cover only kTailRows unfinished
+    // problems (few blocks per CU) are tuned on their own
+    if (g.nprob > kTailRows) {
+      Schedule tail;
+      if ((s = autotune_tail(g, precision, reps, kTailRows, &tail)) != LSHOM_OK) return s;
+      apply_schedule(g, tuned, precision);
+      c->schedules[SchedKey(g.d, g.N[0], g.N[1], g.N[2], precision + 2)] = tail;
+      if (best && (int)(bp.groups.size() + n_tail) < cap)
+        to_c_schedule(g, tail, precision, &best[bp.groups.size() + n_tail]);
+      ++n_tail;
+    }
   }
   drop_batch_graphs(c);  // captured with the previous schedules
-  if (n_best) *n_best = (int32_t)bp.groups.size();
+  if (n_best) *n_best = (int32_t)(bp.groups.size() + n_tail);
   c->err.clear();
   return LSHOM_OK;
 }
@@ -728,7 +750,7 @@ lshom_status lshom_save_schedules(lshom_ctx* c, const char* path) {
   const std::string arch = arch_name(c->device);
   for (const auto& kv : c->schedules) {
     const int d = std::get<0>(kv.first);
-    const int prec = std::get<4>(kv.first);
+    const int prec = std::get<4>(kv.first) & 1;
     const Schedule& s = kv.second;
     std::fprintf(f, "{\"arch\": \"%s\", \"d\": %d, \"N\": [%lld, %lld, %lld], \"precision\": %d, "
                     "\"rows_per_block\": %d, \"row_split\": %d, \"threads_row\": %d, \"threads_col\": %d, "
@@ -741,7 +763,7 @@ lshom_status lshom_save_schedules(lshom_ctx* c, const char* path) {
       for (int k = 0; k < s.plan[a].nstages; ++k) std::fprintf(f, "%s%d", k ? ", " : "", s.plan[a].radix[k]);
       std::fprintf(f, "]");
     }
-    std::fprintf(f, "], \"ms_per_iter\": %.9g}\n", s.ms_per_iter);
+    std::fprintf(f, "], \"ms_per_iter\": %.9g, \"tail_rows\": %d}\n", s.ms_per_iter, s.tail_rows);
   }
   std::fclose(f);
   return LSHOM_OK;
@@ -817,6 +839,8 @@ lshom_status lshom_load_schedules(lshom_ctx* c, const char* path) {
     in.row_split = (json_ints(line, "row_split", &split) && split.size() == 1) ? (int)split[0] : 0;
     in.threads_row = (json_ints(line, "threads_row", &ntr) && ntr.size() == 1) ? (int)ntr[0] : 0;
     in.threads_col = (json_ints(line, "threads_col", &ntc) && ntc.size() == 1) ? (int)ntc[0] : 0;
+    std::vector<long long> tr;
+    in.tail_rows = (json_ints(line, "tail_rows", &tr) && tr.size() == 1) ? (int)tr[0] : 0;
     // radix lists: split the bracketed value by inner brackets
     const size_t rp = line.find("\"radix\"");
     if (rp == std::string::npos) {

@@ -105,6 +105,7 @@ class lshom_schedule(Structure):
         ("nstages", c_int32 * 3),
         ("radix", (c_int32 * 16) * 3),
         ("ms_per_iter", c_double),
+        ("tail_rows", c_int32),
     ]
 
     def as_dict(self):
@@ -121,6 +122,7 @@ class lshom_schedule(Structure):
             "threads_col": int(self.threads_col),
             "radix": [[int(self.radix[a][k]) for k in range(self.nstages[a])] for a in range(d)],
             "ms_per_iter": float(self.ms_per_iter),
+            "tail_rows": int(self.tail_rows),
         }
 
     @classmethod
@@ -141,6 +143,7 @@ class lshom_schedule(Structure):
             for k, r in enumerate(rad):
                 out.radix[a][k] = int(r)
         out.ms_per_iter = float(s.get("ms_per_iter", 0.0))
+        out.tail_rows = int(s.get("tail_rows", 0))
         return out
 
 

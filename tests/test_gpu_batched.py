@@ -108,3 +108,40 @@ def test_batch_with_uneven_convergence_equals_single(precision):
         assert infos[i]["iterations"] == info["iterations"], i
         assert torch.equal(fields[i], e), i
         assert np.array_equal(leff[i][:2], l1), i
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tail_schedules(precision, tmp_path):
+    """The batched autotuner also tunes the launches that cover only the last
+    two unfinished problems; a batch that switches to that schedule in its
+    tail still meets the FP64 bar, also with an explicitly set tail shape."""
+    from paper_1004_1122_amd import lshom
+    probs = []
+    for i, rho in enumerate(np.geomspace(2.0, 500.0, 6)):
+        m = ms.grf_two_phase(27, 0.15, 0.4, float(rho), seed=900 + i)
+        probs.append(dict(phase=m.phase, cond=[1.0, float(rho)], E=(1.0, 0.0), tol=1e-8, want_field=True))
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=1)
+    scheds = bs.autotune(precision=precision, reps=2)
+    assert [s["tail_rows"] for s in scheds] == [0, 2]
+    fields, _, infos = bs.run(precision=precision, graph_block=4)
+    for i, pr in enumerate(probs):
+        assert infos[i]["status"] == 0
+        if precision == 0:
+            lam = ms.lam_field(pr["phase"], pr["cond"])
+            ref = o.cg(lam, o.optimal_reference(lam), pr["E"], n_iter=infos[i]["iterations"])
+            assert np.linalg.norm(fields[i].cpu().numpy() - ref["e"]) / np.linalg.norm(ref["e"]) < 1e-10, i
+        else:
+            assert infos[i]["rel_res_true"] <= 1.01e-8
+    # a different tail shape: same answers within the bar
+    main = scheds[0]
+    bs.set_schedule(dict(main, rows_per_block=2, threads_row=128, row_split=0, tail_rows=2))
+    f2, _, inf2 = bs.run(precision=precision, graph_block=4)
+    for i in range(len(probs)):
+        assert abs(inf2[i]["iterations"] - infos[i]["iterations"]) <= 1
+        ref = fields[i].cpu().numpy()
+        tol = 1e-9 if precision == 0 else 1e-6
+        assert np.linalg.norm(f2[i].cpu().numpy() - ref) / np.linalg.norm(ref) < tol, i
+    path = tmp_path / "sched.jsonl"
+    bs.save_schedules(str(path))
+    assert '"tail_rows": 2' in path.read_text()
