@@ -53,6 +53,8 @@ except Exception:  # pragma: no cover - scipy is present in this image
 __all__ = [
     "frequencies",
     "grid_frequencies",
+    "wave_vectors",
+    "Medium",
     "green_hat",
     "apply_B",
     "apply_A",
@@ -127,14 +129,68 @@ def _nyquist_mask(shape):
     return keep
 
 
-def _green_factors(shape, l0):
-    """Integer frequencies and ``1 / (k . L0 . k)`` (zero where Gamma0 is 0)."""
+def wave_vectors(shape, cell=None):
+    """Wave vector components xi_alpha = k_alpha / Y_alpha on the DFT grid.
+
+    The basis of Sec. 2.1, Eq. (6) has exp(i pi x_alpha k_alpha / Y_alpha) on
+    the cell prod (-Y_alpha, Y_alpha): derivatives scale mode k by k / Y, so
+    the Green operator of Eq. (7) for a non-cubic cell takes xi in place of
+    the integer k (a common factor pi cancels in it).  ``cell`` holds the d
+    side lengths (None: a cubic cell, xi = k)."""
     ks = grid_frequencies(shape)
+    if cell is None:
+        return ks
+    return [k / float(c) for k, c in zip(ks, cell)]
+
+
+def _green_factors(shape, l0, cell=None):
+    """Wave vectors and ``1 / (xi . L0 . xi)`` (zero where Gamma0 is 0)."""
+    ks = wave_vectors(shape, cell)
     k2 = sum(k * k for k in ks)
     keep = _nyquist_mask(shape) & (k2 > 0)
     inv = np.zeros(shape)
     inv[keep] = 1.0 / (l0 * k2[keep])
     return ks, inv
+
+
+class Medium:
+    """A digital microstructure and its cell.
+
+    ``lam`` is a scalar conductivity per node (shape ``N``: isotropic phases,
+    Sec. 3) or a symmetric tensor per node (shape ``(d, d, *N)``: the
+    second-order conductivity of Sec. 2.1, Eq. (1)); ``cell`` holds the d
+    side lengths of the cell (None: cubic).  Functions of this module accept
+    a Medium wherever they take ``lam``; a plain array is an isotropic medium
+    on a cubic cell."""
+
+    def __init__(self, lam, cell=None):
+        lam = np.asarray(lam, dtype=np.float64)
+        self.tensor = lam.ndim >= 4 and lam.shape[0] == lam.shape[1] == lam.ndim - 2
+        self.lam = lam
+        self.shape = lam.shape[2:] if self.tensor else lam.shape
+        self.d = len(self.shape)
+        self.cell = None if cell is None else tuple(float(c) for c in cell)
+        if self.cell is not None and len(self.cell) != self.d:
+            raise ValueError("cell needs one length per axis")
+
+    def times(self, p, shift=0.0):
+        """``(L - shift I) p`` at every node (p: ``(d, *N)``)."""
+        if self.tensor:
+            out = np.einsum("ab...,b...->a...", self.lam, p)
+            return out - shift * p if shift else out
+        return (self.lam - shift)[None, ...] * p
+
+    def eigen_range(self):
+        """Smallest and largest eigenvalue of L over all nodes."""
+        if not self.tensor:
+            return float(self.lam.min()), float(self.lam.max())
+        m = np.moveaxis(self.lam.reshape(self.d, self.d, -1), -1, 0)
+        w = np.linalg.eigvalsh(m)
+        return float(w.min()), float(w.max())
+
+
+def _medium(lam):
+    return lam if isinstance(lam, Medium) else Medium(lam)
 
 
 def green_hat(shape, l0: float) -> np.ndarray:
@@ -161,19 +217,21 @@ def green_hat(shape, l0: float) -> np.ndarray:
 # The operator of the collocation system (Sec. 2.2, Eqs. (15)-(17))
 # ---------------------------------------------------------------------------
 
-def apply_B(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
-    """``B p = F^{-1} Gamma0_hat F (dL p)`` with ``dL = lambda - l0``.
+def apply_B(p: np.ndarray, lam, l0: float) -> np.ndarray:
+    """``B p = F^{-1} Gamma0_hat F (dL p)`` with ``dL = L - l0 I``.
 
-    Sec. 2.2, Eq. (16): polarisation by the diagonal blocks ``dL`` (Eq. (3)
-    and Eq. (17)), forward DFT of each component, the block-diagonal Green
-    operator of Eq. (7), inverse DFT.  The result is real for real input.
+    Sec. 2.2, Eq. (16): polarisation by the blocks ``dL_ab`` (Eq. (3) and
+    Eq. (17); diagonal in the nodes, full d x d for tensor phases), forward
+    DFT of each component, the block-diagonal Green operator of Eq. (7),
+    inverse DFT.  The result is real for real input.
     """
-    shape = lam.shape
+    med = _medium(lam)
+    shape = med.shape
     d = len(shape)
     axes = tuple(range(1, d + 1))
-    tau = (lam - l0)[None, ...] * p
+    tau = med.times(p, l0)
     tau_hat = _fftn(tau, axes)
-    ks, inv = _green_factors(shape, l0)
+    ks, inv = _green_factors(shape, l0, med.cell)
     w_hat = np.zeros_like(tau_hat)
     for a in range(d):
         for b in range(d):
@@ -182,28 +240,30 @@ def apply_B(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
     return _ifftn(w_hat, axes).real
 
 
-def apply_A(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+def apply_A(p: np.ndarray, lam, l0: float) -> np.ndarray:
     """``(I + B) p``, the left-hand side of the collocation system, Eq. (15)."""
     return p + apply_B(p, lam, l0)
 
 
-def apply_BT(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+def apply_BT(p: np.ndarray, lam, l0: float) -> np.ndarray:
     """``B^T p = dL F^{-1} Gamma0_hat F p``: the factors of Eq. (16) in the
-    other order (``dL`` is diagonal and ``F^{-1} Gamma0_hat F`` is a real
-    symmetric matrix), the product BiCG needs besides ``B`` (Sec. 2.3)."""
-    shape = lam.shape
+    other order (``dL`` is symmetric block-diagonal and ``F^{-1} Gamma0_hat
+    F`` is a real symmetric matrix), the product BiCG needs besides ``B``
+    (Sec. 2.3)."""
+    med = _medium(lam)
+    shape = med.shape
     d = len(shape)
     axes = tuple(range(1, d + 1))
     p_hat = _fftn(np.asarray(p, dtype=np.float64), axes)
-    ks, inv = _green_factors(shape, l0)
+    ks, inv = _green_factors(shape, l0, med.cell)
     w_hat = np.zeros_like(p_hat)
     for a in range(d):
         for b in range(d):
             w_hat[a] += (ks[a] * ks[b] * inv) * p_hat[b]
-    return (lam - l0)[None, ...] * _ifftn(w_hat, axes).real
+    return med.times(_ifftn(w_hat, axes).real, l0)
 
 
-def apply_AT(p: np.ndarray, lam: np.ndarray, l0: float) -> np.ndarray:
+def apply_AT(p: np.ndarray, lam, l0: float) -> np.ndarray:
     """``(I + B)^T p``."""
     return p + apply_BT(p, lam, l0)
 
@@ -220,9 +280,11 @@ def _rhs(E, shape):
     return np.broadcast_to(E.reshape((d,) + (1,) * d), (d,) + tuple(shape)).copy()
 
 
-def optimal_reference(lam: np.ndarray) -> float:
-    """``l0 = (lambda_min + lambda_max) / 2``, Sec. 2.3, Eq. (19)."""
-    return 0.5 * (float(lam.min()) + float(lam.max()))
+def optimal_reference(lam) -> float:
+    """``l0 = (lambda_min + lambda_max) / 2``, Sec. 2.3, Eq. (19): the extreme
+    eigenvalues of L over the cell."""
+    lo, hi = _medium(lam).eigen_range()
+    return 0.5 * (lo + hi)
 
 
 def reference_omega(omega: float, rho: float) -> float:
@@ -261,7 +323,7 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     """
     if norm not in ("r", "eta_e"):
         raise ValueError("norm must be 'r' or 'eta_e'")
-    lam = np.asarray(lam, dtype=np.float64)
+    lam = _medium(lam)
     shape = lam.shape
     A = apply if apply is not None else (lambda v: apply_A(v, lam, l0))
     b = _rhs(E, shape)
@@ -332,7 +394,7 @@ def bicg(lam, l0, E, tol=1e-8, max_iter=10000, n_iter=None):
     ``p* = r* + beta p*``.  The test ``||r|| <= tol ||b||`` precedes each
     iteration (as in ``cg``); ``n_iter`` forces that many iterations.
     """
-    lam = np.asarray(lam, dtype=np.float64)
+    lam = _medium(lam)
     shape = lam.shape
     b = _rhs(E, shape)
     bnorm = math.sqrt(_dot(b, b))
@@ -377,7 +439,7 @@ def bicg(lam, l0, E, tol=1e-8, max_iter=10000, n_iter=None):
 
 def true_residual(lam, l0, E, e) -> float:
     """``||b - (I + B) e|| / ||b||`` evaluated afresh (Eq. (15))."""
-    b = _rhs(E, lam.shape)
+    b = _rhs(E, _medium(lam).shape)
     bn = math.sqrt(_dot(b, b))
     res = b - apply_A(e, lam, l0)
     return math.sqrt(_dot(res, res)) / bn if bn > 0 else 0.0
@@ -399,7 +461,7 @@ def ffth(lam, l0, E, tol=1e-8, max_iter=100000, norm="r", eta_history=False):
     """
     if norm not in ("r", "eta_e"):
         raise ValueError("norm must be 'r' or 'eta_e'")
-    lam = np.asarray(lam, dtype=np.float64)
+    lam = _medium(lam)
     b = _rhs(E, lam.shape)
     bnorm = math.sqrt(_dot(b, b))
     e = b.copy()
@@ -446,8 +508,8 @@ def dense_operator(lam, l0, cell_measure=1.0):
     ``[component][node]`` with nodes in the centred order, and ``order`` maps
     each centred node to its flat array index (``j = k mod N``).
     """
-    lam = np.asarray(lam, dtype=np.float64)
-    shape = lam.shape
+    med = _medium(lam)
+    shape = med.shape
     d = len(shape)
     idx = [_centred_indices(n) for n in shape]
     grids = np.meshgrid(*idx, indexing="ij")
@@ -458,32 +520,43 @@ def dense_operator(lam, l0, cell_measure=1.0):
     F = cell_measure ** -0.5 * np.exp(phase)
     Finv = cell_measure ** 0.5 / nn * np.exp(-phase)
     flat = np.ravel_multi_index(tuple((K % np.array(shape)).T), shape)
-    dl = lam.ravel()[flat] - l0
-    k2 = (K.astype(np.float64) ** 2).sum(axis=1)
+    # node blocks dL_ab (Eq. (17)): diagonal matrices, all d x d of them for tensors
+    if med.tensor:
+        dl = [[med.lam[a, b].ravel()[flat] - (l0 if a == b else 0.0) for b in range(d)] for a in range(d)]
+    else:
+        diag = med.lam.ravel()[flat] - l0
+        dl = [[diag if a == b else np.zeros(nn) for b in range(d)] for a in range(d)]
+    # Green operator blocks (Eq. (7)) at xi = k / Y
+    Y = np.ones(d) if med.cell is None else np.array(med.cell)
+    X = K.astype(np.float64) / Y[None, :]
+    k2 = (X ** 2).sum(axis=1)
     keep = k2 > 0
     for a, n in enumerate(shape):
         if n % 2 == 0:
             keep &= K[:, a] != n // 2
+    G = [[np.where(keep, X[:, a] * X[:, b] / (l0 * np.where(keep, k2, 1.0)), 0.0) for b in range(d)]
+         for a in range(d)]
     B = np.zeros((d * nn, d * nn), dtype=np.complex128)
-    FD = F * dl[None, :]
     for a in range(d):
-        for b in range(d):
-            gdiag = np.where(keep, K[:, a] * K[:, b] / (l0 * np.where(keep, k2, 1.0)), 0.0)
-            B[a * nn:(a + 1) * nn, b * nn:(b + 1) * nn] = Finv @ (gdiag[:, None] * FD)
+        for c in range(d):
+            # block (a, c) of Eq. (16): sum_b F^-1 G_ab F dL_bc
+            blk = np.zeros((nn, nn), dtype=np.complex128)
+            for b in range(d):
+                blk += Finv @ (G[a][b][:, None] * (F * dl[b][c][None, :]))
+            B[a * nn:(a + 1) * nn, c * nn:(c + 1) * nn] = blk
     M = np.eye(d * nn) + B
     return M, flat
 
 
 def dense_solve(lam, l0, E, cell_measure=1.0):
     """Direct solution of Eq. (15) with the dense matrix of ``dense_operator``."""
-    lam = np.asarray(lam, dtype=np.float64)
-    shape = lam.shape
+    shape = _medium(lam).shape
     d = len(shape)
     M, flat = dense_operator(lam, l0, cell_measure)
     nn = flat.size
     rhs = np.concatenate([np.full(nn, float(E[a])) for a in range(d)]).astype(np.complex128)
     sol = np.linalg.solve(M, rhs)
-    e = np.zeros((d, lam.size))
+    e = np.zeros((d, int(np.prod(shape))))
     for a in range(d):
         e[a, flat] = sol[a * nn:(a + 1) * nn].real
     return e.reshape((d,) + shape), float(np.abs(sol.imag).max())
@@ -500,15 +573,15 @@ def leff(lam, e) -> np.ndarray:
     current is the average of ``j``.  Returns ``d`` numbers (one column of the
     effective tensor for the load case that produced ``e``).
     """
-    lam = np.asarray(lam, dtype=np.float64)
-    d = lam.ndim
-    return np.array([float(np.mean(lam * e[a])) for a in range(d)])
+    med = _medium(lam)
+    j = med.times(e)
+    return np.array([float(np.mean(j[a])) for a in range(med.d)])
 
 
 def homogenize(lam, l0=None, tol=1e-10, max_iter=10000):
     """Full effective tensor from the ``d`` load cases ``E = e_beta``."""
-    lam = np.asarray(lam, dtype=np.float64)
-    d = lam.ndim
+    lam = _medium(lam)
+    d = lam.d
     l0 = optimal_reference(lam) if l0 is None else l0
     L = np.zeros((d, d))
     iters = []
@@ -533,11 +606,11 @@ def eta_e(lam, e) -> float:
     ``eta_e^2 = sum_k |k . j_hat(k)|^2 / |j_hat(0)|^2`` with ``j = lambda e``
     and integer frequencies; the ratio does not depend on DFT scaling.
     """
-    lam = np.asarray(lam, dtype=np.float64)
-    d = lam.ndim
+    med = _medium(lam)
+    d = med.d
     axes = tuple(range(1, d + 1))
-    j_hat = _fftn(lam[None, ...] * e, axes)
-    ks = grid_frequencies(lam.shape)
+    j_hat = _fftn(med.times(e), axes)
+    ks = wave_vectors(med.shape, med.cell)
     div = sum(ks[a] * j_hat[a] for a in range(d))
     num = float(np.sum(np.abs(div) ** 2))
     zero = (0,) * d
@@ -555,15 +628,15 @@ def eta_e_from_residual(lam, l0, E, e) -> float:
     the gradient fields of Sec. 2.1, hence ``|k . r_hat| = |k| |r_hat|``.
     Valid for odd grids (no Nyquist modes, where the Green operator is zero).
     """
-    lam = np.asarray(lam, dtype=np.float64)
-    d = lam.ndim
+    med = _medium(lam)
+    d = med.d
     axes = tuple(range(1, d + 1))
-    r = _rhs(E, lam.shape) - apply_A(e, lam, l0)
+    r = _rhs(E, med.shape) - apply_A(e, med, l0)
     r_hat = _fftn(r, axes)
-    ks = grid_frequencies(lam.shape)
+    ks = wave_vectors(med.shape, med.cell)
     k2 = sum(ks[a].astype(np.float64) ** 2 for a in range(d))
     num = float(np.sum(k2 * sum(np.abs(r_hat[a]) ** 2 for a in range(d))))
-    j_hat = _fftn(lam[None, ...] * e, axes)
+    j_hat = _fftn(med.times(e), axes)
     zero = (0,) * d
     den = float(sum(abs(j_hat[a][zero]) ** 2 for a in range(d)))
     return l0 * math.sqrt(num / den)

@@ -464,3 +464,94 @@ def test_bicg_iterates_equal_cg(rho):
     assert abs(a["iterations"] - b["iterations"]) <= (0 if rho < 100 else 0.06 * a["iterations"])
     # both meet the residual test; the fields agree to the conditioning times tol
     assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(a["e"]) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# General phases and cells (Sec. 2.1: tensor conductivity, cell prod(-Y, Y))
+# ---------------------------------------------------------------------------
+
+def _rand_tensor_field(shape, seed, lo=1.0, hi=20.0):
+    """Symmetric positive-definite d x d tensors per node."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    a = rng.standard_normal((d, d) + tuple(shape))
+    spd = np.einsum("ac...,bc...->ab...", a, a)
+    spd += lo * np.eye(d).reshape((d, d) + (1,) * d)
+    return spd * (hi / (1.0 + np.abs(spd).max()))
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 5, 3)])
+def test_tensor_and_cell_apply_match_dense_matrix(shape):
+    d = len(shape)
+    rng = np.random.default_rng(41)
+    p = rng.standard_normal((d,) + shape)
+    for med in (o.Medium(_rand_tensor_field(shape, 42) + 2 * np.eye(d).reshape((d, d) + (1,) * d)),
+                o.Medium(_rand_lam(shape, 43), cell=tuple(1.0 + 0.7 * a for a in range(d))),
+                o.Medium(_rand_tensor_field(shape, 44) + np.eye(d).reshape((d, d) + (1,) * d),
+                         cell=tuple(2.0 - 0.5 * a for a in range(d)))):
+        l0 = 7.0
+        M, flat = o.dense_operator(med, l0)
+        vec = np.concatenate([p[a].ravel()[flat] for a in range(d)])
+        ref = (M @ vec).real
+        got = o.apply_A(p, med, l0)
+        got_vec = np.concatenate([got[a].ravel()[flat] for a in range(d)])
+        np.testing.assert_allclose(got_vec, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        refT = (M.T @ vec).real
+        gotT = o.apply_AT(p, med, l0)
+        gotT_vec = np.concatenate([gotT[a].ravel()[flat] for a in range(d)])
+        np.testing.assert_allclose(gotT_vec, refT, rtol=0, atol=1e-12 * np.abs(refT).max())
+
+
+def test_anisotropic_laminate_closed_form():
+    """Layers along x0 with tensor phases: j0 and e1 are uniform, so
+    L_eff = [<1/L00>^-1, <L01/L00> H; ., <L11 - L01^2/L00> + <L01/L00>^2 H],
+    H = <1/L00>^-1 (Sec. 2.1, Eqs. (1)-(2) solved by hand)."""
+    n = 27
+    rng = np.random.default_rng(50)
+    layers = rng.integers(0, 3, n)
+    tens = np.array([[[4.0, 1.0], [1.0, 2.0]], [[1.0, -0.3], [-0.3, 3.0]], [[9.0, 2.5], [2.5, 6.0]]])
+    L = np.zeros((2, 2, n, n))
+    for i in range(n):
+        L[:, :, i, :] = tens[layers[i]][:, :, None]
+    med = o.Medium(L)
+    l0 = o.optimal_reference(med)
+    L00, L01, L11 = L[0, 0, :, 0], L[0, 1, :, 0], L[1, 1, :, 0]
+    H = 1.0 / np.mean(1.0 / L00)
+    ref = np.array([[H, np.mean(L01 / L00) * H],
+                    [np.mean(L01 / L00) * H, np.mean(L11 - L01 ** 2 / L00) + np.mean(L01 / L00) ** 2 * H]])
+    got = np.zeros((2, 2))
+    for b in range(2):
+        E = np.zeros(2)
+        E[b] = 1.0
+        res = o.cg(med, l0, E, tol=1e-13)
+        got[:, b] = o.leff(med, res["e"])
+    np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("cell", [(1.0, 2.5), (0.4, 1.0)])
+def test_stretched_cell_equals_anisotropic_unit_cell(cell):
+    """x' = x / Y maps the isotropic problem on a cell of side lengths Y to
+    the unit cell with L' = lambda diag(1/Y^2), E' = Y E, e' = Y e: the two
+    discrete solutions agree node by node."""
+    lam = ms.grf_two_phase(27, 0.2, 0.4, 20.0, seed=5).lam()
+    Y = np.array(cell)
+    E = np.array([0.6, -0.8])
+    a = o.cg(o.Medium(lam, cell=cell), o.optimal_reference(lam), E, tol=1e-13)
+    Lp = np.zeros((2, 2) + lam.shape)
+    for k in range(2):
+        Lp[k, k] = lam / Y[k] ** 2
+    medp = o.Medium(Lp)
+    b = o.cg(medp, o.optimal_reference(medp), Y * E, tol=1e-13)
+    mapped = Y[:, None, None] * a["e"]
+    assert np.linalg.norm(b["e"] - mapped) / np.linalg.norm(mapped) < 1e-10
+    # and the effective tensors: L'_eff = diag(1/Y) L_eff diag(1/Y)
+    np.testing.assert_allclose(o.leff(medp, b["e"]), o.leff(o.Medium(lam, cell=cell), a["e"]) / Y, rtol=1e-10)
+
+
+def test_tensor_phase_effective_tensor_symmetric():
+    L = _rand_tensor_field((15, 21), 60) + np.eye(2).reshape(2, 2, 1, 1)
+    Leff, _ = o.homogenize(o.Medium(L), tol=1e-12)
+    assert abs(Leff[0, 1] - Leff[1, 0]) < 1e-10 * np.abs(Leff).max()
+    # between the harmonic and arithmetic averages of the tensor field
+    arith = L.mean(axis=(2, 3))
+    assert np.all(np.linalg.eigvalsh(arith - Leff) > -1e-10)
