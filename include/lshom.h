@@ -137,6 +137,26 @@ lshom_status lshom_set_microstructure(lshom_ctx* ctx, int d, const int64_t* N,
                                       const uint8_t* phase_dev, int n_phases,
                                       const double* cond_host);
 
+/*
+ * As lshom_set_microstructure with a second-order conductivity tensor per
+ * phase (Sec. 2.1, Eq. (1)): cond_tensor_host holds n_phases symmetric
+ * positive-definite d x d matrices, row-major, copied.  n_phases is at most
+ * 256 / (d (d + 1) / 2).  l0 defaults to (smallest + largest eigenvalue) / 2
+ * over the phases (Sec. 2.3, Eq. (19)).  Single solves (lshom_solve,
+ * lshom_homogenize, lshom_apply) with any method and precision.
+ */
+lshom_status lshom_set_microstructure_tensor(lshom_ctx* ctx, int d, const int64_t* N,
+                                             const uint8_t* phase_dev, int n_phases,
+                                             const double* cond_tensor_host);
+
+/*
+ * Side lengths of the periodic cell (Sec. 2.1, the cell prod (-Y_a, Y_a); d
+ * finite values > 0, only their ratios matter).  The Green operator then
+ * takes the wave vector xi_a = k_a / Y_a in place of the integer frequency
+ * (and so does the equilibrium norm).  The default is a cubic cell.
+ */
+lshom_status lshom_set_cell(lshom_ctx* ctx, const double* lengths);
+
 /* Reference medium L0 = l0 I (Sec. 2.1, Eq. (3); Sec. 3, Eq. (20)); finite, > 0. */
 lshom_status lshom_set_reference(lshom_ctx* ctx, double l0);
 
@@ -210,6 +230,7 @@ typedef struct lshom_problem {
   double E[3];
   double tol;
   double* e_dev;
+  double cell[3];  /* side lengths of the cell (Sec. 2.1; Green operator at xi = k / Y); all 0: cubic */
 } lshom_problem;
 
 /* Device workspace bytes lshom_solve_batched needs for these problems. */

@@ -88,7 +88,10 @@ struct Group {
   bool transposed = false;      // 2-D spectral arrays stored [k1][k0]
   FftPlan plan64[3], plan32[3];
   PassShape shape64{2, 1, 1, 0, 0, 0}, shape32{2, 1, 1, 0, 0, 0};
-  int n_phases = 1;             // conductivity entries staged per problem
+  int n_phases = 1;             // conductivity-table entries staged per problem
+  int n_phase_ids = 1;          // phases (table entries per phase: 1, or d (d + 1) / 2 for tensors)
+  bool tensor = false;          // symmetric tensor phases (row pass keeps all components together)
+  double cell_inv[3] = {1.0, 1.0, 1.0};  // 1 / cell side lengths (wave vector xi = k / Y)
   // single problem (nprob == 1, batched == false)
   const uint8_t* phase = nullptr;
   double l0 = 0.0;
@@ -116,7 +119,7 @@ struct Group {
 // Fills the geometry, plans and shapes of g (from the context's schedule
 // registry when it has an entry for the grid); UNSUPPORTED if a pass cannot
 // hold its FFT batch in LDS.
-lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases);
+lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases, bool tensor = false);
 bool schedule_fits(const Group& g, const Schedule& s, int precision);
 void apply_schedule(Group& g, const Schedule& s, int precision);
 Schedule current_schedule(const Group& g, int precision);

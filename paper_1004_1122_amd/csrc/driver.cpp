@@ -41,7 +41,10 @@ long long inner0_of(const Group& g) {
 
 }  // namespace
 
-lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
+lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases_in, bool tensor) {
+  const int n_phases = n_phases_in * (tensor ? d * (d + 1) / 2 : 1);  // table entries
+  g.tensor = tensor;
+  g.n_phase_ids = n_phases_in;
   g.d = d;
   g.nvox = 1;
   for (int a = 0; a < 3; ++a) g.N[a] = a < d ? N[a] : 1;
@@ -55,9 +58,9 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
   g.n_phases = n_phases;
   for (int a = 0; a < d; ++a) g.plan64[a] = g.plan32[a] = default_plan((int)N[a]);
   g.shape64 = default_shape(d, g.N, g.plan64, (int)sizeof(cx<double>), kLdsBudget, kMinBlocks,
-                            g.transposed, n_phases);
+                            g.transposed, n_phases, !tensor);
   g.shape32 = default_shape(d, g.N, g.plan32, (int)sizeof(cx<float>), kLdsBudget, kMinBlocks,
-                            g.transposed, n_phases);
+                            g.transposed, n_phases, !tensor);
   if (!shape_fits(d, g.N, g.plan64, g.shape64, (int)sizeof(cx<double>), kLdsBudget, n_phases) ||
       !shape_fits(d, g.N, g.plan32, g.shape32, (int)sizeof(cx<float>), kLdsBudget, n_phases))
     return LSHOM_ERR_UNSUPPORTED;
@@ -78,6 +81,7 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases) {
 }
 
 bool schedule_fits(const Group& g, const Schedule& s, int precision) {
+  if (g.tensor && s.shape.row_split) return false;
   for (int a = 0; a < g.d; ++a) {
     if (s.plan[a].n != g.N[a]) return false;
     FftPlan chk;
@@ -277,6 +281,7 @@ ColArgs<T> col0_args(Group& g, const Bufs<T>& b) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
   }
+  for (int t = 0; t < kMaxDim; ++t) a.cinv[t] = g.cell_inv[t];
   a.dims = g.d;
   a.h = g.h;
   a.plan = b.plan[0];
@@ -310,6 +315,7 @@ ColArgs<T> col1_args(Group& g, const Bufs<T>& b, int dir) {
     a.comp[t] = b.w[t];
     a.nd[t] = (int)g.N[t];
   }
+  for (int t = 0; t < kMaxDim; ++t) a.cinv[t] = g.cell_inv[t];
   a.dims = g.d;
   a.h = g.h;
   a.mode = COL_PLAIN;
@@ -355,6 +361,7 @@ RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
   a.phase = g.phase;
   a.cond = b.cond;
   a.n_phases = g.n_phases;
+  a.tensor = g.tensor ? 1 : 0;
   a.l0 = (T)g.l0;
   a.inv_n = (T)(1.0 / (double)g.nvox);
   a.plan = b.plan[last];
@@ -410,6 +417,7 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   u.dims = g.d;
   for (int t = 0; t < 3; ++t) u.nd[t] = (int)g.N[t];
   u.fd_n1 = make_fastdiv((uint32_t)g.N[1]);
+  for (int t = 0; t < kMaxDim; ++t) u.cinv[t] = g.cell_inv[t];
   return u;
 }
 
@@ -823,7 +831,7 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
     HIP_TRY(c, launch_max_phase(ph, g.nvox, mx, stream_of(g)));
     HIP_TRY(c, hipMemcpyAsync(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost, stream_of(g)));
     HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
-    if (host_max >= (unsigned)g.n_phases)
+    if (host_max >= (unsigned)g.n_phase_ids)
       return fail(c, LSHOM_ERR_INVALID_ARG, "phase image holds an index >= n_phases");
   }
   return LSHOM_OK;

@@ -160,8 +160,9 @@ struct RowArgs {
   double* real_out[kMaxDim];
   const double* real_add[kMaxDim];
   const uint8_t* phase;          // [nrows][n]
-  const T* cond;                 // conductivity per phase (n_phases entries)
-  int n_phases;
+  const T* cond;                 // conductivity table (n_phases entries)
+  int n_phases;                  // table entries (phases x entries per phase)
+  int tensor;                    // symmetric tensor phases: d (d + 1) / 2 entries each (needs !split)
   T l0;
   T E[kMaxDim];
   T inv_n;                       // 1 / |N|
@@ -203,6 +204,7 @@ struct ColArgs {
   int nd[kMaxDim];       // full grid sizes
   int dims;
   int h;                 // half length of the last axis
+  double cinv[kMaxDim];  // 1 / cell side length per axis: wave vector xi = k / Y
   // COL_INV_C
   const cx<T>* c_in;     // used when cg_step == 0
   cx<T>* p_io;           // cg_step: p = r + beta p (written back)
@@ -255,6 +257,7 @@ struct UpdArgs {
   int dims;
   int nd[kMaxDim];
   FastDiv fd_n1;         // nd[1] (3-D index split)
+  double cinv[kMaxDim];  // 1 / cell side length per axis
 };
 
 // BiCG on real d-component nodal fields ([d][n] FP64, components contiguous):

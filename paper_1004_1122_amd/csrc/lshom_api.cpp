@@ -91,6 +91,37 @@ hipError_t order_after_user(lshom_ctx* c) {
   return hipStreamWaitEvent(c->stream, c->ev, 0);
 }
 
+// Eigenvalues of a symmetric d x d matrix (d <= 3) by cyclic Jacobi
+// rotations; a[] is row-major and is overwritten.
+void sym_eigenvalues(double* a, int d, double* w) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) off += a[p * d + q] * a[p * d + q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double apq = a[p * d + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = 0.5 * (a[q * d + q] - a[p * d + p]) / apq;
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < d; ++k) {  // columns p, q
+          const double akp = a[k * d + p], akq = a[k * d + q];
+          a[k * d + p] = cs * akp - sn * akq;
+          a[k * d + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < d; ++k) {  // rows p, q
+          const double apk = a[p * d + k], aqk = a[q * d + k];
+          a[p * d + k] = cs * apk - sn * aqk;
+          a[q * d + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < d; ++i) w[i] = a[i * d + i];
+}
+
+
 lshom_status validate_opts(lshom_ctx* c, const lshom_solve_opts* o) {
   if (o->max_iter < 0) return fail(c, LSHOM_ERR_INVALID_ARG, "max_iter must be >= 0");
   if (o->precision != LSHOM_PRECISION_FP64 && o->precision != LSHOM_PRECISION_MIXED)
@@ -241,6 +272,77 @@ lshom_status lshom_set_microstructure(lshom_ctx* c, int d, const int64_t* N,
   c->g.l0 = 0.5 * (lo + hi);
   c->have_problem = true;
   c->err.clear();
+  return LSHOM_OK;
+}
+
+
+lshom_status lshom_set_microstructure_tensor(lshom_ctx* c, int d, const int64_t* N, const uint8_t* phase_dev,
+                                             int n_phases, const double* cond_tensor_host) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  if (d != 2 && d != 3) return fail(c, LSHOM_ERR_INVALID_ARG, "d must be 2 or 3");
+  const int ncomp = d * (d + 1) / 2;
+  if (n_phases < 1 || n_phases * ncomp > kMaxPhases || !cond_tensor_host)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "n_phases out of range (at most 256 / (d (d + 1) / 2)) or cond NULL");
+  // the scalar check covers d and N (a unit table stands in for the tensors)
+  std::vector<double> ones(n_phases, 1.0);
+  lshom_status s = lshom_check_problem(d, N, n_phases, ones.data(), 0.0, nullptr, -1.0);
+  if (s != LSHOM_OK) return fail(c, s, "invalid microstructure (d, N or n_phases)");
+  if (!phase_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "phase_dev is NULL");
+  std::vector<double> table;
+  double lo = 1e300, hi = -1e300;
+  for (int q = 0; q < n_phases; ++q) {
+    const double* m = cond_tensor_host + (size_t)q * d * d;
+    double scale = 0.0;
+    for (int i = 0; i < d * d; ++i) {
+      if (!std::isfinite(m[i])) return fail(c, LSHOM_ERR_INVALID_ARG, "tensor entries must be finite");
+      scale = std::max(scale, std::fabs(m[i]));
+    }
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j)
+        if (std::fabs(m[i * d + j] - m[j * d + i]) > 1e-12 * scale)
+          return fail(c, LSHOM_ERR_INVALID_ARG, "phase tensors must be symmetric");
+    double a[9], w[3];
+    for (int i = 0; i < d * d; ++i) a[i] = m[i];
+    sym_eigenvalues(a, d, w);
+    for (int i = 0; i < d; ++i) {
+      if (!(w[i] > 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "phase tensors must be positive definite");
+      lo = std::min(lo, w[i]);
+      hi = std::max(hi, w[i]);
+    }
+    for (int i = 0; i < d; ++i)
+      for (int j = i; j < d; ++j) table.push_back(0.5 * (m[i * d + j] + m[j * d + i]));
+  }
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c->graphs);
+  drop_batch_graphs(c);
+  c->ws_ready = false;
+  c->have_problem = false;
+  c->g = Group{};
+  c->g.ctx = c;
+  c->g.graph_cache = &c->graphs;
+  if (group_setup(c->g, d, N, n_phases, true) != LSHOM_OK)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+  c->g.phase = phase_dev;
+  c->cond = table;
+  // Sec. 2.3, Eq. (19): the extreme eigenvalues of L over the cell
+  c->g.l0 = 0.5 * (lo + hi);
+  c->have_problem = true;
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_set_cell(lshom_ctx* c, const double* lengths) {
+  if (!c || !lengths) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
+  for (int a = 0; a < c->g.d; ++a)
+    if (!std::isfinite(lengths[a]) || !(lengths[a] > 0.0))
+      return fail(c, LSHOM_ERR_INVALID_ARG, "cell lengths must be finite and > 0");
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c->graphs);
+  drop_batch_graphs(c);  // the wave vectors are baked into captured launches
+  for (int a = 0; a < 3; ++a) c->g.cell_inv[a] = a < c->g.d ? 1.0 / lengths[a] : 1.0;
   return LSHOM_OK;
 }
 
@@ -429,9 +531,24 @@ lshom_status plan_batch(lshom_ctx* c, int n, const lshom_problem* probs, int pre
     lshom_status s = lshom_check_problem(p.d, p.N, p.n_phases, p.cond_host, p.l0 > 0 ? p.l0 : 0.0, p.E, p.tol);
     if (s != LSHOM_OK) return fail(c, s, "problem " + std::to_string(i) + " is invalid");
     if (!p.phase_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": phase_dev is NULL");
+    {
+      bool zero = true, ok = true;
+      for (int a = 0; a < p.d; ++a) {
+        zero = zero && p.cell[a] == 0.0;
+        ok = ok && std::isfinite(p.cell[a]) && p.cell[a] > 0.0;
+      }
+      if (!zero && !ok)
+        return fail(c, LSHOM_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": cell lengths must be all 0 or > 0");
+    }
     if (!(p.tol >= 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": tol < 0");
+    // problems share launches when they share the grid and the cell
     std::vector<int64_t> key(p.N, p.N + p.d);
     key.insert(key.begin(), p.d);
+    for (int a = 0; a < p.d; ++a) {
+      int64_t bits;
+      std::memcpy(&bits, &p.cell[a], sizeof(bits));
+      key.push_back(bits);
+    }
     auto it = by_grid.find(key);
     if (it == by_grid.end()) {
       it = by_grid.emplace(key, (int)bp->groups.size()).first;
@@ -449,6 +566,7 @@ lshom_status plan_batch(lshom_ctx* c, int n, const lshom_problem* probs, int pre
     g.ctx = c;
     if (group_setup(g, p0.d, p0.N, nph) != LSHOM_OK)
       return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
+    for (int a = 0; a < p0.d; ++a) g.cell_inv[a] = p0.cell[a] > 0.0 ? 1.0 / p0.cell[a] : 1.0;
     g.nprob = (int)bp->members[gi].size();
     g.batched = true;
     g.lay = compute_layout(g, precision == LSHOM_PRECISION_MIXED);
@@ -630,7 +748,8 @@ lshom_status lshom_set_schedule(lshom_ctx* c, const lshom_schedule* in) {
   lshom_status st = from_c_schedule(c, in, &s);
   if (st != LSHOM_OK) return st;
   Group probe;
-  if (group_setup(probe, in->d, in->N, c->have_problem ? c->g.n_phases : 1) != LSHOM_OK)
+  if (group_setup(probe, in->d, in->N, c->have_problem ? c->g.n_phase_ids : 1, c->have_problem && c->g.tensor) !=
+      LSHOM_OK)
     return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch");
   if (!schedule_fits(probe, s, in->precision))
     return fail(c, LSHOM_ERR_INVALID_ARG, "schedule exceeds the FFT batch or LDS limits");

@@ -53,9 +53,9 @@ __device__ __forceinline__ bool khat_axis0(const ColArgs<T>& a, int l, long long
     if (t < a.dims) {
       const int n = a.nd[t];
       if ((n & 1) == 0 && idx[t] == n / 2) return false;
-      // the last axis is stored as its non-negative half
+      // the last axis is stored as its non-negative half; xi = k / Y
       const int k = (t == a.dims - 1) ? idx[t] : freq_of(idx[t], n);
-      kf[t] = (double)k;
+      kf[t] = (double)k * a.cinv[t];
       k2 += kf[t] * kf[t];
     }
   }
@@ -73,6 +73,24 @@ __device__ __forceinline__ double half_weight(long long k_last, int n_last) {
   if (k_last == 0) return 1.0;
   if ((n_last & 1) == 0 && k_last == n_last / 2) return 1.0;
   return 2.0;
+}
+
+// (L_q - shift I) v at one node for a symmetric tensor phase q whose entries
+// are stored as its upper triangle row by row (2-D: 00 01 11; 3-D: 00 01 02
+// 11 12 22): the polarisation of Sec. 2.1, Eq. (3) with tensor phases.
+template <typename T>
+__device__ __forceinline__ void tensor_times(const T* tab, int q, int d, T shift, const T* v, T* out) {
+  if (d == 2) {
+    const T* m = tab + q * 3;
+    out[0] = (m[0] - shift) * v[0] + m[1] * v[1];
+    out[1] = m[1] * v[0] + (m[2] - shift) * v[1];
+    out[2] = T(0);
+  } else {
+    const T* m = tab + q * 6;
+    out[0] = (m[0] - shift) * v[0] + m[1] * v[1] + m[2] * v[2];
+    out[1] = m[1] * v[0] + (m[3] - shift) * v[1] + m[4] * v[2];
+    out[2] = m[2] * v[0] + m[4] * v[1] + (m[5] - shift) * v[2];
+  }
 }
 
 // Loads in flight per thread in the staging and data loops: with few blocks
@@ -180,6 +198,30 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     copy_batched<cx<T>, NT>(tw, a.tw, ntw);
     copy_batched<T, NT>(cond, csrc, a.n_phases);
     __syncthreads();
+    if (a.tensor && (a.flags & ROWF_DL)) {
+      // every component of a node at once (the block holds all of them)
+      for (int idx = tid; idx < half_rows * n; idx += NT) {
+        const int j = (int)fdiv((uint32_t)idx, a.fd_n);
+        const int x = idx - j * n;
+        T t[2][kMaxDim];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int rl = 2 * j + u;
+          T v[kMaxDim] = {T(0), T(0), T(0)};
+#pragma unroll
+          for (int c = 0; c < kMaxDim; ++c) {
+            t[u][c] = T(0);
+            if (c < d && rl < rows_here)
+              v[c] = (a.flags & ROWF_CONST_E) ? pick3(Ev, c) : (T)pick3(a.real_in, c)[(row0 + rl) * n + x];
+          }
+          if (rl < rows_here) tensor_times(cond, ph[rl * n + x], d, l0, v, t[u]);
+        }
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c)
+          if (c < d) Z[(c * half_rows + j) * ss + x] = cx<T>{t[0][c], t[1][c]};
+      }
+      __syncthreads();
+    } else {
     for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = (int)fdiv((uint32_t)idx, a.fd_n);
       const int x = idx - p * n;
@@ -198,6 +240,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       Z[p * ss + x] = cx<T>{v[0], v[1]};
     }
     __syncthreads();
+    }
   } else {
     // Hermitian half rows of two rows -> one full complex row
     const int total = npairs * h;
@@ -273,6 +316,45 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
     if constexpr (MODE == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
+      if (a.tensor && (a.flags & (ROWF_LEFF | ROWF_DL_SCALE))) {
+        for (int idx = tid; idx < half_rows * n; idx += NT) {
+          const int j = (int)fdiv((uint32_t)idx, a.fd_n);
+          const int x = idx - j * n;
+          cx<T> z[kMaxDim];
+#pragma unroll
+          for (int c = 0; c < kMaxDim; ++c) z[c] = c < d ? Z[(c * half_rows + j) * ss + x] : cx<T>{T(0), T(0)};
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int rl = 2 * j + u;
+            if (rl >= rows_here) continue;
+            const long long g = (row0 + rl) * n + x;
+            const int q = ph[rl * n + x];
+            T v[kMaxDim], w[kMaxDim];
+#pragma unroll
+            for (int c = 0; c < kMaxDim; ++c)
+              v[c] = c < d ? (T)((double)pick3(Ev, c) + (double)((u == 0 ? z[c].re : z[c].im) * a.inv_n)) : T(0);
+            if (a.flags & ROWF_DL_SCALE) {
+              tensor_times(cond, q, d, l0, v, w);
+#pragma unroll
+              for (int c = 0; c < kMaxDim; ++c) v[c] = w[c] / l0;
+            }
+#pragma unroll
+            for (int c = 0; c < kMaxDim; ++c) {
+              if (c >= d) continue;
+              double val = (double)v[c];
+              if (a.flags & ROWF_ADD) val += pick3(a.real_add, c)[g];
+              v[c] = (T)val;
+              double* out = pick3(a.real_out, c);
+              if (out) out[g] = val;
+            }
+            if (a.flags & ROWF_LEFF) {
+              tensor_times(cond, q, d, T(0), v, w);
+#pragma unroll
+              for (int c = 0; c < kMaxDim; ++c) acc[c] += (double)w[c];
+            }
+          }
+        }
+      } else {
       for (int idx = tid; idx < npairs * n; idx += NT) {
         const int p = (int)fdiv((uint32_t)idx, a.fd_n);
         const int x = idx - p * n;
@@ -297,6 +379,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           }
         }
       }
+      }
       if (a.flags & ROWF_LEFF) {
         double* dst = parts.region(PART_AUX) + (long long)bx * 3;
         for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);
@@ -305,6 +388,26 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     }
 
     // ROW_FUSED: polarisation dL (E + u) at the nodes (Sec. 2.2, Eq. (17))
+    if (a.tensor) {
+      for (int idx = tid; idx < half_rows * n; idx += NT) {
+        const int j = (int)fdiv((uint32_t)idx, a.fd_n);
+        const int x = idx - j * n;
+        T u0[kMaxDim], u1[kMaxDim], t0[kMaxDim], t1[kMaxDim];
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c) {
+          const cx<T> z = c < d ? Z[(c * half_rows + j) * ss + x] : cx<T>{T(0), T(0)};
+          u0[c] = c < d ? pick3(Ev, c) + z.re * a.inv_n : T(0);
+          u1[c] = c < d ? pick3(Ev, c) + z.im * a.inv_n : T(0);
+          t0[c] = T(0);
+          t1[c] = T(0);
+        }
+        if (2 * j < rows_here) tensor_times(cond, phs[2 * j * n + x], d, l0, u0, t0);
+        if (2 * j + 1 < rows_here) tensor_times(cond, phs[(2 * j + 1) * n + x], d, l0, u1, t1);
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c)
+          if (c < d) Z[(c * half_rows + j) * ss + x] = cx<T>{t0[c], t1[c]};
+      }
+    } else
     for (int idx = tid; idx < npairs * n; idx += NT) {
       const int p = (int)fdiv((uint32_t)idx, a.fd_n);
       const int x = idx - p * n;
@@ -607,8 +710,11 @@ __device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, u
     k0 = (int)i0;
   }
   k0 = freq_of(k0, a.nd[0]);
-  const double kl = (double)k_last;
-  return (double)k0 * k0 + (double)k1 * k1 + kl * kl;
+  const int last = a.dims - 1;
+  const double x0 = (double)k0 * a.cinv[0];
+  const double x1 = a.dims == 2 ? 0.0 : (double)k1 * a.cinv[1];
+  const double xl = (double)k_last * a.cinv[last];
+  return x0 * x0 + x1 * x1 + xl * xl;
 }
 
 // ---------------------------------------------------------------------------

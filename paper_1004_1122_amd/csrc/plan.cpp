@@ -83,7 +83,8 @@ static long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 constexpr int kMaxThreads = 256;
 
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
-                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases) {
+                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases,
+                        bool allow_split) {
   PassShape s{2, 1, 1, 0, 0, 0};
   const int last = d - 1;
   const int n_last = (int)N[last];
@@ -96,7 +97,7 @@ PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_
   // (whole cache lines) with one component per block
   {
     const int cap = plan_batch_cap(plans[last], kMaxThreads);
-    s.row_split = transposed ? 1 : 0;
+    s.row_split = (transposed && allow_split) ? 1 : 0;
     const int comps = s.row_split ? 1 : d;
     const int target = transposed ? (128 / elem_bytes < 2 ? 2 : 128 / elem_bytes) : 64;
     int best = 2;

@@ -35,8 +35,11 @@ struct PassShape {
 // Default shapes within the FFT batch limit (256 threads) and lds_budget
 // bytes of LDS, reduced while a pass would have fewer than min_blocks blocks.
 // `transposed`: 2-D spectral arrays stored [k1][k0] (columns contiguous).
+// `allow_split`: the row pass may hold one component per block (not for
+// tensor phases, whose polarisation couples the components of a node).
 PassShape default_shape(int d, const int64_t* N, const FftPlan* plans, int elem_bytes,
-                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases);
+                        size_t lds_budget, long long min_blocks, bool transposed, int n_phases,
+                        bool allow_split = true);
 
 // True when every pass of the shape respects the FFT batch limit and the LDS
 // budget (otherwise the problem is unsupported at this precision).

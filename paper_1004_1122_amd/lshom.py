@@ -88,6 +88,7 @@ class lshom_problem(Structure):
         ("E", c_double * 3),
         ("tol", c_double),
         ("e_dev", c_void_p),
+        ("cell", c_double * 3),
     ]
 
 
@@ -169,7 +170,9 @@ def load(path: str = LIB_PATH):
         "lshom_create": (c_int32, [POINTER(c_void_p), c_int, P]),
         "lshom_destroy": (None, [P]),
         "lshom_set_microstructure": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
+        "lshom_set_microstructure_tensor": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
         "lshom_set_reference": (c_int32, [P, c_double]),
+        "lshom_set_cell": (c_int32, [P, POINTER(c_double)]),
         "lshom_workspace_size": (c_int32, [P, c_int, POINTER(c_size_t)]),
         "lshom_workspace_size_for": (c_int32, [P, POINTER(lshom_solve_opts), POINTER(c_size_t)]),
         "lshom_set_workspace": (c_int32, [P, P, c_size_t]),
@@ -282,7 +285,9 @@ def lshom_get_pass_timing(ctx):
 class Solver:
     """One microstructure on one device; owns a context and its workspace."""
 
-    def __init__(self, phase, cond, device: int = 0, precision: int = PRECISION_MIXED):
+    def __init__(self, phase, cond, device: int = 0, precision: int = PRECISION_MIXED, cell=None):
+        """cond: one conductivity per phase, or an array [n_phases, d, d] of
+        symmetric tensors; cell: side lengths of the cell (default cubic)."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -295,14 +300,25 @@ class Solver:
         self.shape = tuple(self.phase.shape)
         self.d = len(self.shape)
         self.nvox = int(np.prod(self.shape))
-        self.cond = [float(c) for c in cond]
+        cond_arr = np.asarray(cond, dtype=np.float64)
+        self.tensor = cond_arr.ndim == 3
+        self.cond = cond_arr if self.tensor else [float(c) for c in cond]
         self.device = dev
         stream = torch.cuda.current_stream(dev).cuda_stream
         self.ctx = lshom_create(device, stream)
         Narr = (c_int64 * self.d)(*self.shape)
-        _check(self.ctx, self.lib.lshom_set_microstructure(self.ctx, self.d, Narr,
-                                                           c_void_p(self.phase.data_ptr()),
-                                                           len(self.cond), _dbl_array(self.cond)))
+        if self.tensor:
+            if cond_arr.shape[1:] != (self.d, self.d):
+                raise ValueError(f"tensor phases must have shape [n_phases, {self.d}, {self.d}]")
+            _check(self.ctx, self.lib.lshom_set_microstructure_tensor(
+                self.ctx, self.d, Narr, c_void_p(self.phase.data_ptr()), cond_arr.shape[0],
+                _dbl_array(cond_arr.ravel())))
+        else:
+            _check(self.ctx, self.lib.lshom_set_microstructure(self.ctx, self.d, Narr,
+                                                               c_void_p(self.phase.data_ptr()),
+                                                               len(self.cond), _dbl_array(self.cond)))
+        if cell is not None:
+            self.set_cell(cell)
         size = c_size_t()
         _check(self.ctx, self.lib.lshom_workspace_size(self.ctx, int(precision), ctypes.byref(size)))
         self._attach_workspace(int(size.value))
@@ -345,6 +361,10 @@ class Solver:
 
     def set_reference(self, l0: float):
         _check(self.ctx, self.lib.lshom_set_reference(self.ctx, float(l0)))
+
+    def set_cell(self, lengths):
+        """Side lengths of the periodic cell (only their ratios matter)."""
+        _check(self.ctx, self.lib.lshom_set_cell(self.ctx, _dbl_array(lengths)))
 
     def opts(self, **kw) -> lshom_solve_opts:
         o = lshom_default_opts()
@@ -503,6 +523,8 @@ class BatchSolver:
             a.l0 = float(pr.get("l0") or 0.0)
             a.tol = float(pr["tol"])
             a.e_dev = e.data_ptr() if e is not None else None
+            for t in range(3):
+                a.cell[t] = float(pr["cell"][t]) if pr.get("cell") is not None and t < d else 0.0
         size = c_size_t()
         _check(self.ctx, self.lib.lshom_batch_workspace_size(self.ctx, n, arr, int(precision), ctypes.byref(size)))
         need = int(size.value)
