@@ -16,7 +16,10 @@ Conventions (documented readings of the paper, see also the repository notes):
   shape ``(d, N_1, ..., N_d)``; array index ``j`` sits at coordinate
   ``x = j / N`` of the unit cell (a cyclic shift of the paper's centred node
   numbering, Sec. 2.2, Eq. (10)).
-* Phases are isotropic, ``L(x) = lambda(x) I`` and ``L0 = l0 I`` (Sec. 3).
+* Phases are isotropic, ``L(x) = lambda(x) I``, or symmetric tensors
+  (``Medium``); the reference medium is ``L0 = l0 I`` (Sec. 3) or any
+  symmetric positive definite ``d x d`` matrix (Sec. 2.1, Eq. (7)): every
+  ``l0`` argument takes either form.
 * The DFT is unnormalised forward, ``1/|N|`` inverse.  The ``|Y|^{-1/2}`` and
   ``|Y|^{1/2}`` factors of the Vandermonde matrices (Sec. 2.2, Eqs. (13)-(14))
   cancel inside the operator ``B`` of Eq. (16).
@@ -28,6 +31,12 @@ Conventions (documented readings of the paper, see also the repository notes):
   Saad's Algorithm 6.18, with Euclidean inner products over all ``d |N|``
   entries and ``x0 = e0``.  It stops when ``||r_m||_2 <= tol ||e0||_2`` (the
   relative residual; the paper's ``eta_r`` of Eq. (22) is reported beside it).
+  For an anisotropic ``L0`` the system matrix is self-adjoint (on the
+  fields the iterates live in) only in the energy product of the reference
+  medium, ``<u, v>_L0 = sum_x u(x) . L0 . v(x)``; CG and the basic scheme
+  then take that product and its norm.  For ``L0 = l0 I`` it is ``l0`` times
+  the Euclidean one, so nothing changes.  BiCG, meant for non-symmetric
+  systems, keeps the Euclidean product.
 * The homogenised conductivity is ``L_eff E = <lambda e>``, the cell average
   of the current ``j = L e`` of Sec. 2.1, Eq. (1); the full tensor comes from
   ``d`` load cases.
@@ -55,6 +64,7 @@ __all__ = [
     "grid_frequencies",
     "wave_vectors",
     "Medium",
+    "reference_matrix",
     "green_hat",
     "apply_B",
     "apply_A",
@@ -143,14 +153,66 @@ def wave_vectors(shape, cell=None):
     return [k / float(c) for k, c in zip(ks, cell)]
 
 
+def reference_matrix(l0, d):
+    """The reference conductivity as ``(L0, iso)``.
+
+    ``l0`` is a number (``L0 = l0 I``, the isotropic reference of Sec. 3) or
+    a symmetric positive definite ``d x d`` matrix (the general ``L0`` of
+    Sec. 2.1, Eqs. (3) and (7)).  A matrix equal to a multiple of ``I`` is
+    returned as that number (``iso`` True), so both spellings of an
+    isotropic reference give identical results."""
+    if np.ndim(l0) == 0:
+        return float(l0), True
+    m = np.array(l0, dtype=np.float64)
+    if m.shape != (d, d):
+        raise ValueError(f"L0 must be a number or a {d} x {d} matrix")
+    if not np.allclose(m, m.T, rtol=0.0, atol=1e-12 * np.abs(m).max()):
+        raise ValueError("L0 must be symmetric")
+    m = 0.5 * (m + m.T)
+    if np.linalg.eigvalsh(m).min() <= 0.0:
+        raise ValueError("L0 must be positive definite")
+    if np.all(m == m[0, 0] * np.eye(d)):
+        return float(m[0, 0]), True
+    return m, False
+
+
+def reference_scale(l0, d) -> float:
+    """``l0`` of an isotropic reference, ``tr(L0) / d`` otherwise: the factor
+    in front of the residual norm of Sec. 3, Eq. (22)."""
+    L0, iso = reference_matrix(l0, d)
+    return L0 if iso else float(np.trace(L0)) / d
+
+
+def _quad(L0, xs):
+    """``x . L0 . x`` at every grid point for the component arrays ``xs``."""
+    d = len(xs)
+    return sum(L0[a, b] * xs[a] * xs[b] for a in range(d) for b in range(d))
+
+
 def _green_factors(shape, l0, cell=None):
     """Wave vectors and ``1 / (xi . L0 . xi)`` (zero where Gamma0 is 0)."""
     ks = wave_vectors(shape, cell)
     k2 = sum(k * k for k in ks)
     keep = _nyquist_mask(shape) & (k2 > 0)
     inv = np.zeros(shape)
-    inv[keep] = 1.0 / (l0 * k2[keep])
+    L0, iso = reference_matrix(l0, len(shape))
+    q = L0 * k2 if iso else _quad(L0, ks)
+    inv[keep] = 1.0 / q[keep]
     return ks, inv
+
+
+def _energy_dot(l0, d):
+    """Inner product of CG and of the basic scheme's test: Euclidean for an
+    isotropic reference, ``sum_x u . L0 . v`` otherwise."""
+    L0, iso = reference_matrix(l0, d)
+    if iso:
+        return _dot
+    d = L0.shape[0]
+
+    def dot(u, v):
+        gram = u.reshape(d, -1) @ v.reshape(d, -1).T  # sum_x u_a(x) v_b(x)
+        return float(np.sum(L0 * gram))
+    return dot
 
 
 class Medium:
@@ -174,7 +236,12 @@ class Medium:
             raise ValueError("cell needs one length per axis")
 
     def times(self, p, shift=0.0):
-        """``(L - shift I) p`` at every node (p: ``(d, *N)``)."""
+        """``(L - shift) p`` at every node (p: ``(d, *N)``); ``shift`` is a
+        number (``shift I``) or a constant ``d x d`` matrix (``L - L0`` of
+        Sec. 2.1, Eq. (3) for an anisotropic reference)."""
+        if np.ndim(shift) == 2:
+            m = np.asarray(shift, dtype=np.float64)
+            return self.times(p) - np.einsum("ab,b...->a...", m, p)
         if self.tensor:
             out = np.einsum("ab...,b...->a...", self.lam, p)
             return out - shift * p if shift else out
@@ -197,15 +264,17 @@ def green_hat(shape, l0: float) -> np.ndarray:
     """Blocks of the reference Green operator on the DFT grid.
 
     ``G[alpha, beta][k] = k_alpha k_beta / (k . L0 . k)`` for ``k != 0`` and
-    ``0`` at ``k = 0`` (Sec. 2.1, Eq. (7)), with ``L0 = l0 I``.  Returns an
-    array of shape ``(d, d, *shape)``.
+    ``0`` at ``k = 0`` (Sec. 2.1, Eq. (7)), with ``L0 = l0 I`` or a general
+    matrix ``l0``.  Returns an array of shape ``(d, d, *shape)``.
     """
     ks = grid_frequencies(shape)
     d = len(shape)
     k2 = sum(k * k for k in ks)
     keep = _nyquist_mask(shape) & (k2 > 0)
     inv = np.zeros(shape)
-    inv[keep] = 1.0 / (l0 * k2[keep])
+    L0, iso = reference_matrix(l0, d)
+    q = L0 * k2 if iso else _quad(L0, ks)
+    inv[keep] = 1.0 / q[keep]
     g = np.empty((d, d) + tuple(shape))
     for a in range(d):
         for b in range(d):
@@ -218,7 +287,7 @@ def green_hat(shape, l0: float) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def apply_B(p: np.ndarray, lam, l0: float) -> np.ndarray:
-    """``B p = F^{-1} Gamma0_hat F (dL p)`` with ``dL = L - l0 I``.
+    """``B p = F^{-1} Gamma0_hat F (dL p)`` with ``dL = L - L0``.
 
     Sec. 2.2, Eq. (16): polarisation by the blocks ``dL_ab`` (Eq. (3) and
     Eq. (17); diagonal in the nodes, full d x d for tensor phases), forward
@@ -229,7 +298,7 @@ def apply_B(p: np.ndarray, lam, l0: float) -> np.ndarray:
     shape = med.shape
     d = len(shape)
     axes = tuple(range(1, d + 1))
-    tau = med.times(p, l0)
+    tau = med.times(p, reference_matrix(l0, d)[0])
     tau_hat = _fftn(tau, axes)
     ks, inv = _green_factors(shape, l0, med.cell)
     w_hat = np.zeros_like(tau_hat)
@@ -260,7 +329,7 @@ def apply_BT(p: np.ndarray, lam, l0: float) -> np.ndarray:
     for a in range(d):
         for b in range(d):
             w_hat[a] += (ks[a] * ks[b] * inv) * p_hat[b]
-    return med.times(_ifftn(w_hat, axes).real, l0)
+    return med.times(_ifftn(w_hat, axes).real, reference_matrix(l0, d)[0])
 
 
 def apply_AT(p: np.ndarray, lam, l0: float) -> np.ndarray:
@@ -305,7 +374,10 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
 
     ``r0 = b - A x0``, ``p0 = r0``; per iteration ``q = A p``,
     ``alpha = (r, r) / (p, q)``, ``x += alpha p``, ``r -= alpha q``,
-    ``beta = (r_new, r_new) / (r, r)``, ``p = r + beta p``.
+    ``beta = (r_new, r_new) / (r, r)``, ``p = r + beta p``.  The products
+    are Euclidean for ``L0 = l0 I`` and the energy product of ``L0``
+    otherwise (module notes), with the norm of the test and of ``eta_r``
+    taken from the same product.
 
     The test ``||r|| <= tol ||b||`` is made before each iteration, so the
     returned iteration count is the number of operator applies in the loop.
@@ -326,8 +398,10 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     lam = _medium(lam)
     shape = lam.shape
     A = apply if apply is not None else (lambda v: apply_A(v, lam, l0))
+    dot = _energy_dot(l0, lam.d)
+    lsc = reference_scale(l0, lam.d)
     b = _rhs(E, shape)
-    bnorm = math.sqrt(_dot(b, b))
+    bnorm = math.sqrt(dot(b, b))
     if bnorm == 0.0:
         return dict(e=np.zeros_like(b), iterations=0, rel_res=0.0,
                     converged=True, breakdown=False, r=np.zeros_like(b),
@@ -335,14 +409,14 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
     x = b.copy() if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     r = b - A(x)
     p = r.copy()
-    rr = _dot(r, r)
+    rr = dot(r, r)
     hist = [math.sqrt(rr) / bnorm]
     etas = []
 
     def stop_test():
         eta_e_x = eta_e(lam, x) if (norm == "eta_e" or eta_history) else None
         if eta_history:
-            etas.append((l0 * math.sqrt(rr) / bnorm, eta_e_x))
+            etas.append((lsc * math.sqrt(rr) / bnorm, eta_e_x))
         if norm == "eta_e":
             return eta_e_x <= tol
         return math.sqrt(rr) <= tol * bnorm
@@ -359,14 +433,14 @@ def cg(lam, l0, E, tol=1e-8, max_iter=10000, x0=None, n_iter=None,
         if m >= limit:
             break
         q = A(p)
-        pq = _dot(p, q)
+        pq = dot(p, q)
         if not (pq > 0.0) or not math.isfinite(pq):
             breakdown = True
             break
         alpha = rr / pq
         x += alpha * p
         r -= alpha * q
-        rr_new = _dot(r, r)
+        rr_new = dot(r, r)
         beta = rr_new / rr
         p = r + beta * p
         rr = rr_new
@@ -393,6 +467,7 @@ def bicg(lam, l0, E, tol=1e-8, max_iter=10000, n_iter=None):
     ``beta = (r_new, r*_new) / (r, r*)``, ``p = r + beta p``,
     ``p* = r* + beta p*``.  The test ``||r|| <= tol ||b||`` precedes each
     iteration (as in ``cg``); ``n_iter`` forces that many iterations.
+    Products and norms are Euclidean for every reference medium.
     """
     lam = _medium(lam)
     shape = lam.shape
@@ -437,12 +512,16 @@ def bicg(lam, l0, E, tol=1e-8, max_iter=10000, n_iter=None):
     return dict(e=x, iterations=m, rel_res=rel, converged=converged, breakdown=breakdown)
 
 
-def true_residual(lam, l0, E, e) -> float:
-    """``||b - (I + B) e|| / ||b||`` evaluated afresh (Eq. (15))."""
-    b = _rhs(E, _medium(lam).shape)
-    bn = math.sqrt(_dot(b, b))
+def true_residual(lam, l0, E, e, euclidean=False) -> float:
+    """``||b - (I + B) e|| / ||b||`` evaluated afresh (Eq. (15)), in the norm
+    of ``cg`` (the energy norm of an anisotropic ``L0``; Euclidean with
+    ``euclidean=True``, the norm of ``bicg``)."""
+    med = _medium(lam)
+    dot = _dot if euclidean else _energy_dot(l0, med.d)
+    b = _rhs(E, med.shape)
+    bn = math.sqrt(dot(b, b))
     res = b - apply_A(e, lam, l0)
-    return math.sqrt(_dot(res, res)) / bn if bn > 0 else 0.0
+    return math.sqrt(dot(res, res)) / bn if bn > 0 else 0.0
 
 
 # ---------------------------------------------------------------------------
@@ -455,24 +534,27 @@ def ffth(lam, l0, E, tol=1e-8, max_iter=100000, norm="r", eta_history=False):
     Sec. 2.3, Eq. (18), evaluated as ``e^(m+1) = e0 - B e^(m)``.  Stops after
     the apply in which the test on ``e^(m)`` holds and returns ``e^(m+1)``:
     ``||e^(m+1) - e^(m)|| <= tol ||e0||`` (``eta_r / l0`` of Eq. (22)), or with
-    ``norm="eta_e"`` ``eta_e(e^(m)) <= tol`` (Eq. (21)).  ``eta_history``
+    ``norm="eta_e"`` ``eta_e(e^(m)) <= tol`` (Eq. (21)); the step norm is
+    that of ``cg`` (energy norm of an anisotropic ``L0``).  ``eta_history``
     records ``(eta_r, eta_e)`` of ``e^(0) .. e^(m)``, where the residual of
     ``e^(m)`` is the step ``e^(m+1) - e^(m)``.
     """
     if norm not in ("r", "eta_e"):
         raise ValueError("norm must be 'r' or 'eta_e'")
     lam = _medium(lam)
+    dot = _energy_dot(l0, lam.d)
+    lsc = reference_scale(l0, lam.d)
     b = _rhs(E, lam.shape)
-    bnorm = math.sqrt(_dot(b, b))
+    bnorm = math.sqrt(dot(b, b))
     e = b.copy()
     etas = []
     for m in range(1, max_iter + 1):
         e_new = b - apply_B(e, lam, l0)
         diff = e_new - e
-        step = math.sqrt(_dot(diff, diff))
+        step = math.sqrt(dot(diff, diff))
         eta_e_m = eta_e(lam, e) if (norm == "eta_e" or eta_history) else None
         if eta_history:
-            etas.append((l0 * step / bnorm, eta_e_m))
+            etas.append((lsc * step / bnorm, eta_e_m))
         e = e_new
         ok = eta_e_m <= tol if norm == "eta_e" else step <= tol * bnorm
         if ok:
@@ -520,12 +602,14 @@ def dense_operator(lam, l0, cell_measure=1.0):
     F = cell_measure ** -0.5 * np.exp(phase)
     Finv = cell_measure ** 0.5 / nn * np.exp(-phase)
     flat = np.ravel_multi_index(tuple((K % np.array(shape)).T), shape)
-    # node blocks dL_ab (Eq. (17)): diagonal matrices, all d x d of them for tensors
+    # node blocks dL_ab = L_ab - L0_ab (Eqs. (3), (17)): diagonal matrices
+    L0m, iso = reference_matrix(l0, d)
+    L0 = L0m * np.eye(d) if iso else L0m
     if med.tensor:
-        dl = [[med.lam[a, b].ravel()[flat] - (l0 if a == b else 0.0) for b in range(d)] for a in range(d)]
+        dl = [[med.lam[a, b].ravel()[flat] - L0[a, b] for b in range(d)] for a in range(d)]
     else:
-        diag = med.lam.ravel()[flat] - l0
-        dl = [[diag if a == b else np.zeros(nn) for b in range(d)] for a in range(d)]
+        diag = med.lam.ravel()[flat]
+        dl = [[(diag if a == b else np.zeros(nn)) - L0[a, b] for b in range(d)] for a in range(d)]
     # Green operator blocks (Eq. (7)) at xi = k / Y
     Y = np.ones(d) if med.cell is None else np.array(med.cell)
     X = K.astype(np.float64) / Y[None, :]
@@ -534,7 +618,8 @@ def dense_operator(lam, l0, cell_measure=1.0):
     for a, n in enumerate(shape):
         if n % 2 == 0:
             keep &= K[:, a] != n // 2
-    G = [[np.where(keep, X[:, a] * X[:, b] / (l0 * np.where(keep, k2, 1.0)), 0.0) for b in range(d)]
+    xLx = np.einsum("na,ab,nb->n", X, L0, X)
+    G = [[np.where(keep, X[:, a] * X[:, b] / np.where(keep, xLx, 1.0), 0.0) for b in range(d)]
          for a in range(d)]
     B = np.zeros((d * nn, d * nn), dtype=np.complex128)
     for a in range(d):
@@ -595,9 +680,12 @@ def homogenize(lam, l0=None, tol=1e-10, max_iter=10000):
 
 
 def eta_r(r, l0, E, shape) -> float:
-    """Residual norm ``l0 ||r|| / ||e0||`` (Sec. 3, Eq. (22))."""
+    """Residual norm ``l0 ||r|| / ||e0||`` (Sec. 3, Eq. (22)); for an
+    anisotropic ``L0``, ``tr(L0) / d`` times the energy-norm ratio."""
+    d = len(shape)
+    dot = _energy_dot(l0, d)
     b = _rhs(E, shape)
-    return l0 * math.sqrt(_dot(r, r)) / math.sqrt(_dot(b, b))
+    return reference_scale(l0, d) * math.sqrt(dot(r, r)) / math.sqrt(dot(b, b))
 
 
 def eta_e(lam, e) -> float:
@@ -626,6 +714,8 @@ def eta_e_from_residual(lam, l0, E, e) -> float:
     ``k . r_hat = -k . e_hat - k . tau_hat / l0`` (Sec. 2.2, Eqs. (15)-(17)),
     so ``k . j_hat = -l0 k . r_hat``; ``r_hat(k)`` is parallel to ``k`` for
     the gradient fields of Sec. 2.1, hence ``|k . r_hat| = |k| |r_hat|``.
+    For a general ``L0`` the same steps give ``r_hat = -k (k . j_hat) /
+    (k . L0 . k)``, so ``|k . j_hat| = |r_hat| (k . L0 . k) / |k|``.
     Valid for odd grids (no Nyquist modes, where the Green operator is zero).
     """
     med = _medium(lam)
@@ -635,11 +725,18 @@ def eta_e_from_residual(lam, l0, E, e) -> float:
     r_hat = _fftn(r, axes)
     ks = wave_vectors(med.shape, med.cell)
     k2 = sum(ks[a].astype(np.float64) ** 2 for a in range(d))
-    num = float(np.sum(k2 * sum(np.abs(r_hat[a]) ** 2 for a in range(d))))
+    r2 = sum(np.abs(r_hat[a]) ** 2 for a in range(d))
+    L0, iso = reference_matrix(l0, d)
+    if iso:
+        num = float(np.sum(k2 * r2))
+    else:
+        q = _quad(L0, ks)
+        nz = k2 > 0
+        num = float(np.sum(q[nz] ** 2 / k2[nz] * r2[nz]))
     j_hat = _fftn(med.times(e), axes)
     zero = (0,) * d
     den = float(sum(abs(j_hat[a][zero]) ** 2 for a in range(d)))
-    return l0 * math.sqrt(num / den)
+    return (L0 if iso else 1.0) * math.sqrt(num / den)
 
 
 def project_gradient(v: np.ndarray) -> np.ndarray:

@@ -555,3 +555,137 @@ def test_tensor_phase_effective_tensor_symmetric():
     # between the harmonic and arithmetic averages of the tensor field
     arith = L.mean(axis=(2, 3))
     assert np.all(np.linalg.eigvalsh(arith - Leff) > -1e-10)
+
+
+# ---------------------------------------------------------------------------
+# General reference medium (Sec. 2.1, Eqs. (3) and (7) with any SPD L0)
+# ---------------------------------------------------------------------------
+
+def _spd(d, seed, lo=0.5, scale=6.0):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((d, d))
+    return scale * (a @ a.T / d + lo * np.eye(d))
+
+
+def _sqrtm(m):
+    w, v = np.linalg.eigh(m)
+    return (v * np.sqrt(w)) @ v.T
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (4, 6), (3, 5, 3)])
+def test_general_reference_apply_matches_dense_matrix(shape):
+    d = len(shape)
+    L0 = _spd(d, 70)
+    p = np.random.default_rng(71).standard_normal((d,) + shape)
+    for med in (o.Medium(_rand_lam(shape, 72)),
+                o.Medium(_rand_tensor_field(shape, 73) + np.eye(d).reshape((d, d) + (1,) * d)),
+                o.Medium(_rand_lam(shape, 74), cell=tuple(1.0 + 0.6 * a for a in range(d)))):
+        M, flat = o.dense_operator(med, L0)
+        vec = np.concatenate([p[a].ravel()[flat] for a in range(d)])
+        for got, ref in ((o.apply_A(p, med, L0), (M @ vec).real), (o.apply_AT(p, med, L0), (M.T @ vec).real)):
+            got_vec = np.concatenate([got[a].ravel()[flat] for a in range(d)])
+            np.testing.assert_allclose(got_vec, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (6, 4), (3, 4, 3)])
+def test_solution_does_not_depend_on_the_reference(shape):
+    """Eq. (15) holds exactly when the field is admissible and its current is
+    divergence-free in the collocation sense (Gamma0 kills j = L e for k != 0,
+    whatever L0 is), so the discrete solution is the same for every L0."""
+    d = len(shape)
+    med = o.Medium(_rand_tensor_field(shape, 75) + np.eye(d).reshape((d, d) + (1,) * d))
+    E = np.linspace(1.0, -0.5, d)
+    ref, _ = o.dense_solve(med, 9.0, E)
+    for L0 in (_spd(d, 76), _spd(d, 77, scale=40.0)):
+        e, imag = o.dense_solve(med, L0, E)
+        assert imag < 1e-10
+        assert np.linalg.norm(e - ref) / np.linalg.norm(ref) < 1e-11
+        res = o.cg(med, L0, E, tol=1e-13)
+        assert res["converged"] and np.linalg.norm(res["e"] - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_energy_cg_is_euclidean_cg_of_the_symmetrised_system():
+    """u' = L0^(1/2) u turns A into a matrix that is symmetric on the Krylov
+    space; Euclidean CG on it (b' = L0^(1/2) e0) generates L0^(1/2) times the
+    iterates of CG in the energy product of L0, with the same residual norms."""
+    shape = (15, 21)
+    med = o.Medium(_rand_tensor_field(shape, 78) + np.eye(2).reshape(2, 2, 1, 1))
+    L0 = _spd(2, 79, scale=10.0)
+    S = _sqrtm(L0)
+    Si = np.linalg.inv(S)
+    E = np.array([0.7, 0.4])
+
+    def A_sym(v):
+        return np.einsum("ab,b...->a...", S, o.apply_A(np.einsum("ab,b...->a...", Si, v), med, L0))
+
+    for k in (1, 3, 9):
+        a = o.cg(med, L0, E, n_iter=k)
+        b = o.cg(med, 1.0, S @ E, n_iter=k, apply=A_sym)
+        mapped = np.einsum("ab,b...->a...", S, a["e"])
+        assert np.linalg.norm(b["e"] - mapped) / np.linalg.norm(mapped) < 1e-12
+        assert abs(a["rel_res"] - b["rel_res"]) <= 1e-10 * a["rel_res"]
+    # the symmetrised operator is symmetric on admissible zero-mean fields
+    rng = np.random.default_rng(80)
+    u = np.einsum("ab,b...->a...", S, o.project_gradient(rng.standard_normal((2,) + shape)))
+    v = np.einsum("ab,b...->a...", S, o.project_gradient(rng.standard_normal((2,) + shape)))
+    assert abs(np.vdot(u, A_sym(v)) - np.vdot(A_sym(u), v)) < 1e-10 * np.linalg.norm(u) * np.linalg.norm(v) * 50
+
+
+def test_anisotropic_reference_as_preconditioner():
+    """L(x) = s(x) M with a fixed anisotropic M: L0 = l M removes M from the
+    spectrum (the isotropic choice sees the contrast of s times that of M),
+    so CG needs several times fewer iterations for the same field."""
+    phase = ms.grf_two_phase(45, 0.15, 0.4, 5.0, seed=9).phase
+    M = np.array([[1.0, 0.0], [0.0, 60.0]])
+    s = np.where(phase == 1, 5.0, 1.0)
+    L = s[None, None] * M[:, :, None, None]
+    med = o.Medium(L)
+    E = np.array([1.0, 1.0])
+    iso = o.cg(med, o.optimal_reference(med), E, tol=1e-10)
+    ani = o.cg(med, 3.0 * M, E, tol=1e-10)
+    assert ani["converged"] and iso["converged"]
+    assert 4 * ani["iterations"] < iso["iterations"]
+    assert np.linalg.norm(ani["e"] - iso["e"]) / np.linalg.norm(iso["e"]) < 1e-8
+    # laminate closed form holds with the anisotropic reference too
+    layers = np.random.default_rng(81).integers(0, 2, 27)
+    tens = np.array([[[4.0, 1.0], [1.0, 2.0]], [[9.0, 2.5], [2.5, 6.0]]])
+    Ll = np.zeros((2, 2, 27, 27))
+    for i in range(27):
+        Ll[:, :, i, :] = tens[layers[i]][:, :, None]
+    L00, L01, L11 = Ll[0, 0, :, 0], Ll[0, 1, :, 0], Ll[1, 1, :, 0]
+    H = 1.0 / np.mean(1.0 / L00)
+    ref = np.array([[H, np.mean(L01 / L00) * H],
+                    [np.mean(L01 / L00) * H, np.mean(L11 - L01 ** 2 / L00) + np.mean(L01 / L00) ** 2 * H]])
+    Leff, _ = o.homogenize(o.Medium(Ll), l0=tens.mean(axis=0), tol=1e-13)
+    np.testing.assert_allclose(Leff, ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(15, 21), (9, 7, 5)])
+def test_eta_e_residual_identity_general_reference(shape):
+    d = len(shape)
+    med = o.Medium(_rand_tensor_field(shape, 82) + np.eye(d).reshape((d, d) + (1,) * d))
+    L0 = _spd(d, 83, scale=8.0)
+    E = np.linspace(1.0, 0.2, d)
+    for k in (2, 6):
+        e = o.cg(med, L0, E, n_iter=k)["e"]
+        assert abs(o.eta_e_from_residual(med, L0, E, e) - o.eta_e(med, e)) <= 1e-10 * o.eta_e(med, e)
+
+
+def test_ffth_and_bicg_with_general_reference():
+    shape = (15, 13)
+    phase = ms.grf_two_phase(15, 0.2, 0.4, 4.0, seed=4).phase[:, :13]
+    M = np.array([[2.0, 0.5], [0.5, 1.0]])
+    s = np.where(phase == 1, 4.0, 1.0)
+    med = o.Medium(s[None, None] * M[:, :, None, None])
+    E = np.array([1.0, -0.3])
+    ref, _ = o.dense_solve(med, 2.5 * M, E)
+    f = o.ffth(med, 2.5 * M, E, tol=1e-12)
+    b = o.bicg(med, 2.5 * M, E, tol=1e-12)
+    assert f["converged"] and b["converged"]
+    for e in (f["e"], b["e"]):
+        assert np.linalg.norm(e - ref) / np.linalg.norm(ref) < 1e-9
+    # L0 = 2.5 M makes the basic scheme contract like the isotropic scheme
+    # at contrast 4 with l0 = 2.5: rate (4 - 1) / (4 + 1)
+    iso = o.ffth(o.Medium(s), 2.5, E, tol=1e-12)
+    assert abs(f["iterations"] - iso["iterations"]) <= 2
+    assert o.true_residual(med, 2.5 * M, E, b["e"], euclidean=True) < 1e-11
