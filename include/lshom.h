@@ -160,6 +160,25 @@ lshom_status lshom_set_cell(lshom_ctx* ctx, const double* lengths);
 /* Reference medium L0 = l0 I (Sec. 2.1, Eq. (3); Sec. 3, Eq. (20)); finite, > 0. */
 lshom_status lshom_set_reference(lshom_ctx* ctx, double l0);
 
+/*
+ * A general reference medium (Sec. 2.1, Eqs. (3) and (7): dL = L - L0 and the
+ * Green operator xi (x) xi / (xi . L0 . xi)).  L0_host holds a symmetric
+ * positive-definite d x d matrix, row-major, copied; INVALID_ARG otherwise.
+ * A multiple of the identity acts as lshom_set_reference.  Otherwise:
+ *  - scalar phases are turned into the tensors lambda I (the context then
+ *    holds a tensor problem, as after lshom_set_microstructure_tensor; an
+ *    attached workspace stays attached and is refilled);
+ *  - CG and the basic scheme work in the energy product of L0,
+ *    <u, v> = sum_x u . L0 . v, in which the system is self-adjoint: the
+ *    residual test and rel_res, rel_res_true use ||r||_L0 / ||E||_L0, and
+ *    eta_r uses tr(L0) / d in place of l0.  BiCG keeps Euclidean products.
+ *  - eta_e (Eq. (21)) does not depend on L0.
+ * Single solves only (lshom_solve, lshom_homogenize, lshom_apply); the
+ * converged field does not depend on L0, the iteration count does.
+ * lshom_set_reference returns to an isotropic reference.
+ */
+lshom_status lshom_set_reference_tensor(lshom_ctx* ctx, const double* L0_host);
+
 /* Bytes of device workspace the current problem needs (both precisions). */
 lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* bytes);
 

@@ -94,7 +94,10 @@ struct Group {
   double cell_inv[3] = {1.0, 1.0, 1.0};  // 1 / cell side lengths (wave vector xi = k / Y)
   // single problem (nprob == 1, batched == false)
   const uint8_t* phase = nullptr;
-  double l0 = 0.0;
+  double l0 = 0.0;              // l0, or tr(L0) / d for an anisotropic reference
+  bool aniso = false;           // anisotropic reference L0 (needs tensor)
+  double L0u[6] = {0, 0, 0, 0, 0, 0};  // L0, upper triangle row by row
+  double L0n[6] = {0, 0, 0, 0, 0, 0};  // L0 / l0
   // batch
   int nprob = 1;
   bool batched = false;         // per-problem data come from the device table

@@ -291,6 +291,8 @@ ColArgs<T> col0_args(Group& g, const Bufs<T>& b) {
   a.inv_n = 1.0 / (double)g.nvox;
   a.gate = GATE_ACTIVE;
   a.l0 = g.l0;
+  a.aniso = g.aniso ? 1 : 0;
+  for (int i = 0; i < 6; ++i) a.L0n[i] = g.L0n[i];
   a.bt = batch_of(g);
   return a;
 }
@@ -362,6 +364,8 @@ RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
   a.cond = b.cond;
   a.n_phases = g.n_phases;
   a.tensor = g.tensor ? 1 : 0;
+  a.aniso = g.aniso ? 1 : 0;
+  for (int i = 0; i < 6; ++i) a.L0u[i] = (T)g.L0u[i];
   a.l0 = (T)g.l0;
   a.inv_n = (T)(1.0 / (double)g.nvox);
   a.plan = b.plan[last];
@@ -418,6 +422,8 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   for (int t = 0; t < 3; ++t) u.nd[t] = (int)g.N[t];
   u.fd_n1 = make_fastdiv((uint32_t)g.N[1]);
   for (int t = 0; t < kMaxDim; ++t) u.cinv[t] = g.cell_inv[t];
+  u.aniso = g.aniso ? 1 : 0;
+  for (int i = 0; i < 6; ++i) u.L0n[i] = g.L0n[i];
   return u;
 }
 
@@ -552,8 +558,9 @@ hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>*
   return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS, eq);
 }
 
-// Real FP64 field v (d x |N|) -> spectral coordinate of P v (of P dL v / l0).
-hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bool with_dl,
+// Real FP64 field v (d x |N|) -> spectral coordinate of P v (green: of
+// Gamma0 v, with dL: of Gamma0 dL v).
+hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bool with_dl, bool green,
                             cx<double>* out, int gate = GATE_ALWAYS) {
   hipError_t e;
   RowArgs<double> r = row_args(g, b);
@@ -562,19 +569,19 @@ hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bo
   for (int t = 0; t < g.d; ++t) r.real_in[t] = v + (size_t)t * g.nvox;
   r.gate = gate;
   if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
-  return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, with_dl ? 1 : 0, 0, PART_AUX, gate);
+  return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, green ? 1 : 0, 0, PART_AUX, gate);
 }
 
 // Real field out = add + E + u(x); with leff, <lambda out> into state.leff.
-// dl_scale: out = add + (lambda - l0) / l0 (E + u(x)).
+// dl_out: out = add + (L - L0) (E + u(x)).
 hipError_t enq_field_out(Group& g, const Bufs<double>& b, const cx<double>* x, const double* E,
-                         const double* add, double* out, bool leff, bool dl_scale = false,
+                         const double* add, double* out, bool leff, bool dl_out = false,
                          int gate = GATE_ALWAYS) {
   hipError_t e;
   if ((e = enq_inverse_from_c<double>(g, b, x, nullptr, nullptr, gate)) != hipSuccess) return e;
   RowArgs<double> r = row_args(g, b);
   r.mode = ROW_INV;
-  r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0) | (dl_scale ? ROWF_DL_SCALE : 0);
+  r.flags = (add ? ROWF_ADD : 0) | (leff ? ROWF_LEFF : 0) | (dl_out ? ROWF_DL_OUT : 0);
   if (!E) r.flags |= ROWF_STATE_E;
   for (int t = 0; t < g.d; ++t) {
     r.E[t] = E ? E[t] : 0.0;
@@ -591,15 +598,15 @@ const double kNoE[3] = {0.0, 0.0, 0.0};
 
 // q = (I + B) v = v + Gamma0 dL v on real nodal fields (Sec. 2.2, Eq. (16)).
 hipError_t enq_apply_A_real(Group& g, const Bufs<double>& b, const double* v, double* q, int gate) {
-  hipError_t e = enq_project_real(g, b, v, true, b.v[3], gate);
+  hipError_t e = enq_project_real(g, b, v, true, true, b.v[3], gate);
   if (e != hipSuccess) return e;
   return enq_field_out(g, b, b.v[3], kNoE, v, q, false, false, gate);
 }
 
-// q = (I + B)^T v = v + dL Gamma0 v = v + (dL / l0) P v: the same passes in
-// the other order (projection first, polarisation at the nodes last).
+// q = (I + B)^T v = v + dL Gamma0 v: the same passes in the other order
+// (Green operator first, polarisation at the nodes last).
 hipError_t enq_apply_AT_real(Group& g, const Bufs<double>& b, const double* v, double* q, int gate) {
-  hipError_t e = enq_project_real(g, b, v, false, b.v[3], gate);
+  hipError_t e = enq_project_real(g, b, v, false, true, b.v[3], gate);
   if (e != hipSuccess) return e;
   return enq_field_out(g, b, b.v[3], kNoE, v, q, false, true, gate);
 }
@@ -888,7 +895,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     // residual of E for the admissibility test, then of E + P x0
     HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, PART_AUX)));
     HIP_TRY(c, enq_finalize(g, FZ_AUX, ncol, GATE_ALWAYS));
-    HIP_TRY(c, enq_project_real(g, b64, x0, false, x64));
+    HIP_TRY(c, enq_project_real(g, b64, x0, false, false, x64));
     HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS, eq_loop)));
     HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS, eq_loop));
     HIP_TRY(c, sync_states(g));
@@ -976,7 +983,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
 lshom_status apply_real(Group& g, const double* p, double* q) {
   lshom_ctx* c = g.ctx;
   Bufs<double> b = get_bufs<double>(g);
-  HIP_TRY(c, enq_project_real(g, b, p, true, b.v[3]));
+  HIP_TRY(c, enq_project_real(g, b, p, true, true, b.v[3]));
   HIP_TRY(c, enq_field_out(g, b, b.v[3], kNoE, p, q, false));
   HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
   return LSHOM_OK;
@@ -1009,6 +1016,7 @@ lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& 
   v.atp = atp;
   v.phase = g.phase;
   v.cond = b.cond;
+  v.tensor = g.tensor ? 1 : 0;
   v.st = dev_state(g);
   v.parts = dev_parts(g);
   v.fd_n = make_fastdiv((uint32_t)g.nvox);

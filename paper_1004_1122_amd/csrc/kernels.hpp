@@ -34,7 +34,9 @@ struct DevState {
   double drop2;         // mixed: refresh when rr < drop2 * rr_ref
   double leff[3];       // <lambda e>
   double E[3];          // macroscopic field of the solve (set with the initial state)
-  double l0;            // reference conductivity (the norms of Sec. 3, Eqs. (21)-(22))
+  double l0;            // reference conductivity (the norms of Sec. 3, Eqs. (21)-(22));
+                        // tr(L0) / d for an anisotropic reference
+  double l0E[3];        // L0 E: the current of the reference medium under E
   double nvox;          // |N|
   double tol2;          // tol^2 (equilibrium test)
   double jx[3];         // DFT at k = 0 of dL (E + u(x)) for the iterate being tested
@@ -139,7 +141,7 @@ enum RowFlags : int {
   ROWF_ADD = 4,       // ROW_INV: add real_add to the output
   ROWF_LEFF = 8,      // ROW_INV: partial sums of <lambda out> into AUX
   ROWF_STATE_E = 16,  // E of each problem from its device state (not the argument)
-  ROWF_DL_SCALE = 32, // ROW_INV: multiply E + u by (lambda - l0) / l0 before adding real_add
+  ROWF_DL_OUT = 32,   // ROW_INV: multiply E + u by dL = L - L0 before adding real_add
 };
 
 template <typename T>
@@ -163,6 +165,8 @@ struct RowArgs {
   const T* cond;                 // conductivity table (n_phases entries)
   int n_phases;                  // table entries (phases x entries per phase)
   int tensor;                    // symmetric tensor phases: d (d + 1) / 2 entries each (needs !split)
+  int aniso;                     // anisotropic reference (needs tensor): dL = L - L0 with L0 below
+  T L0u[6];                      // L0, upper triangle row by row (2-D: 00 01 11)
   T l0;
   T E[kMaxDim];
   T inv_n;                       // 1 / |N|
@@ -205,6 +209,10 @@ struct ColArgs {
   int dims;
   int h;                 // half length of the last axis
   double cinv[kMaxDim];  // 1 / cell side length per axis: wave vector xi = k / Y
+  // anisotropic reference: upper triangle of L0 / (tr(L0) / d); the spectral
+  // coordinate then carries the factor 1 / sqrt(khat . L0n . khat)
+  int aniso;
+  double L0n[6];
   // COL_INV_C
   const cx<T>* c_in;     // used when cg_step == 0
   cx<T>* p_io;           // cg_step: p = r + beta p (written back)
@@ -258,6 +266,8 @@ struct UpdArgs {
   int nd[kMaxDim];
   FastDiv fd_n1;         // nd[1] (3-D index split)
   double cinv[kMaxDim];  // 1 / cell side length per axis
+  int aniso;             // equilibrium weight xi . L0n . xi in place of |xi|^2
+  double L0n[6];
 };
 
 // BiCG on real d-component nodal fields ([d][n] FP64, components contiguous):
@@ -285,6 +295,7 @@ struct BicgArgs {
   const double* atp;
   const uint8_t* phase;  // BV_LEFF
   const double* cond;
+  int tensor;            // cond holds symmetric tensors (upper triangles)
   DevState* st;
   Partials parts;
   int gate;

@@ -36,14 +36,42 @@ lshom_status check_ready(lshom_ctx* c, int precision) {
   return LSHOM_OK;
 }
 
-// Initial device scalars of one problem.
+// x . M . y for the upper triangle M of a symmetric d x d matrix (row by row).
+double sym_form(const double* m, int d, const double* x, const double* y) {
+  double full[9];
+  int k = 0;
+  for (int i = 0; i < d; ++i)
+    for (int j = i; j < d; ++j) full[i * d + j] = full[j * d + i] = m[k++];
+  double s = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) s += x[i] * full[i * d + j] * y[j];
+  return s;
+}
+
+// Initial device scalars of one problem.  With an anisotropic reference
+// (L0n = L0 / l0, upper triangle; not for BiCG, which iterates on the nodal
+// fields in the Euclidean product) the norms are those of the scaled
+// spectral coordinate: ||b||^2 = |N| E . L0n . E.
 DevState initial_state(int d, long long nvox, const double* E, double tol, double l0, const lshom_solve_opts& o,
-                       bool with_history) {
+                       bool with_history, const double* L0n = nullptr) {
   DevState s{};
   double e2 = 0.0;
   for (int t = 0; t < d; ++t) e2 += E[t] * E[t];
+  const bool aniso = L0n && o.method != LSHOM_METHOD_BICG;
+  if (aniso) e2 = sym_form(L0n, d, E, E);
   s.b2 = e2 * (double)nvox;
   for (int t = 0; t < 3; ++t) s.E[t] = t < d ? E[t] : 0.0;
+  for (int t = 0; t < 3; ++t) {
+    double v = 0.0;
+    if (t < d && L0n) {
+      double et[3] = {0.0, 0.0, 0.0};
+      et[t] = 1.0;
+      v = l0 * sym_form(L0n, d, et, E);
+    } else if (t < d) {
+      v = l0 * E[t];
+    }
+    s.l0E[t] = v;
+  }
   s.tol2b2 = tol * tol * s.b2;
   s.tol2 = tol * tol;
   s.l0 = l0;
@@ -355,6 +383,72 @@ lshom_status lshom_set_reference(lshom_ctx* c, double l0) {
   drop_graphs(c->graphs);
   drop_batch_graphs(c);  // l0 is baked into captured launches
   c->g.l0 = l0;
+  c->g.aniso = false;
+  return LSHOM_OK;
+}
+
+lshom_status lshom_set_reference_tensor(lshom_ctx* c, const double* L0) {
+  if (!c || !L0) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
+  Group& gr = c->g;
+  const int d = gr.d;
+  double scale = 0.0;
+  for (int i = 0; i < d * d; ++i) {
+    if (!std::isfinite(L0[i])) return fail(c, LSHOM_ERR_INVALID_ARG, "L0 entries must be finite");
+    scale = std::max(scale, std::fabs(L0[i]));
+  }
+  for (int i = 0; i < d; ++i)
+    for (int j = i + 1; j < d; ++j)
+      if (std::fabs(L0[i * d + j] - L0[j * d + i]) > 1e-12 * scale)
+        return fail(c, LSHOM_ERR_INVALID_ARG, "L0 must be symmetric");
+  double a[9], w[3];
+  for (int i = 0; i < d * d; ++i) a[i] = L0[i];
+  sym_eigenvalues(a, d, w);
+  for (int i = 0; i < d; ++i)
+    if (!(w[i] > 0.0)) return fail(c, LSHOM_ERR_INVALID_ARG, "L0 must be positive definite");
+  bool iso = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j)
+      if (L0[i * d + j] != (i == j ? L0[0] : 0.0)) iso = false;
+  if (iso) return lshom_set_reference(c, L0[0]);
+  DeviceGuard g(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  drop_graphs(c->graphs);
+  drop_batch_graphs(c);
+  if (!gr.tensor) {
+    // dL = L - L0 couples the components of a node: scalar phases become
+    // the tensors lambda I (the row pass then keeps every component of a
+    // node in one block)
+    const int nph = gr.n_phase_ids;
+    if (nph * d * (d + 1) / 2 > kMaxPhases)
+      return fail(c, LSHOM_ERR_UNSUPPORTED, "too many phases for tensor tables (at most 256 / (d (d + 1) / 2))");
+    std::vector<double> table;
+    for (int q = 0; q < nph; ++q)
+      for (int i = 0; i < d; ++i)
+        for (int j = i; j < d; ++j) table.push_back(i == j ? c->cond[q] : 0.0);
+    int64_t N[3] = {gr.N[0], gr.N[1], gr.N[2]};
+    if (group_setup(gr, d, N, nph, true) != LSHOM_OK)
+      return fail(c, LSHOM_ERR_UNSUPPORTED, "grid too long for one LDS-resident FFT batch with tensor phases");
+    c->cond = table;
+    if (c->ws_ready) {
+      c->ws_ready = false;
+      lshom_status s = prepare_workspace(gr, c->cond, nullptr, {gr.phase});
+      if (s != LSHOM_OK) return s;
+      c->ws_ready = true;
+    }
+  }
+  double tr = 0.0;
+  for (int i = 0; i < d; ++i) tr += L0[i * d + i];
+  gr.l0 = tr / d;
+  int k = 0;
+  for (int i = 0; i < d; ++i)
+    for (int j = i; j < d; ++j, ++k) {
+      gr.L0u[k] = 0.5 * (L0[i * d + j] + L0[j * d + i]);
+      gr.L0n[k] = gr.L0u[k] / gr.l0;
+    }
+  for (; k < 6; ++k) gr.L0u[k] = gr.L0n[k] = 0.0;
+  gr.aniso = true;
+  c->err.clear();
   return LSHOM_OK;
 }
 
@@ -449,7 +543,8 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
     }
     return LSHOM_OK;
   }
-  std::vector<DevState> init(1, initial_state(gr.d, gr.nvox, E_host, tol, gr.l0, o, true));
+  std::vector<DevState> init(
+      1, initial_state(gr.d, gr.nvox, E_host, tol, gr.l0, o, true, gr.aniso ? gr.L0n : nullptr));
   if (o.method == LSHOM_METHOD_BICG)
     s = solve_bicg(gr, init[0], o, e_dev);
   else

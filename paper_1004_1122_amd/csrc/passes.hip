@@ -19,6 +19,14 @@
 //                               khat, q = p + s / l0 and the dot (p, q).
 // Twiddles (and, in the row pass, phase bytes and conductivities) are staged
 // in LDS at block start.
+//
+// A general reference medium L0 (Sec. 2.1, Eqs. (3) and (7): Green operator
+// k (x) k / (k . L0 . k)) keeps this structure with the coordinate scaled:
+// u_hat = i khat s(k) c with s = 1 / sqrt(khat . L0n . khat), L0n = L0 / lbar,
+// lbar = tr(L0) / d, and the forward projection s (-i khat) . tau_hat / lbar.
+// The operator on c is then symmetric in the Euclidean product (it equals
+// the operator on fields in the energy product of L0), so CG runs unchanged;
+// for L0 = l0 I, s = 1 and lbar = l0.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -75,22 +83,52 @@ __device__ __forceinline__ double half_weight(long long k_last, int n_last) {
   return 2.0;
 }
 
-// (L_q - shift I) v at one node for a symmetric tensor phase q whose entries
-// are stored as its upper triangle row by row (2-D: 00 01 11; 3-D: 00 01 02
-// 11 12 22): the polarisation of Sec. 2.1, Eq. (3) with tensor phases.
+// (L_q - S) v at one node for a symmetric tensor phase q whose entries are
+// stored as its upper triangle row by row (2-D: 00 01 11; 3-D: 00 01 02 11
+// 12 22), S symmetric in the same layout: the polarisation of Sec. 2.1,
+// Eq. (3) with tensor phases (S = L0) or the current L v (S = 0).
 template <typename T>
-__device__ __forceinline__ void tensor_times(const T* tab, int q, int d, T shift, const T* v, T* out) {
+__device__ __forceinline__ void tensor_times(const T* tab, int q, int d, const T* S, const T* v, T* out) {
   if (d == 2) {
     const T* m = tab + q * 3;
-    out[0] = (m[0] - shift) * v[0] + m[1] * v[1];
-    out[1] = m[1] * v[0] + (m[2] - shift) * v[1];
+    const T m0 = m[0] - S[0], m1 = m[1] - S[1], m2 = m[2] - S[2];
+    out[0] = m0 * v[0] + m1 * v[1];
+    out[1] = m1 * v[0] + m2 * v[1];
     out[2] = T(0);
   } else {
     const T* m = tab + q * 6;
-    out[0] = (m[0] - shift) * v[0] + m[1] * v[1] + m[2] * v[2];
-    out[1] = m[1] * v[0] + (m[3] - shift) * v[1] + m[4] * v[2];
-    out[2] = m[2] * v[0] + m[4] * v[1] + (m[5] - shift) * v[2];
+    const T m0 = m[0] - S[0], m1 = m[1] - S[1], m2 = m[2] - S[2];
+    const T m3 = m[3] - S[3], m4 = m[4] - S[4], m5 = m[5] - S[5];
+    out[0] = m0 * v[0] + m1 * v[1] + m2 * v[2];
+    out[1] = m1 * v[0] + m3 * v[1] + m4 * v[2];
+    out[2] = m2 * v[0] + m4 * v[1] + m5 * v[2];
   }
+}
+
+// The shift of tensor_times for dL = L - L0: L0 of an anisotropic reference,
+// else l0 on the diagonal.
+template <typename T>
+__device__ __forceinline__ void reference_shift(const RowArgs<T>& a, T l0, T* S) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) S[i] = a.aniso ? a.L0u[i] : T(0);
+  if (!a.aniso) {
+    if (a.d == 2) {
+      S[0] = l0;
+      S[2] = l0;
+    } else {
+      S[0] = l0;
+      S[3] = l0;
+      S[5] = l0;
+    }
+  }
+}
+
+// x . M . x for the upper triangle M (layout of tensor_times) and a vector
+// with dims components.
+__device__ __forceinline__ double sym_quad(const double* m, int dims, const double* x) {
+  if (dims == 2) return m[0] * x[0] * x[0] + 2.0 * m[1] * x[0] * x[1] + m[2] * x[1] * x[1];
+  return m[0] * x[0] * x[0] + m[3] * x[1] * x[1] + m[5] * x[2] * x[2] +
+         2.0 * (m[1] * x[0] * x[1] + m[2] * x[0] * x[2] + m[4] * x[1] * x[2]);
 }
 
 // Loads in flight per thread in the staging and data loops: with few blocks
@@ -160,6 +198,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   parts.base += (long long)pb * a.bt.pstride;
   const uint8_t* phase = pe ? pe->phase : a.phase;
   const T l0 = pe ? (T)pe->l0 : a.l0;
+  T shift[6], zero6[6];
+  reference_shift(a, l0, shift);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) zero6[i] = T(0);
   T Ev[kMaxDim];
 #pragma unroll
   for (int c = 0; c < kMaxDim; ++c) Ev[c] = (a.flags & ROWF_STATE_E) ? (T)st->E[c] : a.E[c];
@@ -214,7 +256,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
             if (c < d && rl < rows_here)
               v[c] = (a.flags & ROWF_CONST_E) ? pick3(Ev, c) : (T)pick3(a.real_in, c)[(row0 + rl) * n + x];
           }
-          if (rl < rows_here) tensor_times(cond, ph[rl * n + x], d, l0, v, t[u]);
+          if (rl < rows_here) tensor_times(cond, ph[rl * n + x], d, shift, v, t[u]);
         }
 #pragma unroll
         for (int c = 0; c < kMaxDim; ++c)
@@ -316,7 +358,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
     if constexpr (MODE == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
-      if (a.tensor && (a.flags & (ROWF_LEFF | ROWF_DL_SCALE))) {
+      if (a.tensor && (a.flags & (ROWF_LEFF | ROWF_DL_OUT))) {
         for (int idx = tid; idx < half_rows * n; idx += NT) {
           const int j = (int)fdiv((uint32_t)idx, a.fd_n);
           const int x = idx - j * n;
@@ -333,10 +375,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 #pragma unroll
             for (int c = 0; c < kMaxDim; ++c)
               v[c] = c < d ? (T)((double)pick3(Ev, c) + (double)((u == 0 ? z[c].re : z[c].im) * a.inv_n)) : T(0);
-            if (a.flags & ROWF_DL_SCALE) {
-              tensor_times(cond, q, d, l0, v, w);
+            if (a.flags & ROWF_DL_OUT) {
+              tensor_times(cond, q, d, shift, v, w);
 #pragma unroll
-              for (int c = 0; c < kMaxDim; ++c) v[c] = w[c] / l0;
+              for (int c = 0; c < kMaxDim; ++c) v[c] = w[c];
             }
 #pragma unroll
             for (int c = 0; c < kMaxDim; ++c) {
@@ -348,7 +390,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
               if (out) out[g] = val;
             }
             if (a.flags & ROWF_LEFF) {
-              tensor_times(cond, q, d, T(0), v, w);
+              tensor_times(cond, q, d, zero6, v, w);
 #pragma unroll
               for (int c = 0; c < kMaxDim; ++c) acc[c] += (double)w[c];
             }
@@ -367,7 +409,7 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           if (rl >= rows_here) continue;
           const long long g = (row0 + rl) * n + x;
           double val = (double)pick3(Ev, c) + (double)((u == 0 ? z.re : z.im) * a.inv_n);
-          if (a.flags & ROWF_DL_SCALE) val *= ((double)cond[ph[rl * n + x]] - (double)l0) / (double)l0;
+          if (a.flags & ROWF_DL_OUT) val *= (double)cond[ph[rl * n + x]] - (double)l0;
           if (a.flags & ROWF_ADD) val += pick3(a.real_add, c)[g];
           double* out = pe ? (pe->e_out ? pe->e_out + c * nvox : nullptr) : pick3(a.real_out, c);
           if (out) out[g] = val;
@@ -401,8 +443,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
           t0[c] = T(0);
           t1[c] = T(0);
         }
-        if (2 * j < rows_here) tensor_times(cond, phs[2 * j * n + x], d, l0, u0, t0);
-        if (2 * j + 1 < rows_here) tensor_times(cond, phs[(2 * j + 1) * n + x], d, l0, u1, t1);
+        if (2 * j < rows_here) tensor_times(cond, phs[2 * j * n + x], d, shift, u0, t0);
+        if (2 * j + 1 < rows_here) tensor_times(cond, phs[(2 * j + 1) * n + x], d, shift, u1, t1);
 #pragma unroll
         for (int c = 0; c < kMaxDim; ++c)
           if (c < d) Z[(c * half_rows + j) * ss + x] = cx<T>{t0[c], t1[c]};
@@ -534,10 +576,11 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
           }
           double kh[kMaxDim];
           const bool nz = khat_axis0(a, l, i0 + c, kh);
+          const double sk = (a.aniso && nz) ? 1.0 / sqrt(sym_quad(a.L0n, a.dims, kh)) : 1.0;
 #pragma unroll
           for (int al = 0; al < kMaxDim; ++al) {
             if (al >= d) break;
-            const T k = nz ? (T)kh[al] : T(0);
+            const T k = nz ? (T)(kh[al] * sk) : T(0);
             Z[(al * C + c) * ss + l] = cx<T>{-k * cv.im, k * cv.re};  // i khat_a c
           }
         } else {
@@ -640,6 +683,15 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       double kh[kMaxDim];
       double k2 = 0.0;
       const bool nz = khat_axis0(a, l, i0 + c, kh, &k2);
+      double sk = 1.0;
+      if (a.aniso && nz) {
+        // the Green operator takes 1 / sqrt(q) like the inverse pass; the
+        // plain projection of a field takes the inverse scale sqrt(q); the
+        // equilibrium weight |xi|^2 becomes xi . L0n . xi
+        const double q = sym_quad(a.L0n, a.dims, kh);
+        sk = a.s_inv_l0 ? 1.0 / sqrt(q) : sqrt(q);
+        k2 *= q;
+      }
       if (a.eq && l == 0 && i0 + c == 0) {
         // k = 0: the cell sum of the transformed field (dL (E + u) or dL u)
         double* dst = a.dot == 1 ? st->taup : st->jx;
@@ -652,7 +704,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
         for (int al = 0; al < kMaxDim; ++al) {
           if (al >= d) break;
           const cx<T> v = Z[(al * C + c) * ss + l];
-          const T k = (T)kh[al];
+          const T k = (T)(kh[al] * sk);
           t.re += k * v.re;
           t.im += k * v.im;
         }
@@ -695,8 +747,9 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   }
 }
 
-// |k|^2 (integer frequencies) of half-spectrum entry i: 2-D arrays are
-// stored [k1][k0] (kq = i / N0 is k1), 3-D arrays [k0][k1][k2] (kq = i).
+// |xi|^2 (xi = k / Y) of half-spectrum entry i, or xi . L0n . xi for an
+// anisotropic reference: 2-D arrays are stored [k1][k0] (kq = i / N0 is k1),
+// 3-D arrays [k0][k1][k2] (kq = i).
 template <typename T>
 __device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, uint32_t kq, uint32_t k_last) {
   int k0, k1;
@@ -714,6 +767,10 @@ __device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, u
   const double x0 = (double)k0 * a.cinv[0];
   const double x1 = a.dims == 2 ? 0.0 : (double)k1 * a.cinv[1];
   const double xl = (double)k_last * a.cinv[last];
+  if (a.aniso) {
+    const double xs[kMaxDim] = {x0, a.dims == 2 ? xl : x1, xl};
+    return sym_quad(a.L0n, a.dims, xs);
+  }
   return x0 * x0 + x1 * x1 + xl * xl;
 }
 
@@ -861,11 +918,23 @@ __global__ __launch_bounds__(256) void bicg_kernel(BicgArgs a) {
   const long long i0 = (long long)blockIdx.x * NT + threadIdx.x;
   if (a.mode == BV_LEFF) {
     double acc[kMaxDim] = {0.0, 0.0, 0.0};
-    for (int c = 0; c < a.d; ++c) {
-      const double* xc = a.x + (long long)c * a.n;
-      double s = 0.0;
-      for (long long j = i0; j < a.n; j += stride) s += a.cond[a.phase[j]] * xc[j];
-      acc[c] = s;
+    if (a.tensor) {
+      const double zero6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (long long j = i0; j < a.n; j += stride) {
+        double v[kMaxDim], w[kMaxDim];
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c) v[c] = c < a.d ? a.x[(long long)c * a.n + j] : 0.0;
+        tensor_times(a.cond, a.phase[j], a.d, zero6, v, w);
+#pragma unroll
+        for (int c = 0; c < kMaxDim; ++c) acc[c] += w[c];
+      }
+    } else {
+      for (int c = 0; c < a.d; ++c) {
+        const double* xc = a.x + (long long)c * a.n;
+        double s = 0.0;
+        for (long long j = i0; j < a.n; j += stride) s += a.cond[a.phase[j]] * xc[j];
+        acc[c] = s;
+      }
     }
     double* dst = a.parts.region(PART_AUX) + (long long)blockIdx.x * 3;
     for (int c = 0; c < 3; ++c) store_partial<NT>(acc[c], dst + c);

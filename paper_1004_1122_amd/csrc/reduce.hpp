@@ -136,14 +136,17 @@ __device__ __forceinline__ bool block_sums_gated(double (&v)[NS], int skip0) {
 // |k|^2-weighted spectral residual sum eq: for an admissible field the
 // divergence of the current in Fourier space is k . j_hat = -l0 k . r_hat and
 // r_hat is parallel to k, so eta_e = l0 sqrt(eq) / |j_hat(0)| with
-// j_hat(0) = jx + l0 |N| E.  The lead thread records eta_e and, for m >= 0,
-// history entry m.  Returns whether eta_e <= tol.
+// j_hat(0) = jx + |N| L0 E.  (An anisotropic L0 has |k . j_hat| =
+// |r_hat| (k . L0 . k) / |k|; with the scaled coordinate and the weight
+// k . L0n . k in eq the same formula holds with l0 = tr(L0) / d.)  The lead
+// thread records eta_e and, for m >= 0, history entry m.  Returns whether
+// eta_e <= tol.
 __device__ inline bool equilibrium_test(DevState* st, int m, double rr, double eq, bool lead) {
   const double l0 = st->l0;
   double j2 = 0.0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double jc = st->jx[c] + l0 * st->nvox * st->E[c];
+    const double jc = st->jx[c] + st->nvox * st->l0E[c];
     j2 += jc * jc;
   }
   const double eta_e = l0 * sqrt(eq / j2);

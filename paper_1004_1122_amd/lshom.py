@@ -172,6 +172,7 @@ def load(path: str = LIB_PATH):
         "lshom_set_microstructure": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
         "lshom_set_microstructure_tensor": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
         "lshom_set_reference": (c_int32, [P, c_double]),
+        "lshom_set_reference_tensor": (c_int32, [P, POINTER(c_double)]),
         "lshom_set_cell": (c_int32, [P, POINTER(c_double)]),
         "lshom_workspace_size": (c_int32, [P, c_int, POINTER(c_size_t)]),
         "lshom_workspace_size_for": (c_int32, [P, POINTER(lshom_solve_opts), POINTER(c_size_t)]),
@@ -359,8 +360,16 @@ class Solver:
         except Exception:
             pass
 
-    def set_reference(self, l0: float):
-        _check(self.ctx, self.lib.lshom_set_reference(self.ctx, float(l0)))
+    def set_reference(self, l0):
+        """Reference medium: a number l0 (L0 = l0 I) or a symmetric positive
+        definite d x d matrix L0."""
+        if np.ndim(l0) == 0:
+            _check(self.ctx, self.lib.lshom_set_reference(self.ctx, float(l0)))
+        else:
+            m = np.ascontiguousarray(l0, dtype=np.float64)
+            if m.shape != (self.d, self.d):
+                raise ValueError(f"L0 must be a number or a {self.d} x {self.d} matrix")
+            _check(self.ctx, self.lib.lshom_set_reference_tensor(self.ctx, _dbl_array(m.ravel())))
 
     def set_cell(self, lengths):
         """Side lengths of the periodic cell (only their ratios matter)."""
