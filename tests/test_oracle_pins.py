@@ -689,3 +689,36 @@ def test_ffth_and_bicg_with_general_reference():
     iso = o.ffth(o.Medium(s), 2.5, E, tol=1e-12)
     assert abs(f["iterations"] - iso["iterations"]) <= 2
     assert o.true_residual(med, 2.5 * M, E, b["e"], euclidean=True) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# Pipelined CG (one reduction phase per iteration): the iterates of CG
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,rho", [((7, 9), 10.0), ((15, 13), 100.0), ((5, 7, 3), 30.0)])
+def test_pipelined_cg_matches_dense_solve(shape, rho):
+    rng = np.random.default_rng(90)
+    lam = np.where(rng.random(shape) < 0.4, rho, 1.0)
+    E = np.linspace(1.0, -0.4, len(shape))
+    ref, _ = o.dense_solve(lam, o.optimal_reference(lam), E)
+    res = o.pipelined_cg(lam, o.optimal_reference(lam), E, tol=1e-12)
+    assert res["converged"]
+    assert np.linalg.norm(res["e"] - ref) / np.linalg.norm(ref) < 1e-9
+
+
+@pytest.mark.parametrize("l0_kind", ["iso", "aniso"])
+def test_pipelined_cg_iterates_equal_cg(l0_kind):
+    """Same Krylov recurrences: the iterates of CG up to rounding, at every
+    count, and the same stopping iteration."""
+    lam = ms.grf_two_phase(45, 0.15, 0.4, 50.0, seed=12).lam()
+    l0 = o.optimal_reference(lam) if l0_kind == "iso" else np.array([[30.0, 6.0], [6.0, 18.0]])
+    E = (0.6, -0.8)
+    for k in (1, 2, 5, 20):
+        a = o.cg(lam, l0, E, n_iter=k)
+        b = o.pipelined_cg(lam, l0, E, n_iter=k)
+        assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(a["e"]) < 1e-11, k
+        assert abs(a["rel_res"] - b["rel_res"]) <= 1e-8 * a["rel_res"]
+    full_a = o.cg(lam, l0, E, tol=1e-8)
+    full_b = o.pipelined_cg(lam, l0, E, tol=1e-8)
+    assert abs(full_a["iterations"] - full_b["iterations"]) <= 1
+    assert np.linalg.norm(full_a["e"] - full_b["e"]) / np.linalg.norm(full_a["e"]) < 1e-7
