@@ -53,6 +53,7 @@ typedef int32_t lshom_status;
 #define LSHOM_METHOD_CG 0       /* conjugate gradients on Eq. (15) (Sec. 2.3, Sec. 3) */
 #define LSHOM_METHOD_FFTH 1     /* the basic scheme: Neumann series of Sec. 2.3, Eq. (18) */
 #define LSHOM_METHOD_BICG 2     /* biconjugate gradients on the nodal system (Sec. 2.3; Sec. 3) */
+#define LSHOM_METHOD_PIPECG 3   /* CG with one reduction phase per iteration (pipelined, w = A r) */
 
 #define LSHOM_NORM_RESIDUAL 0    /* stop when ||r|| <= tol ||e0|| (eta_r / l0, Eq. (22)) */
 #define LSHOM_NORM_EQUILIBRIUM 1 /* stop when eta_e <= tol (Sec. 3, Eq. (21)) */
@@ -67,8 +68,9 @@ typedef struct lshom_solve_opts {
   double refresh_drop;   /* 0.1: mixed only, refresh when ||r|| fell by this factor */
   int32_t graph_block;   /* 16: iterations per captured HIP graph launch (0: no graph) */
   int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop (and eta_e, odd N) */
-  int32_t method;        /* LSHOM_METHOD_CG; FFTH and BICG: FP64 only, no x0; BICG: single
-                            solves, residual norm, workspace from lshom_workspace_size_for */
+  int32_t method;        /* LSHOM_METHOD_CG; FFTH, BICG and PIPECG: FP64 only, no x0; BICG and
+                            PIPECG: single solves, residual norm, no history, workspace from
+                            lshom_workspace_size_for */
   int32_t norm;          /* LSHOM_NORM_RESIDUAL; EQUILIBRIUM: FP64 and odd N only */
   /*
    * NULL, or (single solves, FP64, odd N) a caller-owned device buffer of
@@ -185,7 +187,8 @@ lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* b
 /*
  * Bytes of device workspace a solve with these options needs (opts NULL =
  * defaults).  BiCG iterates on d-component nodal fields and needs seven of
- * them (x, r, r*, p, p*, A p, A^T p*) on top of the CG workspace.
+ * them (x, r, r*, p, p*, A p, A^T p*) on top of the CG workspace; pipelined
+ * CG uses the same extra area.
  */
 lshom_status lshom_workspace_size_for(const lshom_ctx* ctx, const lshom_solve_opts* opts, size_t* bytes);
 
@@ -200,6 +203,11 @@ lshom_status lshom_set_workspace(lshom_ctx* ctx, void* dev, size_t bytes);
  * (recursive residual; for the basic scheme the step e^(m+1) - e^(m)), or
  * with LSHOM_METHOD_BICG by BiCG on the nodal fields (shadow residual
  * r0* = r0; info->applies_fp64 counts both products per iteration), or
+ * with LSHOM_METHOD_PIPECG by pipelined CG (the iterates of CG in exact
+ * arithmetic; both inner products of an iteration come from one reduction
+ * in the update pass, so a distributed solve needs one all-reduce per
+ * iteration, which can overlap the operator apply; the three extra
+ * spectral vectors w = A r, s = A p, z = A s take the BiCG field area), or
  * with LSHOM_NORM_EQUILIBRIUM when eta_e <= tol, or after max_iter.  The
  * basic scheme tests iterate m in the apply that forms m + 1 and returns
  * e^(m+1).

@@ -148,6 +148,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
 lshom_status apply_real(Group& g, const double* p, double* q);
 // BiCG (single problem, FP64, workspace with the BiCG fields): e_out may be null.
 lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out);
+lshom_status solve_pipecg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out);
 lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out);
 // Algorithmic HBM bytes of each pass class for one problem and one CG iteration.
 void pass_model_bytes(const Group& g, int precision, double* out);

@@ -436,7 +436,7 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
 template <typename T>
 hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<T>* base,
                                T coef_base, T coef_s, int s_inv_l0, int dot, int dot_region, int gate,
-                               int eq = 0) {
+                               int eq = 0, int pipe = 0) {
   hipError_t e;
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, -1);
@@ -456,6 +456,7 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
   a.eq = eq;
   a.eq_region = PART_EQ0;
   a.gate = gate;
+  a.pipe = pipe;
   return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, stream_of(g)); });
 }
 
@@ -1081,6 +1082,109 @@ lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& 
   if (e_out)
     HIP_TRY(c, hipMemcpyAsync(e_out, x, sizeof(double) * g.d * g.nvox, hipMemcpyDeviceToDevice, stream_of(g)));
   HIP_TRY(c, sync_states(g));
+  return LSHOM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined CG (single problem, FP64): the iterates of CG with one reduction
+// per iteration.  Spectral vectors x, r, p (the CG slots) and w = A r,
+// s = A p, z = A s (the extra-field area).
+// ---------------------------------------------------------------------------
+
+// One iteration: the scalar step (alpha, beta, stop) with the inverse pass of
+// n = A w, the row pass, z = n + beta z with the forward pass, the update
+// (which also reduces (r, r) and (w, r) for the next step).
+hipError_t enq_pipe_iteration(Group& g, const Bufs<double>& b, cx<double>* w, cx<double>* s, cx<double>* z,
+                              int gate) {
+  hipError_t e;
+  static const double kZero[3] = {0.0, 0.0, 0.0};
+  g.in_cg = true;
+  struct InCg {
+    Group& g;
+    ~InCg() { g.in_cg = false; }
+  } in_cg{g};
+  ColArgs<double> a = col0_args(g, b);
+  a.mode = COL_INV_C;
+  a.c_in = w;
+  a.pipe = 1;
+  a.gate = gate;
+  if ((e = timed_launch(g, LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_col(a, stream_of(g)); })) != hipSuccess)
+    return e;
+  if (g.d == 3) {
+    ColArgs<double> m = col1_args(g, b, +1);
+    m.gate = gate;
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_col(m, stream_of(g)); })) != hipSuccess)
+      return e;
+  }
+  RowArgs<double> r = row_args(g, b);
+  r.mode = ROW_FUSED;
+  for (int t = 0; t < g.d; ++t) r.E[t] = kZero[t];
+  r.gate = gate;
+  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row(r, stream_of(g)); })) != hipSuccess) return e;
+  if ((e = enq_forward_project<double>(g, b, z, w, 1.0, 1.0, 1, 0, PART_AUX, gate, 0, 1)) != hipSuccess) return e;
+  PipeArgs<double> u{};
+  u.n = g.nhalf;
+  u.h = g.h;
+  u.n_last = (int)g.N[g.d - 1];
+  u.klast_div = klast_div_of(g);
+  u.fd_kd = make_fastdiv((uint32_t)u.klast_div);
+  u.fd_h = make_fastdiv((uint32_t)g.h);
+  u.x = b.v[0];
+  u.r = b.v[1];
+  u.p = b.v[2];
+  u.w = w;
+  u.s = s;
+  u.z = z;
+  u.st = dev_state(g);
+  u.parts = dev_parts(g);
+  u.gate = gate;
+  u.bt = batch_of(g);
+  return timed_launch(g, LSHOM_PASS_UPDATE, [&] { return launch_pipe_update(u, stream_of(g)); });
+}
+
+lshom_status solve_pipecg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out) {
+  lshom_ctx* c = g.ctx;
+  Bufs<double> b = get_bufs<double>(g);
+  auto field = [&](int i) { return reinterpret_cast<cx<double>*>(g.ws + g.lay.off_bicg[i]); };
+  cx<double>* w = field(0);
+  cx<double>* s = field(1);
+  cx<double>* z = field(2);
+  cx<double>* x = b.v[0];
+  cx<double>* r = b.v[1];
+  DevState* init_dev = reinterpret_cast<DevState*>(g.ws + g.lay.off_partials);
+  HIP_TRY(c, hipMemcpyAsync(init_dev, &init, sizeof(DevState), hipMemcpyHostToDevice, stream_of(g)));
+  HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, 1, stream_of(g)));
+  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  for (cx<double>* v : {x, b.v[2], s, z}) HIP_TRY(c, launch_fill_zero(v, g.nhalf, stream_of(g)));
+  // x0 = E: r0 and (r0, r0), the test on it; w0 = A r0 and (w0, r0)
+  HIP_TRY(c, (enq_residual_of_E<double>(g, b, nullptr, r, PART_RR0)));
+  HIP_TRY(c, enq_finalize(g, FZ_CHECK, 0, GATE_ALWAYS));
+  static const double kZero[3] = {0.0, 0.0, 0.0};
+  HIP_TRY(c, (enq_apply_spec<double>(g, b, r, nullptr, nullptr, kZero, w, r, 1.0, 1.0, 1, PART_PQ, GATE_ALWAYS)));
+  HIP_TRY(c, sync_states(g));
+  PassTimer& tm = c->timer;
+  g.timer = tm.on ? &tm : nullptr;
+  const int K = tm.on ? 0 : o.graph_block;
+  const int per = o.graph_block > 0 ? o.graph_block : 8;
+  tm.kinds.clear();
+  pass_model_bytes(g, LSHOM_PRECISION_FP64, tm.unit_bytes);
+  lshom_status st = run_blocks(g, 6, K, (long long)o.max_iter / per + 4, [&]() -> hipError_t {
+    const Bufs<double> f64 = get_bufs<double>(g);
+    for (int k = 0; k < per; ++k) {
+      hipError_t e = enq_pipe_iteration(g, f64, w, s, z, GATE_ACTIVE);
+      if (e != hipSuccess) return e;
+    }
+    return enq_finalize(g, FZ_CHECK, 0, GATE_ACTIVE);
+  });
+  if (st != LSHOM_OK) return st;
+  const long long ncol = col0_block_count(g, b);
+  if (o.true_residual) {
+    HIP_TRY(c, (enq_true_residual<double>(g, b, x, nullptr, b.v[3], PART_AUX, GATE_ALWAYS)));
+    HIP_TRY(c, enq_finalize(g, FZ_RR_TRUE, ncol, GATE_ALWAYS));
+  }
+  HIP_TRY(c, enq_field_out(g, b, x, nullptr, nullptr, e_out, true));
+  HIP_TRY(c, sync_states(g));
+  g.warm_used = 0;
   return LSHOM_OK;
 }
 

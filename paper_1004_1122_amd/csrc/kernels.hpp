@@ -46,6 +46,8 @@ struct DevState {
   double bicg_rho;      // BiCG: (r, r*) of the current iterate
   double bicg_alpha;    // BiCG: step of the current iteration
   double bicg_beta;     // BiCG: direction update of the current iteration
+  double pipe_alpha[2]; // pipelined CG: step of iteration k at [k & 1]
+  double pipe_beta[2];  // pipelined CG: direction update of iteration k at [k & 1]
   double* hist;         // (eta_r, eta_e) of iterate m at [2m], [2m + 1], m < hist_len (or null)
   int hist_len;
   int norm;             // 0: ||r|| <= tol ||b||; 1: eta_e <= tol
@@ -59,7 +61,8 @@ struct DevState {
   int k_ref;            // mixed: iteration count at the last refresh
   int n_refresh;
   int nparts[2];        // number of partials in the two (r, r) buffers
-  int pad[3];
+  int nparts_pq;        // number of partials in the PQ region (set by its producer)
+  int pad[2];
 };
 
 // When a kernel returns at entry.
@@ -218,7 +221,10 @@ struct ColArgs {
   cx<T>* p_io;           // cg_step: p = r + beta p (written back)
   const cx<T>* r_in;
   int cg_step;           // this launch is the CG direction step (decides beta, stop)
+  int pipe;              // pipelined CG: COL_INV_C takes the scalar step (alpha, beta,
+                         // stop) from (r, r), (w, r); COL_FWD_PROJ adds beta * out
   // COL_FWD_PROJ: out = coef_base * base + coef_s * [1 / l0 if s_inv_l0] * s
+  // (+ beta out for pipelined CG: z = A w + beta z)
   cx<T>* out;
   const cx<T>* base;
   T coef_base, coef_s;
@@ -268,6 +274,26 @@ struct UpdArgs {
   double cinv[kMaxDim];  // 1 / cell side length per axis
   int aniso;             // equilibrium weight xi . L0n . xi in place of |xi|^2
   double L0n[6];
+};
+
+// Pipelined CG update (spectral coordinate): s = w + beta s, p = r + beta p,
+// x += alpha p, r -= alpha s, w -= alpha z; partials of (r, r) and (w, r).
+template <typename T>
+struct PipeArgs {
+  long long n;
+  int h, n_last;
+  long long klast_div;
+  cx<T>* x;
+  cx<T>* r;
+  cx<T>* p;
+  cx<T>* w;
+  cx<T>* s;
+  const cx<T>* z;
+  DevState* st;
+  Partials parts;
+  int gate;
+  Batch bt;
+  FastDiv fd_kd, fd_h;
 };
 
 // BiCG on real d-component nodal fields ([d][n] FP64, components contiguous):
@@ -337,6 +363,7 @@ struct FinArgs {
 template <typename T> hipError_t launch_row(const RowArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_col(const ColArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s);
+hipError_t launch_pipe_update(const PipeArgs<double>& a, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);

@@ -161,16 +161,18 @@ lshom_status validate_opts(lshom_ctx* c, const lshom_solve_opts* o) {
     if (!(o->refresh_drop > 0.0 && o->refresh_drop < 1.0))
       return fail(c, LSHOM_ERR_INVALID_ARG, "refresh_drop must be in (0, 1)");
   }
-  if (o->method != LSHOM_METHOD_CG && o->method != LSHOM_METHOD_FFTH && o->method != LSHOM_METHOD_BICG)
-    return fail(c, LSHOM_ERR_INVALID_ARG, "method must be CG (0), FFTH (1) or BICG (2)");
+  if (o->method != LSHOM_METHOD_CG && o->method != LSHOM_METHOD_FFTH && o->method != LSHOM_METHOD_BICG &&
+      o->method != LSHOM_METHOD_PIPECG)
+    return fail(c, LSHOM_ERR_INVALID_ARG, "method must be CG (0), FFTH (1), BICG (2) or PIPECG (3)");
   if (o->norm != LSHOM_NORM_RESIDUAL && o->norm != LSHOM_NORM_EQUILIBRIUM)
     return fail(c, LSHOM_ERR_INVALID_ARG, "norm must be RESIDUAL (0) or EQUILIBRIUM (1)");
   if (o->history_len < 0) return fail(c, LSHOM_ERR_INVALID_ARG, "history_len must be >= 0");
   const bool mixed = o->precision == LSHOM_PRECISION_MIXED;
   if (mixed && o->method != LSHOM_METHOD_CG)
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme and BiCG run in FP64 only");
-  if (o->method == LSHOM_METHOD_BICG && (o->norm != LSHOM_NORM_RESIDUAL || o->history_dev))
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG stops on the residual norm and keeps no history");
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme, BiCG and pipelined CG run in FP64 only");
+  if ((o->method == LSHOM_METHOD_BICG || o->method == LSHOM_METHOD_PIPECG) &&
+      (o->norm != LSHOM_NORM_RESIDUAL || o->history_dev))
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG and pipelined CG stop on the residual norm and keep no history");
   if (mixed && (o->norm == LSHOM_NORM_EQUILIBRIUM || o->history_dev))
     return fail(c, LSHOM_ERR_UNSUPPORTED, "the equilibrium norm and the history are FP64 only");
   return LSHOM_OK;
@@ -468,7 +470,8 @@ lshom_status lshom_workspace_size_for(const lshom_ctx* c, const lshom_solve_opts
   lshom_default_opts(&o);
   if (opts) o = *opts;
   if (o.precision != LSHOM_PRECISION_FP64 && o.precision != LSHOM_PRECISION_MIXED) return LSHOM_ERR_INVALID_ARG;
-  *bytes = compute_layout(c->g, o.precision == LSHOM_PRECISION_MIXED, o.method == LSHOM_METHOD_BICG).total;
+  const bool extra = o.method == LSHOM_METHOD_BICG || o.method == LSHOM_METHOD_PIPECG;
+  *bytes = compute_layout(c->g, o.precision == LSHOM_PRECISION_MIXED, extra).total;
   return LSHOM_OK;
 }
 
@@ -519,7 +522,9 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
     if (!std::isfinite(E_host[a])) return fail(c, LSHOM_ERR_INVALID_ARG, "E must be finite");
   if ((s = check_equilibrium_grid(c, o, c->g.N, c->g.d)) != LSHOM_OK) return s;
   if (o.method != LSHOM_METHOD_CG && x0_dev)
-    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme and BiCG start from e = E (no x0)");
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme, BiCG and pipelined CG start from e = E (no x0)");
+  if (o.method == LSHOM_METHOD_PIPECG && !c->g.lay.has_bicg)
+    return fail(c, LSHOM_ERR_WORKSPACE, "workspace has no extra fields (size it with lshom_workspace_size_for)");
   if (o.method == LSHOM_METHOD_BICG) {
     if (!c->g.lay.has_bicg)
       return fail(c, LSHOM_ERR_WORKSPACE, "workspace has no BiCG fields (size it with lshom_workspace_size_for)");
@@ -547,6 +552,8 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
       1, initial_state(gr.d, gr.nvox, E_host, tol, gr.l0, o, true, gr.aniso ? gr.L0n : nullptr));
   if (o.method == LSHOM_METHOD_BICG)
     s = solve_bicg(gr, init[0], o, e_dev);
+  else if (o.method == LSHOM_METHOD_PIPECG)
+    s = solve_pipecg(gr, init[0], o, e_dev);
   else
     s = solve_group(gr, init, o, E_host, x0_dev, e_dev);
   if (s != LSHOM_OK) return s;
@@ -789,7 +796,8 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
   lshom_status s = validate_opts(c, &o);
   if (s != LSHOM_OK) return s;
   if (o.history_dev) return fail(c, LSHOM_ERR_INVALID_ARG, "history_dev must be NULL for batched solves");
-  if (o.method == LSHOM_METHOD_BICG) return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG runs single solves only");
+  if (o.method == LSHOM_METHOD_BICG || o.method == LSHOM_METHOD_PIPECG)
+    return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG and pipelined CG run single solves only");
   BatchPlan bp;
   if ((s = plan_batch(c, n, probs, o.precision, &bp)) != LSHOM_OK) return s;
   for (int32_t i = 0; i < n; ++i)

@@ -503,7 +503,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   // sums (block 0 of the same launch may set the flags); the other modes
   // see flags that only earlier launches write
   constexpr bool kDirGate = MODE == COL_INV_C;
-  if (!(kDirGate && a.cg_step) && gated_out_stable(st, a.gate)) return;
+  if (!(kDirGate && (a.cg_step || a.pipe)) && gated_out_stable(st, a.gate)) return;
   const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
@@ -537,7 +537,11 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
 
   if constexpr (MODE == COL_INV_C) {
     double beta = 0.0;
-    if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq)) return;
+    if (a.pipe) {
+      if (!pipe_direction<NT>(st, parts, a.inv_n, a.gate)) return;
+    } else if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq)) {
+      return;
+    }
     const T tb = (T)beta;
     const int total = L * C;
     for (int base = 0; base < total; base += NT * kBatch) {
@@ -660,16 +664,23 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int n_last = a.nd[a.dims - 1];
   const int total = L * C;
   const T cs = a.coef_s * (a.s_inv_l0 ? (T)(1.0 / (pe ? pe->l0 : a.l0)) : T(1));
+  // pipelined CG: z = A w + beta z (beta of this iteration, set by the inverse pass)
+  const T pbeta = a.pipe ? (T)st->pipe_beta[st->iter_u & 1] : T(0);
   for (int base = 0; base < total; base += NT * kBatch) {
-    cx<T> bv[kBatch];
+    cx<T> bv[kBatch], zv[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int idx = base + u * NT + tid;
       bv[u] = zero;
-      if (a.base && idx < total) {
+      zv[u] = zero;
+      if (idx < total) {
         int l, c;
         split(idx, l, c);
-        if (c < width) bv[u] = a.base[base_o + l * a.sl + (i0 + c) * a.sii];
+        if (c < width) {
+          const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
+          if (a.base) bv[u] = a.base[g];
+          if (a.pipe) zv[u] = a.out[g];
+        }
       }
     }
 #pragma unroll
@@ -714,6 +725,10 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       const cx<T> b = bv[u];
       val.re += a.coef_base * b.re;
       val.im += a.coef_base * b.im;
+      if (a.pipe) {
+        val.re += pbeta * zv[u].re;
+        val.im += pbeta * zv[u].im;
+      }
       a.out[g] = val;
       if (a.dot) {
         const uint32_t kl = (uint32_t)(i0 + c);
@@ -743,6 +758,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
     }
     if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
+    if (a.dot_region == PART_PQ && blockIdx.x == 0 && tid == 0) st->nparts_pq = (int)gridDim.x;
   }
   }
 }
@@ -861,6 +877,83 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     // cell sum of dL (E + u(x)) follows x += alpha p linearly
     if (a.eq)
       for (int c = 0; c < kMaxDim; ++c) st->jx[c] += alpha * st->taup[c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined CG update: s = w + beta s, p = r + beta p, x += alpha p,
+// r -= alpha s, w -= alpha z; (r, r) and (w, r) of the new iterate in one
+// reduction (the only one of the iteration)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void pipe_update_kernel(PipeArgs<double> a) {
+  constexpr int NT = 256;
+  const int pb = batch_prob(a.bt);
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  const long long vo = (long long)pb * a.bt.vstride;
+  const int k = st->iter_u;
+  const double alpha = st->pipe_alpha[k & 1];
+  const double beta = st->pipe_beta[k & 1];
+  cx<double>* __restrict__ X = a.x + vo;
+  cx<double>* __restrict__ Rv = a.r + vo;
+  cx<double>* __restrict__ P = a.p + vo;
+  cx<double>* __restrict__ W = a.w + vo;
+  cx<double>* __restrict__ S = a.s + vo;
+  const cx<double>* __restrict__ Z = a.z + vo;
+  double acc_rr = 0.0, acc_wr = 0.0;
+  const long long stride = (long long)gridDim.x * NT;
+  for (long long i0 = (long long)blockIdx.x * NT + threadIdx.x; i0 < a.n; i0 += stride * 2) {
+    cx<double> x[2], r[2], p[2], w[2], sv[2], z[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long long i = i0 + u * stride;
+      if (i < a.n) {
+        x[u] = X[i];
+        r[u] = Rv[i];
+        p[u] = P[i];
+        w[u] = W[i];
+        sv[u] = S[i];
+        z[u] = Z[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const long long i = i0 + u * stride;
+      if (i >= a.n) continue;
+      sv[u] = cx<double>{w[u].re + beta * sv[u].re, w[u].im + beta * sv[u].im};
+      p[u] = cx<double>{r[u].re + beta * p[u].re, r[u].im + beta * p[u].im};
+      x[u].re += alpha * p[u].re;
+      x[u].im += alpha * p[u].im;
+      r[u].re -= alpha * sv[u].re;
+      r[u].im -= alpha * sv[u].im;
+      w[u].re -= alpha * z[u].re;
+      w[u].im -= alpha * z[u].im;
+      X[i] = x[u];
+      Rv[i] = r[u];
+      P[i] = p[u];
+      W[i] = w[u];
+      S[i] = sv[u];
+      const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
+      const double wt = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
+      acc_rr += wt * (r[u].re * r[u].re + r[u].im * r[u].im);
+      acc_wr += wt * (w[u].re * r[u].re + w[u].im * r[u].im);
+    }
+  }
+  const int nxt = (k + 1) & 1;
+  double v[2] = {acc_rr, acc_wr};
+  (void)block_sums_gated<NT, 2>(v, 0);
+  if (threadIdx.x == 0) {
+    parts.region(nxt)[blockIdx.x] = v[0];
+    parts.region(PART_PQ)[blockIdx.x] = v[1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->nparts[nxt] = (int)gridDim.x;
+    st->nparts_pq = (int)gridDim.x;
+    st->iter_a = k + 1;
+    st->alpha_log = alpha;
   }
 }
 
@@ -1351,6 +1444,12 @@ hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
 
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1, (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pipe_update(const PipeArgs<double>& a, hipStream_t s) {
+  hipLaunchKernelGGL(pipe_update_kernel, dim3((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt)), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
 

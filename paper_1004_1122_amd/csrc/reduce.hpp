@@ -220,4 +220,60 @@ __device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, 
   return !stop;
 }
 
+// The scalar step of pipelined CG at the start of iteration k = iter_a, from
+// gamma_k = (r_k, r_k) (region k & 1) and delta_k = (w_k, r_k) (PQ), both
+// reduced by the update that formed r_k and w_k: the stop tests as in
+// cg_direction (residual norm only), then beta = gamma_k / gamma_{k-1} and
+// alpha = gamma_k / (delta_k - beta gamma_k / alpha_{k-1}) (beta = 0,
+// alpha = gamma_k / delta_k at k = 0).  gamma_{k-1} comes from the other
+// (r, r) region and alpha_{k-1} from the state slot of parity k - 1, so no
+// block reads a value block 0 writes in this launch.  Block 0 records alpha
+// and beta at parity k for the later passes of the iteration.
+template <int NT>
+__device__ bool pipe_direction(DevState* st, const Partials& parts, double inv_n, int gate) {
+  const int skip0 = gate_flags(st, gate);
+  const int k = st->iter_a;
+  double v[3] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
+                 partial_share<NT>(parts.region(PART_PQ), st->nparts_pq),
+                 k > 0 ? partial_share<NT>(parts.region((k + 1) & 1), st->nparts[(k + 1) & 1]) : 0.0};
+  if (block_sums_gated<NT, 3>(v, skip0)) return false;
+  const double gamma = v[0] * inv_n;
+  const double delta = v[1] * inv_n;
+  const double gamma_prev = v[2] * inv_n;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  double beta = 0.0, alpha = 0.0;
+  bool stop = false;
+  if (!isfinite(gamma)) {
+    if (lead) st->status = -6;
+    stop = true;
+  } else if (gamma <= st->tol2b2) {
+    stop = true;
+  } else if (k >= st->max_iter) {
+    if (lead) st->status = -5;
+    stop = true;
+  } else {
+    if (k > 0) {
+      beta = gamma / gamma_prev;
+      alpha = gamma / (delta - beta * gamma / st->pipe_alpha[(k + 1) & 1]);
+    } else {
+      alpha = gamma / delta;
+    }
+    if (!(alpha > 0.0) || !isfinite(alpha)) {
+      if (lead) {
+        st->status = -6;
+        st->pq_log = delta;
+      }
+      stop = true;
+    }
+  }
+  if (lead) {
+    if (stop) st->done = 1;
+    st->iter_u = k;
+    st->rr_log = gamma;
+    st->pipe_alpha[k & 1] = alpha;
+    st->pipe_beta[k & 1] = beta;
+  }
+  return !stop;
+}
+
 }  // namespace lshom

@@ -39,6 +39,7 @@ PRECISION_MIXED = 1
 METHOD_CG = 0
 METHOD_FFTH = 1
 METHOD_BICG = 2
+METHOD_PIPECG = 3
 
 NORM_RESIDUAL = 0
 NORM_EQUILIBRIUM = 1
@@ -335,11 +336,12 @@ class Solver:
         _check(self.ctx, self.lib.lshom_set_workspace(self.ctx, c_void_p(self.ws_ptr), self.ws_bytes))
 
     def _ensure_workspace(self, o):
-        """Grows the workspace when the options need more (BiCG fields)."""
+        """Grows the workspace when the options need more (the extra fields of
+        BiCG and pipelined CG)."""
         size = c_size_t()
         _check(self.ctx, self.lib.lshom_workspace_size_for(self.ctx, ctypes.byref(o), ctypes.byref(size)))
         need = int(size.value)
-        if o.method == METHOD_BICG:
+        if o.method in (METHOD_BICG, METHOD_PIPECG):
             # keep the FP32 part as well, so that mixed solves still fit
             mixed = lshom_default_opts()
             mixed.precision = PRECISION_MIXED
