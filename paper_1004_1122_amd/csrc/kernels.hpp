@@ -193,6 +193,11 @@ enum ColMode : int {
   COL_PLAIN = 1,    // comp[a] -> FFT (direction dir) -> comp[a]
   COL_FWD_PROJ = 2, // comp[a] -> forward FFT -> s = -i khat . tau_hat -> out
   COL_PLAIN_FWD = 3, // kernel specialisation of COL_PLAIN with dir < 0 (launcher-internal)
+  // launcher-internal specialisations of COL_INV_C / COL_FWD_PROJ that carry
+  // the anisotropic-reference scale and the pipelined-CG steps (the plain
+  // ones stay free of that code)
+  COL_INV_C_GEN = 4,
+  COL_FWD_PROJ_GEN = 5,
 };
 
 template <typename T>

@@ -198,10 +198,6 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
   parts.base += (long long)pb * a.bt.pstride;
   const uint8_t* phase = pe ? pe->phase : a.phase;
   const T l0 = pe ? (T)pe->l0 : a.l0;
-  T shift[6], zero6[6];
-  reference_shift(a, l0, shift);
-#pragma unroll
-  for (int i = 0; i < 6; ++i) zero6[i] = T(0);
   T Ev[kMaxDim];
 #pragma unroll
   for (int c = 0; c < kMaxDim; ++c) Ev[c] = (a.flags & ROWF_STATE_E) ? (T)st->E[c] : a.E[c];
@@ -242,6 +238,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     __syncthreads();
     if (a.tensor && (a.flags & ROWF_DL)) {
       // every component of a node at once (the block holds all of them)
+      T shift[6];
+      reference_shift(a, l0, shift);
       for (int idx = tid; idx < half_rows * n; idx += NT) {
         const int j = (int)fdiv((uint32_t)idx, a.fd_n);
         const int x = idx - j * n;
@@ -359,6 +357,10 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
     if constexpr (MODE == ROW_INV) {
       double acc[kMaxDim] = {0.0, 0.0, 0.0};
       if (a.tensor && (a.flags & (ROWF_LEFF | ROWF_DL_OUT))) {
+        T shift[6], zero6[6];
+        reference_shift(a, l0, shift);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zero6[i] = T(0);
         for (int idx = tid; idx < half_rows * n; idx += NT) {
           const int j = (int)fdiv((uint32_t)idx, a.fd_n);
           const int x = idx - j * n;
@@ -431,6 +433,8 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
     // ROW_FUSED: polarisation dL (E + u) at the nodes (Sec. 2.2, Eq. (17))
     if (a.tensor) {
+      T shift[6];
+      reference_shift(a, l0, shift);
       for (int idx = tid; idx < half_rows * n; idx += NT) {
         const int j = (int)fdiv((uint32_t)idx, a.fd_n);
         const int x = idx - j * n;
@@ -502,8 +506,11 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   // the direction step of the inverse pass reads its gate with the (r, r)
   // sums (block 0 of the same launch may set the flags); the other modes
   // see flags that only earlier launches write
-  constexpr bool kDirGate = MODE == COL_INV_C;
-  if (!(kDirGate && (a.cg_step || a.pipe)) && gated_out_stable(st, a.gate)) return;
+  constexpr bool kInv = MODE == COL_INV_C || MODE == COL_INV_C_GEN;
+  constexpr bool kGen = MODE == COL_INV_C_GEN || MODE == COL_FWD_PROJ_GEN;
+  const bool pipe = kGen && a.pipe;
+  const bool aniso = kGen && a.aniso;
+  if (!(kInv && (a.cg_step || pipe)) && gated_out_stable(st, a.gate)) return;
   const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
@@ -535,9 +542,9 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
     }
   };
 
-  if constexpr (MODE == COL_INV_C) {
+  if constexpr (kInv) {
     double beta = 0.0;
-    if (a.pipe) {
+    if (pipe) {
       if (!pipe_direction<NT>(st, parts, a.inv_n, a.gate)) return;
     } else if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq)) {
       return;
@@ -580,7 +587,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
           }
           double kh[kMaxDim];
           const bool nz = khat_axis0(a, l, i0 + c, kh);
-          const double sk = (a.aniso && nz) ? 1.0 / sqrt(sym_quad(a.L0n, a.dims, kh)) : 1.0;
+          const double sk = (aniso && nz) ? 1.0 / sqrt(sym_quad(a.L0n, a.dims, kh)) : 1.0;
 #pragma unroll
           for (int al = 0; al < kMaxDim; ++al) {
             if (al >= d) break;
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   const int total = L * C;
   const T cs = a.coef_s * (a.s_inv_l0 ? (T)(1.0 / (pe ? pe->l0 : a.l0)) : T(1));
   // pipelined CG: z = A w + beta z (beta of this iteration, set by the inverse pass)
-  const T pbeta = a.pipe ? (T)st->pipe_beta[st->iter_u & 1] : T(0);
+  const T pbeta = pipe ? (T)st->pipe_beta[st->iter_u & 1] : T(0);
   for (int base = 0; base < total; base += NT * kBatch) {
     cx<T> bv[kBatch], zv[kBatch];
 #pragma unroll
@@ -679,7 +686,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
         if (c < width) {
           const long long g = base_o + l * a.sl + (i0 + c) * a.sii;
           if (a.base) bv[u] = a.base[g];
-          if (a.pipe) zv[u] = a.out[g];
+          if (pipe) zv[u] = a.out[g];
         }
       }
     }
@@ -695,7 +702,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       double k2 = 0.0;
       const bool nz = khat_axis0(a, l, i0 + c, kh, &k2);
       double sk = 1.0;
-      if (a.aniso && nz) {
+      if (aniso && nz) {
         // the Green operator takes 1 / sqrt(q) like the inverse pass; the
         // plain projection of a field takes the inverse scale sqrt(q); the
         // equilibrium weight |xi|^2 becomes xi . L0n . xi
@@ -725,7 +732,7 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       const cx<T> b = bv[u];
       val.re += a.coef_base * b.re;
       val.im += a.coef_base * b.im;
-      if (a.pipe) {
+      if (pipe) {
         val.re += pbeta * zv[u].re;
         val.im += pbeta * zv[u].im;
       }
@@ -794,7 +801,8 @@ __device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, u
 // CG update: alpha = (r, r) / (p, q); x += alpha p, r -= alpha q, (r, r)
 // ---------------------------------------------------------------------------
 
-template <typename T>
+// EQ: the equilibrium sums ride along (a.eq); the plain kernel has no code for them.
+template <typename T, bool EQ>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
   const int pb = batch_prob(a.bt);
@@ -855,11 +863,11 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
       const double w = half_weight(k_last, a.n_last);
       const double m2 = (double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im;
       acc += w * m2;
-      if (a.eq) acc_eq += w * spectral_k2(a, (uint32_t)i, kq, k_last) * m2;
+      if constexpr (EQ) acc_eq += w * spectral_k2(a, (uint32_t)i, kq, k_last) * m2;
     }
   }
   const int nxt = (k + 1) & 1;
-  if (a.eq) {
+  if constexpr (EQ) {
     double v[2] = {acc, acc_eq};
     (void)block_sums_gated<NT, 2>(v, 0);
     if (threadIdx.x == 0) {
@@ -875,7 +883,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     st->alpha_log = alpha;
     st->pq_log = pq;
     // cell sum of dL (E + u(x)) follows x += alpha p linearly
-    if (a.eq)
+    if constexpr (EQ)
       for (int c = 0; c < kMaxDim; ++c) st->jx[c] += alpha * st->taup[c];
   }
 }
@@ -1401,9 +1409,12 @@ static void launch_col_m(const ColArgs<T>& a, size_t lds, long long nb, int nt, 
 
 template <typename T, int RS>
 static void launch_col_rs(const ColArgs<T>& a, size_t lds, long long nb, int nt, hipStream_t s) {
-  if (a.mode == COL_INV_C) launch_col_m<T, RS, COL_INV_C>(a, lds, nb, nt, s);
+  const bool gen = a.aniso || a.pipe;
+  if (a.mode == COL_INV_C && gen) launch_col_m<T, RS, COL_INV_C_GEN>(a, lds, nb, nt, s);
+  else if (a.mode == COL_INV_C) launch_col_m<T, RS, COL_INV_C>(a, lds, nb, nt, s);
   else if (a.mode == COL_PLAIN && a.dir > 0) launch_col_m<T, RS, COL_PLAIN>(a, lds, nb, nt, s);
   else if (a.mode == COL_PLAIN) launch_col_m<T, RS, COL_PLAIN_FWD>(a, lds, nb, nt, s);
+  else if (gen) launch_col_m<T, RS, COL_FWD_PROJ_GEN>(a, lds, nb, nt, s);
   else launch_col_m<T, RS, COL_FWD_PROJ>(a, lds, nb, nt, s);
 }
 
@@ -1438,7 +1449,9 @@ hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
 
 template <typename T>
 hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel<T>, dim3((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt)), dim3(256), 0, s, a);
+  const dim3 grid((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt));
+  if (a.eq) hipLaunchKernelGGL((update_kernel<T, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((update_kernel<T, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
