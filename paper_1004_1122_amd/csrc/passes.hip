@@ -810,6 +810,30 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
   const long long vo = (long long)pb * a.bt.vstride;
+  const cx<T>* __restrict__ P = a.p + vo;
+  const cx<T>* __restrict__ Q = a.q + vo;
+  cx<T>* __restrict__ X = a.x + vo;
+  cx<T>* __restrict__ Rv = a.r + vo;
+  const long long stride = (long long)gridDim.x * NT;
+  cx<T> p[kBatch], q[kBatch], x[kBatch], r[kBatch];
+  auto load = [&](long long base) {
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const long long i = base + u * stride;
+      if (i < a.n) {
+        p[u] = P[i];
+        q[u] = Q[i];
+        x[u] = X[i];
+        r[u] = Rv[i];
+      }
+    }
+  };
+  // a problem finished by an earlier launch returns before any load; the
+  // first chunk of vectors does not depend on alpha and is requested before
+  // the scalar sums, so its latency overlaps their reduction
+  if (gated_out_stable(st, a.gate)) return;
+  const long long first = (long long)blockIdx.x * NT + threadIdx.x;
+  load(first);
   // gate, iteration index and both sums in one reduction (block 0 of this
   // launch sets the done flag on a breakdown)
   const int skip0 = gate_flags(st, a.gate);
@@ -828,26 +852,11 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     }
     return;
   }
-  const cx<T>* __restrict__ P = a.p + vo;
-  const cx<T>* __restrict__ Q = a.q + vo;
-  cx<T>* __restrict__ X = a.x + vo;
-  cx<T>* __restrict__ Rv = a.r + vo;
   const double alpha = rr / pq;
   const T ta = (T)alpha;
   double acc = 0.0, acc_eq = 0.0;
-  const long long stride = (long long)gridDim.x * NT;
-  for (long long i0 = (long long)blockIdx.x * NT + threadIdx.x; i0 < a.n; i0 += stride * kBatch) {
-    cx<T> p[kBatch], q[kBatch], x[kBatch], r[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const long long i = i0 + u * stride;
-      if (i < a.n) {
-        p[u] = P[i];
-        q[u] = Q[i];
-        x[u] = X[i];
-        r[u] = Rv[i];
-      }
-    }
+  for (long long i0 = first; i0 < a.n; i0 += stride * kBatch) {
+    if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const long long i = i0 + u * stride;
