@@ -65,7 +65,7 @@ typedef struct lshom_solve_opts {
   int32_t max_iter;      /* 10000: CG iterations (operator applies in the loop) */
   int32_t precision;     /* LSHOM_PRECISION_FP64 */
   int32_t refresh_every; /* 50: mixed only, FP64 refresh at least this often */
-  double refresh_drop;   /* 0.1: mixed only, refresh when ||r|| fell by this factor */
+  double refresh_drop;   /* 0.01: mixed only, refresh when ||r|| fell by this factor */
   int32_t graph_block;   /* 16: iterations per captured HIP graph launch (0: no graph) */
   int32_t true_residual; /* 1: recompute b - A x in FP64 after the loop (and eta_e, odd N) */
   int32_t method;        /* LSHOM_METHOD_CG; FFTH, BICG and PIPECG: FP64 only, no x0; BICG and

@@ -213,7 +213,7 @@ void lshom_default_opts(lshom_solve_opts* o) {
   o->max_iter = 10000;
   o->precision = LSHOM_PRECISION_FP64;
   o->refresh_every = 50;
-  o->refresh_drop = 0.1;
+  o->refresh_drop = 0.01;
   o->graph_block = 16;
   o->true_residual = 1;
   o->method = LSHOM_METHOD_CG;

@@ -36,7 +36,7 @@ def test_status_strings(lib):
 def test_default_opts():
     o = lshom.lshom_default_opts()
     assert o.max_iter == 10000 and o.precision == 0 and o.graph_block == 16
-    assert o.refresh_every == 50 and abs(o.refresh_drop - 0.1) < 1e-15 and o.true_residual == 1
+    assert o.refresh_every == 50 and abs(o.refresh_drop - 0.01) < 1e-15 and o.true_residual == 1
 
 
 @pytest.mark.parametrize("d,N,cond,l0,E,tol,expect", [
