@@ -145,3 +145,37 @@ def test_tail_schedules(precision, tmp_path):
     path = tmp_path / "sched.jsonl"
     bs.save_schedules(str(path))
     assert '"tail_rows": 2' in path.read_text()
+
+
+def test_bench_sweep_full_size():
+    """The measured workload itself: the 729^2 circle cell (seed 2), rho = 1e1 .. 1e4, E = e1 and
+    e2, one batch per form with autotuned schedules, as the benchmark runs it.  At this size the
+    oracle checks every returned field through its own FP64 evaluation of the residual and of
+    <L e> (one apply each); the FP64 field of rho = 10, E = e1 equals the oracle's CG at the same
+    iteration count; both forms give the same effective conductivities."""
+    from paper_1004_1122_amd import lshom
+    m = ms.circles_729(seed=2)
+    probs = [dict(phase=m.phase, cond=[1.0, rho], E=E, tol=1e-6, want_field=True)
+             for rho in (1e1, 1e2, 1e3, 1e4) for E in ((1.0, 0.0), (0.0, 1.0))]
+    leffs = {}
+    for prec in (0, 1):
+        bs = lshom.BatchSolver()
+        bs.prepare(probs, precision=prec)
+        bs.autotune(precision=prec, reps=1)
+        fields, leff, infos = bs.run(precision=prec)
+        for i, pr in enumerate(probs):
+            lam = ms.lam_field(pr["phase"], pr["cond"])
+            l0 = o.optimal_reference(lam)
+            e = fields[i].cpu().numpy()
+            assert infos[i]["status"] == 0, (prec, i)
+            true = o.true_residual(lam, l0, pr["E"], e)
+            assert true <= 1.5e-6, (prec, i, true)
+            assert abs(true - infos[i]["rel_res_true"]) <= 1e-3 * true, (prec, i)
+            np.testing.assert_allclose(leff[i][:2], o.leff(lam, e), rtol=1e-10, atol=1e-13)
+            if prec == 0 and i == 0:
+                ref = o.cg(lam, l0, pr["E"], n_iter=infos[i]["iterations"])
+                assert np.linalg.norm(e - ref["e"]) / np.linalg.norm(ref["e"]) < 1e-10
+        leffs[prec] = np.array([x[:2] for x in leff])
+        bs.close()
+    # diagonal entries are second order in the field error, off-diagonal ones first order
+    np.testing.assert_allclose(leffs[1], leffs[0], rtol=1e-5, atol=1e-6)
