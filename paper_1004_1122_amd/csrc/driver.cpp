@@ -879,7 +879,6 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   HIP_TRY(c, hipMemcpyAsync(init_dev, init.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice,
                             stream_of(g)));
   HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, g.nprob, stream_of(g)));
-  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
   HIP_TRY(c, launch_fill_zero(x64, nall, stream_of(g)));
   Bufs<float> b32{};
   if (mixed) {
@@ -921,7 +920,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     }
   }
   if (mixed) HIP_TRY(c, launch_mix_convert(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
-  HIP_TRY(c, sync_states(g));
+  // (run_blocks starts by reading the states back)
   int max_iter = 0;
   for (const DevState& s : init) max_iter = std::max(max_iter, s.max_iter);
   // with pass timing on, the blocks are queued eagerly (events around each launch)
