@@ -678,8 +678,31 @@ int ladder_rows(int nprob, int n_live) {
 // has a cache); with K == 0 it is queued eagerly.  In a batch, the launches
 // cover only the unfinished problems once enough have finished: a block then
 // starts by listing them on the device, and its graph is cached per row count.
+// Iterations for the next block: `per`, or, once the residuals of the live
+// problems have fallen over a block, the smallest per / 2^j that still covers
+// the iterations they need at the rate of that block (with a margin), so that
+// the last block of a solve does not queue many launches that would only
+// return at entry.  Falls back to `per` whenever the rate is not usable.
+int next_block_length(const Group& g, int per, const std::vector<double>& rr_prev,
+                      const std::vector<int>& it_prev) {
+  int need_max = 0;
+  for (int p = 0; p < g.nprob; ++p) {
+    const DevState& s = g.host_states[p];
+    if (s.done) continue;
+    const int di = s.iter_a - it_prev[p];
+    if (!(rr_prev[p] > 0.0) || !(s.rr_log > 0.0) || !(s.rr_log < rr_prev[p]) || di <= 0) return per;
+    const double rate = std::log(s.rr_log / rr_prev[p]) / di;  // log (r, r) per iteration, < 0
+    const double need = s.rr_log > s.tol2b2 ? std::log(s.tol2b2 / s.rr_log) / rate : 0.0;
+    if (!std::isfinite(need) || need > per) return per;
+    need_max = std::max(need_max, (int)std::ceil(1.25 * need) + 1);
+  }
+  int n = per;
+  while (n > 1 && n / 2 >= need_max) n /= 2;
+  return n;
+}
+
 template <typename F>
-lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqueue_block) {
+lshom_status run_blocks(Group& g, int key, int K, int per, bool adapt, F&& enqueue_block) {
   lshom_ctx* c = g.ctx;
   HIP_TRY(c, sync_states(g));
   // the tail of a batch (few unfinished problems) may run with its own
@@ -702,31 +725,36 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       if (g.has_tail[p]) apply_schedule(g, tail ? g.tail_sched[p] : main_sched[p], p);
   };
   int* live_dev = reinterpret_cast<int*>(g.ws + g.lay.off_live);
-  auto enqueue = [&]() -> hipError_t {
+  auto enqueue = [&](int n) -> hipError_t {
     if (g.live_rows > 0) {
       hipError_t e = launch_compact_live(dev_state(g), g.nprob, g.live_rows, live_dev, stream_of(g));
       if (e != hipSuccess) return e;
     }
-    return enqueue_block();
+    return enqueue_block(n);
   };
+  // graphs per (rows, block length): the group's cache, else owned here
+  std::map<std::pair<int, int>, hipGraphExec_t> owned;
+  struct DropOwned {
+    std::map<std::pair<int, int>, hipGraphExec_t>& m;
+    ~DropOwned() { drop_graphs(m); }
+  } drop_owned{owned};
   hipGraphExec_t ex = nullptr;
-  bool owned = false;
-  auto get_graph = [&]() -> lshom_status {
+  auto get_graph = [&](int n) -> lshom_status {
+    ex = nullptr;
     if (K <= 0) return LSHOM_OK;
     const int rows = g.live_rows > 0 ? g.live_rows : g.nprob;
-    auto gk = std::make_pair(key + 8 * rows, K);
-    if (g.graph_cache) {
-      auto it = g.graph_cache->find(gk);
-      if (it != g.graph_cache->end()) {
-        ex = it->second;
-        return LSHOM_OK;
-      }
+    auto gk = std::make_pair(key + 8 * rows, n);
+    auto& cache = g.graph_cache ? *g.graph_cache : owned;
+    auto it = cache.find(gk);
+    if (it != cache.end()) {
+      ex = it->second;
+      return LSHOM_OK;
     }
     {
       std::lock_guard<std::mutex> lock(setup_mutex());
       hipGraph_t gr = nullptr;
       HIP_TRY(c, hipStreamBeginCapture(stream_of(g), hipStreamCaptureModeThreadLocal));
-      hipError_t e = enqueue();
+      hipError_t e = enqueue(n);
       hipError_t e2 = hipStreamEndCapture(stream_of(g), &gr);
       if (e != hipSuccess || e2 != hipSuccess) {
         if (gr) (void)hipGraphDestroy(gr);
@@ -737,51 +765,62 @@ lshom_status run_blocks(Group& g, int key, int K, long long max_blocks, F&& enqu
       (void)hipGraphDestroy(gr);
       if (e3 != hipSuccess)
         return fail(c, LSHOM_ERR_HIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
-      if (g.graph_cache) g.graph_cache->emplace(gk, ex);
-      else owned = true;
+      cache.emplace(gk, ex);
     }
     return LSHOM_OK;
   };
-  lshom_status st = get_graph();
-  if (st != LSHOM_OK) return st;
-  // the device sets `done` at the latest after max_iter iterations; the
-  // block bound only guards against a state that stopped advancing
-  for (long long blocks = 0;; ++blocks) {
+  lshom_status st = LSHOM_OK;
+  std::vector<double> rr_prev(g.nprob, -1.0);
+  std::vector<int> it_prev(g.nprob, 0);
+  // the device sets `done` at the latest after max_iter iterations; every
+  // block advances an iteration or (mixed precision) a refresh of some live
+  // problem, so a block that advances neither means the state stopped
+  // advancing
+  for (;;) {
     if (all_done(g)) break;
-    if (blocks > max_blocks) {
-      st = fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
-      break;
-    }
     if (g.nprob > 1) {
       int n_live = 0;
       for (const DevState& s : g.host_states) n_live += s.done == 0;
       const int rows = ladder_rows(g.nprob, n_live);
       const int cur = g.live_rows > 0 ? g.live_rows : g.nprob;
       if (rows < cur) {
-        if (owned) (void)hipGraphExecDestroy(ex);
-        ex = nullptr;
-        owned = false;
         g.live_rows = rows;
         use_schedules_for(rows);
-        st = get_graph();
-        if (st != LSHOM_OK) return st;
       }
     }
-    long long before = 0;
-    for (const DevState& s : g.host_states) before += s.iter_a;
-    hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue();
+    const int n = adapt ? next_block_length(g, per, rr_prev, it_prev) : per;
+    // short final blocks are queued directly (a capture would cost more)
+    if (n == per || n >= 8) {
+      if ((st = get_graph(n)) != LSHOM_OK) return st;
+    } else {
+      ex = nullptr;
+    }
+    long long before = 0, moves_before = 0;
+    for (int p = 0; p < g.nprob; ++p) {
+      before += g.host_states[p].iter_a;
+      moves_before += g.host_states[p].iter_a + g.host_states[p].n_refresh;
+      rr_prev[p] = g.host_states[p].rr_log;
+      it_prev[p] = g.host_states[p].iter_a;
+    }
+    hipError_t e = ex ? hipGraphLaunch(ex, stream_of(g)) : enqueue(n);
     if (e == hipSuccess) e = sync_states(g);
+    long long after = 0, moves_after = 0;
     if (e == hipSuccess) {
-      long long after = 0;
-      for (const DevState& s : g.host_states) after += s.iter_a;
+      for (const DevState& s : g.host_states) {
+        after += s.iter_a;
+        moves_after += s.iter_a + s.n_refresh;
+      }
       e = harvest_timing(g, after - before);
     }
     if (e != hipSuccess) {
       st = fail(c, LSHOM_ERR_HIP, std::string("iteration block: ") + hipGetErrorString(e));
       break;
     }
+    if (moves_after == moves_before && !all_done(g)) {
+      st = fail(c, LSHOM_ERR_HIP, "device CG state stopped advancing");
+      break;
+    }
   }
-  if (owned) (void)hipGraphExecDestroy(ex);
   return st;
 }
 
@@ -928,24 +967,26 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   g.timer = tm.on ? &tm : nullptr;
   const int K = tm.on ? 0 : o.graph_block;
   const int per = o.graph_block > 0 ? o.graph_block : 8;
+  // block lengths follow the residual only when the residual is the test
+  const bool adapt = o.norm == LSHOM_NORM_RESIDUAL;
   tm.kinds.clear();
   pass_model_bytes(g, o.precision, tm.unit_bytes);
   lshom_status s;
   // the blocks take the buffers (and launch shapes) current when they are
   // queued: the tail of a batch may switch schedules
   if (ffth) {
-    s = run_blocks(g, 3 + eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+    s = run_blocks(g, 3 + eq_loop, K, per, adapt, [&](int n) -> hipError_t {
       const Bufs<double> f64 = get_bufs<double>(g);
-      for (int k = 0; k < per; ++k) {
+      for (int k = 0; k < n; ++k) {
         hipError_t e = enq_ffth_iteration(g, f64, GATE_ACTIVE);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     });
   } else if (!mixed) {
-    s = run_blocks(g, 2 * eq_loop, K, (long long)max_iter / per + 4, [&]() -> hipError_t {
+    s = run_blocks(g, 2 * eq_loop, K, per, adapt, [&](int n) -> hipError_t {
       const Bufs<double> f64 = get_bufs<double>(g);
-      for (int k = 0; k < per; ++k) {
+      for (int k = 0; k < n; ++k) {
         hipError_t e = enq_cg_iteration<double>(g, f64, GATE_ACTIVE);
         if (e != hipSuccess) return e;
       }
@@ -953,10 +994,10 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     });
   } else {
     // a refresh may cut a block short: at least one iteration per block is certain
-    s = run_blocks(g, 1, K, (long long)max_iter + 4, [&]() -> hipError_t {
+    s = run_blocks(g, 1, K, per, adapt, [&](int n) -> hipError_t {
       const Bufs<double> f64 = get_bufs<double>(g);
       const Bufs<float> f32 = get_bufs<float>(g);
-      for (int k = 0; k < per; ++k) {
+      for (int k = 0; k < n; ++k) {
         hipError_t e = enq_cg_iteration<float>(g, f32, GATE_NO_REFRESH);
         if (e != hipSuccess) return e;
       }
@@ -1056,8 +1097,8 @@ lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& 
   const int per = o.graph_block > 0 ? o.graph_block : 8;
   tm.kinds.clear();
   pass_model_bytes(g, LSHOM_PRECISION_FP64, tm.unit_bytes);
-  lshom_status s = run_blocks(g, 5, K, (long long)o.max_iter / per + 4, [&]() -> hipError_t {
-    for (int k = 0; k < per; ++k) {
+  lshom_status s = run_blocks(g, 5, K, per, true, [&](int n) -> hipError_t {
+    for (int k = 0; k < n; ++k) {
       hipError_t e;
       if ((e = enq_apply_A_real(g, b, p, ap, GATE_ACTIVE)) != hipSuccess) return e;
       if ((e = enq_apply_AT_real(g, b, ps, atp, GATE_ACTIVE)) != hipSuccess) return e;
@@ -1167,9 +1208,9 @@ lshom_status solve_pipecg(Group& g, const DevState& init, const lshom_solve_opts
   const int per = o.graph_block > 0 ? o.graph_block : 8;
   tm.kinds.clear();
   pass_model_bytes(g, LSHOM_PRECISION_FP64, tm.unit_bytes);
-  lshom_status st = run_blocks(g, 6, K, (long long)o.max_iter / per + 4, [&]() -> hipError_t {
+  lshom_status st = run_blocks(g, 6, K, per, true, [&](int n) -> hipError_t {
     const Bufs<double> f64 = get_bufs<double>(g);
-    for (int k = 0; k < per; ++k) {
+    for (int k = 0; k < n; ++k) {
       hipError_t e = enq_pipe_iteration(g, f64, w, s, z, GATE_ACTIVE);
       if (e != hipSuccess) return e;
     }
