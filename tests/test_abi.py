@@ -75,6 +75,23 @@ def test_null_context_is_rejected(lib):
     size = ctypes.c_size_t()
     assert lib.lshom_workspace_size(None, 0, ctypes.byref(size)) == -1
     assert lshom.load().lshom_last_error(None) == b""
+    # the entry points of tensor phases, cells, general references and sizing by options
+    eye = (ctypes.c_double * 4)(1.0, 0.0, 0.0, 1.0)
+    assert lib.lshom_set_reference_tensor(None, eye) == -1
+    assert lib.lshom_set_cell(None, eye) == -1
+    N = (ctypes.c_int64 * 2)(9, 9)
+    assert lib.lshom_set_microstructure_tensor(None, 2, N, None, 1, eye) == -1
+    o = lshom.lshom_default_opts()
+    assert lib.lshom_workspace_size_for(None, ctypes.byref(o), ctypes.byref(size)) == -1
+
+
+def test_method_constants_match_header():
+    import re
+    text = open(lshom.HEADER_PATH).read()
+    for name in ("METHOD_CG", "METHOD_FFTH", "METHOD_BICG", "METHOD_PIPECG", "NORM_RESIDUAL",
+                 "NORM_EQUILIBRIUM", "PRECISION_FP64", "PRECISION_MIXED"):
+        m = re.search(r"#define LSHOM_%s (-?\d+)" % name, text)
+        assert m and int(m.group(1)) == getattr(lshom, name), name
 
 
 def test_create_without_gpu_fails_cleanly(lib):
