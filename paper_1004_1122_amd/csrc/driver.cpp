@@ -679,10 +679,13 @@ int ladder_rows(int nprob, int n_live) {
 // cover only the unfinished problems once enough have finished: a block then
 // starts by listing them on the device, and its graph is cached per row count.
 // Iterations for the next block: `per`, or, once the residuals of the live
-// problems have fallen over a block, the smallest per / 2^j that still covers
-// the iterations they need at the rate of that block (with a margin), so that
-// the last block of a solve does not queue many launches that would only
-// return at entry.  Falls back to `per` whenever the rate is not usable.
+// problems have fallen over a block, just enough to cover the iterations they
+// need at the rate of that block plus one, so that the last block of a solve
+// does not queue many launches that would only return at entry (an estimate
+// that falls short costs one more block; CG usually speeds up, so it rarely
+// does).  Blocks of 8 or more iterations stay per / 2^j (one graph each);
+// shorter ones are queued directly.  Falls back to `per` whenever the rate is
+// not usable.
 int next_block_length(const Group& g, int per, const std::vector<double>& rr_prev,
                       const std::vector<int>& it_prev) {
   int need_max = 0;
@@ -694,10 +697,12 @@ int next_block_length(const Group& g, int per, const std::vector<double>& rr_pre
     const double rate = std::log(s.rr_log / rr_prev[p]) / di;  // log (r, r) per iteration, < 0
     const double need = s.rr_log > s.tol2b2 ? std::log(s.tol2b2 / s.rr_log) / rate : 0.0;
     if (!std::isfinite(need) || need > per) return per;
-    need_max = std::max(need_max, (int)std::ceil(1.25 * need) + 1);
+    need_max = std::max(need_max, (int)std::ceil(need) + 1);
   }
+  if (need_max >= per) return per;
+  if (need_max < 8) return std::max(need_max, 1);
   int n = per;
-  while (n > 1 && n / 2 >= need_max) n /= 2;
+  while (n / 2 >= need_max) n /= 2;
   return n;
 }
 

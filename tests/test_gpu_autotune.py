@@ -145,3 +145,27 @@ def test_pass_timing_inside_solves(precision):
     for k, (ms_, by, n) in t.items():
         assert ms_ > 0 and n >= max(i["iterations"] for i in inf1)
         assert by == pytest.approx(iters * unit[k], rel=1e-12), k
+
+
+def test_last_block_covers_the_remaining_iterations():
+    """Once the residual has fallen over a block, the next block is sized to
+    the iterations still needed at that rate: a single solve launches its
+    passes for little more than its own iteration count (counted with pass
+    timing, where blocks are queued directly), with the same result as fixed
+    blocks of 16 in a graph."""
+    from paper_1004_1122_amd import lshom
+    m = ms.grf_two_phase(81, 0.1, 0.4, 10.0, seed=520)
+    s = lshom.Solver(m.phase, [1.0, 10.0])
+    e_graph, _, i_graph = s.solve((1.0, 0.0), tol=1e-6)
+    s.set_pass_timing(True)
+    e_eager, _, i_eager = s.solve((1.0, 0.0), tol=1e-6)
+    t = s.pass_timing()
+    s.set_pass_timing(False)
+    assert i_graph["iterations"] == i_eager["iterations"] and torch.equal(e_graph, e_eager)
+    n_it = i_eager["iterations"]
+    # 18 iterations here (the oracle's count): the first block of 16 has no
+    # rate yet, the second is sized to what the residual still needs (about
+    # 2 at the rate of the first block) instead of another 16
+    assert 16 < n_it <= 20
+    for k, (_, _, n) in t.items():
+        assert n_it <= n <= n_it + 4, (k, n, n_it)
