@@ -83,6 +83,7 @@ __all__ = [
     "eta_e_from_residual",
     "project_gradient",
     "optimal_reference",
+    "mean_reference",
     "reference_omega",
     "voigt_reuss",
     "cg_rate_bound_iterations",
@@ -355,6 +356,18 @@ def optimal_reference(lam) -> float:
     eigenvalues of L over the cell."""
     lo, hi = _medium(lam).eigen_range()
     return 0.5 * (lo + hi)
+
+
+def mean_reference(lam):
+    """``L0 = <L>``, the cell average of the conductivity (a matrix; a number
+    for isotropic phases).  In the spectral coordinate the diagonal of the
+    operator K*LK (K: c -> i khat c) is ``khat . <L> . khat``, so this
+    reference is the Fourier-space Jacobi preconditioner of CG in the energy
+    product of L0 (Sec. 2.1, Eq. (7) with a general L0)."""
+    med = _medium(lam)
+    if not med.tensor:
+        return float(np.mean(med.lam))
+    return med.lam.reshape(med.d, med.d, -1).mean(axis=2)
 
 
 def reference_omega(omega: float, rho: float) -> float:

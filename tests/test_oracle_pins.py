@@ -722,3 +722,31 @@ def test_pipelined_cg_iterates_equal_cg(l0_kind):
     full_b = o.pipelined_cg(lam, l0, E, tol=1e-8)
     assert abs(full_a["iterations"] - full_b["iterations"]) <= 1
     assert np.linalg.norm(full_a["e"] - full_b["e"]) / np.linalg.norm(full_a["e"]) < 1e-7
+
+
+def test_mean_reference_is_the_fourier_jacobi_preconditioner():
+    """<L> gives the diagonal of the spectral operator: for a single mode c
+    at wave vector k, (K*LK c, c) = khat . <L> . khat |c|^2 (a plane wave
+    sees the cell average of L); and CG iterates do not depend on the scale
+    of L0, so <L> and any multiple give the same solve."""
+    shape = (9, 11)
+    L = _rand_tensor_field(shape, 95) + np.eye(2).reshape(2, 2, 1, 1)
+    med = o.Medium(L)
+    M = o.mean_reference(med)
+    np.testing.assert_allclose(M, L.mean(axis=(2, 3)), rtol=1e-14)
+    # a gradient plane wave u = grad cos(2 pi k.x): (u, L u) / (u, u) = khat . <L> . khat up to the
+    # cos^2 weighting, exactly <L> for L constant along the wave; check against the dense operator
+    ks = o.grid_frequencies(shape)
+    for kk in ((1, 0), (0, 2), (3, 4)):
+        phase = 2 * np.pi * (kk[0] * np.arange(9)[:, None] / 9 + kk[1] * np.arange(11)[None, :] / 11)
+        u = np.stack([kk[0] / 9 * np.exp(1j * phase), kk[1] / 11 * np.exp(1j * phase)])
+        Lu = np.einsum("ab...,b...->a...", L, u)
+        quad = np.vdot(u, Lu) / np.vdot(u, u)
+        khat = np.array([kk[0] / 9, kk[1] / 11]) / np.hypot(kk[0] / 9, kk[1] / 11)
+        assert abs(quad - khat @ M @ khat) < 1e-12 * abs(quad)
+    E = (1.0, 0.4)
+    a = o.cg(med, M, E, n_iter=6)
+    b = o.cg(med, 7.5 * M, E, n_iter=6)
+    assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(a["e"]) < 1e-12
+    # isotropic phases: a number
+    assert o.mean_reference(np.array([[1.0, 3.0], [5.0, 7.0]])) == 4.0
