@@ -181,6 +181,18 @@ lshom_status lshom_set_reference(lshom_ctx* ctx, double l0);
  */
 lshom_status lshom_set_reference_tensor(lshom_ctx* ctx, const double* L0_host);
 
+/*
+ * L0 = <L>, the cell average of the conductivity (phase counts of the
+ * phase image times the phase tables), set as by lshom_set_reference_tensor
+ * (a number for isotropic phases).  In the spectral coordinate of the
+ * solver k_hat . <L> . k_hat is the diagonal of the operator, so this
+ * reference is the Fourier-space Jacobi preconditioner of CG in the energy
+ * product of L0 (Sec. 2.1, Eq. (7) with a general L0); CG does not depend on
+ * the scale of L0, only on its shape.  Needs an attached workspace (it holds
+ * the counts); WORKSPACE otherwise.
+ */
+lshom_status lshom_set_reference_mean(lshom_ctx* ctx);
+
 /* Bytes of device workspace the current problem needs (both precisions). */
 lshom_status lshom_workspace_size(const lshom_ctx* ctx, int precision, size_t* bytes);
 

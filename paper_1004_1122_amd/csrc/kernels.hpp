@@ -382,6 +382,8 @@ hipError_t launch_state_copy(DevState* st, const DevState* src, int nprob, hipSt
 hipError_t launch_compact_live(const DevState* st, int nprob, int rows, int* live, hipStream_t s);
 template <typename T> hipError_t launch_fill_zero(cx<T>* p, long long n, hipStream_t s);
 hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipStream_t s);
+// counts[0..256): nodes of each phase index (counts zero on entry)
+hipError_t launch_phase_histogram(const uint8_t* ph, long long n, unsigned* counts, hipStream_t s);
 
 template <typename T> long long row_blocks(const RowArgs<T>& a);
 template <typename T> long long col_blocks(const ColArgs<T>& a);

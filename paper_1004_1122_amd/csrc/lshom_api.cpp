@@ -389,6 +389,42 @@ lshom_status lshom_set_reference(lshom_ctx* c, double l0) {
   return LSHOM_OK;
 }
 
+lshom_status lshom_set_reference_mean(lshom_ctx* c) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
+  if (!c->ws_ready) return fail(c, LSHOM_ERR_WORKSPACE, "attach a workspace first (it holds the phase counts)");
+  Group& gr = c->g;
+  DeviceGuard g(c->device);
+  HIP_TRY(c, order_after_user(c));
+  // the partial-sum area is free between solves
+  unsigned* counts = reinterpret_cast<unsigned*>(gr.ws + gr.lay.off_partials);
+  std::vector<unsigned> h(256, 0u);
+  HIP_TRY(c, hipMemsetAsync(counts, 0, 256 * sizeof(unsigned), c->stream));
+  HIP_TRY(c, launch_phase_histogram(gr.phase, gr.nvox, counts, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(h.data(), counts, 256 * sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int d = gr.d;
+  const int ncomp = gr.tensor ? d * (d + 1) / 2 : 1;
+  double M[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < gr.n_phase_ids; ++q) {
+    const double f = (double)h[q] / (double)gr.nvox;
+    if (f == 0.0) continue;
+    if (!gr.tensor) {
+      for (int i = 0; i < d; ++i) M[i * d + i] += f * c->cond[q];
+      continue;
+    }
+    int k = 0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i; j < d; ++j, ++k) {
+        const double v = f * c->cond[(size_t)q * ncomp + k];
+        M[i * d + j] += v;
+        if (j != i) M[j * d + i] += v;
+      }
+  }
+  if (!gr.tensor) return lshom_set_reference(c, M[0]);
+  return lshom_set_reference_tensor(c, M);
+}
+
 lshom_status lshom_set_reference_tensor(lshom_ctx* c, const double* L0) {
   if (!c || !L0) return LSHOM_ERR_INVALID_ARG;
   if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");

@@ -1389,6 +1389,23 @@ hipError_t launch_max_phase(const uint8_t* ph, long long n, unsigned* out, hipSt
   return hipGetLastError();
 }
 
+// Node count of every phase index (256 bins): block counts in LDS, then one
+// global atomic add per bin and block.  counts must be zero on entry.
+__global__ __launch_bounds__(256) void phase_histogram_kernel(const uint8_t* ph, long long n, unsigned* counts) {
+  __shared__ unsigned bins[256];
+  bins[threadIdx.x] = 0u;
+  __syncthreads();
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) atomicAdd(&bins[ph[i]], 1u);
+  __syncthreads();
+  if (bins[threadIdx.x]) atomicAdd(&counts[threadIdx.x], bins[threadIdx.x]);
+}
+
+hipError_t launch_phase_histogram(const uint8_t* ph, long long n, unsigned* counts, hipStream_t s) {
+  hipLaunchKernelGGL(phase_histogram_kernel, dim3((unsigned)update_blocks(n)), dim3(256), 0, s, ph, n, counts);
+  return hipGetLastError();
+}
+
 // One kernel symbol per (precision, block size, radix set, pass mode): the
 // compiler specialises each mode, and profiles attribute time per pass.
 template <typename T, int RS, int MODE>

@@ -174,6 +174,7 @@ def load(path: str = LIB_PATH):
         "lshom_set_microstructure_tensor": (c_int32, [P, c_int, POINTER(c_int64), P, c_int, POINTER(c_double)]),
         "lshom_set_reference": (c_int32, [P, c_double]),
         "lshom_set_reference_tensor": (c_int32, [P, POINTER(c_double)]),
+        "lshom_set_reference_mean": (c_int32, [P]),
         "lshom_set_cell": (c_int32, [P, POINTER(c_double)]),
         "lshom_workspace_size": (c_int32, [P, c_int, POINTER(c_size_t)]),
         "lshom_workspace_size_for": (c_int32, [P, POINTER(lshom_solve_opts), POINTER(c_size_t)]),
@@ -363,9 +364,14 @@ class Solver:
             pass
 
     def set_reference(self, l0):
-        """Reference medium: a number l0 (L0 = l0 I) or a symmetric positive
-        definite d x d matrix L0."""
-        if np.ndim(l0) == 0:
+        """Reference medium: a number l0 (L0 = l0 I), a symmetric positive
+        definite d x d matrix L0, or "mean" (L0 = <L>, the Fourier-space
+        Jacobi preconditioner)."""
+        if isinstance(l0, str):
+            if l0 != "mean":
+                raise ValueError('the only named reference is "mean"')
+            _check(self.ctx, self.lib.lshom_set_reference_mean(self.ctx))
+        elif np.ndim(l0) == 0:
             _check(self.ctx, self.lib.lshom_set_reference(self.ctx, float(l0)))
         else:
             m = np.ascontiguousarray(l0, dtype=np.float64)

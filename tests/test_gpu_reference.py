@@ -220,3 +220,31 @@ def test_errors():
     s.set_reference(np.diag([3.0, 3.0]))
     _, _, info = s.solve((1.0, 0.0), tol=1e-9)
     assert info["status"] == 0 and info["iterations"] == 0
+
+
+def test_mean_reference_preconditions():
+    """L0 = <L> (the Fourier-space Jacobi preconditioner, from the phase counts
+    on the device) takes the anisotropy of L = s(x) M out of the spectrum; for
+    isotropic phases it is a number and CG does not see its scale."""
+    phase = ms.grf_two_phase(45, 0.15, 0.4, 5.0, seed=9).phase
+    M = np.array([[1.0, 0.0], [0.0, 60.0]])
+    tens = np.array([M, 5.0 * M])
+    E = (1.0, 1.0)
+    s = _solver(phase, tens)
+    e_iso, _, i_iso = s.solve(E, tol=1e-10)
+    s.set_reference("mean")
+    e_m, _, i_m = s.solve(E, tol=1e-10)
+    med = _medium(phase, tens, None)
+    ref = o.cg(med, o.mean_reference(med), E, tol=1e-10)
+    assert abs(i_m["iterations"] - ref["iterations"]) <= 1
+    assert 4 * i_m["iterations"] < i_iso["iterations"]
+    assert _rel(e_m.cpu().numpy(), e_iso.cpu().numpy()) < 1e-8
+    ref_n = o.cg(med, o.mean_reference(med), E, n_iter=i_m["iterations"])
+    assert _rel(e_m.cpu().numpy(), ref_n["e"]) < 1e-10
+    s2 = _solver(phase, [1.0, 5.0])
+    _, _, a = s2.solve(E, tol=1e-10)
+    s2.set_reference("mean")
+    _, _, b = s2.solve(E, tol=1e-10)
+    assert abs(a["iterations"] - b["iterations"]) <= 1
+    with pytest.raises(ValueError):
+        s2.set_reference("voigt")
