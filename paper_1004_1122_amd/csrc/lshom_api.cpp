@@ -652,6 +652,8 @@ lshom_status lshom_time_passes(lshom_ctx* c, int precision, int reps, double* ms
 // Many problems: one group (same launches) per distinct grid
 // ---------------------------------------------------------------------------
 
+}  // extern "C"
+
 namespace {
 
 struct BatchPlan {
@@ -809,6 +811,8 @@ std::string arch_name(int device) {
 }
 
 }  // namespace
+
+extern "C" {
 
 lshom_status lshom_batch_workspace_size(lshom_ctx* c, int32_t n, const lshom_problem* probs,
                                         int precision, size_t* bytes) {
