@@ -164,27 +164,32 @@ __device__ __forceinline__ V pick3(const V (&arr)[kMaxDim], int c) {
   return c == 0 ? arr[0] : (c == 1 ? arr[1] : arr[2]);
 }
 
+// The dispatcher deals the blocks of a launch to the 8 XCDs (each with its own
+// L2) in linear order, one each in turn.  Neighbouring blocks of a pass read
+// the two halves (or quarters) of the same cache lines, so the linear id is
+// re-mapped to give each XCD one contiguous run of (problem, block) pairs:
+// the shared lines are then fetched once into one L2.  A bijection of the
+// grid: XCD x owns q + (x < rem) consecutive ids.
+__device__ __forceinline__ void xcd_order(unsigned& bx, unsigned& by) {
+  const unsigned gx = gridDim.x, total = gx * gridDim.y;
+  const unsigned lin = blockIdx.y * gx + blockIdx.x;
+  const unsigned xcd = lin & 7u, slot = lin >> 3;
+  const unsigned q = total >> 3, rem = total & 7u;
+  const unsigned lin2 = xcd * q + (xcd < rem ? xcd : rem) + slot;
+  by = lin2 / gx;
+  bx = lin2 - by * gx;
+}
+
 // ---------------------------------------------------------------------------
 // Row pass
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
-  // The dispatcher deals blocks to the 8 XCDs (each with its own L2) in
-  // linear order, one each in turn.  Neighbouring row blocks share the cache
-  // lines at their edges in the transposed layout, so the linear id is
-  // re-mapped to give each XCD one contiguous run of (problem, row block)
-  // pairs: the shared lines are then fetched once into one L2.
+  // neighbouring row blocks share the cache lines at their edges in the
+  // transposed layout: XCD-aware order
   unsigned bx, by;
-  {
-    const unsigned gx = gridDim.x, total = gx * gridDim.y;
-    const unsigned lin = blockIdx.y * gx + blockIdx.x;
-    const unsigned xcd = lin & 7u, slot = lin >> 3;
-    const unsigned q = total >> 3, rem = total & 7u;
-    const unsigned lin2 = xcd * q + (xcd < rem ? xcd : rem) + slot;
-    by = lin2 / gx;
-    bx = lin2 - by * gx;
-  }
+  xcd_order(bx, by);
   const int pb = a.bt.live ? a.bt.live[by] : (int)by;
   DevState* st = a.st + pb;
   // the flags a row pass gates on are written only by earlier launches; the
@@ -501,7 +506,13 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
 
 template <typename T, int NT, int RS, int MODE>
 __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
-  const int pb = batch_prob(a.bt);
+  // in the natural layout a tile reads C consecutive elements per transform
+  // index; below one 128-byte line per segment, neighbouring tiles read the
+  // halves or quarters of the same lines: XCD-aware order then.  (Tiles of the
+  // transposed layout read whole columns and keep the dispatch order.)
+  unsigned bx = blockIdx.x, by = blockIdx.y;
+  if (a.sii == 1 && a.tile * (int)sizeof(cx<T>) < 128) xcd_order(bx, by);
+  const int pb = a.bt.live ? a.bt.live[by] : (int)by;
   DevState* st = a.st + pb;
   // the direction step of the inverse pass reads its gate with the (r, r)
   // sums (block 0 of the same launch may set the flags); the other modes
@@ -522,8 +533,8 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw + align16((size_t)nseq * ss * sizeof(cx<T>)));
   copy_batched<cx<T>, NT>(tw, a.tw, twiddle_entries(L));
 
-  const long long o = blockIdx.x / a.tiles_per_outer;
-  const long long i0 = (long long)(blockIdx.x - o * a.tiles_per_outer) * C;
+  const long long o = bx / a.tiles_per_outer;
+  const long long i0 = (long long)(bx - o * a.tiles_per_outer) * C;
   const long long rem = a.inner - i0;
   const int width = rem < C ? (int)rem : C;
   // every array of problem pb starts vstride elements after that of pb - 1
@@ -545,8 +556,8 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
   if constexpr (kInv) {
     double beta = 0.0;
     if (pipe) {
-      if (!pipe_direction<NT>(st, parts, a.inv_n, a.gate)) return;
-    } else if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq)) {
+      if (!pipe_direction<NT>(st, parts, a.inv_n, a.gate, bx == 0)) return;
+    } else if (a.cg_step && !cg_direction<NT>(st, parts, a.inv_n, &beta, a.gate, a.eq, bx == 0)) {
       return;
     }
     const T tb = (T)beta;
@@ -758,14 +769,14 @@ __global__ __launch_bounds__(NT) void col_kernel(ColArgs<T> a) {
       double v[2] = {acc, acc_eq};
       (void)block_sums_gated<NT, 2>(v, 0);
       if (tid == 0) {
-        parts.region(a.dot_region)[blockIdx.x] = v[0];
-        parts.region(a.eq_region)[blockIdx.x] = v[1];
+        parts.region(a.dot_region)[bx] = v[0];
+        parts.region(a.eq_region)[bx] = v[1];
       }
     } else {
-      store_partial<NT>(acc, parts.region(a.dot_region) + blockIdx.x);
+      store_partial<NT>(acc, parts.region(a.dot_region) + bx);
     }
-    if (a.dot_region == PART_RR0 && blockIdx.x == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
-    if (a.dot_region == PART_PQ && blockIdx.x == 0 && tid == 0) st->nparts_pq = (int)gridDim.x;
+    if (a.dot_region == PART_RR0 && bx == 0 && tid == 0) st->nparts[0] = (int)gridDim.x;
+    if (a.dot_region == PART_PQ && bx == 0 && tid == 0) st->nparts_pq = (int)gridDim.x;
   }
   }
 }

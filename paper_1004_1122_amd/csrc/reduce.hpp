@@ -168,14 +168,14 @@ __device__ inline bool equilibrium_test(DevState* st, int m, double rr, double e
 // (r_k, r_k), iteration limit, and beta = (r_k, r_k) / (r_{k-1}, r_{k-1}).
 // Mixed precision requests an FP64 refresh instead of stopping.  Returns
 // false when the block must not compute the iteration.  Identical decision
-// in every block; block 0 records it.
+// in every block; the one block with lead_block set records it.
 // The entry gate is read with the sums: a block it sends back returns false
 // without touching the state.
 // With eq (plain FP64 CG only) the equilibrium sums of the same producer are
 // summed too and the test follows the state's norm.
 template <int NT>
 __device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, double* beta_out, int gate,
-                             int eq) {
+                             int eq, bool lead_block) {
   const int skip0 = gate_flags(st, gate);
   const int k = st->iter_a;
   double v[3] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
@@ -184,7 +184,7 @@ __device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, 
   if (block_sums_gated<NT, 3>(v, skip0)) return false;
   const double rr = v[0] * inv_n;
   const double rr_prev = v[1] * inv_n;
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool lead = lead_block && threadIdx.x == 0;
   bool stop = false;
   if (st->refresh_every > 0) {
     const int since = k - st->k_ref;
@@ -227,10 +227,11 @@ __device__ bool cg_direction(DevState* st, const Partials& parts, double inv_n, 
 // alpha = gamma_k / (delta_k - beta gamma_k / alpha_{k-1}) (beta = 0,
 // alpha = gamma_k / delta_k at k = 0).  gamma_{k-1} comes from the other
 // (r, r) region and alpha_{k-1} from the state slot of parity k - 1, so no
-// block reads a value block 0 writes in this launch.  Block 0 records alpha
-// and beta at parity k for the later passes of the iteration.
+// block reads a value the lead block writes in this launch.  The lead block
+// (lead_block) records alpha and beta at parity k for the later passes of
+// the iteration.
 template <int NT>
-__device__ bool pipe_direction(DevState* st, const Partials& parts, double inv_n, int gate) {
+__device__ bool pipe_direction(DevState* st, const Partials& parts, double inv_n, int gate, bool lead_block) {
   const int skip0 = gate_flags(st, gate);
   const int k = st->iter_a;
   double v[3] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
@@ -240,7 +241,7 @@ __device__ bool pipe_direction(DevState* st, const Partials& parts, double inv_n
   const double gamma = v[0] * inv_n;
   const double delta = v[1] * inv_n;
   const double gamma_prev = v[2] * inv_n;
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const bool lead = lead_block && threadIdx.x == 0;
   double beta = 0.0, alpha = 0.0;
   bool stop = false;
   if (!isfinite(gamma)) {
