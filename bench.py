@@ -53,7 +53,8 @@ def measured_traffic(pass_name, form):
     if it was taken on the current kernel sources (else None)."""
     from paper_1004_1122_amd.profiling import kernel_source_hash
     src = kernel_source_hash()
-    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*.md"))):
+    # the summaries of this workload's grid (others cover other grids)
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*_729.md"))):
         with open(path) as f:
             for line in f:
                 m = re.match(r"^traffic-json:\s*(\{.*\})\s*$", line)
