@@ -221,17 +221,19 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
   const int jobs = nseq * NR;
   const int step = NR / Ns;  // n / (Ns R)
   cx<T> v[JM][R];
+  int out_at[JM];  // store offset of each job, kept across the barrier
 #pragma unroll
   for (int q = 0; q < JM; ++q) {
     const int job = tid + q * NT;
+    out_at[q] = 0;
     if (job < jobs) {
       const int s = (int)fdiv((uint32_t)job, fnr);
       const int j = job - s * NR;
       const cx<T>* b = buf + s * ss + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = b[r * NR];
+      const int k = Ns > 1 ? j - (int)fdiv((uint32_t)j, fns) * Ns : 0;
       if (Ns > 1) {
-        const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> w = twiddle(tw, r * k * step);
@@ -240,17 +242,14 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int nseq, int ss, int n, i
         }
       }
       dft<T, R, S>(v[q]);
+      out_at[q] = s * ss + (j - k) * R + k;
     }
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < JM; ++q) {
-    const int job = tid + q * NT;
-    if (job < jobs) {
-      const int s = (int)fdiv((uint32_t)job, fnr);
-      const int j = job - s * NR;
-      const int k = j - (int)fdiv((uint32_t)j, fns) * Ns;
-      cx<T>* b = buf + s * ss + (j - k) * R + k;
+    if (tid + q * NT < jobs) {
+      cx<T>* b = buf + out_at[q];
 #pragma unroll
       for (int r = 0; r < R; ++r) b[r * Ns] = v[q][r];
     }
