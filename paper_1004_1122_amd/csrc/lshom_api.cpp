@@ -231,6 +231,21 @@ lshom_status lshom_check_problem(int d, const int64_t* N, int n_phases, const do
     if (N[a] > 4096 || !fft_size_ok(N[a])) return LSHOM_ERR_UNSUPPORTED;
   }
   if (n_phases < 1 || n_phases > kMaxPhases || !cond) return LSHOM_ERR_INVALID_ARG;
+  {
+    // the same limits the device set-up applies: index range, and the LDS
+    // footprint of the default pass shapes of both precisions
+    long long nvox = 1;
+    FftPlan plans[3];
+    for (int a = 0; a < d; ++a) {
+      nvox *= N[a];
+      plans[a] = default_plan((int)N[a]);
+    }
+    if (nvox >= (1ll << 31)) return LSHOM_ERR_UNSUPPORTED;
+    for (int es : {(int)sizeof(cx<double>), (int)sizeof(cx<float>)}) {
+      const PassShape sh = default_shape(d, N, plans, es, kLdsBudget, kMinBlocks, d == 2, n_phases, true);
+      if (!shape_fits(d, N, plans, sh, es, kLdsBudget, n_phases)) return LSHOM_ERR_UNSUPPORTED;
+    }
+  }
   for (int i = 0; i < n_phases; ++i)
     if (!std::isfinite(cond[i]) || !(cond[i] > 0.0)) return LSHOM_ERR_INVALID_ARG;
   if (!std::isfinite(l0) || l0 < 0.0) return LSHOM_ERR_INVALID_ARG;

@@ -49,6 +49,16 @@ def test_default_opts():
     (2, (19, 63), [1.0], 1.0, None, 1e-6, -7),                # prime factor 19
     (2, (255, 39), [1.0], 1.0, None, 1e-6, 0),                # prime factors 17 and 13
     (2, (8192, 3), [1.0], 1.0, None, 1e-6, -7),               # too long
+    # the LDS footprint of the default pass shapes (both precisions) bounds
+    # the axis lengths below 4096: 1331 in 2-D, 975 in 3-D
+    (2, (729, 729), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (2, (1331, 1331), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (2, (1600, 1600), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (2, (4096, 9), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (3, (243, 243, 243), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (3, (975, 975, 975), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (3, (1024, 1024, 1024), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (3, (1331, 1331, 1331), [1.0, 10.0], 0.0, None, 1e-6, -7),  # 2^31 or more nodes
     (2, (9, 9), [1.0, 0.0], 1.0, None, 1e-6, -1),             # cond <= 0
     (2, (9, 9), [1.0, math.inf], 1.0, None, 1e-6, -1),        # cond not finite
     (2, (9, 9), [1.0, math.nan], 1.0, None, 1e-6, -1),
