@@ -355,3 +355,23 @@ def test_solver_reuse_across_load_cases(precision):
         E = (1.0, 0.0) if b == 0 else (0.0, 1.0)
         _, l, _ = lshom.Solver(m.phase, m.cond).solve(E, tol=1e-8, precision=precision)
         assert np.array_equal(t[:, b], l)
+
+
+@pytest.mark.parametrize("shape", [(1331, 1331), (1600, 1600), (975, 9, 9), (1024, 9, 9)],
+                         ids=["1331^2", "1600^2", "975x9x9", "1024x9x9"])
+def test_set_up_agrees_with_host_check(shape):
+    """The device set-up accepts exactly the grids the host-only check accepts
+    (the LDS fit of the pass kernels bounds the axis lengths)."""
+    from paper_1004_1122_amd import lshom
+    want = lshom.lshom_check_problem(len(shape), shape, [1.0, 10.0])
+    phase = np.zeros(shape, np.uint8)
+    phase.flat[::7] = 1
+    if want == 0:
+        s = lshom.Solver(phase, [1.0, 10.0])
+        e, _, info = s.solve((1.0,) + (0.0,) * (len(shape) - 1), tol=1e-3)
+        assert info["status"] == 0 and bool(torch.isfinite(e).all())
+    else:
+        assert want == lshom.LSHOM_ERR_UNSUPPORTED
+        with pytest.raises(lshom.LshomError) as ex:
+            lshom.Solver(phase, [1.0, 10.0])
+        assert ex.value.status == lshom.LSHOM_ERR_UNSUPPORTED
