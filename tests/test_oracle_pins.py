@@ -750,3 +750,141 @@ def test_mean_reference_is_the_fourier_jacobi_preconditioner():
     assert np.linalg.norm(a["e"] - b["e"]) / np.linalg.norm(a["e"]) < 1e-12
     # isotropic phases: a number
     assert o.mean_reference(np.array([[1.0, 3.0], [5.0, 7.0]])) == 4.0
+
+
+# ---------------------------------------------------------------------------
+# Helpers of the oracle that the solvers above do not exercise: the Green
+# operator blocks, the residual norm, the reference of Eq. (20) and the CG
+# iteration bound of Eq. (23)
+# ---------------------------------------------------------------------------
+
+def test_green_hat_by_hand():
+    """Sec. 2.1, Eq. (7): Gamma0_hat(k) = k (x) k / (k . L0 . k), zero at k = 0.
+    Entries at a few frequencies worked out by hand (array index j holds the
+    frequency j, or j - N past N / 2)."""
+    g = o.green_hat((5, 7), 3.0)
+    assert g.shape == (2, 2, 5, 7)
+    assert np.all(g[:, :, 0, 0] == 0.0)
+    # k = (1, 2): [[1, 2], [2, 4]] / (3 * 5)
+    np.testing.assert_allclose(g[:, :, 1, 2], np.array([[1.0, 2.0], [2.0, 4.0]]) / 15.0, rtol=1e-15)
+    # index (4, 5) is k = (-1, -2): the same block (even in k)
+    np.testing.assert_allclose(g[:, :, 4, 5], g[:, :, 1, 2], rtol=1e-15)
+    # k = (2, -3) at index (2, 4): [[4, -6], [-6, 9]] / (3 * 13)
+    np.testing.assert_allclose(g[:, :, 2, 4], np.array([[4.0, -6.0], [-6.0, 9.0]]) / 39.0, rtol=1e-15)
+    # general L0 = [[2, 1], [1, 3]] at k = (1, 1): k . L0 . k = 7
+    g2 = o.green_hat((5, 7), np.array([[2.0, 1.0], [1.0, 3.0]]))
+    np.testing.assert_allclose(g2[:, :, 1, 1], np.ones((2, 2)) / 7.0, rtol=1e-15)
+    # even grid: the Nyquist modes carry no Green operator
+    g4 = o.green_hat((4, 5), 1.0)
+    assert np.all(g4[:, :, 2, :] == 0.0)
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 5, 3)])
+def test_green_hat_gives_the_dense_operator(shape):
+    """B p assembled from green_hat and explicit Vandermonde DFT matrices
+    (Sec. 2.2, Eqs. (13), (14), (16)) equals the dense matrix of Eq. (16)."""
+    lam = _rand_lam(shape, 31, 1.0, 20.0)
+    l0 = 7.5
+    d = len(shape)
+    nn = int(np.prod(shape))
+    rng = np.random.default_rng(32)
+    p = rng.standard_normal((d,) + shape)
+    idx = np.stack(np.unravel_index(np.arange(nn), shape), axis=1)
+    ph = (idx[:, None, :] * idx[None, :, :] / np.array(shape)).sum(axis=2)
+    F = np.exp(-2j * np.pi * ph)
+    Finv = np.exp(2j * np.pi * ph) / nn
+    g = o.green_hat(shape, l0).reshape(d, d, nn)
+    tau_hat = [F @ ((lam.ravel() - l0) * p[b].ravel()) for b in range(d)]
+    Bp = np.stack([(Finv @ sum(g[a, b] * tau_hat[b] for b in range(d))).real for a in range(d)])
+    M, flat = o.dense_operator(lam, l0)
+    vec = np.concatenate([p[a].ravel()[flat] for a in range(d)])
+    ref = (M @ vec).real - vec
+    got = np.concatenate([Bp[a][flat] for a in range(d)])
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-11 * np.abs(ref).max())
+
+
+def test_eta_r_by_hand():
+    """Sec. 3, Eq. (22): eta_r = l0 ||r|| / ||e0|| with e0 the constant field E.
+    For a constant residual field r(x) = c the ratio is l0 |c| / |E|."""
+    shape = (9, 5)
+    r = np.stack([np.full(shape, 3.0), np.full(shape, -4.0)])
+    assert abs(o.eta_r(r, 2.5, [0.0, 2.0], shape) - 2.5 * 5.0 / 2.0) < 1e-14
+    # one nonzero node: ||r|| = |r(x0)|, ||e0|| = |E| sqrt(|N|)
+    r1 = np.zeros((2,) + shape)
+    r1[1, 3, 2] = 6.0
+    assert abs(o.eta_r(r1, 1.0, [1.0, 0.0], shape) - 6.0 / math.sqrt(45.0)) < 1e-14
+    # anisotropic L0 = diag(2, 4): tr(L0) / d = 3 times the energy-norm ratio
+    # sqrt(r . L0 . r / E . L0 . E) = sqrt(2 / 4)
+    r2 = np.stack([np.ones(shape), np.zeros(shape)])
+    got = o.eta_r(r2, np.diag([2.0, 4.0]), [0.0, 1.0], shape)
+    assert abs(got - 3.0 * math.sqrt(0.5)) < 1e-14
+
+
+def test_eta_r_is_the_basic_scheme_step():
+    """Sec. 3, Eq. (22) defines eta_r by the step of the basic scheme,
+    l0 ||e^(m+1) - e^(m)|| / ||e0||; that step is the residual of e^(m)
+    (Eq. (18)), so eta_r of the residual equals the step norm."""
+    lam = ms.square_inclusion(rho=10.0).lam()
+    l0 = o.optimal_reference(lam)
+    E = [1.0, 0.0]
+    e0 = o._rhs(E, lam.shape)
+    e1 = e0 - o.apply_B(e0, lam, l0)          # Eq. (18), one step from e^(0) = e0
+    e2 = e0 - o.apply_B(e1, lam, l0)
+    for e_m, e_next in ((e0, e1), (e1, e2)):
+        r = e0 - o.apply_A(e_m, lam, l0)
+        step = l0 * np.linalg.norm(e_next - e_m) / np.linalg.norm(e0)
+        assert abs(o.eta_r(r, l0, E, lam.shape) - step) <= 1e-13 * step
+
+
+def test_reference_omega():
+    """Sec. 3, Eq. (20): L0(omega) = (1 - omega + rho omega) I; omega = 0 is the
+    matrix, omega = 1 the particles, omega = 1/2 the optimal reference of
+    Eq. (19) for the two-phase medium {1, rho}."""
+    for rho in (10.0, 1e3, 1e4):
+        assert o.reference_omega(0.0, rho) == 1.0
+        assert o.reference_omega(1.0, rho) == rho
+        lam = ms.square_inclusion(rho=rho).lam()
+        assert abs(o.reference_omega(0.5, rho) - o.optimal_reference(lam)) <= 1e-15 * rho
+        # linear in omega
+        assert abs(o.reference_omega(0.25, rho) - (0.75 + 0.25 * rho)) <= 1e-15 * rho
+
+
+@pytest.mark.parametrize("rho,expected", [(10.0, 24), (100.0, 84), (1000.0, 284), (1e4, 956)])
+def test_cg_rate_bound_values(rho, expected):
+    """Sec. 3.2, Eq. (23): gamma = (sqrt(rho) - 1) / (sqrt(rho) + 1) and the
+    textbook bound ||r_m|| <= 2 sqrt(rho) gamma^m ||r_0||.  The iteration counts
+    at tol 1e-6 (24 / 84 / 284 / 956) were worked out independently of this
+    module; m is the first count whose bound meets the tolerance."""
+    m = o.cg_rate_bound_iterations(rho, 1e-6)
+    assert m == expected
+    g = (math.sqrt(rho) - 1.0) / (math.sqrt(rho) + 1.0)
+    assert 2.0 * math.sqrt(rho) * g ** m <= 1e-6
+    assert 2.0 * math.sqrt(rho) * g ** (m - 1) > 1e-6
+
+
+def test_cg_rate_bound_on_chebyshev_spectrum():
+    """The bound of Eq. (23) is what CG attains on a spectrum spread over
+    [1, rho]: on a diagonal SPD matrix with eigenvalues at the Chebyshev
+    points of [1, rho] CG needs close to (and never more than) the bound."""
+    rho, tol = 100.0, 1e-6
+    n = 400
+    t = np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    lam = 0.5 * (rho + 1.0) + 0.5 * (rho - 1.0) * t
+    b = np.ones(n)
+    x = np.zeros(n)
+    r = b.copy()
+    p = r.copy()
+    rr = r @ r
+    m = 0
+    while math.sqrt(rr) > tol * math.sqrt(b @ b):
+        q = lam * p
+        a = rr / (p @ q)
+        x += a * p
+        r -= a * q
+        rn = r @ r
+        p = r + (rn / rr) * p
+        rr = rn
+        m += 1
+    bound = o.cg_rate_bound_iterations(rho, tol)
+    assert m <= bound
+    assert m >= 0.6 * bound
