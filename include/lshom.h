@@ -7,13 +7,18 @@
  * J. Comput. Phys. 2010.  The library solves the collocation system
  * (I + B) e = e0 of Sec. 2.2, Eq. (15), with B = F^-1 Gamma0_hat F dL
  * (Eq. (16)), by the conjugate-gradient method of Sec. 2.3 (Saad's
- * Algorithm 6.18, named in Sec. 3), for isotropic phases L = lambda I and a
- * reference medium L0 = l0 I.
+ * Algorithm 6.18, named in Sec. 3).  Phases are isotropic, L = lambda I
+ * (lshom_set_microstructure), or symmetric tensors per phase
+ * (lshom_set_microstructure_tensor); the reference medium is L0 = l0 I
+ * (lshom_set_reference) or any symmetric positive definite matrix
+ * (lshom_set_reference_tensor, lshom_set_reference_mean); the cell may have
+ * unequal side lengths (lshom_set_cell).
  *
  * Conventions shared by every entry point:
  *  - Grids are d = 2 or 3 dimensional, N[0..d) nodes per axis, C order (the
  *    last axis is contiguous).  Node j of an axis sits at coordinate j / N of
- *    the unit cell.  Every N[a] >= 3 and N[a] has no prime factor above 7.
+ *    the unit cell.  Every N[a] >= 3, and every prime factor of N[a] is one
+ *    of 2, 3, 5, 7, 11, 13, 17 (lshom_check_problem states the size limits).
  *  - A real field with d components is stored component-major, FP64:
  *    field[a * |N| + flat_index], |N| = N[0] * ... * N[d-1].
  *  - Device pointers (suffix _dev) are HIP device memory owned by the caller;
@@ -277,6 +282,10 @@ typedef struct lshom_problem {
   double tol;
   double* e_dev;
   double cell[3];  /* side lengths of the cell (Sec. 2.1; Green operator at xi = k / Y); all 0: cubic */
+  /* initial guess (d x |N| FP64, device, caller-owned, read during the call;
+   * NULL: start from e = E), taken as for lshom_solve: projected to
+   * E + P x0 and dropped in favour of e = E unless its residual is smaller */
+  const double* x0_dev;
 } lshom_problem;
 
 /* Device workspace bytes lshom_solve_batched needs for these problems. */
@@ -284,8 +293,10 @@ lshom_status lshom_batch_workspace_size(lshom_ctx* ctx, int32_t n, const lshom_p
                                         int precision, size_t* bytes);
 
 /*
- * Solve n problems (warm starts are not taken here; opts->method and
- * opts->norm apply to every problem, opts->history_dev must be NULL).
+ * Solve n problems (each may carry its own warm start x0_dev, CG only;
+ * opts->method and opts->norm apply to every problem, opts->history_dev must
+ * be NULL).  A warm start that is dropped leaves its problem on e = E; the
+ * report's warm_start_used says which happened.
  * ws_dev: caller-owned
  * device workspace of at least lshom_batch_workspace_size bytes, 256-byte
  * aligned (it is not kept after the call).  leff_host: n x 3 (row i is

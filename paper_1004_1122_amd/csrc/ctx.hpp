@@ -113,6 +113,9 @@ struct Group {
   Layout lay;
   std::vector<DevState> host_states;
   int warm_used = 0;
+  std::vector<int> warm_flags;  // warm start taken, per problem
+  bool warm_any = false;        // batched: some problem brings a warm start
+  std::vector<int> warm_has;    // batched: problem p brings one
   std::map<std::pair<int, int>, hipGraphExec_t>* graph_cache = nullptr;
   bool in_cg = false;           // the CG-loop passes are being queued (timed when enabled)
   bool eq = false;              // the iteration loop forms the equilibrium norm (FP64)

@@ -851,7 +851,6 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
   std::vector<std::vector<float>> tw32(g.d);
   const int np = g.nprob;
   std::vector<DevState> zero(np);
-  unsigned host_max = 0;
   std::vector<double> c64((size_t)kCondStride * np, 0.0);
   std::vector<float> c32((size_t)kCondStride * np, 0.0f);
   for (int p = 0; p < np; ++p)
@@ -876,16 +875,18 @@ lshom_status prepare_workspace(Group& g, const std::vector<double>& cond, const 
   HIP_TRY(c, hipMemcpyAsync(g.ws + use.off_state, zero.data(), sizeof(DevState) * np, hipMemcpyHostToDevice,
                             stream_of(g)));
   g.host_states.assign(np, DevState{});
-  // every phase index must name a conductivity
-  unsigned* mx = reinterpret_cast<unsigned*>(g.ws + use.off_scratch);
-  for (const uint8_t* ph : phases) {
-    HIP_TRY(c, hipMemsetAsync(mx, 0, sizeof(unsigned), stream_of(g)));
-    HIP_TRY(c, launch_max_phase(ph, g.nvox, mx, stream_of(g)));
-    HIP_TRY(c, hipMemcpyAsync(&host_max, mx, sizeof(unsigned), hipMemcpyDeviceToHost, stream_of(g)));
-    HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
-    if (host_max >= (unsigned)g.n_phase_ids)
-      return fail(c, LSHOM_ERR_INVALID_ARG, "phase image holds an index >= n_phases");
-  }
+  // every phase index must name a conductivity: one maximum per image into
+  // the (still unused) partial-sum area, read back with one synchronisation
+  unsigned* mx = reinterpret_cast<unsigned*>(g.ws + use.off_partials);
+  const size_t nimg = phases.size();
+  HIP_TRY(c, hipMemsetAsync(mx, 0, sizeof(unsigned) * nimg, stream_of(g)));
+  for (size_t i = 0; i < nimg; ++i) HIP_TRY(c, launch_max_phase(phases[i], g.nvox, mx + i, stream_of(g)));
+  std::vector<unsigned> host_max(nimg, 0u);
+  HIP_TRY(c, hipMemcpyAsync(host_max.data(), mx, sizeof(unsigned) * nimg, hipMemcpyDeviceToHost, stream_of(g)));
+  HIP_TRY(c, hipStreamSynchronize(stream_of(g)));
+  for (size_t i = 0; i < nimg; ++i)
+    if (host_max[i] >= (unsigned)g.n_phase_ids)
+      return fail(c, LSHOM_ERR_INVALID_ARG, "phase image " + std::to_string(i) + " holds an index >= n_phases");
   return LSHOM_OK;
 }
 
@@ -935,7 +936,11 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   const int fin_init = mixed ? FZ_REFRESH_INIT : FZ_CHECK;
   const int init_region = mixed ? PART_AUX : PART_RR0;
   int warm_used = 0;
-  if (x0) {
+  g.warm_flags.assign(g.nprob, 0);
+  // batched problems bring their warm starts in the problem table (the row
+  // pass reads a missing one as zero)
+  const bool warm_batch = g.batched && g.warm_any;
+  if (x0 || warm_batch) {
     // residual of E for the admissibility test, then of E + P x0
     HIP_TRY(c, (enq_residual_of_E<double>(g, b64, E, r64, PART_AUX)));
     HIP_TRY(c, enq_finalize(g, FZ_AUX, ncol, GATE_ALWAYS));
@@ -943,12 +948,31 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS, eq_loop)));
     HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS, eq_loop));
     HIP_TRY(c, sync_states(g));
-    const DevState& hs = g.host_states[0];
-    const double rr = mixed ? hs.rr_true : hs.rr_log;
-    if (std::isfinite(rr) && rr < hs.dot_aux) {
-      warm_used = 1;
-    } else {
-      HIP_TRY(c, launch_fill_zero(x64, nall, stream_of(g)));
+    int rejected = 0;
+    for (int p = 0; p < g.nprob; ++p) {
+      const DevState& hs = g.host_states[p];
+      const double rr = mixed ? hs.rr_true : hs.rr_log;
+      const bool has = x0 || g.warm_has[p];
+      if (has && std::isfinite(rr) && rr < hs.dot_aux) {
+        g.warm_flags[p] = 1;
+      } else {
+        // start this problem from e = E instead
+        HIP_TRY(c, launch_fill_zero(x64 + (long long)p * g.nhalf, g.nhalf, stream_of(g)));
+        rejected += has ? 1 : 0;
+      }
+    }
+    int taken = 0;
+    for (int f : g.warm_flags) taken += f;
+    warm_used = taken > 0;
+    if (warm_used && (rejected > 0 || taken < g.nprob)) {
+      // some problems of the batch start from e = E: every residual is
+      // formed again from the (partly zeroed) iterates with the initial
+      // scalars (the kept warm starts get the same values as before)
+      HIP_TRY(c, hipMemcpyAsync(init_dev, init.data(), sizeof(DevState) * g.nprob, hipMemcpyHostToDevice,
+                                stream_of(g)));
+      HIP_TRY(c, launch_state_copy(dev_state(g), init_dev, g.nprob, stream_of(g)));
+      HIP_TRY(c, (enq_true_residual<double>(g, b64, x64, E, r64, init_region, GATE_ALWAYS, eq_loop)));
+      HIP_TRY(c, enq_finalize(g, fin_init, mixed ? ncol : 0, GATE_ALWAYS, eq_loop));
     }
   }
   if (!warm_used) {

@@ -743,8 +743,12 @@ lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const l
   tab->assign(g.nprob, ProbEntry{});
   init->assign(g.nprob, DevState{});
   std::vector<const uint8_t*> phases;
+  g.warm_has.assign(g.nprob, 0);
+  g.warm_any = false;
   for (int j = 0; j < g.nprob; ++j) {
     const lshom_problem& p = probs[mem[j]];
+    g.warm_has[j] = p.x0_dev ? 1 : 0;
+    g.warm_any = g.warm_any || p.x0_dev;
     double lo = p.cond_host[0], hi = p.cond_host[0];
     for (int i = 0; i < p.n_phases; ++i) {
       cond[(size_t)j * g.n_phases + i] = p.cond_host[i];
@@ -754,7 +758,7 @@ lshom_status prepare_batch_group(lshom_ctx* c, BatchPlan& bp, size_t gi, const l
     ProbEntry& e = (*tab)[j];
     e.phase = p.phase_dev;
     e.e_out = p.e_dev;
-    e.x0 = nullptr;
+    e.x0 = p.x0_dev;
     e.l0 = p.l0 > 0.0 ? p.l0 : 0.5 * (lo + hi);
     phases.push_back(p.phase_dev);
     (*init)[j] = initial_state(p.d, g.nvox, p.E, p.tol, e.l0, o, false);
@@ -855,6 +859,11 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
     return fail(c, LSHOM_ERR_UNSUPPORTED, "BiCG and pipelined CG run single solves only");
   BatchPlan bp;
   if ((s = plan_batch(c, n, probs, o.precision, &bp)) != LSHOM_OK) return s;
+  if (o.method != LSHOM_METHOD_CG)
+    for (int32_t i = 0; i < n; ++i)
+      if (probs[i].x0_dev)
+        return fail(c, LSHOM_ERR_UNSUPPORTED, "the basic scheme starts from e = E (problem " + std::to_string(i) +
+                                                  " has x0_dev)");
   for (int32_t i = 0; i < n; ++i)
     if ((s = check_equilibrium_grid(c, o, probs[i].N, probs[i].d)) != LSHOM_OK) return s;
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) != 0)
@@ -869,9 +878,16 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
     std::vector<DevState> init;
     if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tab, &init)) != LSHOM_OK) return s;
     if (c->batch_graphs.size() > 64) drop_batch_graphs(c);
-    const std::vector<long long> tag = {(long long)reinterpret_cast<uintptr_t>(g.ws), g.d, (long long)g.N[0],
-                                        (long long)g.N[1], (long long)g.N[2], g.nprob, g.n_phases,
-                                        (long long)g.lay.total, g.lay.has32 ? 1 : 0};
+    // the captured launches carry the group's wave-vector scale 1 / Y (cell
+    // side lengths) as kernel arguments, so the cell is part of the tag
+    std::vector<long long> tag = {(long long)reinterpret_cast<uintptr_t>(g.ws), g.d, (long long)g.N[0],
+                                  (long long)g.N[1], (long long)g.N[2], g.nprob, g.n_phases,
+                                  (long long)g.lay.total, g.lay.has32 ? 1 : 0};
+    for (int a = 0; a < 3; ++a) {
+      long long bits;
+      std::memcpy(&bits, &g.cell_inv[a], sizeof(bits));
+      tag.push_back(bits);
+    }
     g.graph_cache = &c->batch_graphs[tag];
     if ((s = solve_group(g, init, o, nullptr, nullptr, nullptr)) != LSHOM_OK) return s;
     const std::vector<int>& mem = bp.members[gi];
@@ -880,7 +896,7 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
       const int i = mem[j];
       if (leff_host)
         for (int t = 0; t < 3; ++t) leff_host[(size_t)i * 3 + t] = t < g.d ? hs.leff[t] : 0.0;
-      if (infos) fill_info(hs, tab[j].l0, o, 0, &infos[i]);
+      if (infos) fill_info(hs, tab[j].l0, o, j < (int)g.warm_flags.size() ? g.warm_flags[j] : 0, &infos[i]);
       if (hs.status != LSHOM_OK && worst == LSHOM_OK) worst = hs.status;
     }
   }

@@ -277,8 +277,9 @@ __global__ __launch_bounds__(NT) void row_kernel(RowArgs<T> a) {
       for (int u = 0; u < 2; ++u) {
         const int rl = ra + u;
         if (rl >= rows_here) continue;
+        // a batched problem without a warm start projects the zero field
         const double* rin = pe ? (pe->x0 ? pe->x0 + c * nvox : nullptr) : pick3(a.real_in, c);
-        T val = (a.flags & ROWF_CONST_E) ? pick3(Ev, c) : (T)rin[(row0 + rl) * n + x];
+        T val = (a.flags & ROWF_CONST_E) ? pick3(Ev, c) : (rin ? (T)rin[(row0 + rl) * n + x] : T(0));
         if (a.flags & ROWF_DL) val *= cond[ph[rl * n + x]] - l0;
         v[u] = val;
       }

@@ -90,6 +90,7 @@ class lshom_problem(Structure):
         ("tol", c_double),
         ("e_dev", c_void_p),
         ("cell", c_double * 3),
+        ("x0_dev", c_void_p),
     ]
 
 
@@ -389,8 +390,11 @@ class Solver:
             setattr(o, k, v)
         return o
 
-    def solve(self, E, tol=1e-8, x0=None, want_field=True, allow_fail=False, history=0, **opt_kw):
+    def solve(self, E, tol=1e-8, x0=None, want_field=True, allow_fail=False, history=0, out=None, **opt_kw):
         """Returns (e [d, *N] float64 device tensor or None, leff ndarray, info dict).
+
+        ``out``: a contiguous FP64 device tensor of shape (d, *N) that receives
+        the field (no allocation).
 
         ``method`` / ``norm`` select the basic scheme and the equilibrium test
         (METHOD_*, NORM_*); ``history=n`` records (eta_r, eta_e) of the first
@@ -404,7 +408,13 @@ class Solver:
             hist = torch.full((int(history), 2), float("nan"), dtype=torch.float64, device=self.device)
             o.history_dev = hist.data_ptr()
             o.history_len = int(history)
-        e = torch.empty((self.d,) + self.shape, dtype=torch.float64, device=self.device) if want_field else None
+        if out is not None:
+            if (tuple(out.shape) != (self.d,) + self.shape or out.dtype != torch.float64
+                    or out.device != self.device or not out.is_contiguous()):
+                raise ValueError("out must be a contiguous float64 tensor of shape (d, *N) on the solver's device")
+            e = out
+        else:
+            e = torch.empty((self.d,) + self.shape, dtype=torch.float64, device=self.device) if want_field else None
         leff = (c_double * self.d)()
         info = lshom_solve_info()
         x0p = None
@@ -483,8 +493,9 @@ class BatchSolver:
     """Solves lists of problems with lshom_solve_batched on one device.
 
     A problem is a dict with ``phase`` (uint8 array or tensor), ``cond``,
-    ``E``, ``tol`` and optionally ``l0`` (default (min + max) / 2) and
-    ``want_field`` (default False).  Workspace and device copies of the
+    ``E``, ``tol`` and optionally ``l0`` (default (min + max) / 2),
+    ``want_field`` (default False), ``cell`` and ``x0`` (an initial guess,
+    d x N FP64, projected and kept only if its residual is the smaller).  Workspace and device copies of the
     phase images are owned by torch and kept until ``prepare`` is called with
     other problems.
     """
@@ -542,6 +553,13 @@ class BatchSolver:
             a.e_dev = e.data_ptr() if e is not None else None
             for t in range(3):
                 a.cell[t] = float(pr["cell"][t]) if pr.get("cell") is not None and t < d else 0.0
+            x0 = pr.get("x0")
+            if x0 is not None:
+                x0 = torch.as_tensor(x0).to(device=self.device, dtype=torch.float64).contiguous()
+                if tuple(x0.shape) != (d,) + tuple(ph.shape):
+                    raise ValueError(f"problem {i}: x0 must have shape {(d,) + tuple(ph.shape)}")
+                keep.append(x0)
+            a.x0_dev = x0.data_ptr() if x0 is not None else None
         size = c_size_t()
         _check(self.ctx, self.lib.lshom_batch_workspace_size(self.ctx, n, arr, int(precision), ctypes.byref(size)))
         need = int(size.value)

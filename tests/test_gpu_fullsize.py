@@ -1,0 +1,130 @@
+"""Parity on the launch shapes the measured workloads use: 3-D grids with a
+243-point axis in each position (the 9 9 3 plans and column tiles of the
+243^3 cell, XCD-ordered launches of thousands of blocks), the 243^3 sphere
+cell itself with autotuned schedules, the 729^2 circle cell at the highest
+contrast, the largest supported grids, and the symmetry of the discrete
+operator on the admissible fields (Sec. 2.2, Eq. (16))."""
+
+import numpy as np
+import pytest
+
+from oracle import lshom_oracle as o
+from paper_1004_1122_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _two_phase(shape, seed, vf=0.3):
+    rng = np.random.default_rng(seed)
+    return (rng.random(shape) < vf).astype(np.uint8)
+
+
+def _fp64_parity(phase, cond, E, n_iter, autotune=False):
+    """GPU FP64 CG stopped after n_iter iterations against the oracle's CG
+    after the same count: field and <lambda e> within 1e-10."""
+    from paper_1004_1122_amd import lshom
+    s = lshom.Solver(phase, cond)
+    if autotune:
+        s.autotune(precision=0, reps=2)
+    e, leff, info = s.solve(E, tol=0.0, max_iter=n_iter, precision=0, allow_fail=True)
+    assert info["iterations"] == n_iter and info["status"] == lshom.LSHOM_ERR_NOT_CONVERGED
+    lam = ms.lam_field(phase, cond)
+    ref = o.cg(lam, o.optimal_reference(lam), E, n_iter=n_iter)
+    err = _rel(e.cpu().numpy(), ref["e"])
+    assert err < 1e-10, err
+    Lref = o.leff(lam, ref["e"])
+    assert np.abs(leff - Lref).max() <= 1e-10 * np.abs(Lref).max()
+    assert abs(info["rel_res"] - ref["rel_res"]) <= 1e-8 * ref["rel_res"]
+    s.close()
+    return err
+
+
+@pytest.mark.parametrize("shape", [(243, 27, 27), (27, 243, 27), (27, 27, 243), (27, 243, 243)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_3d_243_axis(shape):
+    print("case", shape, flush=True)
+    _fp64_parity(_two_phase(shape, sum(shape)), [1.0, 1e3], [0.2, 1.0, -0.5], 25)
+
+
+def test_c3_cell_autotuned_schedules():
+    """The 243^3 sphere cell (seed 3, contrast 1e3) with the schedules the
+    autotuner picks for it: every pass at its measured shape (7400-29600
+    blocks per launch)."""
+    m = ms.spheres_243(seed=3, rho=1e3)
+    _fp64_parity(m.phase, m.cond, [1.0, 0.0, 0.0], 3, autotune=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c3_cell_converged_forms_agree(precision):
+    """Full C3 solve to 1e-6 (load case e3) in both forms: the FP64 true
+    residual meets the tolerance and the field is within the a-posteriori
+    bound (l0 / lambda_min) tol of the tightly converged FP64 GPU field."""
+    from paper_1004_1122_amd import lshom
+    m = ms.spheres_243(seed=3, rho=1e3)
+    s = lshom.Solver(m.phase, m.cond)
+    s.autotune(precision=precision, reps=2)
+    e, leff, info = s.solve([0.0, 0.0, 1.0], tol=1e-6, precision=precision)
+    assert info["status"] == 0 and info["rel_res_true"] <= 1.01e-6
+    tight, lt, _ = s.solve([0.0, 0.0, 1.0], tol=1e-11, precision=0)
+    l0 = 0.5 * (1.0 + 1e3)
+    bound = 2.0 * l0 * 1e-6
+    err = float((e - tight).norm() / tight.norm())
+    assert err <= bound, (err, bound)
+    # <lambda e> moves by at most lambda_max times the field error (rms)
+    rms = float(tight.norm()) / np.sqrt(tight.numel() / 3)
+    assert np.abs(leff - lt).max() <= 1e3 * err * rms * 1.0001 + 1e-15
+
+
+def test_729_highest_contrast_forced_iterations():
+    """The 729^2 circle cell at rho = 1e4, 60 iterations: the field, not only
+    the residual and <lambda e>, within 1e-10 of the oracle."""
+    m = ms.circles_729(2, rho=1e4)
+    for E in ([1.0, 0.0], [0.0, 1.0]):
+        _fp64_parity(m.phase, m.cond, E, 60)
+
+
+@pytest.mark.parametrize("shape", [(1331, 1331), (975, 9, 9)], ids=["1331^2", "975x9x9"])
+def test_largest_supported_grids(shape):
+    """The longest axes one LDS-resident FFT batch holds (radix 11^3 in 2-D;
+    radices 5 5 3 13 with one-column tiles in 3-D) against the oracle."""
+    E = [1.0, 0.5] if len(shape) == 2 else [1.0, 0.5, -0.25]
+    _fp64_parity(_two_phase(shape, 5), [1.0, 30.0], E, 20)
+
+
+@pytest.mark.parametrize("shape", [(81, 81), (729, 729), (243, 27, 27), (27, 27, 243), (45, 27, 33), (255, 255)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_operator_symmetric_on_admissible_fields(shape):
+    """For u, v in U (zero-mean curl-free fields) A = I + B of Eq. (16) is
+    symmetric: (A u, v) = (u, A v) = (u, v) + (dL u, v) / l0.  Through the C
+    ABI's FP64 apply; the bar is a few ulps of the terms."""
+    from paper_1004_1122_amd import lshom
+    d = len(shape)
+    phase = _two_phase(shape, 11 + d, vf=0.4)
+    cond = [1.0, 1e4]
+    lam = ms.lam_field(phase, cond)
+    rng = np.random.default_rng(13)
+    u = o.project_gradient(rng.standard_normal((d,) + shape))
+    v = o.project_gradient(rng.standard_normal((d,) + shape))
+    s = lshom.Solver(phase, cond)
+    l0 = 0.5 * (1.0 + 1e4)
+    Au = s.apply(torch.from_numpy(u)).cpu().numpy()
+    Av = s.apply(torch.from_numpy(v)).cpu().numpy()
+    a, b = float(np.vdot(Au, v)), float(np.vdot(u, Av))
+    nu, nv = np.linalg.norm(u), np.linalg.norm(v)
+    norm_A = 1.0 + (1e4 - l0) / l0   # |dL| / l0 <= (rho - 1) / (rho + 1)
+    assert abs(a - b) <= 1e-13 * nu * nv * norm_A, (a, b)
+    # and both equal the closed form on U
+    c = float(np.vdot(u, v)) + float(np.vdot((lam - l0) * u, v)) / l0
+    assert abs(a - c) <= 1e-12 * nu * nv * norm_A, (a, c)
