@@ -22,6 +22,7 @@ LIB = os.path.join(PKG, "liblshom.so")
 
 SOURCES = [
     "passes.hip",
+    "wave3d.hip",
     "plan.cpp",
     "driver.cpp",
     "lshom_api.cpp",

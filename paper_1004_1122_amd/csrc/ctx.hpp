@@ -34,6 +34,8 @@ struct Layout {
   size_t off_tw64[3] = {0, 0, 0}, off_tw32[3] = {0, 0, 0};
   size_t off_v64[4] = {0, 0, 0, 0}, off_w64[3] = {0, 0, 0};
   size_t off_v32[4] = {0, 0, 0, 0}, off_w32[3] = {0, 0, 0};
+  // wave passes (3-D grids of 27/81/243): the axis-0 inverse output Gl
+  size_t off_g64[3] = {0, 0, 0}, off_g32[3] = {0, 0, 0};
   // BiCG: real d x |N| FP64 fields x, r, r*, p, p*, A p, A^T p* (single problems)
   size_t off_bicg[7] = {0, 0, 0, 0, 0, 0, 0};
   long long part_stride = 0;  // doubles per partial region
@@ -46,6 +48,7 @@ template <typename T>
 struct Bufs {
   cx<T>* v[4];   // x, r, p, q (half spectrum) of problem 0
   cx<T>* w[3];   // per-component pass buffers of problem 0
+  cx<T>* gl[3];  // wave passes: axis-0 inverse output (layout Gl)
   const T* cond;
   const cx<T>* tw[3];
   PassShape shape;
@@ -84,6 +87,13 @@ struct Group {
   int d = 0;
   int64_t N[3] = {1, 1, 1};
   long long nvox = 0, nrows = 0, nhalf = 0;
+  // wave passes: the grid qualifies (3-D, axes of 27, 81 or 243 nodes,
+  // isotropic phases), they are in use for the current solve, the padded
+  // spectral entries per problem, and the entries allocated per problem and
+  // vector (the larger of nhalf and nhp where the grid qualifies)
+  bool w3ok = false;
+  bool w3 = false;
+  long long nhp = 0, nvec = 0;
   int h = 0;
   bool transposed = false;      // 2-D spectral arrays stored [k1][k0]
   FftPlan plan64[3], plan32[3];

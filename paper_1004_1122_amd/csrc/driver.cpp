@@ -52,6 +52,10 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases_in, boo
   g.h = (int)(N[d - 1] / 2 + 1);
   g.nrows = g.nvox / N[d - 1];
   g.nhalf = g.nrows * g.h;
+  g.w3ok = d == 3 && !tensor && wave_fft_length(N[0]) && wave_fft_length(N[1]) && wave_fft_length(N[2]);
+  g.w3 = false;
+  g.nhp = g.w3ok ? w3_entries(N[0], N[1], N[2]) : 0;
+  g.nvec = std::max(g.nhalf, g.nhp);
   // in-kernel index arithmetic is 32-bit
   if (g.nvox >= (1ll << 31)) return LSHOM_ERR_UNSUPPORTED;
   g.transposed = (d == 2);
@@ -134,14 +138,18 @@ Layout compute_layout(const Group& g, bool with32, bool with_bicg) {
     L.off_tw64[a] = take((size_t)g.N[a] * sizeof(cx<double>));
     L.off_tw32[a] = take((size_t)g.N[a] * sizeof(cx<float>));
   }
-  const size_t v64 = (size_t)g.nhalf * np * sizeof(cx<double>);
-  const size_t v32 = (size_t)g.nhalf * np * sizeof(cx<float>);
+  const size_t v64 = (size_t)g.nvec * np * sizeof(cx<double>);
+  const size_t v32 = (size_t)g.nvec * np * sizeof(cx<float>);
   for (int i = 0; i < 4; ++i) L.off_v64[i] = take(v64);
   for (int a = 0; a < g.d; ++a) L.off_w64[a] = take(v64);
+  if (g.w3ok)
+    for (int a = 0; a < g.d; ++a) L.off_g64[a] = take(v64);
   L.has32 = with32;
   if (with32) {
     for (int i = 0; i < 4; ++i) L.off_v32[i] = take(v32);
     for (int a = 0; a < g.d; ++a) L.off_w32[a] = take(v32);
+    if (g.w3ok)
+      for (int a = 0; a < g.d; ++a) L.off_g32[a] = take(v32);
   }
   L.has_bicg = with_bicg;
   if (with_bicg)
@@ -172,7 +180,7 @@ Partials dev_parts(Group& g) {
 Batch batch_of(Group& g) {
   Batch b{};
   b.nprob = g.live_rows > 0 ? g.live_rows : g.nprob;
-  b.vstride = g.nhalf;
+  b.vstride = g.nvec;
   b.pstride = g.lay.pstride;
   b.tab = g.batched ? reinterpret_cast<const ProbEntry*>(g.ws + g.lay.off_tab) : nullptr;
   b.live = g.live_rows > 0 ? reinterpret_cast<const int*>(g.ws + g.lay.off_live) : nullptr;
@@ -188,6 +196,7 @@ Bufs<double> get_bufs<double>(Group& g) {
   for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<double>*>(g.ws + g.lay.off_v64[i]);
   for (int a = 0; a < g.d; ++a) {
     b.w[a] = reinterpret_cast<cx<double>*>(g.ws + g.lay.off_w64[a]);
+    b.gl[a] = g.w3ok ? reinterpret_cast<cx<double>*>(g.ws + g.lay.off_g64[a]) : nullptr;
     b.tw[a] = reinterpret_cast<const cx<double>*>(g.ws + g.lay.off_tw64[a]);
   }
   b.cond = reinterpret_cast<const double*>(g.ws + g.lay.off_cond64);
@@ -202,6 +211,7 @@ Bufs<float> get_bufs<float>(Group& g) {
   for (int i = 0; i < 4; ++i) b.v[i] = reinterpret_cast<cx<float>*>(g.ws + g.lay.off_v32[i]);
   for (int a = 0; a < g.d; ++a) {
     b.w[a] = reinterpret_cast<cx<float>*>(g.ws + g.lay.off_w32[a]);
+    b.gl[a] = g.w3ok ? reinterpret_cast<cx<float>*>(g.ws + g.lay.off_g32[a]) : nullptr;
     b.tw[a] = reinterpret_cast<const cx<float>*>(g.ws + g.lay.off_tw32[a]);
   }
   b.cond = reinterpret_cast<const float*>(g.ws + g.lay.off_cond32);
@@ -379,8 +389,41 @@ RowArgs<T> row_args(Group& g, const Bufs<T>& b) {
 
 long long klast_div_of(const Group& g) { return g.transposed ? g.N[0] : 1; }
 
+// Entries per problem the elementwise kernels of the current solve cover.
+long long vec_entries(const Group& g) { return g.w3 ? g.nhp : g.nhalf; }
+
+template <typename T>
+W3Args<T> w3_args(Group& g, const Bufs<T>& b) {
+  W3Args<T> a{};
+  a.N0 = (int)g.N[0];
+  a.N1 = (int)g.N[1];
+  a.N2 = (int)g.N[2];
+  a.h = g.h;
+  a.G = w3_groups(g.h);
+  a.nhp = g.nhp;
+  for (int t = 0; t < kMaxDim; ++t) {
+    a.gl[t] = b.gl[t];
+    a.hl[t] = b.w[t];
+    a.tw[t] = b.tw[t];
+    a.cinv[t] = g.cell_inv[t];
+  }
+  a.phase = g.phase;
+  a.cond = b.cond;
+  a.n_phases = g.n_phases;
+  a.l0 = (T)g.l0;
+  a.l0d = g.l0;
+  a.inv_n = (T)(1.0 / (double)g.nvox);
+  a.inv_nd = 1.0 / (double)g.nvox;
+  a.st = dev_state(g);
+  a.parts = dev_parts(g);
+  a.gate = GATE_ACTIVE;
+  a.bt = batch_of(g);
+  return a;
+}
+
 template <typename T>
 long long col0_block_count(Group& g, const Bufs<T>& b) {
+  if (g.w3) return w3_blocks(W3_FWD0, (int)g.N[0], (int)g.N[1], (int)g.N[2]);
   return col_blocks(col0_args(g, b));
 }
 
@@ -401,7 +444,10 @@ hipError_t enq_finalize(Group& g, int mode, long long n, int gate, int eq = 0) {
 template <typename T>
 UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   UpdArgs<T> u{};
-  u.n = g.nhalf;
+  u.n = vec_entries(g);
+  u.w3 = g.w3 ? 1 : 0;
+  u.fd_w3n0 = make_fastdiv((uint32_t)g.N[0]);
+  u.w3g = w3_groups(g.h);
   u.h = g.h;
   u.n_last = (int)g.N[g.d - 1];
   u.klast_div = klast_div_of(g);
@@ -427,6 +473,29 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   return u;
 }
 
+// The row pass of r: the wave pass when the solve uses them, else r itself.
+template <typename T>
+hipError_t launch_row_pass(Group& g, const Bufs<T>& b, const RowArgs<T>& r) {
+  if (!g.w3) return launch_row(r, stream_of(g));
+  W3Args<T> a = w3_args(g, b);
+  a.mode = r.mode;
+  a.flags = r.flags;
+  for (int t = 0; t < kMaxDim; ++t) {
+    a.real_in[t] = r.real_in[t];
+    a.real_out[t] = r.real_out[t];
+    a.real_add[t] = r.real_add[t];
+    a.E[t] = r.E[t];
+  }
+  a.gate = r.gate;
+  return launch_w3(W3_ROW, a, stream_of(g));
+}
+
+template <typename T>
+long long row_block_count(Group& g, const RowArgs<T>& r) {
+  if (g.w3) return w3_blocks(W3_ROW, (int)g.N[0], (int)g.N[1], (int)g.N[2]);
+  return row_blocks(r);
+}
+
 // ---------------------------------------------------------------------------
 // Operator sequences (see the pass kernels for the algebra)
 // ---------------------------------------------------------------------------
@@ -438,6 +507,24 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
                                T coef_base, T coef_s, int s_inv_l0, int dot, int dot_region, int gate,
                                int eq = 0, int pipe = 0) {
   hipError_t e;
+  if (g.w3) {
+    W3Args<T> m = w3_args(g, b);
+    m.dir = -1;
+    m.gate = gate;
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS1_FORWARD, [&] { return launch_w3(W3_COL1, m, stream_of(g)); })) !=
+        hipSuccess)
+      return e;
+    W3Args<T> f = w3_args(g, b);
+    f.out = out;
+    f.base = base;
+    f.coef_base = coef_base;
+    f.coef_s = coef_s;
+    f.s_inv_l0 = s_inv_l0;
+    f.dot = dot;
+    f.dot_region = dot_region;
+    f.gate = gate;
+    return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_w3(W3_FWD0, f, stream_of(g)); });
+  }
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, -1);
     m.gate = gate;
@@ -466,6 +553,21 @@ template <typename T>
 hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* p_io,
                               const cx<T>* r_in, int gate, int eq = 0) {
   hipError_t e;
+  if (g.w3) {
+    W3Args<T> a = w3_args(g, b);
+    a.c_in = c_in;
+    a.p_io = p_io;
+    a.r_in = r_in;
+    a.cg_step = p_io != nullptr;
+    a.gate = gate;
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_w3(W3_INV0, a, stream_of(g)); })) !=
+        hipSuccess)
+      return e;
+    W3Args<T> m = w3_args(g, b);
+    m.dir = +1;
+    m.gate = gate;
+    return timed_launch(g, LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_w3(W3_COL1, m, stream_of(g)); });
+  }
   ColArgs<T> a = col0_args(g, b);
   a.mode = COL_INV_C;
   a.c_in = c_in;
@@ -497,7 +599,7 @@ hipError_t enq_apply_spec(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<T>* 
   for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
   if (!E) r.flags |= ROWF_STATE_E;
   r.gate = gate;
-  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row(r, stream_of(g)); })) != hipSuccess) return e;
+  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row_pass(g, b, r); })) != hipSuccess) return e;
   return enq_forward_project(g, b, out, base, coef_base, coef_s, 1, dot, dot_region, gate, eq);
 }
 
@@ -555,7 +657,7 @@ hipError_t enq_residual_of_E(Group& g, const Bufs<T>& b, const double* E, cx<T>*
   for (int t = 0; t < g.d; ++t) r.E[t] = E ? (T)E[t] : T(0);
   if (!E) r.flags |= ROWF_STATE_E;
   r.gate = GATE_ALWAYS;
-  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  if ((e = launch_row_pass(g, b, r)) != hipSuccess) return e;
   return enq_forward_project<T>(g, b, out, nullptr, T(0), T(-1), 1, 2, dot_region, GATE_ALWAYS, eq);
 }
 
@@ -569,7 +671,7 @@ hipError_t enq_project_real(Group& g, const Bufs<double>& b, const double* v, bo
   r.flags = with_dl ? ROWF_DL : 0;
   for (int t = 0; t < g.d; ++t) r.real_in[t] = v + (size_t)t * g.nvox;
   r.gate = gate;
-  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
+  if ((e = launch_row_pass(g, b, r)) != hipSuccess) return e;
   return enq_forward_project<double>(g, b, out, nullptr, 0.0, 1.0, green ? 1 : 0, 0, PART_AUX, gate);
 }
 
@@ -590,8 +692,8 @@ hipError_t enq_field_out(Group& g, const Bufs<double>& b, const cx<double>* x, c
     r.real_add[t] = add ? add + (size_t)t * g.nvox : nullptr;
   }
   r.gate = gate;
-  if ((e = launch_row(r, stream_of(g))) != hipSuccess) return e;
-  if (leff) return enq_finalize(g, FZ_LEFF, row_blocks(r), gate);
+  if ((e = launch_row_pass(g, b, r)) != hipSuccess) return e;
+  if (leff) return enq_finalize(g, FZ_LEFF, row_block_count(g, r), gate);
   return hipSuccess;
 }
 
@@ -614,7 +716,10 @@ hipError_t enq_apply_AT_real(Group& g, const Bufs<double>& b, const double* v, d
 
 MixArgs mix_args(Group& g, const Bufs<double>& b64, const Bufs<float>& b32, int gate) {
   MixArgs m{};
-  m.n = g.nhalf;
+  m.n = vec_entries(g);
+  m.w3 = g.w3 ? 1 : 0;
+  m.fd_w3n0 = make_fastdiv((uint32_t)g.N[0]);
+  m.w3g = w3_groups(g.h);
   m.h = g.h;
   m.n_last = (int)g.N[g.d - 1];
   m.klast_div = klast_div_of(g);
@@ -903,16 +1008,22 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   // them (FP64, odd grids: checked by the caller)
   struct EqReset {
     Group& g;
-    ~EqReset() { g.eq = false; }
+    ~EqReset() {
+      g.eq = false;
+      g.w3 = false;
+    }
   } eq_reset{g};
   g.eq = !mixed && (o.norm == LSHOM_NORM_EQUILIBRIUM || o.history_dev != nullptr);
+  // CG on a qualifying 3-D grid with an isotropic reference runs the wave
+  // passes (the basic scheme and the equilibrium sums keep the block passes)
+  g.w3 = g.w3ok && !g.eq && !ffth && !g.aniso && !g.tensor;
   bool odd = true;
   for (int a = 0; a < g.d; ++a) odd = odd && (g.N[a] & 1);
   const int eq_final = odd ? 1 : 0;
   const int eq_loop = g.eq ? 1 : 0;
   Bufs<double> b64 = get_bufs<double>(g);
   const long long ncol = col0_block_count(g, b64);
-  const long long nall = g.nhalf * g.nprob;
+  const long long nall = g.nvec * g.nprob;
   // E of every problem is read from its device state: a captured graph then
   // serves every load case
   (void)E_single;
@@ -957,7 +1068,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
         g.warm_flags[p] = 1;
       } else {
         // start this problem from e = E instead
-        HIP_TRY(c, launch_fill_zero(x64 + (long long)p * g.nhalf, g.nhalf, stream_of(g)));
+        HIP_TRY(c, launch_fill_zero(x64 + (long long)p * g.nvec, g.nvec, stream_of(g)));
         rejected += has ? 1 : 0;
       }
     }
@@ -1189,7 +1300,7 @@ hipError_t enq_pipe_iteration(Group& g, const Bufs<double>& b, cx<double>* w, cx
   r.mode = ROW_FUSED;
   for (int t = 0; t < g.d; ++t) r.E[t] = kZero[t];
   r.gate = gate;
-  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row(r, stream_of(g)); })) != hipSuccess) return e;
+  if ((e = timed_launch(g, LSHOM_PASS_ROW, [&] { return launch_row_pass(g, b, r); })) != hipSuccess) return e;
   if ((e = enq_forward_project<double>(g, b, z, w, 1.0, 1.0, 1, 0, PART_AUX, gate, 0, 1)) != hipSuccess) return e;
   PipeArgs<double> u{};
   u.n = g.nhalf;
@@ -1279,6 +1390,14 @@ void pass_model_bytes(const Group& g, int precision, double* out) {
   out[LSHOM_PASS_AXIS0_FORWARD] = (d + 2.0) * nh * cs;
   // reads x, r, p, q; writes x, r
   out[LSHOM_PASS_UPDATE] = 6.0 * nh * cs;
+  if (g.w3) {
+    // wave passes: the axis-0 passes carry two fields (xi_1 and xi_2 are
+    // applied in the axis-1 and last-axis spectra)
+    out[LSHOM_PASS_AXIS0_INVERSE] = 5.0 * nh * cs;
+    out[LSHOM_PASS_AXIS1_INVERSE] = 5.0 * nh * cs;
+    out[LSHOM_PASS_AXIS1_FORWARD] = 5.0 * nh * cs;
+    out[LSHOM_PASS_AXIS0_FORWARD] = 4.0 * nh * cs;
+  }
 }
 
 namespace {
@@ -1292,7 +1411,7 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
   (void)mask;
   lshom_ctx* c = g.ctx;
   hipStream_t sm = stream_of(g);
-  const long long nall = g.nhalf * g.nprob;
+  const long long nall = g.nvec * g.nprob;
   DevState init{};
   init.max_iter = 1 << 30;
   init.tol2b2 = -1.0;
@@ -1334,6 +1453,12 @@ lshom_status time_passes_t(Group& g, const Bufs<T>& b, int reps, double* ms_out,
 }  // namespace
 
 lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out) {
+  // the passes a CG solve of this grid runs: the wave passes where they apply
+  struct W3Reset {
+    Group& g;
+    ~W3Reset() { g.w3 = false; }
+  } w3_reset{g};
+  g.w3 = g.w3ok && !g.aniso && !g.tensor;
   if (precision == LSHOM_PRECISION_FP64)
     return time_passes_t<double>(g, get_bufs<double>(g), reps, ms_out, bytes_out, ~0u);
   return time_passes_t<float>(g, get_bufs<float>(g), reps, ms_out, bytes_out, ~0u);

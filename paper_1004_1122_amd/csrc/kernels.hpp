@@ -279,6 +279,9 @@ struct UpdArgs {
   double cinv[kMaxDim];  // 1 / cell side length per axis
   int aniso;             // equilibrium weight xi . L0n . xi in place of |xi|^2
   double L0n[6];
+  int w3;                // vectors in the wave-pass layout V (k_last from (cg, cc))
+  FastDiv fd_w3n0;       // N0
+  int w3g;               // G
 };
 
 // Pipelined CG update (spectral coordinate): s = w + beta s, p = r + beta p,
@@ -350,6 +353,9 @@ struct MixArgs {
   int gate;
   Batch bt;
   FastDiv fd_kd, fd_h;
+  int w3;                // vectors in the wave-pass layout V
+  FastDiv fd_w3n0;
+  int w3g;
 };
 
 struct FinArgs {
@@ -363,6 +369,78 @@ struct FinArgs {
   Batch bt;
   int eq;                // the equilibrium sums beside the (r, r) sums are present
 };
+
+// ---------------------------------------------------------------------------
+// Wave passes of 3-D grids whose axes are 27, 81 or 243 long (wave3d.hip).
+// The last-axis half spectrum (h = N2 / 2 + 1 entries) is padded to
+// G = ceil(h / 8) groups of 8 (cg, cc), c = 8 cg + cc; padded entries hold
+// zeros.  Per problem, with (a, b) the indices of axes 0 and 1:
+//   V  (CG vectors x, r, p, q): ((b G + cg) 8 + cc) N0 + a   (axis 0 fastest)
+//   Gl (axis-0 inverse -> axis-1 inverse): ((b G + cg) N0 + a) 8 + cc
+//   Hl (axis-1 inverse -> row pass -> axis-1 forward -> axis-0 forward,
+//       in place): ((a G + cg) N1 + b) 8 + cc
+// so that every pass writes whole tiles contiguously.
+// ---------------------------------------------------------------------------
+constexpr int kW3Group = 8;
+
+__host__ __device__ constexpr int w3_groups(int h) { return (h + kW3Group - 1) / kW3Group; }
+// axis lengths the wave FFTs take (nine points per lane, whole sequences per wave)
+__host__ __device__ constexpr bool wave_fft_length(long long n) { return n == 27 || n == 81 || n == 243; }
+
+enum W3Pass : int {
+  W3_INV0 = 0,    // axis-0 inverse from the scalar c (or the CG direction step)
+  W3_COL1 = 1,    // axis-1 transform Gl -> Hl (inverse) or Hl -> Hl (forward)
+  W3_ROW = 2,     // row pass (modes of RowMode, flags of RowFlags)
+  W3_FWD0 = 3,    // axis-0 forward + projection
+};
+
+template <typename T>
+struct W3Args {
+  int N0, N1, N2, h, G;
+  long long nhp;                 // padded entries per problem (N0 N1 G 8)
+  cx<T>* gl[kMaxDim];
+  cx<T>* hl[kMaxDim];
+  const cx<T>* tw[kMaxDim];      // exp(-2 pi i m / N_a), per axis
+  double cinv[kMaxDim];          // 1 / cell side lengths: wave vector xi = k / Y
+  // W3_INV0
+  const cx<T>* c_in;
+  cx<T>* p_io;
+  const cx<T>* r_in;
+  int cg_step;
+  // W3_COL1
+  int dir;
+  // W3_ROW
+  int mode, flags;
+  const double* real_in[kMaxDim];
+  double* real_out[kMaxDim];
+  const double* real_add[kMaxDim];
+  const uint8_t* phase;
+  const T* cond;
+  int n_phases;
+  T l0;
+  T E[kMaxDim];
+  T inv_n;
+  // W3_FWD0: out = coef_base base + coef_s [1 / l0] (-i khat) . tau_hat
+  cx<T>* out;
+  const cx<T>* base;
+  T coef_base, coef_s;
+  int s_inv_l0;
+  double l0d;
+  int dot, dot_region;
+  DevState* st;
+  Partials parts;
+  int gate;
+  double inv_nd;
+  Batch bt;
+};
+
+// Blocks of one problem of each wave pass, and their launchers.
+long long w3_blocks(int pass, int N0, int N1, int N2);
+template <typename T> hipError_t launch_w3(int pass, const W3Args<T>& a, hipStream_t s);
+// Entries of the padded spectral layout per problem.
+__host__ __device__ inline long long w3_entries(long long N0, long long N1, long long N2) {
+  return N0 * N1 * (long long)w3_groups((int)(N2 / 2 + 1)) * kW3Group;
+}
 
 // Host launchers (passes.hip).
 template <typename T> hipError_t launch_row(const RowArgs<T>& a, hipStream_t s);

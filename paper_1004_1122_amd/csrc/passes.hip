@@ -809,6 +809,18 @@ __device__ __forceinline__ double spectral_k2(const UpdArgs<T>& a, uint32_t i, u
   return x0 * x0 + x1 * x1 + xl * xl;
 }
 
+// Weight of entry i of a vector in the wave-pass layout V
+// (((b G + cg) 8 + cc) N0 + a; the last-axis column is c = 8 cg + cc, the
+// last axis odd): 1 for c = 0, 2 below h, 0 on the padding.
+__device__ __forceinline__ double w3_entry_weight(uint32_t i, const FastDiv& fd_n0, int G, int h) {
+  const uint32_t col = fdiv(i, fd_n0);           // (b G + cg) 8 + cc
+  const uint32_t cc = col & 7u;
+  const uint32_t bg = col >> 3;                   // b G + cg
+  const uint32_t cg = bg - (bg / (uint32_t)G) * (uint32_t)G;
+  const uint32_t c = cg * 8u + cc;
+  return c == 0 ? 1.0 : (c < (uint32_t)h ? 2.0 : 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // CG update: alpha = (r, r) / (p, q); x += alpha p, r -= alpha q, (r, r)
 // ---------------------------------------------------------------------------
@@ -879,12 +891,16 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
       r[u].im -= ta * q[u].im;
       X[i] = x[u];
       Rv[i] = r[u];
-      const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
-      const uint32_t k_last = kq - fdiv(kq, a.fd_h) * (uint32_t)a.h;
-      const double w = half_weight(k_last, a.n_last);
       const double m2 = (double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im;
-      acc += w * m2;
-      if constexpr (EQ) acc_eq += w * spectral_k2(a, (uint32_t)i, kq, k_last) * m2;
+      if (a.w3) {
+        acc += w3_entry_weight((uint32_t)i, a.fd_w3n0, a.w3g, a.h) * m2;
+      } else {
+        const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
+        const uint32_t k_last = kq - fdiv(kq, a.fd_h) * (uint32_t)a.h;
+        const double w = half_weight(k_last, a.n_last);
+        acc += w * m2;
+        if constexpr (EQ) acc_eq += w * spectral_k2(a, (uint32_t)i, kq, k_last) * m2;
+      }
     }
   }
   const int nxt = (k + 1) & 1;
@@ -1019,8 +1035,13 @@ __global__ __launch_bounds__(256) void mix_convert_kernel(MixArgs a) {
     const cx<double> r = a.r64[vo + i];
     const cx<float> f = cx<float>{(float)r.re, (float)r.im};
     a.r32[vo + i] = f;
-    const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
-    const double w = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
+    double w;
+    if (a.w3) {
+      w = w3_entry_weight((uint32_t)i, a.fd_w3n0, a.w3g, a.h);
+    } else {
+      const uint32_t kq = fdiv((uint32_t)i, a.fd_kd);
+      w = half_weight(kq - fdiv(kq, a.fd_h) * (uint32_t)a.h, a.n_last);
+    }
     acc += w * ((double)f.re * (double)f.re + (double)f.im * (double)f.im);
   }
   store_partial<256>(acc, parts.region(k & 1) + blockIdx.x);

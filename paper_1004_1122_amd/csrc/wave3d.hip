@@ -1,0 +1,612 @@
+// Wave passes of the operator apply on 3-D grids whose axes are 27, 81 or 243
+// nodes long (the layouts V, Gl, Hl are described in kernels.hpp).
+//
+// Same algebra as the block passes of passes.hip: the CG vectors are the
+// spectral coordinate c of the admissible fields, u_hat = i khat c, and one
+// apply is
+//   axis-0 inverse (W3_INV0): c -> F0^-1 [i xi_0 c / |xi|], F0^-1 [i c / |xi|]   V -> Gl
+//   axis-1 inverse (W3_COL1): F1^-1, u_1 also times xi_1                Gl -> Hl
+//   row pass       (W3_ROW):  u_2 times xi_2, F2^-1, dL (E + u), F2,
+//                             tau_2 times xi_2                          Hl -> Hl
+//   axis-1 forward (W3_COL1): F1 tau_0, xi_1 F1 tau_1 + F1 (xi_2 tau_2)   Hl -> Hl
+//   axis-0 forward (W3_FWD0): t = xi_0 F0 [..] + F0 [..] = xi . tau_hat,
+//                             s = -i t / |xi|, out, dot                 Hl -> V
+// (Sec. 2.2, Eqs. (15)-(17): the Green operator k (x) k / (l0 |k|^2) of
+// Sec. 2.1, Eq. (7) becomes the projection on khat and 1 / l0.)  The wave
+// vector components xi_1 and xi_2 are constant along axis 0, so the axis-0
+// passes carry two fields instead of three: xi_1 is applied in the axis-1
+// spectrum and xi_2 in the last-axis spectrum (by linearity of the other
+// transforms), which saves two of the eighteen 1-D transforms of an apply
+// and a sixth of its bytes.
+//
+// Every 1-D transform is a wave-level FFT (wave_fft.hpp): a block is a few
+// independent waves, each owning whole sequences, with one block barrier
+// after the twiddle table is staged.  A block owns one tile (8 columns of
+// one cg group, all points of the transformed axis) and writes it as one
+// contiguous region of its output layout; reads are strided in 128-byte
+// rows (column passes) or contiguous.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "reduce.hpp"
+#include "wave_fft.hpp"
+
+namespace lshom {
+
+namespace {
+
+// columns of a tile transformed by one wave (the tile is 8 columns wide)
+template <int N>
+__host__ __device__ constexpr int w3_cpw() {
+  return N == 243 ? 2 : (N == 81 ? 4 : 8);
+}
+template <int N>
+__host__ __device__ constexpr int w3_col_threads() {
+  return 64 * (kW3Group / w3_cpw<N>());
+}
+// rows per row-pass block: four waves, two real rows per complex sequence
+template <int N>
+__host__ __device__ constexpr int w3_rows_per_block() {
+  return 4 * 2 * WaveGeom<N>::SPW;
+}
+
+__device__ __forceinline__ int w3_freq(int m, int n) { return (m <= n / 2) ? m : m - n; }
+
+// Weight of half-spectrum column c in a full-spectrum sum (the last axis is
+// odd here: column 0 stands for itself, the others for two; padding: 0).
+__device__ __forceinline__ double w3_weight(int c, int h) { return c == 0 ? 1.0 : (c < h ? 2.0 : 0.0); }
+
+// The dispatcher deals the blocks of a launch to the 8 XCDs in turn; the
+// blocks of one tile's three components (consecutive linear ids) should share
+// an XCD (and its L2), so each XCD is given one contiguous run of ids.
+__device__ __forceinline__ unsigned w3_xcd_block() {
+  const unsigned total = gridDim.x, lin = blockIdx.x;
+  const unsigned xcd = lin & 7u, slot = lin >> 3;
+  const unsigned q = total >> 3, rem = total & 7u;
+  return xcd * q + (xcd < rem ? xcd : rem) + slot;
+}
+
+// arr[c] for a runtime c without a dynamically indexed register array
+template <typename V>
+__device__ __forceinline__ V w3_pick(const V (&arr)[kMaxDim], int c) {
+  return c == 0 ? arr[0] : (c == 1 ? arr[1] : arr[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_twiddles(cx<T>* tw, const cx<T>* __restrict__ src, int n, int nt) {
+  for (int i = threadIdx.x; i < n; i += nt) tw[i] = src[i];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Axis-0 inverse: V -> Gl
+// ---------------------------------------------------------------------------
+template <typename T, int N0>
+__global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T> a) {
+  constexpr int NT = w3_col_threads<N0>();
+  constexpr int LPS = WaveGeom<N0>::LPS, CPW = w3_cpw<N0>();
+  const int pb = a.bt.live ? a.bt.live[blockIdx.y] : (int)blockIdx.y;
+  DevState* st = a.st + pb;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  const unsigned bx = blockIdx.x;
+  double beta = 0.0;
+  // the direction step decides beta (and the stop) from the (r, r) sums; all
+  // threads take part in the block reduction before anything else
+  if (a.cg_step) {
+    if (!cg_direction<NT>(st, parts, a.inv_nd, &beta, a.gate, 0, bx == 0)) return;
+  } else if (gated_out_stable(st, a.gate)) {
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  stage_twiddles(tw, a.tw[0], N0, NT);
+  __syncthreads();
+  const int G = a.G, N1 = a.N1;
+  const int b = (int)(bx / (unsigned)G), cg = (int)(bx - (unsigned)b * G);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s = lane / LPS, j = lane - s * LPS;
+  const bool act = s < CPW;
+  const int cc = w * CPW + (act ? s : 0);
+  const int c = cg * kW3Group + cc;
+  cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
+  const long long vo = (long long)pb * a.bt.vstride;
+  // V: ((b G + cg) 8 + cc) N0 + a;  Gl: ((b G + cg) N0 + a) 8 + cc
+  const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
+  const long long gcol = vo + (long long)(b * G + cg) * N0 * kW3Group + cc;
+  cx<T> cv[9];
+  const T tb = (T)beta;
+  if (act) {
+    if (a.cg_step) {
+      cx<T> rv[9], pv[9];
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        rv[r] = a.r_in[vcol + j + LPS * r];
+        pv[r] = a.p_io[vcol + j + LPS * r];
+      }
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        cv[r] = cx<T>{rv[r].re + tb * pv[r].re, rv[r].im + tb * pv[r].im};
+        a.p_io[vcol + j + LPS * r] = cv[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) cv[r] = a.c_in[vcol + j + LPS * r];
+    }
+  }
+  // khat at each point: xi_0 depends on a, xi_1 and xi_2 on the column
+  const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
+  const double x2 = (double)c * a.cinv[2];
+  const bool col_ok = c < a.h;
+  double inv[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) {
+    const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
+    const double k2 = x0 * x0 + x1 * x1 + x2 * x2;
+    inv[r] = (col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0;
+  }
+  (void)x1;
+  (void)x2;
+  // field 0: i xi_0 c / |xi|; field 1: i c / |xi| (xi_1, xi_2 come later)
+#pragma unroll 1
+  for (int al = 0; al < 2; ++al) {
+    cx<T> v[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const double kx = al == 0 ? (double)w3_freq(j + LPS * r, N0) * a.cinv[0] : 1.0;
+      const T k = (T)(kx * inv[r]);
+      v[r] = cx<T>{-k * cv[r].im, k * cv[r].re};
+    }
+    wave_fft<T, N0, +1>(v, buf, tw, j, act);
+    cx<T>* dst = w3_pick(a.gl, al) + gcol;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = buf[j + LPS * r];
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Axis-1 transform: Gl -> Hl (inverse, dir > 0) or Hl -> Hl (forward)
+// ---------------------------------------------------------------------------
+template <typename T, int N1, int DIR>
+__global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T> a) {
+  constexpr int NT = w3_col_threads<N1>();
+  constexpr int LPS = WaveGeom<N1>::LPS, CPW = w3_cpw<N1>();
+  const int pb = a.bt.live ? a.bt.live[blockIdx.y] : (int)blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out_stable(st, a.gate)) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  stage_twiddles(tw, a.tw[1], N1, NT);
+  __syncthreads();
+  const int G = a.G, N0 = a.N0;
+  // block = (tile, output field), the field fastest: inverse u_0, u_1, u_2;
+  // forward the two fields the axis-0 pass takes
+  constexpr unsigned NF = DIR > 0 ? 3u : 2u;
+  const unsigned lin = w3_xcd_block();
+  const int al = (int)(lin % NF);
+  const unsigned bx = lin / NF;
+  const int ai = (int)(bx / (unsigned)G), cg = (int)(bx - (unsigned)ai * G);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s = lane / LPS, j = lane - s * LPS;
+  const bool act = s < CPW;
+  const int cc = w * CPW + (act ? s : 0);
+  cx<T>* buf = tw + N1 + (w * CPW + (act ? s : 0)) * N1;
+  const long long vo = (long long)pb * a.bt.vstride;
+  // Gl: ((b G + cg) N0 + a) 8 + cc (stride in b: G N0 8);  Hl: ((a G + cg) N1 + b) 8 + cc
+  const long long hcol = vo + (long long)(ai * G + cg) * N1 * kW3Group + cc;
+  const long long gcol = vo + ((long long)cg * N0 + ai) * kW3Group + cc;
+  const long long gstep = (long long)G * N0 * kW3Group;
+  cx<T> v[9];
+  if constexpr (DIR > 0) {
+    // u_0 from field 0; u_1 (times xi_1 of the input index) and u_2 from field 1
+    if (act) {
+      const cx<T>* src = (al == 0 ? a.gl[0] : a.gl[1]) + gcol;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        v[r] = src[(long long)(j + LPS * r) * gstep];
+        if (al == 1) {
+          const T k1 = (T)((double)w3_freq(j + LPS * r, N1) * a.cinv[1]);
+          v[r] = cx<T>{k1 * v[r].re, k1 * v[r].im};
+        }
+      }
+    }
+    wave_fft<T, N1, DIR>(v, buf, tw, j, act);
+    cx<T>* dst = w3_pick(a.hl, al) + hcol;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = buf[j + LPS * r];
+    }
+  } else {
+    // field 0: F1 tau_0; field 1: xi_1 F1 tau_1 + F1 (xi_2 tau_2), written over tau_1
+    if (act) {
+      const cx<T>* src = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * kW3Group];
+    }
+    wave_fft<T, N1, DIR>(v, buf, tw, j, act);
+    cx<T> acc[9];
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        acc[r] = buf[j + LPS * r];
+        if (al == 1) {
+          const T k1 = (T)((double)w3_freq(j + LPS * r, N1) * a.cinv[1]);
+          acc[r] = cx<T>{k1 * acc[r].re, k1 * acc[r].im};
+        }
+      }
+    }
+    if (al == 1) {
+      if (act) {
+        const cx<T>* src = a.hl[2] + hcol;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * kW3Group];
+      }
+      wave_fft<T, N1, DIR>(v, buf, tw, j, act);
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          const cx<T> z = buf[j + LPS * r];
+          acc[r] = cx<T>{acc[r].re + z.re, acc[r].im + z.im};
+        }
+      }
+    }
+    cx<T>* dst = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = acc[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass (last axis), Hl in place: rows rho = a N1 + b, two real rows per
+// complex sequence (rho even: first, rho + 1: second).
+// ---------------------------------------------------------------------------
+template <typename T, int N2, int MODE>
+__global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
+  constexpr int LPS = WaveGeom<N2>::LPS, SPW = WaveGeom<N2>::SPW;
+  constexpr int RB = w3_rows_per_block<N2>();
+  const int pb = a.bt.live ? a.bt.live[blockIdx.y] : (int)blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out_stable(st, a.gate)) return;
+  const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  T* cond = reinterpret_cast<T*>(tw + N2 + 4 * SPW * N2);
+  // phase bytes of the block's rows, after the conductivity table (16-byte aligned)
+  uint8_t* phs = reinterpret_cast<uint8_t*>(cond) + ((size_t)a.n_phases * sizeof(T) + 15) / 16 * 16;
+  // block = (row block, component), the component fastest
+  const unsigned lin = w3_xcd_block();
+  const int al = (int)(lin % 3u);
+  const unsigned rb = lin / 3u;
+  const int G = a.G, N1 = a.N1, h = a.h;
+  const long long nrows = (long long)a.N0 * N1;
+  const long long nvox = nrows * N2;
+  const uint8_t* phase = pe ? pe->phase : a.phase;
+  const long long row0 = (long long)rb * RB;
+  stage_twiddles(tw, a.tw[2], N2, 256);
+  const T* csrc = a.cond + (long long)pb * kCondStride;
+  for (int i = threadIdx.x; i < a.n_phases; i += 256) cond[i] = csrc[i];
+  {
+    const long long rows_here = nrows - row0 < RB ? nrows - row0 : RB;
+    const int nb = (int)(rows_here * N2);
+    const uint8_t* src = phase + row0 * N2;
+    if ((reinterpret_cast<uintptr_t>(src) & 3u) == 0) {
+      const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
+      uint32_t* d4 = reinterpret_cast<uint32_t*>(phs);
+      for (int i = threadIdx.x; i < nb / 4; i += 256) d4[i] = s4[i];
+      for (int i = (nb / 4) * 4 + threadIdx.x; i < nb; i += 256) phs[i] = src[i];
+    } else {
+      for (int i = threadIdx.x; i < nb; i += 256) phs[i] = src[i];
+    }
+  }
+  __syncthreads();
+  const T l0 = pe ? (T)pe->l0 : a.l0;
+  const T Ea = (a.flags & ROWF_STATE_E) ? (T)st->E[al] : w3_pick(a.E, al);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s = lane / LPS, j = lane - s * LPS;
+  const bool lane_ok = s < SPW;
+  const long long rhoA = (long long)rb * RB + (long long)(w * SPW + (lane_ok ? s : 0)) * 2;
+  const bool hasA = lane_ok && rhoA < nrows;
+  const bool hasB = lane_ok && rhoA + 1 < nrows;
+  cx<T>* buf = tw + N2 + (w * SPW + (lane_ok ? s : 0)) * N2;
+  const long long vo = (long long)pb * a.bt.vstride;
+  // Hl entry (rho, c): a = rho / N1, b = rho % N1 -> ((a G + cg) N1 + b) 8 + cc
+  auto hidx = [&](long long rho) -> long long {
+    const long long ai = rho / N1, bi = rho - ai * N1;
+    return vo + (ai * G * N1 + bi) * kW3Group;
+  };
+  const long long hA = hasA ? hidx(rhoA) : 0;
+  const long long hB = hasB ? hidx(rhoA + 1) : 0;
+  // entry c of a row relative to its entry 0 (same a and b, cg = c / 8)
+  auto hoff = [&](int c) -> long long { return (long long)(c >> 3) * N1 * kW3Group + (c & 7); };
+  cx<T> v[9];
+  if constexpr (MODE == ROW_FWD) {
+    // real rows in (or the constant E), times dL when asked
+    const double* rin = pe ? (pe->x0 ? pe->x0 + al * nvox : nullptr) : w3_pick(a.real_in, al);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int x = j + LPS * r;
+      T t[2] = {T(0), T(0)};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool has = u == 0 ? hasA : hasB;
+        if (!has) continue;
+        const long long g = (rhoA + u) * N2 + x;
+        T val = (a.flags & ROWF_CONST_E) ? Ea : (rin ? (T)rin[g] : T(0));
+        if (a.flags & ROWF_DL) val *= cond[phs[(int)(g - row0 * N2)]] - l0;
+        t[u] = val;
+      }
+      v[r] = cx<T>{t[0], t[1]};
+    }
+  } else {
+    // two Hermitian half rows -> one full complex row, inverse transform
+    const cx<T>* src = w3_pick(a.hl, al);
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const int k = j + LPS * r;
+      const bool lo = k < h;
+      const int m = lo ? k : N2 - k;
+      cx<T> A = hasA ? src[hA + hoff(m)] : cx<T>{T(0), T(0)};
+      cx<T> B = hasB ? src[hB + hoff(m)] : cx<T>{T(0), T(0)};
+      if (al == 2) {
+        // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
+        const T k2 = (T)((double)m * a.cinv[2]);
+        A = cx<T>{k2 * A.re, k2 * A.im};
+        B = cx<T>{k2 * B.re, k2 * B.im};
+      }
+      v[r] = lo ? cx<T>{A.re - B.im, A.im + B.re} : cx<T>{A.re + B.im, B.re - A.im};
+    }
+    wave_fft<T, N2, +1>(v, buf, tw, j, lane_ok);
+    if constexpr (MODE == ROW_INV) {
+      double* out = pe ? (pe->e_out ? pe->e_out + al * nvox : nullptr) : w3_pick(a.real_out, al);
+      const double* add = w3_pick(a.real_add, al);
+      double acc = 0.0;
+      if (lane_ok) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          const int x = j + LPS * r;
+          const cx<T> z = buf[x];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const bool has = u == 0 ? hasA : hasB;
+            if (!has) continue;
+            const long long g = (rhoA + u) * N2 + x;
+            const int q = phs[(int)(g - row0 * N2)];
+            double val = (double)Ea + (double)((u == 0 ? z.re : z.im) * a.inv_n);
+            if (a.flags & ROWF_DL_OUT) val *= (double)cond[q] - (double)l0;
+            if (a.flags & ROWF_ADD) val += add[g];
+            if (out) out[g] = val;
+            if (a.flags & ROWF_LEFF) acc += (double)cond[q] * val;
+          }
+        }
+      }
+      if (a.flags & ROWF_LEFF) store_partial<256>(acc, parts.region(PART_AUX) + (long long)rb * 3 + al);
+      return;
+    } else {
+      // polarisation dL (E + u) at the nodes (Sec. 2.2, Eq. (17))
+      if (lane_ok) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          const int x = j + LPS * r;
+          const cx<T> z = buf[x];
+          T t0 = T(0), t1 = T(0);
+          const int pa = (int)(rhoA - row0) * N2 + x;
+          if (hasA) t0 = (cond[phs[pa]] - l0) * (Ea + z.re * a.inv_n);
+          if (hasB) t1 = (cond[phs[pa + N2]] - l0) * (Ea + z.im * a.inv_n);
+          v[r] = cx<T>{t0, t1};
+        }
+      }
+    }
+  }
+  if constexpr (MODE != ROW_INV) {
+    wave_fft<T, N2, -1>(v, buf, tw, j, lane_ok);
+    // split the two rows' spectra; the padding of the half rows gets zeros
+    cx<T>* dst = w3_pick(a.hl, al);
+    if (lane_ok) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const int k = j + LPS * r;
+        if (k >= G * kW3Group) continue;
+        cx<T> oa = {T(0), T(0)}, ob = {T(0), T(0)};
+        if (k < h) {
+          const cx<T> Y = buf[k];
+          const cx<T> Ym = buf[k == 0 ? 0 : N2 - k];
+          // tau_2 leaves times xi_2 (the axis-1 pass adds it to xi_1 tau_1)
+          const T half = al == 2 ? T(0.5 * (double)k * a.cinv[2]) : T(0.5);
+          oa = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
+          ob = cx<T>{(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
+        }
+        if (hasA) dst[hA + hoff(k)] = oa;
+        if (hasB) dst[hB + hoff(k)] = ob;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Axis-0 forward + projection: Hl -> V
+// ---------------------------------------------------------------------------
+template <typename T, int N0>
+__global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T> a) {
+  constexpr int NT = w3_col_threads<N0>();
+  constexpr int LPS = WaveGeom<N0>::LPS, CPW = w3_cpw<N0>();
+  const int pb = a.bt.live ? a.bt.live[blockIdx.y] : (int)blockIdx.y;
+  DevState* st = a.st + pb;
+  if (gated_out_stable(st, a.gate)) return;
+  const ProbEntry* pe = a.bt.tab ? a.bt.tab + pb : nullptr;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  stage_twiddles(tw, a.tw[0], N0, NT);
+  __syncthreads();
+  const int G = a.G, N1 = a.N1;
+  const unsigned bx = blockIdx.x;
+  const int b = (int)(bx / (unsigned)G), cg = (int)(bx - (unsigned)b * G);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int s = lane / LPS, j = lane - s * LPS;
+  const bool act = s < CPW;
+  const int cc = w * CPW + (act ? s : 0);
+  const int c = cg * kW3Group + cc;
+  cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
+  const long long vo = (long long)pb * a.bt.vstride;
+  // Hl: ((a G + cg) N1 + b) 8 + cc (stride in a: G N1 8);  V: ((b G + cg) 8 + cc) N0 + a
+  const long long hcol = vo + ((long long)cg * N1 + b) * kW3Group + cc;
+  const long long hstep = (long long)G * N1 * kW3Group;
+  const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
+  const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
+  const double x2 = (double)c * a.cinv[2];
+  const bool col_ok = c < a.h;
+  // t = xi . tau_hat over the components; the factor 1 / |xi| of khat is
+  // applied once at the end (fewer registers live across the transforms)
+  cx<T> t[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) t[r] = cx<T>{T(0), T(0)};
+  (void)x1;
+#pragma unroll 1
+  for (int al = 0; al < 2; ++al) {
+    cx<T> v[9];
+    if (act) {
+      const cx<T>* src = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
+#pragma unroll
+      for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * hstep];
+    }
+    wave_fft<T, N0, -1>(v, buf, tw, j, act);
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        // field 0 carries tau_0 (times xi_0 here), field 1 xi_1 tau_1 + xi_2 tau_2
+        const T k = al == 0 ? (T)((double)w3_freq(j + LPS * r, N0) * a.cinv[0]) : T(1);
+        const cx<T> z = buf[j + LPS * r];
+        t[r].re += k * z.re;
+        t[r].im += k * z.im;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const T cs = a.coef_s * (a.s_inv_l0 ? (T)(1.0 / (pe ? pe->l0 : a.l0d)) : T(1));
+  const double wgt = w3_weight(c, a.h);
+  double acc = 0.0;
+  if (act) {
+    cx<T> bv[9];
+#pragma unroll
+    for (int r = 0; r < 9; ++r) bv[r] = a.base ? a.base[vcol + j + LPS * r] : cx<T>{T(0), T(0)};
+#pragma unroll
+    for (int r = 0; r < 9; ++r) {
+      const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
+      const double k2 = x0 * x0 + x1 * x1 + x2 * x2;
+      const T csk = cs * (T)((col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0);
+      // s = -i khat . tau_hat
+      cx<T> val = {csk * t[r].im, -csk * t[r].re};
+      val.re += a.coef_base * bv[r].re;
+      val.im += a.coef_base * bv[r].im;
+      a.out[vcol + j + LPS * r] = val;
+      if (a.dot == 1) acc += wgt * ((double)bv[r].re * (double)val.re + (double)bv[r].im * (double)val.im);
+      else if (a.dot == 2) acc += wgt * ((double)val.re * (double)val.re + (double)val.im * (double)val.im);
+    }
+  }
+  if (a.dot) {
+    store_partial<NT>(acc, parts.region(a.dot_region) + bx);
+    if (a.dot_region == PART_RR0 && bx == 0 && threadIdx.x == 0) st->nparts[0] = (int)gridDim.x;
+    if (a.dot_region == PART_PQ && bx == 0 && threadIdx.x == 0) st->nparts_pq = (int)gridDim.x;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <int N>
+long long w3_col_blocks_of(int N_other, int G) {
+  return (long long)N_other * G;
+}
+
+template <int N>
+size_t w3_col_lds(int elem) {
+  return (size_t)(N + kW3Group * N) * elem;
+}
+
+template <int N>
+size_t w3_row_lds(int elem, int n_phases) {
+  return (size_t)(N + 4 * WaveGeom<N>::SPW * N) * elem + ((size_t)n_phases * (elem / 2) + 15) / 16 * 16 +
+         (size_t)w3_rows_per_block<N>() * N;
+}
+
+template <typename T, template <typename, int> class K>
+struct Dummy;
+
+template <typename T, int N>
+hipError_t launch_w3_n(int pass, const W3Args<T>& a, hipStream_t s) {
+  const unsigned rows = (unsigned)(a.bt.nprob > 0 ? a.bt.nprob : 1);
+  const int elem = (int)sizeof(cx<T>);
+  switch (pass) {
+    case W3_INV0:
+      hipLaunchKernelGGL((w3_inv0_kernel<T, N>), dim3((unsigned)(a.N1 * a.G), rows), dim3(w3_col_threads<N>()),
+                         w3_col_lds<N>(elem), s, a);
+      break;
+    case W3_COL1:
+      if (a.dir > 0)
+        hipLaunchKernelGGL((w3_col1_kernel<T, N, +1>), dim3((unsigned)(3 * a.N0 * a.G), rows),
+                           dim3(w3_col_threads<N>()), w3_col_lds<N>(elem), s, a);
+      else
+        hipLaunchKernelGGL((w3_col1_kernel<T, N, -1>), dim3((unsigned)(2 * a.N0 * a.G), rows),
+                           dim3(w3_col_threads<N>()), w3_col_lds<N>(elem), s, a);
+      break;
+    case W3_ROW: {
+      const long long nrows = (long long)a.N0 * a.N1;
+      const unsigned nb = 3u * (unsigned)((nrows + w3_rows_per_block<N>() - 1) / w3_rows_per_block<N>());
+      const size_t lds = w3_row_lds<N>(elem, a.n_phases);
+      if (a.mode == ROW_FUSED) hipLaunchKernelGGL((w3_row_kernel<T, N, ROW_FUSED>), dim3(nb, rows), dim3(256), lds, s, a);
+      else if (a.mode == ROW_INV) hipLaunchKernelGGL((w3_row_kernel<T, N, ROW_INV>), dim3(nb, rows), dim3(256), lds, s, a);
+      else hipLaunchKernelGGL((w3_row_kernel<T, N, ROW_FWD>), dim3(nb, rows), dim3(256), lds, s, a);
+      break;
+    }
+    default:
+      hipLaunchKernelGGL((w3_fwd0_kernel<T, N>), dim3((unsigned)(a.N1 * a.G), rows), dim3(w3_col_threads<N>()),
+                         w3_col_lds<N>(elem), s, a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+long long w3_blocks(int pass, int N0, int N1, int N2) {
+  const int G = w3_groups(N2 / 2 + 1);
+  switch (pass) {
+    case W3_INV0:
+    case W3_FWD0:
+      return (long long)N1 * G;
+    case W3_COL1:
+      return (long long)N0 * G;
+    default: {
+      const long long rb = N2 == 243 ? w3_rows_per_block<243>() : (N2 == 81 ? w3_rows_per_block<81>()
+                                                                            : w3_rows_per_block<27>());
+      return ((long long)N0 * N1 + rb - 1) / rb;
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_w3(int pass, const W3Args<T>& a, hipStream_t s) {
+  // the transformed axis decides the kernel
+  const int n = pass == W3_COL1 ? a.N1 : (pass == W3_ROW ? a.N2 : a.N0);
+  if (n == 243) return launch_w3_n<T, 243>(pass, a, s);
+  if (n == 81) return launch_w3_n<T, 81>(pass, a, s);
+  if (n == 27) return launch_w3_n<T, 27>(pass, a, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_w3<double>(int, const W3Args<double>&, hipStream_t);
+template hipError_t launch_w3<float>(int, const W3Args<float>&, hipStream_t);
+
+}  // namespace lshom

@@ -28,7 +28,8 @@ import re
 import statistics
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("passes.hip", "fft_engine.hpp", "reduce.hpp", "kernels.hpp", "radix_consts.hpp")
+KERNEL_SOURCES = ("passes.hip", "wave3d.hip", "wave_fft.hpp", "fft_engine.hpp", "reduce.hpp", "kernels.hpp",
+                  "radix_consts.hpp")
 
 
 def kernel_source_hash():
