@@ -72,6 +72,45 @@ __device__ __forceinline__ V w3_pick(const V (&arr)[kMaxDim], int c) {
   return c == 0 ? arr[0] : (c == 1 ? arr[1] : arr[2]);
 }
 
+// A tile of 8 columns x L points of one field moves between global memory
+// (entry (p, cc) at g + p * pstride + cc) and the block's LDS sequences
+// (column cc at seq + cc * L, points in natural order) with eight
+// consecutive threads on each 128-byte row.  tile_load multiplies point p by
+// xi = freq(p) * ks when ks != 0.
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_load(cx<T>* seq, const cx<T>* __restrict__ g, long long pstride, double ks) {
+  constexpr int TOT = kW3Group * L, PER = (TOT + NT - 1) / NT;
+  cx<T> v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * NT;
+    v[u] = (TOT % NT == 0 || e < TOT) ? g[(long long)(e >> 3) * pstride + (e & 7)] : cx<T>{T(0), T(0)};
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * NT;
+    if (TOT % NT == 0 || e < TOT) {
+      const int pt = e >> 3, cc = e & 7;
+      cx<T> x = v[u];
+      if (ks != 0.0) {
+        const T k = (T)((double)w3_freq(pt, L) * ks);
+        x = cx<T>{k * x.re, k * x.im};
+      }
+      seq[cc * L + pt] = x;
+    }
+  }
+}
+
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, long long pstride, const cx<T>* seq) {
+  constexpr int TOT = kW3Group * L, PER = (TOT + NT - 1) / NT;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * NT;
+    if (TOT % NT == 0 || e < TOT) g[(long long)(e >> 3) * pstride + (e & 7)] = seq[(e & 7) * L + (e >> 3)];
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void stage_twiddles(cx<T>* tw, const cx<T>* __restrict__ src, int n, int nt) {
   for (int i = threadIdx.x; i < n; i += nt) tw[i] = src[i];
@@ -114,7 +153,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
   const long long vo = (long long)pb * a.bt.vstride;
   // V: ((b G + cg) 8 + cc) N0 + a;  Gl: ((b G + cg) N0 + a) 8 + cc
   const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
-  const long long gcol = vo + (long long)(b * G + cg) * N0 * kW3Group + cc;
+  const long long gtile = vo + (long long)(b * G + cg) * N0 * kW3Group;
   cx<T> cv[9];
   const T tb = (T)beta;
   if (act) {
@@ -159,12 +198,9 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
       v[r] = cx<T>{-k * cv[r].im, k * cv[r].re};
     }
     wave_fft<T, N0, +1>(v, buf, tw, j, act);
-    cx<T>* dst = w3_pick(a.gl, al) + gcol;
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = buf[j + LPS * r];
-    }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    tile_store<T, N0, NT>((al == 0 ? a.gl[0] : a.gl[1]) + gtile, kW3Group, tw + N0);
+    __syncthreads();
   }
 }
 
@@ -180,8 +216,8 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
   if (gated_out_stable(st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  cx<T>* seq = tw + N1;
   stage_twiddles(tw, a.tw[1], N1, NT);
-  __syncthreads();
   const int G = a.G, N0 = a.N0;
   // block = (tile, output field), the field fastest: inverse u_0, u_1, u_2;
   // forward the two fields the axis-0 pass takes
@@ -193,72 +229,48 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int s = lane / LPS, j = lane - s * LPS;
   const bool act = s < CPW;
-  const int cc = w * CPW + (act ? s : 0);
-  cx<T>* buf = tw + N1 + (w * CPW + (act ? s : 0)) * N1;
+  cx<T>* buf = seq + (w * CPW + (act ? s : 0)) * N1;
   const long long vo = (long long)pb * a.bt.vstride;
   // Gl: ((b G + cg) N0 + a) 8 + cc (stride in b: G N0 8);  Hl: ((a G + cg) N1 + b) 8 + cc
-  const long long hcol = vo + (long long)(ai * G + cg) * N1 * kW3Group + cc;
-  const long long gcol = vo + ((long long)cg * N0 + ai) * kW3Group + cc;
+  const long long htile = vo + (long long)(ai * G + cg) * N1 * kW3Group;
+  const long long gtile = vo + ((long long)cg * N0 + ai) * kW3Group;
   const long long gstep = (long long)G * N0 * kW3Group;
-  cx<T> v[9];
   if constexpr (DIR > 0) {
     // u_0 from field 0; u_1 (times xi_1 of the input index) and u_2 from field 1
-    if (act) {
-      const cx<T>* src = (al == 0 ? a.gl[0] : a.gl[1]) + gcol;
-#pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        v[r] = src[(long long)(j + LPS * r) * gstep];
-        if (al == 1) {
-          const T k1 = (T)((double)w3_freq(j + LPS * r, N1) * a.cinv[1]);
-          v[r] = cx<T>{k1 * v[r].re, k1 * v[r].im};
-        }
-      }
-    }
-    wave_fft<T, N1, DIR>(v, buf, tw, j, act);
-    cx<T>* dst = w3_pick(a.hl, al) + hcol;
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = buf[j + LPS * r];
-    }
+    tile_load<T, N1, NT>(seq, (al == 0 ? a.gl[0] : a.gl[1]) + gtile, gstep, al == 1 ? a.cinv[1] : 0.0);
+    __syncthreads();
+    wave_fft_lds<T, N1, DIR>(buf, tw, j, act);
+    __syncthreads();
+    tile_store<T, N1, NT>(w3_pick(a.hl, al) + htile, kW3Group, seq);
   } else {
     // field 0: F1 tau_0; field 1: xi_1 F1 tau_1 + F1 (xi_2 tau_2), written over tau_1
-    if (act) {
-      const cx<T>* src = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
+    tile_load<T, N1, NT>(seq, (al == 0 ? a.hl[0] : a.hl[1]) + htile, kW3Group, 0.0);
+    __syncthreads();
+    wave_fft_lds<T, N1, DIR>(buf, tw, j, act);
+    if (al == 1) {
+      cx<T> acc[9];
+      if (act) {
 #pragma unroll
-      for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * kW3Group];
-    }
-    wave_fft<T, N1, DIR>(v, buf, tw, j, act);
-    cx<T> acc[9];
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        acc[r] = buf[j + LPS * r];
-        if (al == 1) {
+        for (int r = 0; r < 9; ++r) {
           const T k1 = (T)((double)w3_freq(j + LPS * r, N1) * a.cinv[1]);
-          acc[r] = cx<T>{k1 * acc[r].re, k1 * acc[r].im};
+          const cx<T> z = buf[j + LPS * r];
+          acc[r] = cx<T>{k1 * z.re, k1 * z.im};
         }
       }
-    }
-    if (al == 1) {
-      if (act) {
-        const cx<T>* src = a.hl[2] + hcol;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * kW3Group];
-      }
-      wave_fft<T, N1, DIR>(v, buf, tw, j, act);
+      __syncthreads();
+      tile_load<T, N1, NT>(seq, a.hl[2] + htile, kW3Group, 0.0);
+      __syncthreads();
+      wave_fft_lds<T, N1, DIR>(buf, tw, j, act);
       if (act) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           const cx<T> z = buf[j + LPS * r];
-          acc[r] = cx<T>{acc[r].re + z.re, acc[r].im + z.im};
+          buf[j + LPS * r] = cx<T>{acc[r].re + z.re, acc[r].im + z.im};
         }
       }
     }
-    cx<T>* dst = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
-    if (act) {
-#pragma unroll
-      for (int r = 0; r < 9; ++r) dst[(long long)(j + LPS * r) * kW3Group] = acc[r];
-    }
+    __syncthreads();
+    tile_store<T, N1, NT>((al == 0 ? a.hl[0] : a.hl[1]) + htile, kW3Group, seq);
   }
 }
 
@@ -347,23 +359,35 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
     }
   } else {
     // two Hermitian half rows -> one full complex row, inverse transform
+    // each stored half-spectrum entry m < h of the two rows is read once and
+    // placed at m and (its Hermitian image) N2 - m of the packed sequence
     const cx<T>* src = w3_pick(a.hl, al);
+    constexpr int RH = (N2 / 2 + 1 + LPS - 1) / LPS;  // half-entries per lane
+    cx<T> A[RH], B[RH];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) {
-      const int k = j + LPS * r;
-      const bool lo = k < h;
-      const int m = lo ? k : N2 - k;
-      cx<T> A = hasA ? src[hA + hoff(m)] : cx<T>{T(0), T(0)};
-      cx<T> B = hasB ? src[hB + hoff(m)] : cx<T>{T(0), T(0)};
-      if (al == 2) {
-        // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
-        const T k2 = (T)((double)m * a.cinv[2]);
-        A = cx<T>{k2 * A.re, k2 * A.im};
-        B = cx<T>{k2 * B.re, k2 * B.im};
-      }
-      v[r] = lo ? cx<T>{A.re - B.im, A.im + B.re} : cx<T>{A.re + B.im, B.re - A.im};
+    for (int r = 0; r < RH; ++r) {
+      const int m = j + LPS * r;
+      A[r] = (hasA && m < h) ? src[hA + hoff(m)] : cx<T>{T(0), T(0)};
+      B[r] = (hasB && m < h) ? src[hB + hoff(m)] : cx<T>{T(0), T(0)};
     }
-    wave_fft<T, N2, +1>(v, buf, tw, j, lane_ok);
+    __builtin_amdgcn_wave_barrier();
+    if (lane_ok) {
+#pragma unroll
+      for (int r = 0; r < RH; ++r) {
+        const int m = j + LPS * r;
+        if (m >= h) continue;
+        cx<T> Am = A[r], Bm = B[r];
+        if (al == 2) {
+          // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
+          const T k2 = (T)((double)m * a.cinv[2]);
+          Am = cx<T>{k2 * Am.re, k2 * Am.im};
+          Bm = cx<T>{k2 * Bm.re, k2 * Bm.im};
+        }
+        buf[m] = cx<T>{Am.re - Bm.im, Am.im + Bm.re};
+        if (m > 0) buf[N2 - m] = cx<T>{Am.re + Bm.im, Bm.re - Am.im};
+      }
+    }
+    wave_fft_lds<T, N2, +1>(buf, tw, j, lane_ok);
     if constexpr (MODE == ROW_INV) {
       double* out = pe ? (pe->e_out ? pe->e_out + al * nvox : nullptr) : w3_pick(a.real_out, al);
       const double* add = w3_pick(a.real_add, al);
@@ -458,7 +482,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
   const long long vo = (long long)pb * a.bt.vstride;
   // Hl: ((a G + cg) N1 + b) 8 + cc (stride in a: G N1 8);  V: ((b G + cg) 8 + cc) N0 + a
-  const long long hcol = vo + ((long long)cg * N1 + b) * kW3Group + cc;
+  const long long htile = vo + ((long long)cg * N1 + b) * kW3Group;
   const long long hstep = (long long)G * N1 * kW3Group;
   const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
   const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
@@ -472,13 +496,10 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   (void)x1;
 #pragma unroll 1
   for (int al = 0; al < 2; ++al) {
-    cx<T> v[9];
-    if (act) {
-      const cx<T>* src = (al == 0 ? a.hl[0] : a.hl[1]) + hcol;
-#pragma unroll
-      for (int r = 0; r < 9; ++r) v[r] = src[(long long)(j + LPS * r) * hstep];
-    }
-    wave_fft<T, N0, -1>(v, buf, tw, j, act);
+    __syncthreads();
+    tile_load<T, N0, NT>(tw + N0, (al == 0 ? a.hl[0] : a.hl[1]) + htile, hstep, 0.0);
+    __syncthreads();
+    wave_fft_lds<T, N0, -1>(buf, tw, j, act);
     if (act) {
 #pragma unroll
       for (int r = 0; r < 9; ++r) {

@@ -119,4 +119,18 @@ __device__ __forceinline__ void wave_fft(cx<T> (&v)[9], cx<T>* buf, const cx<T>*
   wfft_detail::stages_from<T, N, S, 9>(buf, tw, j, act);
 }
 
+// The same transform for a sequence already stored in natural order in buf
+// (by this wave's lanes or, after a block barrier, by others).
+template <typename T, int N, int S>
+__device__ __forceinline__ void wave_fft_lds(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act) {
+  constexpr int LPS = N / 9;
+  cx<T> v[9];
+  __builtin_amdgcn_wave_barrier();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) v[r] = buf[j + LPS * r];
+  }
+  wave_fft<T, N, S>(v, buf, tw, j, act);
+}
+
 }  // namespace lshom
