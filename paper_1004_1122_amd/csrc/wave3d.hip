@@ -330,14 +330,19 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
   cx<T>* buf = tw + N2 + (w * SPW + (lane_ok ? s : 0)) * N2;
   const long long vo = (long long)pb * a.bt.vstride;
   // Hl entry (rho, c): a = rho / N1, b = rho % N1 -> ((a G + cg) N1 + b) 8 + cc
-  auto hidx = [&](long long rho) -> long long {
-    const long long ai = rho / N1, bi = rho - ai * N1;
-    return vo + (ai * G * N1 + bi) * kW3Group;
-  };
-  const long long hA = hasA ? hidx(rhoA) : 0;
-  const long long hB = hasB ? hidx(rhoA + 1) : 0;
   // entry c of a row relative to its entry 0 (same a and b, cg = c / 8)
   auto hoff = [&](int c) -> long long { return (long long)(c >> 3) * N1 * kW3Group + (c & 7); };
+  // Hl entry 0 of the wave's row wrow + t (t < 2 SPW), without a division per row
+  const int wrow32 = (int)rb * RB + w * SPW * 2;
+  const int wa0 = wrow32 / N1, wb0 = wrow32 - wa0 * N1;
+  auto wbase = [&](int t) -> long long {
+    int ai = wa0, bi = wb0 + t;
+    while (bi >= N1) {
+      bi -= N1;
+      ++ai;
+    }
+    return vo + ((long long)ai * G * N1 + bi) * kW3Group;
+  };
   cx<T> v[9];
   if constexpr (MODE == ROW_FWD) {
     // real rows in (or the constant E), times dL when asked
@@ -359,33 +364,41 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
     }
   } else {
     // two Hermitian half rows -> one full complex row, inverse transform
-    // each stored half-spectrum entry m < h of the two rows is read once and
-    // placed at m and (its Hermitian image) N2 - m of the packed sequence
+    // each stored half-spectrum entry m < h of the wave's rows is read once
+    // (eight consecutive lanes on one 128-byte group of a row) and placed at
+    // m and (its Hermitian image) N2 - m of the packed sequence
     const cx<T>* src = w3_pick(a.hl, al);
-    constexpr int RH = (N2 / 2 + 1 + LPS - 1) / LPS;  // half-entries per lane
-    cx<T> A[RH], B[RH];
+    constexpr int HP = w3_groups(N2 / 2 + 1) * kW3Group;  // padded half length
+    constexpr int TOT = SPW * HP;                          // entries of the wave's rows
+    constexpr int IT = (TOT + 63) / 64;
+    const long long wrow = (long long)rb * RB + (long long)w * SPW * 2;  // the wave's first row
+    cx<T>* wseq = tw + N2 + w * SPW * N2;
+    cx<T> A[IT], B[IT];
 #pragma unroll
-    for (int r = 0; r < RH; ++r) {
-      const int m = j + LPS * r;
-      A[r] = (hasA && m < h) ? src[hA + hoff(m)] : cx<T>{T(0), T(0)};
-      B[r] = (hasB && m < h) ? src[hB + hoff(m)] : cx<T>{T(0), T(0)};
+    for (int it = 0; it < IT; ++it) {
+      const int e = lane + 64 * it;
+      const int qq = (e >> 3) % SPW, m = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      const long long ra = wrow + 2 * qq;
+      const bool ok = e < TOT && m < h;
+      A[it] = (ok && ra < nrows) ? src[wbase(2 * qq) + hoff(m)] : cx<T>{T(0), T(0)};
+      B[it] = (ok && ra + 1 < nrows) ? src[wbase(2 * qq + 1) + hoff(m)] : cx<T>{T(0), T(0)};
     }
     __builtin_amdgcn_wave_barrier();
-    if (lane_ok) {
 #pragma unroll
-      for (int r = 0; r < RH; ++r) {
-        const int m = j + LPS * r;
-        if (m >= h) continue;
-        cx<T> Am = A[r], Bm = B[r];
-        if (al == 2) {
-          // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
-          const T k2 = (T)((double)m * a.cinv[2]);
-          Am = cx<T>{k2 * Am.re, k2 * Am.im};
-          Bm = cx<T>{k2 * Bm.re, k2 * Bm.im};
-        }
-        buf[m] = cx<T>{Am.re - Bm.im, Am.im + Bm.re};
-        if (m > 0) buf[N2 - m] = cx<T>{Am.re + Bm.im, Bm.re - Am.im};
+    for (int it = 0; it < IT; ++it) {
+      const int e = lane + 64 * it;
+      const int qq = (e >> 3) % SPW, m = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      if (e >= TOT || m >= h) continue;
+      cx<T> Am = A[it], Bm = B[it];
+      if (al == 2) {
+        // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
+        const T k2 = (T)((double)m * a.cinv[2]);
+        Am = cx<T>{k2 * Am.re, k2 * Am.im};
+        Bm = cx<T>{k2 * Bm.re, k2 * Bm.im};
       }
+      cx<T>* sq = wseq + qq * N2;
+      sq[m] = cx<T>{Am.re - Bm.im, Am.im + Bm.re};
+      if (m > 0) sq[N2 - m] = cx<T>{Am.re + Bm.im, Bm.re - Am.im};
     }
     wave_fft_lds<T, N2, +1>(buf, tw, j, lane_ok);
     if constexpr (MODE == ROW_INV) {
@@ -431,25 +444,32 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
   }
   if constexpr (MODE != ROW_INV) {
     wave_fft<T, N2, -1>(v, buf, tw, j, lane_ok);
-    // split the two rows' spectra; the padding of the half rows gets zeros
+    __builtin_amdgcn_wave_barrier();
+    // split the two rows' spectra (tau_2 times xi_2: the axis-1 pass adds it
+    // to xi_1 tau_1); eight consecutive lanes write one 128-byte group of a
+    // row; the padding of the half rows gets zeros
     cx<T>* dst = w3_pick(a.hl, al);
-    if (lane_ok) {
+    constexpr int HP = w3_groups(N2 / 2 + 1) * kW3Group;
+    constexpr int TOT = SPW * HP;
+    const long long wrow = (long long)rb * RB + (long long)w * SPW * 2;
+    const cx<T>* wseq = tw + N2 + w * SPW * N2;
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        const int k = j + LPS * r;
-        if (k >= G * kW3Group) continue;
-        cx<T> oa = {T(0), T(0)}, ob = {T(0), T(0)};
-        if (k < h) {
-          const cx<T> Y = buf[k];
-          const cx<T> Ym = buf[k == 0 ? 0 : N2 - k];
-          // tau_2 leaves times xi_2 (the axis-1 pass adds it to xi_1 tau_1)
-          const T half = al == 2 ? T(0.5 * (double)k * a.cinv[2]) : T(0.5);
-          oa = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
-          ob = cx<T>{(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
-        }
-        if (hasA) dst[hA + hoff(k)] = oa;
-        if (hasB) dst[hB + hoff(k)] = ob;
+    for (int e0 = 0; e0 < TOT; e0 += 64) {
+      const int e = e0 + lane;
+      if (TOT % 64 != 0 && e >= TOT) break;
+      const int qq = (e >> 3) % SPW, k = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      const long long ra = wrow + 2 * qq;
+      cx<T> oa = {T(0), T(0)}, ob = {T(0), T(0)};
+      if (k < h) {
+        const cx<T>* sq = wseq + qq * N2;
+        const cx<T> Y = sq[k];
+        const cx<T> Ym = sq[k == 0 ? 0 : N2 - k];
+        const T half = al == 2 ? T(0.5 * (double)k * a.cinv[2]) : T(0.5);
+        oa = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
+        ob = cx<T>{(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
       }
+      if (ra < nrows) dst[wbase(2 * qq) + hoff(k)] = oa;
+      if (ra + 1 < nrows) dst[wbase(2 * qq + 1) + hoff(k)] = ob;
     }
   }
 }
