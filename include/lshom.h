@@ -249,6 +249,27 @@ lshom_status lshom_solve(lshom_ctx* ctx, const double* E_host, double tol,
                          double* leff_host, lshom_solve_info* info);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lshom_solve for the
+ * context's current microstructure with the library's own scratch as the
+ * workspace, a file-scope device array of LSHOM_STATIC_WORKSPACE_BYTES per
+ * GPU, held until the process ends.  No device memory is allocated or freed
+ * and no graph is instantiated (iterations are launched one by one); the
+ * caller still passes the outputs, and the context keeps the workspace it
+ * had (lshom_set_workspace is not needed for this call).
+ * Arguments, outputs and statuses as for lshom_solve, without a warm start.
+ * Returns LSHOM_ERR_UNSUPPORTED when the problem and options need more than
+ * LSHOM_STATIC_WORKSPACE_BYTES (lshom_workspace_size_for tells).  Every call
+ * on one GPU uses the same array: calls from one process are serialised per
+ * GPU (a call waits for the previous one), and each call initialises all it
+ * reads.
+ */
+#define LSHOM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+lshom_status lshom_solve_static(lshom_ctx* ctx, const double* E_host, double tol,
+                                const lshom_solve_opts* opts, double* e_dev, double* leff_host,
+                                lshom_solve_info* info);
+
+/*
  * Effective conductivity tensor from the d load cases E = e_b: column b of
  * leff_host (d x d, row-major) is <lambda e> for E = e_b.  infos: d reports
  * (may be NULL).  Returns the worst status.

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -617,6 +619,98 @@ lshom_status lshom_solve(lshom_ctx* c, const double* E_host, double tol, const l
   else if (s == LSHOM_ERR_NOT_CONVERGED) c->err = "not converged within max_iter";
   else if (s == LSHOM_ERR_BREAKDOWN) c->err = "CG breakdown";
   return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// In host code this name is a stand-in, not a device address: kernels and
+// copies get the per-device address from hipGetSymbolAddress.
+__device__ __align__(256) unsigned char scratch[LSHOM_STATIC_WORKSPACE_BYTES];
+
+struct ScratchTable {
+  std::mutex lock;
+  std::map<int, char*> addr;                        // device -> address of `scratch`
+  std::map<int, std::unique_ptr<std::mutex>> busy;  // device -> one call at a time
+};
+
+ScratchTable& scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
+// Address of this device's copy of `scratch` (the device is current) and the
+// lock that serialises its users.
+lshom_status scratch_for(lshom_ctx* c, char** out, std::mutex** busy) {
+  ScratchTable& t = scratch_table();
+  std::lock_guard<std::mutex> guard(t.lock);
+  auto it = t.addr.find(c->device);
+  if (it == t.addr.end()) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, LSHOM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = t.addr.emplace(c->device, static_cast<char*>(p)).first;
+    t.busy.emplace(c->device, std::make_unique<std::mutex>());
+  }
+  *out = it->second;
+  *busy = t.busy[c->device].get();
+  return LSHOM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lshom_status lshom_solve_static(lshom_ctx* c, const double* E_host, double tol, const lshom_solve_opts* opts,
+                                double* e_dev, double* leff_host, lshom_solve_info* info) {
+  if (!c) return LSHOM_ERR_INVALID_ARG;
+  if (!c->have_problem) return fail(c, LSHOM_ERR_STATE, "set_microstructure has not been called");
+  lshom_solve_opts o;
+  lshom_default_opts(&o);
+  if (opts) o = *opts;
+  lshom_status s = validate_opts(c, &o);
+  if (s != LSHOM_OK) return s;
+  const bool extra = o.method == LSHOM_METHOD_BICG || o.method == LSHOM_METHOD_PIPECG;
+  const Layout need = compute_layout(c->g, o.precision == LSHOM_PRECISION_MIXED, extra);
+  if (need.total > LSHOM_STATIC_WORKSPACE_BYTES)
+    return fail(c, LSHOM_ERR_UNSUPPORTED,
+                "this problem needs " + std::to_string(need.total) + " bytes of workspace; the static scratch holds " +
+                    std::to_string((size_t)LSHOM_STATIC_WORKSPACE_BYTES) + " (use lshom_solve with a workspace)");
+  DeviceGuard dg(c->device);
+  char* ptr = nullptr;
+  std::mutex* busy = nullptr;
+  if ((s = scratch_for(c, &ptr, &busy)) != LSHOM_OK) return s;
+  std::lock_guard<std::mutex> one_at_a_time(*busy);
+  // the context lends its problem; its own workspace (and the iteration
+  // graphs captured on it) come back on every exit
+  struct Restore {
+    lshom_ctx* c;
+    char* ws;
+    Layout lay;
+    size_t bytes;
+    bool ready;
+    ~Restore() {
+      c->g.ws = ws;
+      c->g.lay = lay;
+      c->ws_bytes = bytes;
+      c->ws_ready = ready;
+    }
+  } restore{c, c->g.ws, c->g.lay, c->ws_bytes, c->ws_ready};
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->g.ws = ptr;
+  c->g.lay = need;
+  c->ws_bytes = LSHOM_STATIC_WORKSPACE_BYTES;
+  c->ws_ready = false;
+  if ((s = prepare_workspace(c->g, c->cond, nullptr, {c->g.phase})) != LSHOM_OK) return s;
+  c->ws_ready = true;
+  o.graph_block = 0;
+  return lshom_solve(c, E_host, tol, &o, nullptr, e_dev, leff_host, info);
 }
 
 lshom_status lshom_homogenize(lshom_ctx* c, double tol, const lshom_solve_opts* opts,

@@ -33,6 +33,8 @@ LSHOM_ERR_NOT_CONVERGED = -5
 LSHOM_ERR_BREAKDOWN = -6
 LSHOM_ERR_UNSUPPORTED = -7
 
+LSHOM_STATIC_WORKSPACE_BYTES = 64 << 20
+
 PRECISION_FP64 = 0
 PRECISION_MIXED = 1
 
@@ -182,6 +184,8 @@ def load(path: str = LIB_PATH):
         "lshom_set_workspace": (c_int32, [P, P, c_size_t]),
         "lshom_solve": (c_int32, [P, POINTER(c_double), c_double, POINTER(lshom_solve_opts), P, P,
                                   POINTER(c_double), POINTER(lshom_solve_info)]),
+        "lshom_solve_static": (c_int32, [P, POINTER(c_double), c_double, POINTER(lshom_solve_opts), P,
+                                         POINTER(c_double), POINTER(lshom_solve_info)]),
         "lshom_homogenize": (c_int32, [P, c_double, POINTER(lshom_solve_opts), POINTER(c_double),
                                        POINTER(lshom_solve_info)]),
         "lshom_apply": (c_int32, [P, P, P]),

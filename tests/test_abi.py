@@ -93,6 +93,16 @@ def test_null_context_is_rejected(lib):
     assert lib.lshom_set_microstructure_tensor(None, 2, N, None, 1, eye) == -1
     o = lshom.lshom_default_opts()
     assert lib.lshom_workspace_size_for(None, ctypes.byref(o), ctypes.byref(size)) == -1
+    E = (ctypes.c_double * 2)(1.0, 0.0)
+    assert lib.lshom_solve_static(None, E, 1e-6, None, None, None, None) == -1
+
+
+def test_static_workspace_size_matches_header():
+    import re
+    text = open(lshom.HEADER_PATH).read()
+    m = re.search(r"#define LSHOM_STATIC_WORKSPACE_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "LSHOM_STATIC_WORKSPACE_BYTES not found in the header"
+    assert int(m.group(1)) << int(m.group(2)) == lshom.LSHOM_STATIC_WORKSPACE_BYTES
 
 
 def test_method_constants_match_header():
