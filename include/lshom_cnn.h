@@ -87,6 +87,43 @@ lshom_status lshom_cnn_forward(lshom_cnn* net, const uint8_t* phase_dev, const f
 lshom_status lshom_cnn_train_step(lshom_cnn* net, const uint8_t* phase_dev, const float* log10_rho_dev,
                                   const double* e_dev, int batch, int n, float lr, int update, double* loss_host);
 
+/*
+ * Layer calls: one convolution of the network (the building blocks of
+ * lshom_cnn_forward and lshom_cnn_train_step) on caller tensors, with the
+ * bfloat16 copies of the parameters last set or updated.  layer: index in
+ * the execution order above (0 = enc0a ... 20 = head).  The shape is that of
+ * the workspace set last (batch images of n x n); layer l works on its
+ * level's grid: output side ho = n / 3^level, input side hi = ho except
+ * 3 ho for the down layers (3x3 stride-3 convolution) and ho / 3 for the up
+ * layers (whose convolution reads the nearest-neighbour upsampling of its
+ * input).  Tensors are NHWC; bfloat16 tensors are raw 16-bit words.  cin is
+ * the channel count the layer reads (8 for enc0a, whose channels 2..7 meet
+ * zero weights), cout its output channels, cout8 = cout rounded up to 8.
+ *
+ * lshom_cnn_layer_forward: x_dev bf16 [batch][hi][hi][cin]; the FP32 value
+ *   y = bias + conv(x, w), then ReLU except for the head, goes rounded to
+ *   nearest even into y_dev (bf16 [batch][ho][ho][cout]) and as is into
+ *   yf_dev (FP32, same shape); either may be NULL, not both.
+ * lshom_cnn_layer_dgrad: gy_dev bf16 [batch][ho][ho][cout8], the gradient at
+ *   the layer's pre-activation output (channels >= cout finite; they meet
+ *   zero weights); gx_dev FP32 [batch][hi][hi][cin] receives the gradient
+ *   with respect to the layer's input (the adjoint of the convolution, and
+ *   for up layers that of the upsampling: the sum over each 3 x 3 block).
+ *   Needs a training workspace.
+ * lshom_cnn_layer_wgrad: x_dev, gy_dev as above; the layer's weight and bias
+ *   gradients (sums over all pixels of the batch) overwrite its entries of
+ *   the gradient buffer (read with lshom_cnn_get_grads; the other layers'
+ *   entries are unchanged).  Needs a training workspace.
+ * Products of bfloat16 values are exact in FP32; the sums are FP32 (matrix
+ * cores, then a fixed-order sum of the weight gradient's pixel splits).
+ * Blocking; INVALID_ARG for NULL pointers or a layer out of range,
+ * STATE / WORKSPACE when parameters or a suitable workspace are missing.
+ */
+lshom_status lshom_cnn_layer_forward(lshom_cnn* net, int layer, const uint16_t* x_dev, uint16_t* y_dev,
+                                     float* yf_dev);
+lshom_status lshom_cnn_layer_dgrad(lshom_cnn* net, int layer, const uint16_t* gy_dev, float* gx_dev);
+lshom_status lshom_cnn_layer_wgrad(lshom_cnn* net, int layer, const uint16_t* x_dev, const uint16_t* gy_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -197,15 +197,21 @@ def _input_of(name, acts):
     raise KeyError(name)
 
 
-def backward(params, acts, gy, c0: int = 32):
-    """Gradients of sum(gy * forward(params, x)) for every parameter (and x)."""
+def backward(params, acts, gy, c0: int = 32, round_grad=None):
+    """Gradients of sum(gy * forward(params, x)) for every parameter (and x).
+    round_grad: optional function applied to the gradient at each layer's
+    pre-activation output (after the ReLU mask), the operand of that layer's
+    weight- and input-gradient products (e.g. bf16, to follow a
+    low-precision implementation)."""
     grads = {}
     specs = {n: k for n, k, _, _ in layer_specs(c0, acts["x"].shape[-1])}
+    rnd = round_grad or (lambda a: a)
 
     def back(name, g_out, act=True):
         w, _ = params[name]
         if act:
             g_out = g_out * (acts[name] > 0)
+        g_out = rnd(g_out)
         inp = _input_of(name, acts)
         fn = {"conv3": conv3_backward, "down3": down3_backward, "conv1": conv1_backward}[specs[name]]
         gx, gw, gb = fn(inp, w, g_out)

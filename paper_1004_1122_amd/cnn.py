@@ -36,6 +36,9 @@ def _lib():
             "lshom_cnn_set_workspace": (c_int, [P, P, c_size_t, c_int, c_int, c_int]),
             "lshom_cnn_forward": (c_int, [P, P, P, c_int, c_int, c_int, c_int, P, P]),
             "lshom_cnn_train_step": (c_int, [P, P, P, P, c_int, c_int, c_float, c_int, POINTER(c_double)]),
+            "lshom_cnn_layer_forward": (c_int, [P, c_int, P, P, P]),
+            "lshom_cnn_layer_dgrad": (c_int, [P, c_int, P, P]),
+            "lshom_cnn_layer_wgrad": (c_int, [P, c_int, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -63,6 +66,20 @@ def layer_shapes(c0: int = 32):
               (f"dec{lev}b", (3, 3, c[lev], c[lev]))]
     s.append(("head", (c[0], 2)))
     return [(n, shp, shp[-1]) for n, shp in s]
+
+
+_LEVEL_OUT = (0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0, 0)
+
+
+def layer_geometry(index: int, n: int, c0: int = 32):
+    """Grids and channels of layer `index` (execution order) of a layer call
+    on n x n images: (name, hi, ho, cin, cout) with cin the channels the
+    kernel reads (8 for the input layer)."""
+    name, shp, cout = layer_shapes(c0)[index]
+    ho = n // 3 ** _LEVEL_OUT[index]
+    hi = 3 * ho if name.startswith("down") else (ho // 3 if name.startswith("up") else ho)
+    cin = 8 if index == 0 else shp[-2]
+    return name, hi, ho, cin, cout
 
 
 def he_init(c0: int = 32, seed: int = 0) -> np.ndarray:
@@ -229,6 +246,56 @@ class WarmStartNet:
                                                   c_void_p(e.data_ptr()), B, N, float(lr), int(bool(update)),
                                                   ctypes.byref(loss)))
         return float(loss.value)
+
+
+    # layer calls -------------------------------------------------------
+    def _layer_ws(self, B, N, training):
+        self._ensure_ws(B, N, training)
+
+    def layer_forward(self, index, x, n):
+        """Layer `index` on x (bfloat16 [B, hi, hi, cin]) of n x n images:
+        (y bfloat16, y float32), both [B, ho, ho, cout]."""
+        torch = self.torch
+        _, hi, ho, cin, cout = layer_geometry(index, n, self.c0)
+        x = x.to(device=self.device, dtype=torch.bfloat16).contiguous()
+        if tuple(x.shape[1:]) != (hi, hi, cin):
+            raise ValueError(f"layer {index}: x must be [B, {hi}, {hi}, {cin}], got {tuple(x.shape)}")
+        B = x.shape[0]
+        self._layer_ws(B, n, False)
+        y = torch.empty((B, ho, ho, cout), dtype=torch.bfloat16, device=self.device)
+        yf = torch.empty((B, ho, ho, cout), dtype=torch.float32, device=self.device)
+        self._check(self.lib.lshom_cnn_layer_forward(self.h, int(index), c_void_p(x.data_ptr()),
+                                                     c_void_p(y.data_ptr()), c_void_p(yf.data_ptr())))
+        return y, yf
+
+    def layer_dgrad(self, index, gy, n):
+        """Input gradient (float32 [B, hi, hi, cin]) of layer `index` for the
+        pre-activation gradient gy (bfloat16 [B, ho, ho, cout8])."""
+        torch = self.torch
+        _, hi, ho, cin, cout = layer_geometry(index, n, self.c0)
+        gy = gy.to(device=self.device, dtype=torch.bfloat16).contiguous()
+        if tuple(gy.shape[1:]) != (ho, ho, (cout + 7) // 8 * 8):
+            raise ValueError(f"layer {index}: gy must be [B, {ho}, {ho}, {(cout + 7) // 8 * 8}]")
+        B = gy.shape[0]
+        self._layer_ws(B, n, True)
+        gx = torch.empty((B, hi, hi, cin), dtype=torch.float32, device=self.device)
+        self._check(self.lib.lshom_cnn_layer_dgrad(self.h, int(index), c_void_p(gy.data_ptr()), c_void_p(gx.data_ptr())))
+        return gx
+
+    def layer_wgrad(self, index, x, gy, n):
+        """Weight and bias gradients of layer `index` (sums over the batch's
+        pixels) for input x and pre-activation gradient gy; returns the
+        compact gradient vector (the other layers' entries as they were)."""
+        torch = self.torch
+        _, hi, ho, cin, cout = layer_geometry(index, n, self.c0)
+        x = x.to(device=self.device, dtype=torch.bfloat16).contiguous()
+        gy = gy.to(device=self.device, dtype=torch.bfloat16).contiguous()
+        if tuple(x.shape[1:]) != (hi, hi, cin) or tuple(gy.shape[1:]) != (ho, ho, (cout + 7) // 8 * 8) \
+                or x.shape[0] != gy.shape[0]:
+            raise ValueError(f"layer {index}: x [B, {hi}, {hi}, {cin}] and gy [B, {ho}, {ho}, cout8] required")
+        self._layer_ws(x.shape[0], n, True)
+        self._check(self.lib.lshom_cnn_layer_wgrad(self.h, int(index), c_void_p(x.data_ptr()), c_void_p(gy.data_ptr())))
+        return self.get_grads()
 
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_unet32.npz")

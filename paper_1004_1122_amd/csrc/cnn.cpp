@@ -514,6 +514,31 @@ lshom_status check_ws(lshom_cnn* c, int B, int N, bool training) {
   return LSHOM_OK;
 }
 
+// Grids of one layer call on the workspace shape (batch B, side N): the
+// output side Ho, the input side Hi, the convolution mode and the
+// upsampling factor of the input read.
+struct LayerGeom {
+  int Hi, Ho, mode, up;
+};
+
+LayerGeom layer_geom(const lshom_cnn* c, int li, int N) {
+  static const int lev_out[] = {0, 0, 1, 1, 1, 2, 2, 2, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0, 0};
+  const Layer& L = c->layers[li];
+  int Ho = N;
+  for (int l = 0; l < lev_out[li]; ++l) Ho /= 3;
+  LayerGeom g{Ho, Ho, CM_CONV3, 1};
+  if (L.kind == K_DOWN3) {
+    g.Hi = 3 * Ho;
+    g.mode = CM_DOWN3;
+  } else if (L.kind == K_CONV1) {
+    g.mode = CM_POINT;
+  } else if (L.name.compare(0, 2, "up") == 0) {
+    g.Hi = Ho / 3;
+    g.up = 3;
+  }
+  return g;
+}
+
 bool shape_ok(int B, int N) { return B >= 1 && N >= 27 && N % 27 == 0 && (long long)B * N * N < (1LL << 31) / 64; }
 
 }  // namespace
@@ -703,6 +728,63 @@ lshom_status lshom_cnn_train_step(lshom_cnn* c, const uint8_t* phase_dev, const 
   CNN_TRY(c, hipMemcpyAsync(&h, loss, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   CNN_TRY(c, hipStreamSynchronize(c->stream));
   if (loss_host) *loss_host = h;
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_cnn_layer_forward(lshom_cnn* c, int layer, const uint16_t* x_dev, uint16_t* y_dev,
+                                     float* yf_dev) {
+  if (!c || !x_dev || (!y_dev && !yf_dev)) return LSHOM_ERR_INVALID_ARG;
+  if (layer < 0 || layer >= (int)c->layers.size()) return fail(c, LSHOM_ERR_INVALID_ARG, "layer index out of range");
+  lshom_status s = check_ws(c, c->ws_B, c->ws_N, false);
+  if (s != LSHOM_OK) return s;
+  const Layer& L = c->layers[layer];
+  const LayerGeom gm = layer_geom(c, layer, c->ws_N);
+  DeviceGuard g(c->device);
+  CNN_TRY(c, order_after_user(c));
+  CNN_TRY(c, conv_fwd(c, L, View{x_dev, L.cin, L.cin}, c->ws_B, gm.Hi, gm.Ho, gm.mode, gm.up, y_dev, L.cout, yf_dev,
+                      L.cout, L.kind != K_CONV1));
+  CNN_TRY(c, hipStreamSynchronize(c->stream));
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_cnn_layer_dgrad(lshom_cnn* c, int layer, const uint16_t* gy_dev, float* gx_dev) {
+  if (!c || !gy_dev || !gx_dev) return LSHOM_ERR_INVALID_ARG;
+  if (layer < 0 || layer >= (int)c->layers.size()) return fail(c, LSHOM_ERR_INVALID_ARG, "layer index out of range");
+  lshom_status s = check_ws(c, c->ws_B, c->ws_N, true);
+  if (s != LSHOM_OK) return s;
+  const Layer& L = c->layers[layer];
+  const LayerGeom gm = layer_geom(c, layer, c->ws_N);
+  const Plan p = make_plan(c, c->ws_B, c->ws_N, 1);
+  DeviceGuard g(c->device);
+  CNN_TRY(c, order_after_user(c));
+  if (gm.up == 3) {
+    // the gradient of the upsampled input on the fine grid, then the adjoint
+    // of the upsampling (sum over each 3 x 3 block)
+    float* fine = at<float>(c, p.gA);
+    CNN_TRY(c, conv_dgrad(c, L, gy_dev, c->ws_B, gm.Ho, fine));
+    CNN_TRY(c, launch_pool3_sum(c->ws_B, gm.Hi, gm.Hi, L.cin, fine, gx_dev, c->stream));
+  } else {
+    CNN_TRY(c, conv_dgrad(c, L, gy_dev, c->ws_B, gm.Ho, gx_dev));
+  }
+  CNN_TRY(c, hipStreamSynchronize(c->stream));
+  c->err.clear();
+  return LSHOM_OK;
+}
+
+lshom_status lshom_cnn_layer_wgrad(lshom_cnn* c, int layer, const uint16_t* x_dev, const uint16_t* gy_dev) {
+  if (!c || !x_dev || !gy_dev) return LSHOM_ERR_INVALID_ARG;
+  if (layer < 0 || layer >= (int)c->layers.size()) return fail(c, LSHOM_ERR_INVALID_ARG, "layer index out of range");
+  lshom_status s = check_ws(c, c->ws_B, c->ws_N, true);
+  if (s != LSHOM_OK) return s;
+  const Layer& L = c->layers[layer];
+  const LayerGeom gm = layer_geom(c, layer, c->ws_N);
+  const Plan p = make_plan(c, c->ws_B, c->ws_N, 1);
+  DeviceGuard g(c->device);
+  CNN_TRY(c, order_after_user(c));
+  CNN_TRY(c, conv_wgrad(c, p, L, View{x_dev, L.cin, L.cin}, c->ws_B, gm.Hi, gm.Ho, gm.mode, gm.up, gy_dev));
+  CNN_TRY(c, hipStreamSynchronize(c->stream));
   c->err.clear();
   return LSHOM_OK;
 }

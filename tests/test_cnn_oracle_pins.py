@@ -173,6 +173,32 @@ def test_network_gradients_central_differences():
     assert checked == 48
 
 
+def test_gradient_rounding_points():
+    """round_grad acts on each layer's pre-activation gradient after the ReLU
+    mask: for the head (no ReLU) its weight and bias gradients are the
+    products with the rounded output gradient, and for dec0b the bias
+    gradient is the sum of the rounded, masked product of that rounded
+    gradient with the head's weights."""
+    rng = np.random.default_rng(8)
+    c0 = 2
+    params = co.init_params(c0, seed=4)
+    x = rng.standard_normal((1, 27, 27, 2))
+    y, acts = co.forward(params, x, c0)
+    gy = rng.standard_normal(y.shape) * (1.0 + 2.0 ** -12)  # not bf16-representable
+    g = co.backward(params, acts, gy, c0, round_grad=co.bf16)
+    g_exact = co.backward(params, acts, gy, c0)
+    gq = co.bf16(gy)
+    h = acts["dec0b"]
+    wh = params["head"][0]
+    # head: products with the rounded gradient, by explicit sums
+    np.testing.assert_allclose(g["head"][1], gq.sum(axis=(0, 1, 2)), rtol=1e-13)
+    np.testing.assert_allclose(g["head"][0], np.einsum("bijc,bijo->co", h, gq), rtol=1e-12)
+    assert np.abs(g["head"][1] - g_exact["head"][1]).max() > 0
+    # dec0b: rounding after the mask of its ReLU
+    pre = co.bf16(np.where(h > 0, gq @ wh.T, 0.0))
+    np.testing.assert_allclose(g["dec0b"][1], pre.sum(axis=(0, 1, 2)), rtol=1e-12)
+
+
 def test_rel_mse_and_adam():
     rng = np.random.default_rng(6)
     y = rng.standard_normal((3, 4, 4, 2))

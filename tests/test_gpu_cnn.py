@@ -3,11 +3,14 @@ against the CPU oracle of oracle/cnn_oracle.py.
 
 The GPU stores weights and activations in bfloat16 and accumulates in FP32.
 The oracle is run on the same bfloat16-rounded weights and input, rounding
-every stored activation to bfloat16 as well, so the two differ only where an
-FP32 and an FP64 sum round to different bfloat16 values (rare, one unit in
-the last place).  Gradients additionally pass through bfloat16 on the GPU
-before every matrix product (relative rounding 2^-9 per element), hence the
-looser gradient bar.
+every stored activation to bfloat16 and every pre-activation gradient (the
+operand of the gradient products) to bfloat16 at the same points as the GPU.
+Each operation on identical operands agrees to about 1e-7 of the sum of
+the magnitudes of its terms (tests/test_gpu_cnn_ops.py); through the whole
+network the two differ where an FP32 and an FP64 sum round to different
+bfloat16 values (one unit in the last place, 2^-8 relative), and such flips
+propagate: the forward output agrees to about 1e-4 and the gradients to
+about 5e-3 (relative L2), hence the network-level bars of 1e-3 and 1.5e-2.
 """
 
 import numpy as np
@@ -65,7 +68,8 @@ def test_forward_matches_oracle(N, B):
     e, raw = net.forward(phase, lrho, want_raw=True)
     ref, _ = _oracle_out(used, x)
     got = raw.cpu().numpy().astype(np.float64)
-    assert _rel(got, ref) < 5e-3, _rel(got, ref)
+    print(f"forward N={N} B={B}: rel-L2 {_rel(got, ref):.3e}", flush=True)
+    assert _rel(got, ref) < 1e-3, _rel(got, ref)
     # the field output is E + prediction, planar
     ef = e.cpu().numpy()
     np.testing.assert_allclose(ef[:, 0], 1.0 + got[..., 0], rtol=0, atol=1e-7)
@@ -94,11 +98,14 @@ def test_gradients_match_oracle():
     t = np.moveaxis(tgt - np.array([1.0, 0.0])[None, :, None, None], 1, -1)
     ref_loss, gy = co.rel_mse(y, t)
     assert loss == pytest.approx(ref_loss, rel=1e-3)
-    ref = co.backward(used, acts, gy, C0)
+    ref = co.backward(used, acts, gy, C0, round_grad=co.bf16)
+    worst = 0.0
     for name in used:
         for k in (0, 1):
             err = _rel(gg[name][k], ref[name][k])
-            assert err < 3e-2, (name, k, err)
+            worst = max(worst, err)
+            assert err < 1.5e-2, (name, k, err)
+    print(f"gradients: worst rel-L2 {worst:.3e}", flush=True)
 
 
 def test_adam_step_matches_oracle():
