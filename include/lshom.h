@@ -116,11 +116,13 @@ void lshom_default_opts(lshom_solve_opts* opts);
  * Host-only validation of a problem statement (no device is touched):
  * d in {2, 3}; 3 <= N[a] <= 4096 with prime factors in {2, 3, 5, 7, 11, 13, 17};
  * fewer than 2^31 nodes; and the pass kernels' LDS footprint (one block holds
- * whole transform sequences and a twiddle table of N[a] entries, within a
- * 63 KiB budget) fits for both precisions with scalar phases.  The last
- * condition bounds the axes far below 4096: the largest supported cubes are
- * 1331^2 and 975^3, and some smaller lengths with large prime radices are
- * rejected too.  The same limits apply when a microstructure is set
+ * whole transform sequences and a twiddle table of N[a] entries, within
+ * gfx950's 160 KiB of LDS per workgroup less 1 KiB for the kernels' static
+ * use) fits for both precisions with scalar phases.  The last condition
+ * bounds the axes far below 4096: the largest supported squares and cubes
+ * are 1800^2 and 1224^3, and some smaller lengths whose radix plans need more
+ * threads than a block holds (1458, 1620, 1728, 2048 in 2-D) are rejected
+ * too.  A context further limits the LDS to what its device reports.  The same limits apply when a microstructure is set
  * (UNSUPPORTED there as well; tensor phases need somewhat more LDS);
  * 1 <= n_phases <= 256 with finite cond > 0; l0 finite > 0, or exactly 0 to
  * mean "the default (min + max) / 2" of Sec. 2.3, Eq. (19); E (d values, may

@@ -21,8 +21,14 @@ namespace lshom {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxPhases = kCondStride;
-// dynamic LDS per block; the rest of the 64 KiB holds the reductions' statics
-constexpr size_t kLdsBudget = 63 * 1024;
+// Dynamic LDS per block.  gfx950 gives a workgroup up to 160 KiB; the pass
+// kernels' static LDS (reduction scratch) stays under 1 KiB.  The default
+// shapes aim at kLdsPreferred so that two or more blocks of a pass share a
+// CU; shapes up to the device's limit (wider tiles found by the autotuner,
+// grids whose smallest shape needs more) are accepted as well.
+constexpr size_t kLdsStaticReserve = 1024;
+constexpr size_t kLdsLimit = 160 * 1024 - kLdsStaticReserve;
+constexpr size_t kLdsPreferred = 63 * 1024;
 constexpr long long kMinBlocks = 128;
 
 // Offsets (bytes from the workspace base) of everything a group of nprob
@@ -84,6 +90,7 @@ struct PassTimer {
 // Problems that share one grid (d, N) and are advanced by the same launches.
 struct Group {
   lshom_ctx* ctx = nullptr;     // errors and the context stream
+  hipStream_t stream = nullptr; // the group's own stream (batched groups run concurrently), else the context's
   int d = 0;
   int64_t N[3] = {1, 1, 1};
   long long nvox = 0, nrows = 0, nhalf = 0;
@@ -136,6 +143,11 @@ struct Group {
 // registry when it has an entry for the grid); UNSUPPORTED if a pass cannot
 // hold its FFT batch in LDS.
 lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases, bool tensor = false);
+// Default pass shape: the one for kLdsPreferred when it fits, else the one for
+// the limit; *fits tells whether the result fits within `limit`.
+PassShape default_shape_within(int d, const int64_t* N, const FftPlan* plans, int elem_bytes, size_t limit,
+                               bool transposed, int n_phases, bool allow_split, bool* fits);
+size_t lds_limit_of(const Group& g);
 bool schedule_fits(const Group& g, const Schedule& s, int precision);
 void apply_schedule(Group& g, const Schedule& s, int precision);
 Schedule current_schedule(const Group& g, int precision);
@@ -177,6 +189,9 @@ void drop_batch_graphs(lshom_ctx* c);
 
 struct lshom_ctx {
   int device = 0;
+  // dynamic LDS a block may use on this device (hipDeviceAttributeMaxSharedMemoryPerBlock
+  // less the static reserve, at most kLdsLimit)
+  size_t lds_limit = lshom::kLdsLimit;
   hipStream_t user_stream = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev = nullptr;
@@ -192,6 +207,9 @@ struct lshom_ctx {
   std::map<std::vector<long long>, std::map<std::pair<int, int>, hipGraphExec_t>> batch_graphs;
   std::map<lshom::SchedKey, lshom::Schedule> schedules;  // autotuned or set by the caller
   lshom::PassTimer timer;
+  // streams of the grid groups of a batched solve (one host thread each)
+  std::vector<hipStream_t> group_streams;
+  std::mutex err_mutex;  // fail() from those threads
 };
 
 #define HIP_TRY(ctx, expr)                                                                       \

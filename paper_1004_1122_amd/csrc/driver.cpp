@@ -14,7 +14,10 @@
 namespace lshom {
 
 lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg) {
-  if (c) c->err = msg;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->err_mutex);
+    c->err = msg;
+  }
   return s;
 }
 
@@ -41,6 +44,21 @@ long long inner0_of(const Group& g) {
 
 }  // namespace
 
+size_t lds_limit_of(const Group& g) { return g.ctx ? g.ctx->lds_limit : kLdsLimit; }
+
+PassShape default_shape_within(int d, const int64_t* N, const FftPlan* plans, int elem_bytes, size_t limit,
+                               bool transposed, int n_phases, bool allow_split, bool* fits) {
+  const size_t pref = std::min(limit, kLdsPreferred);
+  PassShape s = default_shape(d, N, plans, elem_bytes, pref, kMinBlocks, transposed, n_phases, allow_split);
+  if (shape_fits(d, N, plans, s, elem_bytes, pref, n_phases)) {
+    *fits = true;
+    return s;
+  }
+  s = default_shape(d, N, plans, elem_bytes, limit, kMinBlocks, transposed, n_phases, allow_split);
+  *fits = shape_fits(d, N, plans, s, elem_bytes, limit, n_phases);
+  return s;
+}
+
 lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases_in, bool tensor) {
   const int n_phases = n_phases_in * (tensor ? d * (d + 1) / 2 : 1);  // table entries
   g.tensor = tensor;
@@ -61,13 +79,12 @@ lshom_status group_setup(Group& g, int d, const int64_t* N, int n_phases_in, boo
   g.transposed = (d == 2);
   g.n_phases = n_phases;
   for (int a = 0; a < d; ++a) g.plan64[a] = g.plan32[a] = default_plan((int)N[a]);
-  g.shape64 = default_shape(d, g.N, g.plan64, (int)sizeof(cx<double>), kLdsBudget, kMinBlocks,
-                            g.transposed, n_phases, !tensor);
-  g.shape32 = default_shape(d, g.N, g.plan32, (int)sizeof(cx<float>), kLdsBudget, kMinBlocks,
-                            g.transposed, n_phases, !tensor);
-  if (!shape_fits(d, g.N, g.plan64, g.shape64, (int)sizeof(cx<double>), kLdsBudget, n_phases) ||
-      !shape_fits(d, g.N, g.plan32, g.shape32, (int)sizeof(cx<float>), kLdsBudget, n_phases))
-    return LSHOM_ERR_UNSUPPORTED;
+  bool fit64 = false, fit32 = false;
+  g.shape64 = default_shape_within(d, g.N, g.plan64, (int)sizeof(cx<double>), lds_limit_of(g), g.transposed,
+                                   n_phases, !tensor, &fit64);
+  g.shape32 = default_shape_within(d, g.N, g.plan32, (int)sizeof(cx<float>), lds_limit_of(g), g.transposed,
+                                   n_phases, !tensor, &fit32);
+  if (!fit64 || !fit32) return LSHOM_ERR_UNSUPPORTED;
   if (g.ctx) {
     for (int prec = 0; prec < 2; ++prec) {
       auto it = g.ctx->schedules.find(SchedKey(d, g.N[0], g.N[1], g.N[2], prec));
@@ -92,7 +109,7 @@ bool schedule_fits(const Group& g, const Schedule& s, int precision) {
     if (!make_plan((int)g.N[a], s.plan[a].radix, s.plan[a].nstages, &chk)) return false;
   }
   const int es = precision == LSHOM_PRECISION_FP64 ? (int)sizeof(cx<double>) : (int)sizeof(cx<float>);
-  return shape_fits(g.d, g.N, s.plan, s.shape, es, kLdsBudget, g.n_phases);
+  return shape_fits(g.d, g.N, s.plan, s.shape, es, lds_limit_of(g), g.n_phases);
 }
 
 void apply_schedule(Group& g, const Schedule& s, int precision) {
@@ -220,7 +237,7 @@ Bufs<float> get_bufs<float>(Group& g) {
   return b;
 }
 
-hipStream_t stream_of(Group& g) { return g.ctx->stream; }
+hipStream_t stream_of(Group& g) { return g.stream ? g.stream : g.ctx->stream; }
 
 // Launch f; inside the CG loop with pass timing on, between two events.
 template <typename F>
@@ -459,7 +476,6 @@ UpdArgs<T> upd_args(Group& g, const Bufs<T>& b) {
   u.q = b.v[3];
   u.st = dev_state(g);
   u.parts = dev_parts(g);
-  u.n_pq = (int)col0_block_count(g, b);
   u.inv_n = 1.0 / (double)g.nvox;
   u.gate = GATE_ACTIVE;
   u.bt = batch_of(g);
@@ -500,6 +516,21 @@ long long row_block_count(Group& g, const RowArgs<T>& r) {
 // Operator sequences (see the pass kernels for the algebra)
 // ---------------------------------------------------------------------------
 
+// After a producer of blocks partials in dot_region (and eq_region): fold
+// them when the producer is wide and the region's consumers read its count
+// in every block.
+hipError_t enq_fold_if_wide(Group& g, long long blocks, int dot, int dot_region, int eq_region, int gate) {
+  if (!dot || blocks <= kFoldAbove || (dot_region != PART_RR0 && dot_region != PART_PQ)) return hipSuccess;
+  FoldArgs f{};
+  f.st = dev_state(g);
+  f.parts = dev_parts(g);
+  f.region = dot_region;
+  f.eq_region = eq_region;
+  f.gate = gate;
+  f.bt = batch_of(g);
+  return launch_fold_partials(f, stream_of(g));
+}
+
 // Forward half: [3-D axis-1 forward], axis-0 forward + projection.
 // out = coef_base * base + coef_s * [1 / l0] * (-i khat) . tau_hat
 template <typename T>
@@ -523,7 +554,11 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
     f.dot = dot;
     f.dot_region = dot_region;
     f.gate = gate;
-    return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_w3(W3_FWD0, f, stream_of(g)); });
+    if ((e = timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_w3(W3_FWD0, f, stream_of(g)); })) !=
+        hipSuccess)
+      return e;
+    return enq_fold_if_wide(g, w3_blocks(W3_FWD0, (int)g.N[0], (int)g.N[1], (int)g.N[2]), dot, dot_region, -1,
+                            gate);
   }
   if (g.d == 3) {
     ColArgs<T> m = col1_args(g, b, -1);
@@ -544,7 +579,11 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
   a.eq_region = PART_EQ0;
   a.gate = gate;
   a.pipe = pipe;
-  return timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, stream_of(g)); });
+  if ((e = timed_launch(g, LSHOM_PASS_AXIS0_FORWARD, [&] { return launch_col(a, stream_of(g)); })) != hipSuccess)
+    return e;
+  if (pipe) return hipSuccess;
+  return enq_fold_if_wide(g, col_blocks(a), dot, dot_region,
+                          (eq && dot != 1 && dot_region == PART_RR0) ? PART_EQ0 : -1, gate);
 }
 
 // Inverse half: axis-0 inverse from the scalar c (or the CG direction step
@@ -1109,8 +1148,10 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   const int per = o.graph_block > 0 ? o.graph_block : 8;
   // block lengths follow the residual only when the residual is the test
   const bool adapt = o.norm == LSHOM_NORM_RESIDUAL;
-  tm.kinds.clear();
-  pass_model_bytes(g, o.precision, tm.unit_bytes);
+  if (tm.on) {
+    tm.kinds.clear();
+    pass_model_bytes(g, o.precision, tm.unit_bytes);
+  }
   lshom_status s;
   // the blocks take the buffers (and launch shapes) current when they are
   // queued: the tail of a batch may switch schedules

@@ -266,7 +266,6 @@ struct UpdArgs {
   const cx<T>* q;
   DevState* st;
   Partials parts;
-  int n_pq;              // partials of (p, q) to sum
   double inv_n;
   int gate;
   Batch bt;
@@ -358,6 +357,18 @@ struct MixArgs {
   int w3g;
 };
 
+// Folding of a wide producer's partials (see fold_partials_kernel).
+struct FoldArgs {
+  DevState* st;
+  Partials parts;
+  int region;            // PART_RR0 (count nparts[0]) or PART_PQ (count nparts_pq)
+  int eq_region;         // region sharing the count (PART_EQ0), or -1
+  int gate;
+  Batch bt;
+};
+// Producers with more blocks than this have their partials folded.
+constexpr long long kFoldAbove = 4096;
+
 struct FinArgs {
   DevState* st;
   Partials parts;
@@ -448,6 +459,7 @@ template <typename T> hipError_t launch_col(const ColArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s);
 hipError_t launch_pipe_update(const PipeArgs<double>& a, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
+hipError_t launch_fold_partials(const FoldArgs& a, hipStream_t s);
 hipError_t launch_mix_accumulate(const MixArgs& a, hipStream_t s);
 hipError_t launch_mix_convert(const MixArgs& a, hipStream_t s);
 hipError_t launch_bicg(const BicgArgs& a, hipStream_t s);

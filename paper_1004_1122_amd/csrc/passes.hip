@@ -863,7 +863,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   const int skip0 = gate_flags(st, a.gate);
   const int k = st->iter_u;
   double sums[2] = {partial_share<NT>(parts.region(k & 1), st->nparts[k & 1]),
-                    partial_share<NT>(parts.region(PART_PQ), a.n_pq)};
+                    partial_share<NT>(parts.region(PART_PQ), st->nparts_pq)};
   if (block_sums_gated<NT, 2>(sums, skip0)) return;
   const double rr = sums[0] * a.inv_n;
   const double pq = sums[1] * a.inv_n;
@@ -1233,10 +1233,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     case FZ_FFTH: {
       // iterate m was transformed into m + 1; the step is its residual
       const int m = st->iter_a;
-      const double rr = sum_partials<NT>(parts.region(PART_RR0), a.n) * a.inv_n;
+      // the step's producer set nparts[0] (a wide one had its partials folded)
+      const double rr = sum_partials<NT>(parts.region(PART_RR0), st->nparts[0]) * a.inv_n;
       bool conv = rr <= st->tol2b2;
       if (a.eq) {
-        const bool eq_ok = equilibrium_test(st, m, rr, sum_partials<NT>(parts.region(PART_EQ0), a.n), lead);
+        const bool eq_ok =
+            equilibrium_test(st, m, rr, sum_partials<NT>(parts.region(PART_EQ0), st->nparts[0]), lead);
         if (st->norm == 1) conv = eq_ok;
       }
       if (lead) {
@@ -1511,6 +1513,35 @@ hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt));
   if (a.eq) hipLaunchKernelGGL((update_kernel<T, true>), grid, dim3(256), 0, s, a);
   else hipLaunchKernelGGL((update_kernel<T, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// The partials of one producer folded into their first entry, the count set
+// to one.  The consumers of these regions run in every block of a launch
+// (the direction step, the CG update): without the fold each of their blocks
+// would read all partials of a producer with many blocks.  One block of 1024
+// threads sums them in a fixed order, so the value is deterministic; thread 0
+// writes after the block barrier that ends every thread's reads.
+__global__ __launch_bounds__(1024) void fold_partials_kernel(FoldArgs a) {
+  constexpr int NT = 1024;
+  const int pb = batch_prob(a.bt);
+  DevState* st = a.st + pb;
+  if (gated_out(st, a.gate)) return;
+  Partials parts = a.parts;
+  parts.base += (long long)pb * a.bt.pstride;
+  int* count = a.region == PART_PQ ? &st->nparts_pq : &st->nparts[0];
+  const int n = *count;
+  const double s0 = block_sum_all<NT>(partial_share<NT>(parts.region(a.region), n));
+  const double s1 = a.eq_region >= 0 ? block_sum_all<NT>(partial_share<NT>(parts.region(a.eq_region), n)) : 0.0;
+  if (threadIdx.x == 0) {
+    parts.region(a.region)[0] = s0;
+    if (a.eq_region >= 0) parts.region(a.eq_region)[0] = s1;
+    *count = 1;
+  }
+}
+
+hipError_t launch_fold_partials(const FoldArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(fold_partials_kernel, dim3(1, (unsigned)nprob_of(a.bt)), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

@@ -49,11 +49,16 @@ def test_default_opts():
     (2, (19, 63), [1.0], 1.0, None, 1e-6, -7),                # prime factor 19
     (2, (255, 39), [1.0], 1.0, None, 1e-6, 0),                # prime factors 17 and 13
     (2, (8192, 3), [1.0], 1.0, None, 1e-6, -7),               # too long
-    # the LDS footprint of the default pass shapes (both precisions) bounds
-    # the axis lengths below 4096: 1331 in 2-D, 975 in 3-D
+    # the LDS footprint of the default pass shapes (both precisions, 160 KiB
+    # per workgroup less the static reserve) and the threads of one block
+    # bound the axis lengths below 4096: 1800 in 2-D, 1224 for cubes
     (2, (729, 729), [1.0, 10.0], 0.0, None, 1e-6, 0),
     (2, (1331, 1331), [1.0, 10.0], 0.0, None, 1e-6, 0),
-    (2, (1600, 1600), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (2, (1600, 1600), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (2, (1800, 1800), [1.0, 10.0], 0.0, None, 1e-6, 0),
+    (2, (1728, 1728), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (2, (2187, 2187), [1.0, 10.0], 0.0, None, 1e-6, -7),
+    (3, (1224, 1224, 1224), [1.0, 10.0], 0.0, None, 1e-6, 0),
     (2, (4096, 9), [1.0, 10.0], 0.0, None, 1e-6, -7),
     (3, (243, 243, 243), [1.0, 10.0], 0.0, None, 1e-6, 0),
     (3, (975, 975, 975), [1.0, 10.0], 0.0, None, 1e-6, 0),

@@ -58,6 +58,47 @@ def test_3d_243_axis(shape):
     _fp64_parity(_two_phase(shape, sum(shape)), [1.0, 1e3], [0.2, 1.0, -0.5], 25)
 
 
+@pytest.mark.parametrize("shape", [(45, 225, 225), (63, 135, 255)], ids=lambda s: "x".join(map(str, s)))
+def test_wide_producer_partials_folded(shape):
+    """3-D grids off the wave passes whose axis-0 forward launch has more
+    than 4096 blocks: its (p, q) and iteration-0 (r, r) partials are folded
+    to one entry before the update and direction kernels read them.  FP64
+    against the oracle at equal iterations, and a batch of two problems
+    bit-identical to the single solves."""
+    from paper_1004_1122_amd import lshom
+    print("case", shape, flush=True)
+    phase = _two_phase(shape, 17)
+    _fp64_parity(phase, [1.0, 1e2], [1.0, -0.5, 0.25], 12)
+    phase2 = _two_phase(shape, 18)
+    singles = []
+    for ph in (phase, phase2):
+        s = lshom.Solver(ph, [1.0, 1e2])
+        singles.append(s.solve([1.0, -0.5, 0.25], tol=1e-5, precision=0))
+        s.close()
+    bs = lshom.BatchSolver()
+    bs.prepare([dict(phase=ph, cond=[1.0, 1e2], E=[1.0, -0.5, 0.25], tol=1e-5, want_field=True)
+                for ph in (phase, phase2)], precision=0)
+    fields, leffs, infos = bs.run()
+    for i, (e, leff, info) in enumerate(singles):
+        assert info["iterations"] == infos[i]["iterations"]
+        assert torch.equal(e, fields[i]) and np.array_equal(leff, leffs[i, :3])
+    bs.close()
+    # the basic scheme and the equilibrium norm read the folded (r, r) and
+    # |k|^2-weighted sums as well
+    lam = ms.lam_field(phase, [1.0, 10.0])
+    l0 = o.optimal_reference(lam)
+    s = lshom.Solver(phase, [1.0, 10.0])
+    e, _, info = s.solve([1.0, -0.5, 0.25], tol=1e-4, method=lshom.METHOD_FFTH, norm=lshom.NORM_EQUILIBRIUM)
+    ref = o.ffth(lam, l0, [1.0, -0.5, 0.25], tol=1e-4, norm="eta_e")
+    assert info["iterations"] == ref["iterations"]
+    assert _rel(e.cpu().numpy(), ref["e"]) < 1e-10
+    e, _, info = s.solve([1.0, -0.5, 0.25], tol=1e-4, precision=0, norm=lshom.NORM_EQUILIBRIUM)
+    ref = o.cg(lam, l0, [1.0, -0.5, 0.25], tol=1e-4, norm="eta_e")
+    assert info["iterations"] == ref["iterations"]
+    assert _rel(e.cpu().numpy(), ref["e"]) < 1e-10
+    s.close()
+
+
 def test_c3_cell_autotuned_schedules():
     """The 243^3 sphere cell (seed 3, contrast 1e3) with the schedules the
     autotuner picks for it: every pass at its measured shape (7400-29600
@@ -95,10 +136,12 @@ def test_729_highest_contrast_forced_iterations():
         _fp64_parity(m.phase, m.cond, E, 60)
 
 
-@pytest.mark.parametrize("shape", [(1331, 1331), (975, 9, 9)], ids=["1331^2", "975x9x9"])
+@pytest.mark.parametrize("shape", [(1331, 1331), (1800, 1800), (975, 9, 9), (1377, 9, 9)],
+                         ids=["1331^2", "1800^2", "975x9x9", "1377x9x9"])
 def test_largest_supported_grids(shape):
-    """The longest axes one LDS-resident FFT batch holds (radix 11^3 in 2-D;
-    radices 5 5 3 13 with one-column tiles in 3-D) against the oracle."""
+    """Long axes whose LDS-resident FFT batches need more than 64 KiB per
+    block (1800^2, 1377x9x9) or nearly all of it (1331^2, 975x9x9) against the
+    oracle."""
     E = [1.0, 0.5] if len(shape) == 2 else [1.0, 0.5, -0.25]
     _fp64_parity(_two_phase(shape, 5), [1.0, 30.0], E, 20)
 

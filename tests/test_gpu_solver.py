@@ -357,8 +357,8 @@ def test_solver_reuse_across_load_cases(precision):
         assert np.array_equal(t[:, b], l)
 
 
-@pytest.mark.parametrize("shape", [(1331, 1331), (1600, 1600), (975, 9, 9), (1024, 9, 9)],
-                         ids=["1331^2", "1600^2", "975x9x9", "1024x9x9"])
+@pytest.mark.parametrize("shape", [(1331, 1331), (1600, 1600), (1728, 1728), (975, 9, 9), (1377, 9, 9), (1024, 9, 9)],
+                         ids=["1331^2", "1600^2", "1728^2", "975x9x9", "1377x9x9", "1024x9x9"])
 def test_set_up_agrees_with_host_check(shape):
     """The device set-up accepts exactly the grids the host-only check accepts
     (the LDS fit of the pass kernels bounds the axis lengths)."""
