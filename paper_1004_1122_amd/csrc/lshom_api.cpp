@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -244,8 +245,9 @@ lshom_status lshom_check_problem(int d, const int64_t* N, int n_phases, const do
     }
     if (nvox >= (1ll << 31)) return LSHOM_ERR_UNSUPPORTED;
     for (int es : {(int)sizeof(cx<double>), (int)sizeof(cx<float>)}) {
-      const PassShape sh = default_shape(d, N, plans, es, kLdsBudget, kMinBlocks, d == 2, n_phases, true);
-      if (!shape_fits(d, N, plans, sh, es, kLdsBudget, n_phases)) return LSHOM_ERR_UNSUPPORTED;
+      bool fits = false;
+      (void)default_shape_within(d, N, plans, es, kLdsLimit, d == 2, n_phases, true, &fits);
+      if (!fits) return LSHOM_ERR_UNSUPPORTED;
     }
   }
   for (int i = 0; i < n_phases; ++i)
@@ -268,6 +270,13 @@ lshom_status lshom_create(lshom_ctx** out, int device, void* hip_stream) {
   lshom_ctx* c = new lshom_ctx();
   c->device = device;
   c->user_stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      lds <= (int)kLdsStaticReserve) {
+    delete c;
+    return LSHOM_ERR_HIP;
+  }
+  c->lds_limit = std::min(kLdsLimit, (size_t)lds - kLdsStaticReserve);
   if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev, hipEventDisableTiming) != hipSuccess) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
@@ -287,6 +296,7 @@ void lshom_destroy(lshom_ctx* c) {
   drop_batch_graphs(c);
   for (hipEvent_t ev : c->timer.pool) (void)hipEventDestroy(ev);
   if (c->ev) (void)hipEventDestroy(c->ev);
+  for (hipStream_t st : c->group_streams) (void)hipStreamDestroy(st);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -966,12 +976,13 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
   DeviceGuard dg(c->device);
   HIP_TRY(c, order_after_user(c));
   lshom_status worst = LSHOM_OK;
-  for (size_t gi = 0; gi < bp.groups.size(); ++gi) {
+  const size_t ng = bp.groups.size();
+  std::vector<std::vector<ProbEntry>> tabs(ng);
+  std::vector<std::vector<DevState>> inits(ng);
+  if (c->batch_graphs.size() + ng > 64) drop_batch_graphs(c);
+  for (size_t gi = 0; gi < ng; ++gi) {
     Group& g = bp.groups[gi];
-    std::vector<ProbEntry> tab;
-    std::vector<DevState> init;
-    if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tab, &init)) != LSHOM_OK) return s;
-    if (c->batch_graphs.size() > 64) drop_batch_graphs(c);
+    if ((s = prepare_batch_group(c, bp, gi, probs, ws_dev, o, &tabs[gi], &inits[gi])) != LSHOM_OK) return s;
     // the captured launches carry the group's wave-vector scale 1 / Y (cell
     // side lengths) as kernel arguments, so the cell is part of the tag
     std::vector<long long> tag = {(long long)reinterpret_cast<uintptr_t>(g.ws), g.d, (long long)g.N[0],
@@ -983,7 +994,45 @@ lshom_status lshom_solve_batched(lshom_ctx* c, int32_t n, const lshom_problem* p
       tag.push_back(bits);
     }
     g.graph_cache = &c->batch_graphs[tag];
-    if ((s = solve_group(g, init, o, nullptr, nullptr, nullptr)) != LSHOM_OK) return s;
+  }
+  // Grids of different sizes run concurrently: each group on a stream of its
+  // own, driven by a host thread of its own (its blocks, read-backs and
+  // schedule switches are independent of the other groups'), so the
+  // launch-bound small grids and the tails of the large ones overlap.  With
+  // pass timing on (one event pool) they run one after another.
+  std::vector<lshom_status> gst(ng, LSHOM_OK);
+  if (ng > 1 && !c->timer.on) {
+    while (c->group_streams.size() < ng) {
+      hipStream_t st = nullptr;
+      HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      c->group_streams.push_back(st);
+    }
+    // the set-up above is ordered on the context stream
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<std::thread> th;
+    th.reserve(ng);
+    for (size_t gi = 0; gi < ng; ++gi) {
+      bp.groups[gi].stream = c->group_streams[gi];
+      th.emplace_back([&, gi] {
+        if (hipSetDevice(c->device) != hipSuccess) {
+          gst[gi] = fail(c, LSHOM_ERR_HIP, "hipSetDevice in a group thread");
+          return;
+        }
+        gst[gi] = solve_group(bp.groups[gi], inits[gi], o, nullptr, nullptr, nullptr);
+        (void)hipStreamSynchronize(bp.groups[gi].stream);
+      });
+    }
+    for (std::thread& t : th) t.join();
+    for (size_t gi = 0; gi < ng; ++gi) bp.groups[gi].stream = nullptr;
+  } else {
+    for (size_t gi = 0; gi < ng && (gi == 0 || gst[gi - 1] == LSHOM_OK); ++gi)
+      gst[gi] = solve_group(bp.groups[gi], inits[gi], o, nullptr, nullptr, nullptr);
+  }
+  for (size_t gi = 0; gi < ng; ++gi)
+    if (gst[gi] != LSHOM_OK) return gst[gi];
+  for (size_t gi = 0; gi < ng; ++gi) {
+    Group& g = bp.groups[gi];
+    const std::vector<ProbEntry>& tab = tabs[gi];
     const std::vector<int>& mem = bp.members[gi];
     for (int j = 0; j < g.nprob; ++j) {
       const DevState& hs = g.host_states[j];

@@ -218,3 +218,34 @@ def test_column_tiles_3d_batch(precision, tiles):
             assert np.linalg.norm(got - ref["e"]) / np.linalg.norm(ref["e"]) < 1e-10, i
         else:
             assert info["rel_res_true"] <= 1.01e-9, i
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_uneven_grid_subset_concurrent_groups(precision):
+    """The first 24 problems of the 512-problem generator (grids of 81^2,
+    243^2 and 729^2, contrasts 10 to 1e4): the three grid groups run on
+    streams of their own at once, and every problem equals its single solve
+    bit for bit; the 81^2 fields match the oracle at equal iterations."""
+    from paper_1004_1122_amd import lshom
+    items = [ms.batched_problem(i) for i in range(24)]
+    sizes = {m.phase.shape[0] for m in items}
+    assert sizes == {81, 243, 729}, sizes
+    probs = [dict(phase=m.phase, cond=list(m.cond), E=(1.0, 0.0), tol=1e-6, want_field=True) for m in items]
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=1)
+    fields, leff, infos = bs.run(precision=precision)
+    for i, pr in enumerate(probs):
+        print("problem", i, pr["phase"].shape, flush=True)
+        s = lshom.Solver(pr["phase"], pr["cond"])
+        e, l1, info = s.solve(pr["E"], tol=pr["tol"], precision=precision)
+        assert infos[i]["status"] == 0 and info["status"] == 0, i
+        assert infos[i]["iterations"] == info["iterations"], i
+        assert torch.equal(fields[i], e), i
+        assert np.array_equal(leff[i][:2], l1), i
+        s.close()
+        if precision == 0 and pr["phase"].shape[0] == 81:
+            lam = ms.lam_field(pr["phase"], pr["cond"])
+            ref = o.cg(lam, o.optimal_reference(lam), pr["E"], n_iter=infos[i]["iterations"])
+            err = np.linalg.norm(fields[i].cpu().numpy() - ref["e"]) / np.linalg.norm(ref["e"])
+            assert err < 1e-10, (i, err)
+    bs.close()
