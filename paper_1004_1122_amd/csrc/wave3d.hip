@@ -400,7 +400,9 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
       sq[m] = cx<T>{Am.re - Bm.im, Am.im + Bm.re};
       if (m > 0) sq[N2 - m] = cx<T>{Am.re + Bm.im, Bm.re - Am.im};
     }
-    wave_fft_lds<T, N2, +1>(buf, tw, j, lane_ok);
+    // the inverse transform stays in registers: z[r] = node j + LPS r
+    cx<T> z[9];
+    wave_fft_lds_regs<T, N2, +1>(buf, tw, j, lane_ok, z);
     if constexpr (MODE == ROW_INV) {
       double* out = pe ? (pe->e_out ? pe->e_out + al * nvox : nullptr) : w3_pick(a.real_out, al);
       const double* add = w3_pick(a.real_add, al);
@@ -409,14 +411,13 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           const int x = j + LPS * r;
-          const cx<T> z = buf[x];
 #pragma unroll
           for (int u = 0; u < 2; ++u) {
             const bool has = u == 0 ? hasA : hasB;
             if (!has) continue;
             const long long g = (rhoA + u) * N2 + x;
             const int q = phs[(int)(g - row0 * N2)];
-            double val = (double)Ea + (double)((u == 0 ? z.re : z.im) * a.inv_n);
+            double val = (double)Ea + (double)((u == 0 ? z[r].re : z[r].im) * a.inv_n);
             if (a.flags & ROWF_DL_OUT) val *= (double)cond[q] - (double)l0;
             if (a.flags & ROWF_ADD) val += add[g];
             if (out) out[g] = val;
@@ -432,11 +433,10 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
           const int x = j + LPS * r;
-          const cx<T> z = buf[x];
           T t0 = T(0), t1 = T(0);
           const int pa = (int)(rhoA - row0) * N2 + x;
-          if (hasA) t0 = (cond[phs[pa]] - l0) * (Ea + z.re * a.inv_n);
-          if (hasB) t1 = (cond[phs[pa + N2]] - l0) * (Ea + z.im * a.inv_n);
+          if (hasA) t0 = (cond[phs[pa]] - l0) * (Ea + z[r].re * a.inv_n);
+          if (hasB) t1 = (cond[phs[pa + N2]] - l0) * (Ea + z[r].im * a.inv_n);
           v[r] = cx<T>{t0, t1};
         }
       }
@@ -519,15 +519,15 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
     __syncthreads();
     tile_load<T, N0, NT>(tw + N0, (al == 0 ? a.hl[0] : a.hl[1]) + htile, hstep, 0.0);
     __syncthreads();
-    wave_fft_lds<T, N0, -1>(buf, tw, j, act);
+    cx<T> z[9];
+    wave_fft_lds_regs<T, N0, -1>(buf, tw, j, act, z);
     if (act) {
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
         // field 0 carries tau_0 (times xi_0 here), field 1 xi_1 tau_1 + xi_2 tau_2
         const T k = al == 0 ? (T)((double)w3_freq(j + LPS * r, N0) * a.cinv[0]) : T(1);
-        const cx<T> z = buf[j + LPS * r];
-        t[r].re += k * z.re;
-        t[r].im += k * z.im;
+        t[r].re += k * z[r].re;
+        t[r].im += k * z[r].im;
       }
     }
     __builtin_amdgcn_wave_barrier();

@@ -36,8 +36,15 @@ namespace wfft_detail {
 // M = N / NS still to combine: radix 9 while 9 divides M, then radix 3.
 // Barriers stay outside the lane predicate (they only order the compiler's
 // memory operations; the whole wave passes them).
-template <typename T, int N, int S, int NS>
-__device__ __forceinline__ void stages_from(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act) {
+//
+// With KEEP the last stage leaves its outputs in registers instead of LDS:
+// its jobs q = j + (N / 9) t write x[q + r N / R] = x[j + (N / 9) s] (the
+// last stage has Ns = N / R and k = q), so the lane keeps out[s] = x[j +
+// (N / 9) s], s < 9: the input order of the first stage, and the order of
+// the lane's nodes in wave_fft.
+template <typename T, int N, int S, int NS, bool KEEP = false>
+__device__ __forceinline__ void stages_from(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act,
+                                            cx<T>* out = nullptr) {
   constexpr int M = N / NS;
   if constexpr (M == 1) {
     return;
@@ -56,13 +63,22 @@ __device__ __forceinline__ void stages_from(cx<T>* buf, const cx<T>* __restrict_
       }
     }
     __builtin_amdgcn_wave_barrier();
-    if (act) {
-      dft<T, R, S>(v);
+    if constexpr (KEEP && M == R) {
+      // last stage (one job per lane, q = j = k): x[j + r N / 9]
+      if (act) {
+        dft<T, R, S>(v);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(j - k) * R + k + r * NS] = v[r];
+        for (int r = 0; r < R; ++r) out[r] = v[r];
+      }
+    } else {
+      if (act) {
+        dft<T, R, S>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[(j - k) * R + k + r * NS] = v[r];
+      }
+      __builtin_amdgcn_wave_barrier();
+      stages_from<T, N, S, NS * R, KEEP>(buf, tw, j, act, out);
     }
-    __builtin_amdgcn_wave_barrier();
-    stages_from<T, N, S, NS * R>(buf, tw, j, act);
   } else {
     static_assert(M == 3, "a radix-3 stage ends the plan");
     constexpr int R = 3, NR = N / R, step = NR / NS, LPS = N / 9;
@@ -85,15 +101,28 @@ __device__ __forceinline__ void stages_from(cx<T>* buf, const cx<T>* __restrict_
       }
     }
     __builtin_amdgcn_wave_barrier();
-    if (act) {
+    if constexpr (KEEP) {
+      // jobs q = j + LPS t (k = q): x[j + LPS (t + 3 r)]
+      (void)kk;
+      if (act) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        dft<T, R, S>(u[t]);
+        for (int t = 0; t < 3; ++t) {
+          dft<T, R, S>(u[t]);
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[kk[t] + r * NS] = u[t][r];
+          for (int r = 0; r < R; ++r) out[t + 3 * r] = u[t][r];
+        }
       }
+    } else {
+      if (act) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          dft<T, R, S>(u[t]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[kk[t] + r * NS] = u[t][r];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -131,6 +160,36 @@ __device__ __forceinline__ void wave_fft_lds(cx<T>* buf, const cx<T>* __restrict
     for (int r = 0; r < 9; ++r) v[r] = buf[j + LPS * r];
   }
   wave_fft<T, N, S>(v, buf, tw, j, act);
+}
+
+// As wave_fft_lds, the transform left in registers: out[s] = X[j + (N / 9) s]
+// for s < 9 (the sequence's LDS region holds intermediate values after it).
+template <typename T, int N, int S>
+__device__ __forceinline__ void wave_fft_lds_regs(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act,
+                                                  cx<T> (&out)[9]) {
+  constexpr int LPS = N / 9;
+  cx<T> v[9];
+  __builtin_amdgcn_wave_barrier();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) v[r] = buf[j + LPS * r];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if constexpr (N == 9) {
+    if (act) {
+      dft<T, 9, S>(v);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) out[r] = v[r];
+    }
+  } else {
+    if (act) {
+      dft<T, 9, S>(v);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) buf[9 * j + r] = v[r];
+    }
+    __builtin_amdgcn_wave_barrier();
+    wfft_detail::stages_from<T, N, S, 9, true>(buf, tw, j, act, out);
+  }
 }
 
 }  // namespace lshom
