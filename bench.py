@@ -266,9 +266,12 @@ def warm_start_leg(items243, items729):
     net = cnn.WarmStartNet.load(cnn.DEFAULT_WEIGHTS)
     out = {"weights": os.path.relpath(cnn.DEFAULT_WEIGHTS, ROOT)}
     for n, items, scale in ((243, items243, 1), (729, items729, 3)):
-        rows = warmstart.evaluate(net, [(ph, lr, cond) for ph, lr, cond, _ in items], scale=scale, reps=3)
+        ev = [(ph, lr, cond) for ph, lr, cond, _ in items]
+        rows = warmstart.evaluate(net, ev, scale=scale, reps=3)
         out[f"{n}x{n}"] = dict(warmstart.summarize(rows), network_grid=n // scale)
-        log(f"warm start {n}^2: {out[f'{n}x{n}']}")
+        log(f"warm start {n}^2 (single solves): {out[f'{n}x{n}']}")
+        out[f"{n}x{n}_batched"] = warmstart.evaluate_batched(net, ev, scale=scale)
+        log(f"warm start {n}^2 (one batch): {out[f'{n}x{n}_batched']}")
     net.close()
     return out
 

@@ -162,18 +162,11 @@ __device__ __forceinline__ void wave_fft_lds(cx<T>* buf, const cx<T>* __restrict
   wave_fft<T, N, S>(v, buf, tw, j, act);
 }
 
-// As wave_fft_lds, the transform left in registers: out[s] = X[j + (N / 9) s]
+// As wave_fft, the transform left in registers: out[s] = X[j + (N / 9) s]
 // for s < 9 (the sequence's LDS region holds intermediate values after it).
 template <typename T, int N, int S>
-__device__ __forceinline__ void wave_fft_lds_regs(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act,
-                                                  cx<T> (&out)[9]) {
-  constexpr int LPS = N / 9;
-  cx<T> v[9];
-  __builtin_amdgcn_wave_barrier();
-  if (act) {
-#pragma unroll
-    for (int r = 0; r < 9; ++r) v[r] = buf[j + LPS * r];
-  }
+__device__ __forceinline__ void wave_fft_regs(cx<T> (&v)[9], cx<T>* buf, const cx<T>* __restrict__ tw, int j,
+                                              bool act, cx<T> (&out)[9]) {
   __builtin_amdgcn_wave_barrier();
   if constexpr (N == 9) {
     if (act) {
@@ -190,6 +183,20 @@ __device__ __forceinline__ void wave_fft_lds_regs(cx<T>* buf, const cx<T>* __res
     __builtin_amdgcn_wave_barrier();
     wfft_detail::stages_from<T, N, S, 9, true>(buf, tw, j, act, out);
   }
+}
+
+// As wave_fft_lds, the transform left in registers (see wave_fft_regs).
+template <typename T, int N, int S>
+__device__ __forceinline__ void wave_fft_lds_regs(cx<T>* buf, const cx<T>* __restrict__ tw, int j, bool act,
+                                                  cx<T> (&out)[9]) {
+  constexpr int LPS = N / 9;
+  cx<T> v[9];
+  __builtin_amdgcn_wave_barrier();
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 9; ++r) v[r] = buf[j + LPS * r];
+  }
+  wave_fft_regs<T, N, S>(v, buf, tw, j, act, out);
 }
 
 }  // namespace lshom

@@ -128,6 +128,54 @@ def evaluate(net, items, tol=1e-6, precision=0, reps=1, scale=1):
     return rows
 
 
+def evaluate_batched(net, items, tol=1e-6, precision=0, reps=3, scale=1):
+    """Cold vs warm solves of [(phase, log10_rho, cond)] (one grid size) as one
+    batch each: lshom_solve_batched from e = E, against one network
+    inference over every image followed by lshom_solve_batched from the
+    predictions (inference included in the warm time).  Best of reps."""
+    import torch
+    from . import lshom
+    phd = torch.from_numpy(np.stack([ph for ph, _, _ in items])).cuda()
+    lr = torch.tensor([lrho for _, lrho, _ in items], dtype=torch.float32, device="cuda")
+    probs = [dict(phase=phd[i], cond=cond, E=(1.0, 0.0), tol=tol) for i, (_, _, cond) in enumerate(items)]
+    n = phd.shape[1]
+    pred = torch.empty((len(items), 2, n, n), dtype=torch.float64, device="cuda")
+    cold = lshom.BatchSolver()
+    cold.prepare(probs, precision=precision)
+    warm = lshom.BatchSolver()
+    warm.prepare([dict(p, x0=pred[i]) for i, p in enumerate(probs)], precision=precision)
+    pred.copy_(net.forward(phd, lr, scale=scale))
+    cold.run(precision=precision)  # graphs and schedules
+    warm.run(precision=precision)
+    best = {"cold": None, "warm": None, "inference": None}
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, ic = cold.run(precision=precision)
+        dt = time.perf_counter() - t
+        best["cold"] = dt if best["cold"] is None else min(best["cold"], dt)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        pred.copy_(net.forward(phd, lr, scale=scale))
+        torch.cuda.synchronize()
+        t_inf = time.perf_counter() - t
+        _, _, iw = warm.run(precision=precision)
+        dt = time.perf_counter() - t
+        if best["warm"] is None or dt < best["warm"]:
+            best["warm"], best["inference"] = dt, t_inf
+    cold.close()
+    warm.close()
+    itc = np.array([i["iterations"] for i in ic], float)
+    itw = np.array([i["iterations"] for i in iw], float)
+    return {"n": len(items), "network_grid": n // scale, "iters_cold_mean": float(itc.mean()),
+            "iters_warm_mean": float(itw.mean()), "iters_cold_max": int(itc.max()), "iters_warm_max": int(itw.max()),
+            "saved_frac_mean": float(((itc - itw) / itc).mean()),
+            "ms_cold": 1e3 * best["cold"], "ms_warm": 1e3 * best["warm"], "ms_inference": 1e3 * best["inference"],
+            "time_ratio_warm_over_cold": best["warm"] / best["cold"],
+            "warm_used": int(sum(i["warm_start_used"] for i in iw)),
+            "worst_rel_res_true": max(i["rel_res_true"] for i in list(ic) + list(iw))}
+
+
 def summarize(rows):
     cold = np.array([r["cold"]["iterations"] for r in rows], float)
     warm = np.array([r["warm"]["iterations"] for r in rows], float)
