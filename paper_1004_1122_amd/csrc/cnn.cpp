@@ -251,6 +251,7 @@ hipError_t conv_fwd(lshom_cnn* c, const Layer& L, View in, int B, int Hi, int Ho
   a.mode = mode;
   a.up = up;
   a.w = c->w16 + L.w_off;
+  a.ldw = L.taps * L.cin;
   a.N = L.cout;
   a.Np = L.np;
   a.bias = c->w + L.b_off;
@@ -271,6 +272,7 @@ hipError_t conv_dgrad(lshom_cnn* c, const Layer& L, const bf16_t* gpre, int B, i
   a.ld0 = L.np;
   a.B = B;
   a.w = c->wt16 + L.w_off;
+  a.ldw = L.taps * L.np;
   a.N = L.cin;
   a.Np = L.cin;
   a.bias = nullptr;
@@ -333,7 +335,7 @@ hipError_t prep(lshom_cnn* c, long long P, int C, int Cp, const float* g0, int l
 hipError_t cast_all(lshom_cnn* c) {
   for (const Layer& L : c->layers) {
     hipError_t e = launch_cast_weights(c->w + L.w_off, L.taps, L.cin, L.np, L.kind == K_CONV3 ? 1 : 0,
-                                       c->w16 + L.w_off, c->wt16 + L.w_off, L.cin, c->stream);
+                                       c->w16 + L.w_off, c->wt16 + L.w_off, c->stream);
     if (e != hipSuccess) return e;
     // bias copies are read in FP32; nothing to cast
   }
@@ -627,7 +629,7 @@ lshom_status lshom_cnn_set_params(lshom_cnn* c, const float* host, int64_t n) {
   CNN_TRY(c, launch_fill_f32(c->g, (long long)c->n_el, 0.f, c->stream));
   CNN_TRY(c, launch_fill_f32(c->m, (long long)c->n_el, 0.f, c->stream));
   CNN_TRY(c, launch_fill_f32(c->v, (long long)c->n_el, 0.f, c->stream));
-  // the transposed copies leave their padding untouched: clear them once
+  // the gaps between the layers' bfloat16 copies are never written: clear both copies once
   CNN_TRY(c, launch_fill_f32(reinterpret_cast<float*>(c->w16), (long long)c->n_el, 0.f, c->stream));
   CNN_TRY(c, cast_all(c));
   CNN_TRY(c, hipStreamSynchronize(c->stream));

@@ -29,7 +29,9 @@ struct ConvArgs {
   int C0, C1, ld0, ld1;  // channel counts (multiples of 8) and pixel strides
   int B, Hi, Wi, Ho, Wo;
   int mode, up;
-  const bf16_t* w;       // [taps][C0 + C1][Np] (CM_DOWN3_T: slice z at z * (C0 + C1) * Np)
+  const bf16_t* w;       // element (k, n) of the reduction k < taps (C0 + C1) at w[n * ldw + k]
+                         // (CM_DOWN3_T: slice z starts at w + z * (C0 + C1))
+  int ldw;
   int N, Np;             // output channels, padded to a multiple of 8
   const float* bias;     // [N] or null
   int relu;
@@ -80,10 +82,12 @@ hipError_t launch_rel_mse(int B, int N, const float* pred, const double* e, doub
 // the prediction for the transposed image to the load case E = e2.
 // scale 3: the field is 3N x 3N, pixel (i, j) takes prediction (i / 3, j / 3).
 hipError_t launch_make_field(int B, int N, const float* pred, int transpose, int scale, double* e, hipStream_t s);
-// Weight copies: w16[k][n] = bf16(w[k][n]); wt16 for the input gradient:
-// conv3 flips the taps (tap 8 - t) and transposes, down3 and 1x1 transpose.
+// Weight copies, rows contiguous in the reduction index: master w[t][c][o]
+// (taps x cin x np) -> w16[o][t cin + c] for the forward convolution and
+// wt16[c][t' np + o] for the input gradient (conv3 flips the taps, t' = 8 - t;
+// down3 and 1x1 keep them).
 hipError_t launch_cast_weights(const float* w, int taps, int cin, int np, int flip, bf16_t* w16, bf16_t* wt16,
-                               int cin_p, hipStream_t s);
+                               hipStream_t s);
 hipError_t launch_adam(long long n, float* w, const float* g, float* m, float* v, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t s);

@@ -6,7 +6,6 @@
 namespace lshom {
 namespace cnn {
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 // Round to nearest even (finite inputs).
@@ -17,12 +16,12 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Tiles: the convolution kernel computes 128 output pixels x 64 output
-// channels per block (each of the 4 waves a 32 x 64 slab of 16 x 16 MFMA
-// tiles), stepping the reduction 32 at a time through LDS.  Rows of the LDS
-// tiles hold 32 reduction elements plus 8 of padding (80 bytes: 16-byte
-// aligned rows, fewer bank conflicts for the fragment reads).
-constexpr int kTM = 128, kTN = 64, kTK = 32, kLd = kTK + 8;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// LDS rows of the tiles hold 32 reduction elements plus 8 of padding (80
+// bytes: 16-byte aligned rows, fewer bank conflicts for the fragment reads).
+constexpr int kTK = 32, kLd = kTK + 8;
+constexpr int kTN = 64;  // weight-gradient tile channels
 constexpr int kWM = 64;  // weight-gradient tile rows
 
 // Input pixel read by output pixel (b, i, j) at tap t.
@@ -48,27 +47,41 @@ __device__ __forceinline__ long long in_pixel(int mode, int up, int Hi, int Wi, 
   return ((long long)b * Hi + i) * Wi + j;
 }
 
+// Implicit-GEMM convolution: out[pixel][n] = sum_k im2col(in)[pixel][k] w[k][n]
+// on the matrix cores (16x16x32 bfloat16 MFMA, FP32 accumulation).  A block
+// of 4 waves computes TM = 4 WM output pixels x WN output channels, each
+// wave a WM x WN slab of 16 x 16 tiles.  The reduction runs 32 at a time
+// through two LDS buffers: the global loads of step s + 1 are in flight
+// while step s multiplies, and one block barrier per step separates the
+// writes of one buffer from the reads of the other.  Both operands are
+// K-contiguous (activations: channels of one pixel and tap; weights: rows
+// w[n][k] of ldw elements), so every LDS store and fragment read is 16
+// bytes.  A lane's fragment is eight consecutive k of one row of each
+// operand, the same k for both operands, so the contraction pairs them.
+template <int WM, int WN>
 __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
-  __shared__ __align__(16) bf16_t As[kTM * kLd];  // [pixel][k]
-  __shared__ __align__(16) bf16_t Bs[kTN * kLd];  // [channel][k]
+  constexpr int TM = 4 * WM, TN = WN, MT = WM / 16, NT = WN / 16;
+  constexpr int A_PER = TM * 4 / 256;                        // uint4 loads of the pixel tile per thread
+  constexpr int B_THREADS = TN * 4;                          // threads loading the weight tile
+  __shared__ __align__(16) bf16_t As[2][TM * kLd];  // [pixel][k]
+  __shared__ __align__(16) bf16_t Bs[2][TN * kLd];  // [channel][k]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const long long hw = (long long)a.Ho * a.Wo;
   const long long M = (long long)a.B * hw;
-  const long long m0 = (long long)blockIdx.x * kTM;
-  const int n0 = blockIdx.y * kTN;
+  const long long m0 = (long long)blockIdx.x * TM;
+  const int n0 = blockIdx.y * TN;
   const int z = blockIdx.z;
   const int Cin = a.C0 + a.C1;
   const int taps = (a.mode == CM_CONV3 || a.mode == CM_DOWN3) ? 9 : 1;
   const int K = taps * Cin;
-  const bf16_t* W = a.w + (a.mode == CM_DOWN3_T ? (long long)z * Cin * a.Np : 0);
+  const bf16_t* W = a.w + (a.mode == CM_DOWN3_T ? (long long)z * Cin : 0);
 
-  // this thread loads rows (tid / 4) and (tid / 4 + 64) of the pixel tile,
-  // 8 reduction elements at column 8 (tid % 4)
+  // pixel rows (tid / 4) + 64 u of the tile, 8 reduction elements at column 8 (tid % 4)
   const int kg = tid & 3;
-  int ab[2], ai[2], aj[2];
-  bool av[2];
+  int ab[A_PER], ai[A_PER], aj[A_PER];
+  bool av[A_PER];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < A_PER; ++u) {
     const long long m = m0 + (tid >> 2) + 64 * u;
     av[u] = m < M;
     const long long mm = av[u] ? m : 0;
@@ -77,60 +90,69 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
     ai[u] = rem / a.Wo;
     aj[u] = rem - ai[u] * a.Wo;
   }
-  float4_t acc[2][4];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+  // weight row n0 + tid / 4 (threads below B_THREADS), 8 elements at column 8 (tid % 4)
+  const int bn = n0 + (tid >> 2);
+  const bool bv = tid < B_THREADS && bn < a.Np;
+  const bf16_t* wrow = W + (long long)(bv ? bn : 0) * a.ldw;
 
-  for (int k0 = 0; k0 < K; k0 += kTK) {
+  uint4 ra[A_PER], rb = {0u, 0u, 0u, 0u};
+  auto fetch = [&](int k0) {
+    const int k = k0 + 8 * kg;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int k = k0 + 8 * kg;
-      uint4 val = {0u, 0u, 0u, 0u};
+    for (int u = 0; u < A_PER; ++u) {
+      ra[u] = uint4{0u, 0u, 0u, 0u};
       if (av[u] && k < K) {
         const int t = k / Cin;
         const int c = k - t * Cin;
         const long long pix = in_pixel(a.mode, a.up, a.Hi, a.Wi, a.Ho, a.Wo, ab[u], ai[u], aj[u], t);
         const bf16_t* src = c < a.C0 ? a.in0 + pix * a.ld0 + c : a.in1 + pix * a.ld1 + (c - a.C0);
-        val = *reinterpret_cast<const uint4*>(src);
+        ra[u] = *reinterpret_cast<const uint4*>(src);
       }
-      *reinterpret_cast<uint4*>(&As[((tid >> 2) + 64 * u) * kLd + 8 * kg]) = val;
     }
-    {
-      const int kk = tid >> 3, ng = tid & 7;
-      const int k = k0 + kk, n = n0 + 8 * ng;
-      uint4 val = {0u, 0u, 0u, 0u};
-      if (k < K && n < a.Np) val = *reinterpret_cast<const uint4*>(W + (long long)k * a.Np + n);
-      const bf16_t* e = reinterpret_cast<const bf16_t*>(&val);
+    rb = uint4{0u, 0u, 0u, 0u};
+    if (bv && k < K) rb = *reinterpret_cast<const uint4*>(wrow + k);
+  };
+  auto stash = [&](int buf) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) Bs[(8 * ng + q) * kLd + kk] = e[q];
-    }
-    __syncthreads();
+    for (int u = 0; u < A_PER; ++u)
+      *reinterpret_cast<uint4*>(&As[buf][((tid >> 2) + 64 * u) * kLd + 8 * kg]) = ra[u];
+    if (tid < B_THREADS) *reinterpret_cast<uint4*>(&Bs[buf][(tid >> 2) * kLd + 8 * kg]) = rb;
+  };
+
+  float4_t acc[MT][NT];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      short4_t af[2], bfr[4];
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        af[mt] = *reinterpret_cast<const short4_t*>(&As[(wave * 32 + mt * 16 + (lane & 15)) * kLd + ks * 16 +
-                                                        4 * (lane >> 4)]);
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  const int steps = (K + kTK - 1) / kTK;
+  for (int s = 0; s < steps; ++s) {
+    const int cur = s & 1;
+    if (s + 1 < steps) fetch((s + 1) * kTK);
+    bf16x8_t af[MT], bfr[NT];
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        bfr[nt] = *reinterpret_cast<const short4_t*>(&Bs[(nt * 16 + (lane & 15)) * kLd + ks * 16 + 4 * (lane >> 4)]);
+    for (int mt = 0; mt < MT; ++mt)
+      af[mt] = *reinterpret_cast<const bf16x8_t*>(&As[cur][(wave * WM + mt * 16 + (lane & 15)) * kLd + 8 * (lane >> 4)]);
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
+    for (int nt = 0; nt < NT; ++nt)
+      bfr[nt] = *reinterpret_cast<const bf16x8_t*>(&Bs[cur][(nt * 16 + (lane & 15)) * kLd + 8 * (lane >> 4)]);
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
-    }
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
+    if (s + 1 < steps) stash(cur ^ 1);
     __syncthreads();
   }
 
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
+  for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const long long m = m0 + wave * 32 + mt * 16 + 4 * (lane >> 4) + i;
+      const long long m = m0 + wave * WM + mt * 16 + 4 * (lane >> 4) + i;
       if (m >= M) continue;
       long long op = m;
       if (a.mode == CM_DOWN3_T) {
@@ -141,7 +163,7 @@ __global__ __launch_bounds__(256) void conv_kernel(ConvArgs a) {
         op = ((long long)b * 3 * a.Ho + 3 * ii + p) * (3LL * a.Wo) + 3 * jj + q;
       }
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
         const int n = n0 + nt * 16 + (lane & 15);
         if (n >= a.N) continue;
         float v = acc[mt][nt][i] + (a.bias ? a.bias[n] : 0.f);
@@ -210,15 +232,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a) {
       for (int q = 0; q < 8; ++q) Bs[(8 * g + q) * kLd + pl] = e[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      const short4_t af =
-          *reinterpret_cast<const short4_t*>(&As[(wave * 16 + (lane & 15)) * kLd + ks * 16 + 4 * (lane >> 4)]);
+    {
+      const bf16x8_t af = *reinterpret_cast<const bf16x8_t*>(&As[(wave * 16 + (lane & 15)) * kLd + 8 * (lane >> 4)]);
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-        const short4_t bfr =
-            *reinterpret_cast<const short4_t*>(&Bs[(nt * 16 + (lane & 15)) * kLd + ks * 16 + 4 * (lane >> 4)]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bfr, acc[nt], 0, 0, 0);
+        const bf16x8_t bfr =
+            *reinterpret_cast<const bf16x8_t*>(&Bs[(nt * 16 + (lane & 15)) * kLd + 8 * (lane >> 4)]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr, acc[nt], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -383,8 +403,7 @@ __global__ void make_field_kernel(int B, int N, const float* pred, int transpose
   }
 }
 
-__global__ void cast_weights_kernel(const float* w, int taps, int cin, int np, int flip, bf16_t* w16, bf16_t* wt16,
-                                    int cin_p) {
+__global__ void cast_weights_kernel(const float* w, int taps, int cin, int np, int flip, bf16_t* w16, bf16_t* wt16) {
   const long long n = (long long)taps * cin * np;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
     const int o = (int)(e % np);
@@ -392,9 +411,10 @@ __global__ void cast_weights_kernel(const float* w, int taps, int cin, int np, i
     const int c = (int)(t2 % cin);
     const int t = (int)(t2 / cin);
     const bf16_t h = f2bf(w[e]);
-    w16[e] = h;
+    // forward: row o, k = t cin + c; input gradient: row c, k = t' np + o
+    w16[(long long)o * taps * cin + t2] = h;
     const int tt = flip ? taps - 1 - t : t;
-    wt16[((long long)tt * np + o) * cin_p + c] = h;
+    wt16[((long long)c * taps + tt) * np + o] = h;
   }
 }
 
@@ -427,8 +447,21 @@ static unsigned grid_for(long long n, int per = 256, long long cap = 8192) {
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const long long M = (long long)a.B * a.Ho * a.Wo;
-  const dim3 grid((unsigned)((M + kTM - 1) / kTM), (unsigned)((a.Np + kTN - 1) / kTN), a.mode == CM_DOWN3_T ? 9 : 1);
-  hipLaunchKernelGGL(conv_kernel, grid, dim3(256), 0, s, a);
+  const unsigned zs = a.mode == CM_DOWN3_T ? 9 : 1;
+  // channel tile sized to the layer (32 or 64 columns); 64-row wave slabs
+  // when there are enough pixels to fill the chip with the larger tiles
+  if (a.Np <= 32) {
+    if (M >= 256LL * 2048) {
+      hipLaunchKernelGGL((conv_kernel<64, 32>), dim3((unsigned)((M + 255) / 256), (unsigned)((a.Np + 31) / 32), zs),
+                         dim3(256), 0, s, a);
+    } else {
+      hipLaunchKernelGGL((conv_kernel<32, 32>), dim3((unsigned)((M + 127) / 128), (unsigned)((a.Np + 31) / 32), zs),
+                         dim3(256), 0, s, a);
+    }
+  } else {
+    hipLaunchKernelGGL((conv_kernel<32, 64>), dim3((unsigned)((M + 127) / 128), (unsigned)((a.Np + 63) / 64), zs),
+                       dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -485,9 +518,9 @@ hipError_t launch_make_field(int B, int N, const float* pred, int transpose, int
 }
 
 hipError_t launch_cast_weights(const float* w, int taps, int cin, int np, int flip, bf16_t* w16, bf16_t* wt16,
-                               int cin_p, hipStream_t s) {
+                               hipStream_t s) {
   hipLaunchKernelGGL(cast_weights_kernel, dim3(grid_for((long long)taps * cin * np)), dim3(256), 0, s, w, taps, cin,
-                     np, flip, w16, wt16, cin_p);
+                     np, flip, w16, wt16);
   return hipGetLastError();
 }
 
