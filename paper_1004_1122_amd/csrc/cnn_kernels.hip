@@ -448,16 +448,11 @@ static unsigned grid_for(long long n, int per = 256, long long cap = 8192) {
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
   const long long M = (long long)a.B * a.Ho * a.Wo;
   const unsigned zs = a.mode == CM_DOWN3_T ? 9 : 1;
-  // channel tile sized to the layer (32 or 64 columns); 64-row wave slabs
-  // when there are enough pixels to fill the chip with the larger tiles
+  // channel tile sized to the layer (32 or 64 columns; 32 x 32 wave slabs
+  // beat 64 x 32 ones on the 32-channel layers: more blocks per CU)
   if (a.Np <= 32) {
-    if (M >= 256LL * 2048) {
-      hipLaunchKernelGGL((conv_kernel<64, 32>), dim3((unsigned)((M + 255) / 256), (unsigned)((a.Np + 31) / 32), zs),
-                         dim3(256), 0, s, a);
-    } else {
-      hipLaunchKernelGGL((conv_kernel<32, 32>), dim3((unsigned)((M + 127) / 128), (unsigned)((a.Np + 31) / 32), zs),
-                         dim3(256), 0, s, a);
-    }
+    hipLaunchKernelGGL((conv_kernel<32, 32>), dim3((unsigned)((M + 127) / 128), (unsigned)((a.Np + 31) / 32), zs),
+                       dim3(256), 0, s, a);
   } else {
     hipLaunchKernelGGL((conv_kernel<32, 64>), dim3((unsigned)((M + 127) / 128), (unsigned)((a.Np + 63) / 64), zs),
                        dim3(256), 0, s, a);
