@@ -11,6 +11,7 @@ when the prediction does not lower the residual), recording iterations and
 the wall time of network inference + solve.
 
   python -m paper_1004_1122_amd.warmstart --train 20000 --epochs 8 --out weights.npz --eval
+  python -m paper_1004_1122_amd.warmstart --weights W.npz --time-inference 64
 """
 
 from __future__ import annotations
@@ -202,7 +203,23 @@ def main():
     ap.add_argument("--eval243", type=int, default=64)
     ap.add_argument("--eval729", type=int, default=16)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--time-inference", type=int, default=0, metavar="B",
+                    help="with --weights: time the network on B random 243^2 images (four runs) and exit")
     args = ap.parse_args()
+    if args.time_inference and args.weights:
+        import torch
+        from . import cnn
+        net = cnn.WarmStartNet.load(args.weights)
+        B = args.time_inference
+        ph = torch.randint(0, 2, (B, 243, 243), dtype=torch.uint8, device="cuda")
+        lr = torch.full((B,), 2.0, device="cuda")
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            net.forward(ph, lr)
+            torch.cuda.synchronize()
+            log(f"inference of {B} images of 243^2: {1e3 * (time.perf_counter() - t):.2f} ms")
+        return
     # every image is generated in worker processes before the GPU is touched
     t = time.perf_counter()
     items = [] if args.weights else generate(_train_item, range(args.train))
