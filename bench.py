@@ -122,6 +122,26 @@ def cpu_baseline(phase, n_iter):
             "host": {"os.cpu_count": os.cpu_count(), "cpu_model": cpu_model(), "scipy_fft_workers": o._WORKERS}}
 
 
+def cpu_baseline_c2(phase, runs=3):
+    """The oracle on the whole 729^2 contrast sweep (8 solves to 1e-6, about
+    half a minute on 16 host cores): the median of `runs` sweeps."""
+    from oracle import lshom_oracle as o
+    from paper_1004_1122_amd import microstructure as ms
+    times, its = [], 0
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        its = 0
+        for rho in C2_CONTRASTS:
+            lam = ms.lam_field(phase, [1.0, rho])
+            for E in C2_LOADS:
+                its += o.cg(lam, 0.5 * (1.0 + rho), list(E), tol=TOL)["iterations"]
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    return {"value": phase.size * its / med / 1e9, "unit": "GVoxel-CG-iters/s", "cores": o._WORKERS,
+            "kind": "oracle", "sample": f"729^2 circles seed 2, rho 1e1..1e4 x E=e1,e2: 8 FP64 CG solves to 1e-6, "
+                                        f"{its} iterations, median of {runs} sweeps {med:.1f} s"}
+
+
 def c3_leg(lshom, torch, phase_dev, n_vox, steps, warmup, sched_prefix=None):
     """The timed steps (FP64) and the same loop for the mixed form."""
     s = lshom.Solver(phase_dev, [1.0, C3_RHO])
@@ -372,6 +392,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(c3.phase, args.cpu_iters)
+        if "c2" in legs:
+            log("timing the CPU oracle on the 729^2 sweep")
+            out["cpu_baseline"]["sweep_729"] = cpu_baseline_c2(c2.phase)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
