@@ -58,6 +58,38 @@ def test_3d_243_axis(shape):
     _fp64_parity(_two_phase(shape, sum(shape)), [1.0, 1e3], [0.2, 1.0, -0.5], 25)
 
 
+@pytest.mark.parametrize("shape", [(81, 27, 27), (27, 81, 27), (27, 27, 81), (81, 81, 81), (243, 81, 27)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_3d_81_axis(shape):
+    """The 81-point wave transforms (four sequences per wave, radix 9 twice)
+    in each position, FP64 CG against the oracle at equal iterations."""
+    print("case", shape, flush=True)
+    _fp64_parity(_two_phase(shape, 3 + sum(shape)), [1.0, 1e2], [0.3, -1.0, 0.6], 20)
+
+
+def test_wave_pass_batch_uneven_convergence():
+    """A batch of 3-D problems on the wave passes whose contrasts differ (the
+    launches drop the converged ones): every problem bit-identical to its
+    single solve, in both forms."""
+    from paper_1004_1122_amd import lshom
+    shape = (27, 81, 27)
+    probs = [dict(phase=_two_phase(shape, 40 + i), cond=[1.0, rho], E=[1.0, 0.5, -0.5], tol=1e-7, want_field=True)
+             for i, rho in enumerate([3.0, 1e2, 1e4, 30.0])]
+    for precision in (0, 1):
+        bs = lshom.BatchSolver()
+        bs.prepare(probs, precision=1)
+        fields, leffs, infos = bs.run(precision=precision)
+        its = [i["iterations"] for i in infos]
+        assert len(set(its)) > 1, its
+        for i, pr in enumerate(probs):
+            s = lshom.Solver(pr["phase"], pr["cond"])
+            e, leff, info = s.solve(pr["E"], tol=pr["tol"], precision=precision)
+            assert info["iterations"] == its[i] and info["status"] == 0
+            assert torch.equal(e, fields[i]) and np.array_equal(leff, leffs[i, :3])
+            s.close()
+        bs.close()
+
+
 @pytest.mark.parametrize("shape", [(45, 225, 225), (63, 135, 255)], ids=lambda s: "x".join(map(str, s)))
 def test_wide_producer_partials_folded(shape):
     """3-D grids off the wave passes whose axis-0 forward launch has more
