@@ -567,11 +567,6 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
 namespace {
 
 template <int N>
-long long w3_col_blocks_of(int N_other, int G) {
-  return (long long)N_other * G;
-}
-
-template <int N>
 size_t w3_col_lds(int elem) {
   return (size_t)(N + kW3Group * N) * elem;
 }
@@ -581,9 +576,6 @@ size_t w3_row_lds(int elem, int n_phases) {
   return (size_t)(N + 4 * WaveGeom<N>::SPW * N) * elem + ((size_t)n_phases * (elem / 2) + 15) / 16 * 16 +
          (size_t)w3_rows_per_block<N>() * N;
 }
-
-template <typename T, template <typename, int> class K>
-struct Dummy;
 
 template <typename T, int N>
 hipError_t launch_w3_n(int pass, const W3Args<T>& a, hipStream_t s) {
