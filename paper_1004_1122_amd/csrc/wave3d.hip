@@ -178,23 +178,22 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
   const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
   const double x2 = (double)c * a.cinv[2];
   const bool col_ok = c < a.h;
-  double inv[9];
+  // c / |xi| in place: only it stays live across the two transforms (the
+  // kernel then holds three waves per SIMD instead of two)
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
     const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
     const double k2 = x0 * x0 + x1 * x1 + x2 * x2;
-    inv[r] = (col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0;
+    const T inv = (T)((col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0);
+    cv[r] = cx<T>{inv * cv[r].re, inv * cv[r].im};
   }
-  (void)x1;
-  (void)x2;
   // field 0: i xi_0 c / |xi|; field 1: i c / |xi| (xi_1, xi_2 come later)
 #pragma unroll 1
   for (int al = 0; al < 2; ++al) {
     cx<T> v[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      const double kx = al == 0 ? (double)w3_freq(j + LPS * r, N0) * a.cinv[0] : 1.0;
-      const T k = (T)(kx * inv[r]);
+      const T k = al == 0 ? (T)((double)w3_freq(j + LPS * r, N0) * a.cinv[0]) : T(1);
       v[r] = cx<T>{-k * cv[r].im, k * cv[r].re};
     }
     wave_fft<T, N0, +1>(v, buf, tw, j, act);
