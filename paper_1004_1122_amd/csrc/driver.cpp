@@ -586,6 +586,10 @@ hipError_t enq_forward_project(Group& g, const Bufs<T>& b, cx<T>* out, const cx<
                           (eq && dot != 1 && dot_region == PART_RR0) ? PART_EQ0 : -1, gate);
 }
 
+// The CG update of the wave passes leaves x += alpha p to the next direction
+// step (the axis-0 inverse pass), which reads p anyway.
+bool cg_defers_x(const Group& g) { return g.w3 && !g.eq; }
+
 // Inverse half: axis-0 inverse from the scalar c (or the CG direction step
 // p = r + beta p), [3-D axis-1 inverse].
 template <typename T>
@@ -598,12 +602,15 @@ hipError_t enq_inverse_from_c(Group& g, const Bufs<T>& b, const cx<T>* c_in, cx<
     a.p_io = p_io;
     a.r_in = r_in;
     a.cg_step = p_io != nullptr;
+    // the CG loop's update leaves x to this step (one read of p fewer)
+    a.x_io = (a.cg_step && g.in_cg && cg_defers_x(g)) ? b.v[0] : nullptr;
     a.gate = gate;
     if ((e = timed_launch(g, LSHOM_PASS_AXIS0_INVERSE, [&] { return launch_w3(W3_INV0, a, stream_of(g)); })) !=
         hipSuccess)
       return e;
     W3Args<T> m = w3_args(g, b);
     m.dir = +1;
+    m.clear_xpend = a.x_io != nullptr;
     m.gate = gate;
     return timed_launch(g, LSHOM_PASS_AXIS1_INVERSE, [&] { return launch_w3(W3_COL1, m, stream_of(g)); });
   }
@@ -657,10 +664,19 @@ hipError_t enq_cg_iteration(Group& g, const Bufs<T>& b, int gate) {
   if (e == hipSuccess) {
     UpdArgs<T> u = upd_args(g, b);
     u.gate = gate;
+    u.defer_x = cg_defers_x(g) ? 1 : 0;
     e = timed_launch(g, LSHOM_PASS_UPDATE, [&] { return launch_update(u, stream_of(g)); });
   }
   g.in_cg = false;
   return e;
+}
+
+// The x step of the last update, for the problems of a CG loop that stopped
+// after an update (wave passes defer it to the next direction step).
+template <typename T>
+hipError_t enq_flush_x(Group& g, const Bufs<T>& b) {
+  if (!cg_defers_x(g)) return hipSuccess;
+  return launch_flush_x(upd_args(g, b), stream_of(g));
 }
 
 // Residual of the spectral iterate x for the load E:
@@ -1186,6 +1202,10 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     });
   }
   if (s != LSHOM_OK) return s;
+  if (!ffth) {
+    if (mixed) HIP_TRY(c, enq_flush_x<float>(g, b32));
+    else HIP_TRY(c, enq_flush_x<double>(g, b64));
+  }
   // fold what a breakdown left in the FP32 correction (no-op after a refresh)
   if (mixed) HIP_TRY(c, launch_mix_accumulate(mix_args(g, b64, b32, GATE_ALWAYS), stream_of(g)));
   if (o.true_residual) {
@@ -1433,8 +1453,11 @@ void pass_model_bytes(const Group& g, int precision, double* out) {
   out[LSHOM_PASS_UPDATE] = 6.0 * nh * cs;
   if (g.w3) {
     // wave passes: the axis-0 passes carry two fields (xi_1 and xi_2 are
-    // applied in the axis-1 and last-axis spectra)
-    out[LSHOM_PASS_AXIS0_INVERSE] = 5.0 * nh * cs;
+    // applied in the axis-1 and last-axis spectra); x += alpha p moves from
+    // the update (reads r, q; writes r) to the direction step (reads x, r, p;
+    // writes x, p and the two fields)
+    out[LSHOM_PASS_UPDATE] = 3.0 * nh * cs;
+    out[LSHOM_PASS_AXIS0_INVERSE] = 7.0 * nh * cs;
     out[LSHOM_PASS_AXIS1_INVERSE] = 5.0 * nh * cs;
     out[LSHOM_PASS_AXIS1_FORWARD] = 5.0 * nh * cs;
     out[LSHOM_PASS_AXIS0_FORWARD] = 4.0 * nh * cs;

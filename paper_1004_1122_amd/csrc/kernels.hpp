@@ -62,7 +62,9 @@ struct DevState {
   int n_refresh;
   int nparts[2];        // number of partials in the two (r, r) buffers
   int nparts_pq;        // number of partials in the PQ region (set by its producer)
-  int pad[2];
+  int x_pend;           // the update left x += alpha_log p to the next direction step
+                        // (set by the update, cleared by the pass after that step)
+  int pad;
 };
 
 // When a kernel returns at entry.
@@ -281,6 +283,9 @@ struct UpdArgs {
   int w3;                // vectors in the wave-pass layout V (k_last from (cg, cc))
   FastDiv fd_w3n0;       // N0
   int w3g;               // G
+  // x is not touched: x += alpha p waits for the next direction step, which
+  // reads p anyway (x_pend, alpha_log)
+  int defer_x;
 };
 
 // Pipelined CG update (spectral coordinate): s = w + beta s, p = r + beta p,
@@ -418,8 +423,10 @@ struct W3Args {
   cx<T>* p_io;
   const cx<T>* r_in;
   int cg_step;
+  cx<T>* x_io;                   // CG step: applies a pending x += alpha_log p (x_pend)
   // W3_COL1
   int dir;
+  int clear_xpend;               // the lead block clears x_pend (after the direction step)
   // W3_ROW
   int mode, flags;
   const double* real_in[kMaxDim];
@@ -457,6 +464,9 @@ __host__ __device__ inline long long w3_entries(long long N0, long long N1, long
 template <typename T> hipError_t launch_row(const RowArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_col(const ColArgs<T>& a, hipStream_t s);
 template <typename T> hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s);
+// x += alpha_log p for every problem whose update was deferred and not yet
+// applied (the end of a CG loop), then x_pend cleared.
+template <typename T> hipError_t launch_flush_x(const UpdArgs<T>& a, hipStream_t s);
 hipError_t launch_pipe_update(const PipeArgs<double>& a, hipStream_t s);
 hipError_t launch_finalize(const FinArgs& a, hipStream_t s);
 hipError_t launch_fold_partials(const FoldArgs& a, hipStream_t s);

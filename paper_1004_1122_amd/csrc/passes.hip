@@ -826,7 +826,9 @@ __device__ __forceinline__ double w3_entry_weight(uint32_t i, const FastDiv& fd_
 // ---------------------------------------------------------------------------
 
 // EQ: the equilibrium sums ride along (a.eq); the plain kernel has no code for them.
-template <typename T, bool EQ>
+// DEFER: x is neither read nor written; the lead records that the next
+// direction step owes x += alpha p (alpha_log, x_pend).
+template <typename T, bool EQ, bool DEFER>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
   const int pb = batch_prob(a.bt);
@@ -845,9 +847,11 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     for (int u = 0; u < kBatch; ++u) {
       const long long i = base + u * stride;
       if (i < a.n) {
-        p[u] = P[i];
+        if constexpr (!DEFER) {
+          p[u] = P[i];
+          x[u] = X[i];
+        }
         q[u] = Q[i];
-        x[u] = X[i];
         r[u] = Rv[i];
       }
     }
@@ -885,11 +889,13 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     for (int u = 0; u < kBatch; ++u) {
       const long long i = i0 + u * stride;
       if (i >= a.n) continue;
-      x[u].re += ta * p[u].re;
-      x[u].im += ta * p[u].im;
+      if constexpr (!DEFER) {
+        x[u].re += ta * p[u].re;
+        x[u].im += ta * p[u].im;
+        X[i] = x[u];
+      }
       r[u].re -= ta * q[u].re;
       r[u].im -= ta * q[u].im;
-      X[i] = x[u];
       Rv[i] = r[u];
       const double m2 = (double)r[u].re * (double)r[u].re + (double)r[u].im * (double)r[u].im;
       if (a.w3) {
@@ -919,6 +925,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
     st->iter_a = k + 1;
     st->alpha_log = alpha;
     st->pq_log = pq;
+    if constexpr (DEFER) st->x_pend = 1;
     // cell sum of dL (E + u(x)) follows x += alpha p linearly
     if constexpr (EQ)
       for (int c = 0; c < kMaxDim; ++c) st->jx[c] += alpha * st->taup[c];
@@ -1511,8 +1518,44 @@ hipError_t launch_col(const ColArgs<T>& a, hipStream_t s) {
 template <typename T>
 hipError_t launch_update(const UpdArgs<T>& a, hipStream_t s) {
   const dim3 grid((unsigned)update_blocks(a.n), (unsigned)nprob_of(a.bt));
-  if (a.eq) hipLaunchKernelGGL((update_kernel<T, true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((update_kernel<T, false>), grid, dim3(256), 0, s, a);
+  if (a.eq && a.defer_x) return hipErrorInvalidValue;
+  if (a.eq) hipLaunchKernelGGL((update_kernel<T, true, false>), grid, dim3(256), 0, s, a);
+  else if (a.defer_x) hipLaunchKernelGGL((update_kernel<T, false, true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((update_kernel<T, false, false>), grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// The x step an update left pending, for problems that stopped before a
+// direction step applied it.  x_pend is read here and cleared by the next
+// kernel, so that no block reads a flag another block of its launch writes.
+template <typename T>
+__global__ __launch_bounds__(256) void flush_x_kernel(UpdArgs<T> a) {
+  const int pb = batch_prob(a.bt);
+  const DevState* st = a.st + pb;
+  if (!st->x_pend) return;
+  const long long vo = (long long)pb * a.bt.vstride;
+  const T ta = (T)st->alpha_log;
+  const long long stride = (long long)gridDim.x * 256;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < a.n; i += stride) {
+    cx<T> x = a.x[vo + i];
+    const cx<T> p = a.p[vo + i];
+    x.re += ta * p.re;
+    x.im += ta * p.im;
+    a.x[vo + i] = x;
+  }
+}
+
+__global__ void clear_xpend_kernel(DevState* st, Batch bt) {
+  if (threadIdx.x == 0) st[batch_prob(bt)].x_pend = 0;
+}
+
+template <typename T>
+hipError_t launch_flush_x(const UpdArgs<T>& a, hipStream_t s) {
+  const unsigned np = (unsigned)nprob_of(a.bt);
+  hipLaunchKernelGGL((flush_x_kernel<T>), dim3((unsigned)update_blocks(a.n), np), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(clear_xpend_kernel, dim3(1, np), dim3(64), 0, s, a.st, a.bt);
   return hipGetLastError();
 }
 
@@ -1583,6 +1626,8 @@ template hipError_t launch_col<double>(const ColArgs<double>&, hipStream_t);
 template hipError_t launch_col<float>(const ColArgs<float>&, hipStream_t);
 template hipError_t launch_update<double>(const UpdArgs<double>&, hipStream_t);
 template hipError_t launch_update<float>(const UpdArgs<float>&, hipStream_t);
+template hipError_t launch_flush_x<double>(const UpdArgs<double>&, hipStream_t);
+template hipError_t launch_flush_x<float>(const UpdArgs<float>&, hipStream_t);
 template hipError_t launch_fill_zero<double>(cx<double>*, long long, hipStream_t);
 template hipError_t launch_fill_zero<float>(cx<float>*, long long, hipStream_t);
 template long long row_blocks<double>(const RowArgs<double>&);

@@ -130,18 +130,19 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
   Partials parts = a.parts;
   parts.base += (long long)pb * a.bt.pstride;
   const unsigned bx = blockIdx.x;
+  // x += alpha p owed by the last CG update (stable during this launch: set
+  // by the update, cleared by the pass after this one)
+  const int xp = (a.cg_step && a.x_io) ? st->x_pend : 0;
   double beta = 0.0;
   // the direction step decides beta (and the stop) from the (r, r) sums; all
   // threads take part in the block reduction before anything else
+  bool go = true;
   if (a.cg_step) {
-    if (!cg_direction<NT>(st, parts, a.inv_nd, &beta, a.gate, 0, bx == 0)) return;
+    go = cg_direction<NT>(st, parts, a.inv_nd, &beta, a.gate, 0, bx == 0);
   } else if (gated_out_stable(st, a.gate)) {
     return;
   }
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  stage_twiddles(tw, a.tw[0], N0, NT);
-  __syncthreads();
+  if (!go && !xp) return;
   const int G = a.G, N1 = a.N1;
   const int b = (int)(bx / (unsigned)G), cg = (int)(bx - (unsigned)b * G);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -149,10 +150,29 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
   const bool act = s < CPW;
   const int cc = w * CPW + (act ? s : 0);
   const int c = cg * kW3Group + cc;
-  cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
   const long long vo = (long long)pb * a.bt.vstride;
   // V: ((b G + cg) 8 + cc) N0 + a;  Gl: ((b G + cg) N0 + a) 8 + cc
   const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
+  const T ta = xp ? (T)st->alpha_log : T(0);
+  if (!go) {
+    // the solve stops here: only the owed step of x
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        cx<T> xv = a.x_io[vcol + j + LPS * r];
+        const cx<T> pv = a.p_io[vcol + j + LPS * r];
+        xv.re += ta * pv.re;
+        xv.im += ta * pv.im;
+        a.x_io[vcol + j + LPS * r] = xv;
+      }
+    }
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  stage_twiddles(tw, a.tw[0], N0, NT);
+  __syncthreads();
+  cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
   const long long gtile = vo + (long long)(b * G + cg) * N0 * kW3Group;
   cx<T> cv[9];
   const T tb = (T)beta;
@@ -163,6 +183,15 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
       for (int r = 0; r < 9; ++r) {
         rv[r] = a.r_in[vcol + j + LPS * r];
         pv[r] = a.p_io[vcol + j + LPS * r];
+      }
+      if (xp) {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+          cx<T> xv = a.x_io[vcol + j + LPS * r];
+          xv.re += ta * pv[r].re;
+          xv.im += ta * pv[r].im;
+          a.x_io[vcol + j + LPS * r] = xv;
+        }
       }
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
@@ -212,6 +241,9 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
   constexpr int LPS = WaveGeom<N1>::LPS, CPW = w3_cpw<N1>();
   const int pb = a.bt.live ? a.bt.live[blockIdx.y] : (int)blockIdx.y;
   DevState* st = a.st + pb;
+  // after a direction step: the x step it owed has been applied (also when
+  // this launch is gated out)
+  if (DIR > 0 && a.clear_xpend && blockIdx.x == 0 && threadIdx.x == 0) st->x_pend = 0;
   if (gated_out_stable(st, a.gate)) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
