@@ -52,6 +52,24 @@ __host__ __device__ constexpr int w3_rows_per_block() {
 
 __device__ __forceinline__ int w3_freq(int m, int n) { return (m <= n / 2) ? m : m - n; }
 
+// Streaming access for vectors that no later pass of the iteration reads
+// again soon (x, p around the axis-0 passes): the non-temporal hint keeps them
+// from displacing the pass fields the next pass reads.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_stream(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return cx<T>{v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cx<T>* p, cx<T> c) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 v;
+  v.x = c.re;
+  v.y = c.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+}
+
 // Weight of half-spectrum column c in a full-spectrum sum (the last axis is
 // odd here: column 0 stands for itself, the others for two; padding: 0).
 __device__ __forceinline__ double w3_weight(int c, int h) { return c == 0 ? 1.0 : (c < h ? 2.0 : 0.0); }
@@ -159,11 +177,11 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
     if (act) {
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
-        cx<T> xv = a.x_io[vcol + j + LPS * r];
+        cx<T> xv = ld_stream(a.x_io + vcol + j + LPS * r);
         const cx<T> pv = a.p_io[vcol + j + LPS * r];
         xv.re += ta * pv.re;
         xv.im += ta * pv.im;
-        a.x_io[vcol + j + LPS * r] = xv;
+        st_stream(a.x_io + vcol + j + LPS * r, xv);
       }
     }
     return;
@@ -187,16 +205,16 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
       if (xp) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-          cx<T> xv = a.x_io[vcol + j + LPS * r];
+          cx<T> xv = ld_stream(a.x_io + vcol + j + LPS * r);
           xv.re += ta * pv[r].re;
           xv.im += ta * pv[r].im;
-          a.x_io[vcol + j + LPS * r] = xv;
+          st_stream(a.x_io + vcol + j + LPS * r, xv);
         }
       }
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
         cv[r] = cx<T>{rv[r].re + tb * pv[r].re, rv[r].im + tb * pv[r].im};
-        a.p_io[vcol + j + LPS * r] = cv[r];
+        st_stream(a.p_io + vcol + j + LPS * r, cv[r]);
       }
     } else {
 #pragma unroll
@@ -569,7 +587,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   if (act) {
     cx<T> bv[9];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) bv[r] = a.base ? a.base[vcol + j + LPS * r] : cx<T>{T(0), T(0)};
+    for (int r = 0; r < 9; ++r) bv[r] = a.base ? ld_stream(a.base + vcol + j + LPS * r) : cx<T>{T(0), T(0)};
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
       const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
