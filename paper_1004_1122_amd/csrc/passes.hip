@@ -831,8 +831,9 @@ __device__ __forceinline__ double w3_entry_weight(uint32_t i, const FastDiv& fd_
 template <typename T, bool EQ, bool DEFER>
 __global__ __launch_bounds__(256) void update_kernel(UpdArgs<T> a) {
   constexpr int NT = 256;
-  // loads in flight per thread: FP32 entries are half the bytes, so twice as many
-  constexpr int UB = sizeof(T) == 4 ? 2 * kBatch : kBatch;
+  // loads in flight per thread: the deferred FP32 update (two vectors of
+  // half-size entries) takes twice as many; the others would lose occupancy
+  constexpr int UB = (sizeof(T) == 4 && DEFER) ? 2 * kBatch : kBatch;
   const int pb = batch_prob(a.bt);
   DevState* st = a.st + pb;
   Partials parts = a.parts;

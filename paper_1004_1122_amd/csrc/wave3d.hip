@@ -52,6 +52,26 @@ __host__ __device__ constexpr int w3_rows_per_block() {
 
 __device__ __forceinline__ int w3_freq(int m, int n) { return (m <= n / 2) ? m : m - n; }
 
+// Wave-vector component xi = k / Y for integer frequency k, in the precision
+// of the pass (FP32 passes form it in FP32).
+template <typename T>
+__device__ __forceinline__ T w3_xi(int k, double cinv) {
+  if constexpr (sizeof(T) == 8) return (double)k * cinv;
+  else return (float)k * (float)cinv;
+}
+
+// 1 / |xi| at a point of the half spectrum; 0 at xi = 0 and in the padding
+// (ok false).  FP64 passes take the correctly rounded value; FP32 passes the
+// hardware reciprocal square root in FP32 (about one FP32 ulp).  Both axis-0
+// passes of one precision form it here, so the factor applied on the way in
+// is the one applied on the way out and the operator stays symmetric.
+template <typename T>
+__device__ __forceinline__ T w3_inv_norm(T x0, T x1, T x2, bool ok) {
+  const T k2 = x0 * x0 + x1 * x1 + x2 * x2;
+  if constexpr (sizeof(T) == 8) return (ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0;
+  else return (ok && k2 > 0.0f) ? __builtin_amdgcn_rsqf(k2) : 0.0f;
+}
+
 // Streaming access for vectors that no later pass of the iteration reads
 // again soon (x, p around the axis-0 passes): the non-temporal hint keeps them
 // from displacing the pass fields the next pass reads.
@@ -222,16 +242,14 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
     }
   }
   // khat at each point: xi_0 depends on a, xi_1 and xi_2 on the column
-  const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
-  const double x2 = (double)c * a.cinv[2];
+  const T x1 = w3_xi<T>(w3_freq(b, N1), a.cinv[1]);
+  const T x2 = w3_xi<T>(c, a.cinv[2]);
   const bool col_ok = c < a.h;
   // c / |xi| in place: only it stays live across the two transforms (the
   // kernel then holds three waves per SIMD instead of two)
 #pragma unroll
   for (int r = 0; r < 9; ++r) {
-    const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
-    const double k2 = x0 * x0 + x1 * x1 + x2 * x2;
-    const T inv = (T)((col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0);
+    const T inv = w3_inv_norm<T>(w3_xi<T>(w3_freq(j + LPS * r, N0), a.cinv[0]), x1, x2, col_ok);
     cv[r] = cx<T>{inv * cv[r].re, inv * cv[r].im};
   }
   // field 0: i xi_0 c / |xi|; field 1: i c / |xi| (xi_1, xi_2 come later)
@@ -240,7 +258,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
     cx<T> v[9];
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      const T k = al == 0 ? (T)((double)w3_freq(j + LPS * r, N0) * a.cinv[0]) : T(1);
+      const T k = al == 0 ? w3_xi<T>(w3_freq(j + LPS * r, N0), a.cinv[0]) : T(1);
       v[r] = cx<T>{-k * cv[r].im, k * cv[r].re};
     }
     wave_fft<T, N0, +1>(v, buf, tw, j, act);
@@ -379,19 +397,34 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
   cx<T>* buf = tw + N2 + (w * SPW + (lane_ok ? s : 0)) * N2;
   const long long vo = (long long)pb * a.bt.vstride;
   // Hl entry (rho, c): a = rho / N1, b = rho % N1 -> ((a G + cg) N1 + b) 8 + cc
-  // entry c of a row relative to its entry 0 (same a and b, cg = c / 8)
-  auto hoff = [&](int c) -> long long { return (long long)(c >> 3) * N1 * kW3Group + (c & 7); };
-  // Hl entry 0 of the wave's row wrow + t (t < 2 SPW), without a division per row
+  // Hl entry 0 of the wave's row wrow + t (t < 2 SPW), without a division per
+  // row: b wraps at most once when 2 SPW <= 27 <= N1, else at most twice
   const int wrow32 = (int)rb * RB + w * SPW * 2;
   const int wa0 = wrow32 / N1, wb0 = wrow32 - wa0 * N1;
   auto wbase = [&](int t) -> long long {
     int ai = wa0, bi = wb0 + t;
-    while (bi >= N1) {
-      bi -= N1;
-      ++ai;
+    const bool w1 = bi >= N1;
+    bi = w1 ? bi - N1 : bi;
+    ai += w1 ? 1 : 0;
+    if constexpr (2 * SPW > 27) {
+      const bool w2 = bi >= N1;
+      bi = w2 ? bi - N1 : bi;
+      ai += w2 ? 1 : 0;
     }
     return vo + ((long long)ai * G * N1 + bi) * kW3Group;
   };
+  // The wave's half-spectrum entries e = lane + 64 it, in groups of eight
+  // (one 128-byte group of a row each): group g = e / 8 is entry group
+  // mg = g / SPW of the wave's row pair qq = g % SPW.  When SPW divides 8 the
+  // pair does not depend on it and mg grows by 8 / SPW per it: the row bases
+  // and the entry offset are formed once.
+  constexpr bool kPairFixed = 8 % SPW == 0;
+  auto pair_of = [&](int e) -> int { return kPairFixed ? (lane >> 3) % SPW : (e >> 3) % SPW; };
+  auto group_of = [&](int e, int it) -> int {
+    return kPairFixed ? (lane >> 3) / SPW + (8 / SPW) * it : (e >> 3) / SPW;
+  };
+  // entry offset of half index mg 8 + (e & 7) within its row
+  auto hoff_g = [&](int mg, int e) -> long long { return (long long)mg * N1 * kW3Group + (e & 7); };
   cx<T> v[9];
   if constexpr (MODE == ROW_FWD) {
     // real rows in (or the constant E), times dL when asked
@@ -426,22 +459,23 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = lane + 64 * it;
-      const int qq = (e >> 3) % SPW, m = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      const int qq = pair_of(e), mg = group_of(e, it), m = mg * kW3Group + (e & 7);
       const long long ra = wrow + 2 * qq;
       const bool ok = e < TOT && m < h;
-      A[it] = (ok && ra < nrows) ? src[wbase(2 * qq) + hoff(m)] : cx<T>{T(0), T(0)};
-      B[it] = (ok && ra + 1 < nrows) ? src[wbase(2 * qq + 1) + hoff(m)] : cx<T>{T(0), T(0)};
+      const long long ho = hoff_g(mg, e);
+      A[it] = (ok && ra < nrows) ? src[wbase(2 * qq) + ho] : cx<T>{T(0), T(0)};
+      B[it] = (ok && ra + 1 < nrows) ? src[wbase(2 * qq + 1) + ho] : cx<T>{T(0), T(0)};
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = lane + 64 * it;
-      const int qq = (e >> 3) % SPW, m = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      const int qq = pair_of(e), m = group_of(e, it) * kW3Group + (e & 7);
       if (e >= TOT || m >= h) continue;
       cx<T> Am = A[it], Bm = B[it];
       if (al == 2) {
         // u_2: the field carries i c / |xi| here; xi_2 of the stored half index
-        const T k2 = (T)((double)m * a.cinv[2]);
+        const T k2 = w3_xi<T>(m, a.cinv[2]);
         Am = cx<T>{k2 * Am.re, k2 * Am.im};
         Bm = cx<T>{k2 * Bm.re, k2 * Bm.im};
       }
@@ -506,19 +540,20 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
     for (int e0 = 0; e0 < TOT; e0 += 64) {
       const int e = e0 + lane;
       if (TOT % 64 != 0 && e >= TOT) break;
-      const int qq = (e >> 3) % SPW, k = ((e >> 3) / SPW) * kW3Group + (e & 7);
+      const int qq = pair_of(e), mg = group_of(e, e0 / 64), k = mg * kW3Group + (e & 7);
       const long long ra = wrow + 2 * qq;
+      const long long ho = hoff_g(mg, e);
       cx<T> oa = {T(0), T(0)}, ob = {T(0), T(0)};
       if (k < h) {
         const cx<T>* sq = wseq + qq * N2;
         const cx<T> Y = sq[k];
         const cx<T> Ym = sq[k == 0 ? 0 : N2 - k];
-        const T half = al == 2 ? T(0.5 * (double)k * a.cinv[2]) : T(0.5);
+        const T half = al == 2 ? T(0.5) * w3_xi<T>(k, a.cinv[2]) : T(0.5);
         oa = cx<T>{(Y.re + Ym.re) * half, (Y.im - Ym.im) * half};
         ob = cx<T>{(Y.im + Ym.im) * half, (Ym.re - Y.re) * half};
       }
-      if (ra < nrows) dst[wbase(2 * qq) + hoff(k)] = oa;
-      if (ra + 1 < nrows) dst[wbase(2 * qq + 1) + hoff(k)] = ob;
+      if (ra < nrows) dst[wbase(2 * qq) + ho] = oa;
+      if (ra + 1 < nrows) dst[wbase(2 * qq + 1) + ho] = ob;
     }
   }
 }
@@ -554,8 +589,8 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   const long long htile = vo + ((long long)cg * N1 + b) * kW3Group;
   const long long hstep = (long long)G * N1 * kW3Group;
   const long long vcol = vo + ((long long)(b * G + cg) * kW3Group + cc) * N0;
-  const double x1 = (double)w3_freq(b, N1) * a.cinv[1];
-  const double x2 = (double)c * a.cinv[2];
+  const T x1 = w3_xi<T>(w3_freq(b, N1), a.cinv[1]);
+  const T x2 = w3_xi<T>(c, a.cinv[2]);
   const bool col_ok = c < a.h;
   // t = xi . tau_hat over the components; the factor 1 / |xi| of khat is
   // applied once at the end (fewer registers live across the transforms)
@@ -574,7 +609,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
 #pragma unroll
       for (int r = 0; r < 9; ++r) {
         // field 0 carries tau_0 (times xi_0 here), field 1 xi_1 tau_1 + xi_2 tau_2
-        const T k = al == 0 ? (T)((double)w3_freq(j + LPS * r, N0) * a.cinv[0]) : T(1);
+        const T k = al == 0 ? w3_xi<T>(w3_freq(j + LPS * r, N0), a.cinv[0]) : T(1);
         t[r].re += k * z[r].re;
         t[r].im += k * z[r].im;
       }
@@ -590,9 +625,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
     for (int r = 0; r < 9; ++r) bv[r] = a.base ? ld_stream(a.base + vcol + j + LPS * r) : cx<T>{T(0), T(0)};
 #pragma unroll
     for (int r = 0; r < 9; ++r) {
-      const double x0 = (double)w3_freq(j + LPS * r, N0) * a.cinv[0];
-      const double k2 = x0 * x0 + x1 * x1 + x2 * x2;
-      const T csk = cs * (T)((col_ok && k2 > 0.0) ? 1.0 / sqrt(k2) : 0.0);
+      const T csk = cs * w3_inv_norm<T>(w3_xi<T>(w3_freq(j + LPS * r, N0), a.cinv[0]), x1, x2, col_ok);
       // s = -i khat . tau_hat
       cx<T> val = {csk * t[r].im, -csk * t[r].re};
       val.re += a.coef_base * bv[r].re;
