@@ -116,14 +116,28 @@ __device__ __forceinline__ V w3_pick(const V (&arr)[kMaxDim], int c) {
 // consecutive threads on each 128-byte row.  tile_load multiplies point p by
 // xi = freq(p) * ks when ks != 0.
 template <typename T, int L, int NT>
-__device__ __forceinline__ void tile_load(cx<T>* seq, const cx<T>* __restrict__ g, long long pstride, double ks) {
-  constexpr int TOT = kW3Group * L, PER = (TOT + NT - 1) / NT;
+struct TileRegs {
+  static constexpr int TOT = kW3Group * L, PER = (TOT + NT - 1) / NT;
   cx<T> v[PER];
+};
+
+// tile_load in two halves: the global loads into registers, then the LDS
+// stores (so that other loads, such as the twiddle table's, can go out
+// between them)
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_fetch(TileRegs<T, L, NT>& t, const cx<T>* __restrict__ g, long long pstride) {
+  constexpr int TOT = TileRegs<T, L, NT>::TOT, PER = TileRegs<T, L, NT>::PER;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = (int)threadIdx.x + u * NT;
-    v[u] = (TOT % NT == 0 || e < TOT) ? g[(long long)(e >> 3) * pstride + (e & 7)] : cx<T>{T(0), T(0)};
+    t.v[u] = (TOT % NT == 0 || e < TOT) ? g[(long long)(e >> 3) * pstride + (e & 7)] : cx<T>{T(0), T(0)};
   }
+}
+
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_put(cx<T>* seq, const TileRegs<T, L, NT>& t, double ks) {
+  constexpr int TOT = TileRegs<T, L, NT>::TOT, PER = TileRegs<T, L, NT>::PER;
+  const cx<T>* v = t.v;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = (int)threadIdx.x + u * NT;
@@ -131,12 +145,19 @@ __device__ __forceinline__ void tile_load(cx<T>* seq, const cx<T>* __restrict__ 
       const int pt = e >> 3, cc = e & 7;
       cx<T> x = v[u];
       if (ks != 0.0) {
-        const T k = (T)((double)w3_freq(pt, L) * ks);
+        const T k = w3_xi<T>(w3_freq(pt, L), ks);
         x = cx<T>{k * x.re, k * x.im};
       }
       seq[cc * L + pt] = x;
     }
   }
+}
+
+template <typename T, int L, int NT>
+__device__ __forceinline__ void tile_load(cx<T>* seq, const cx<T>* __restrict__ g, long long pstride, double ks) {
+  TileRegs<T, L, NT> t;
+  tile_fetch<T, L, NT>(t, g, pstride);
+  tile_put<T, L, NT>(seq, t, ks);
 }
 
 template <typename T, int L, int NT>
@@ -149,9 +170,16 @@ __device__ __forceinline__ void tile_store(cx<T>* __restrict__ g, long long pstr
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void stage_twiddles(cx<T>* tw, const cx<T>* __restrict__ src, int n, int nt) {
-  for (int i = threadIdx.x; i < n; i += nt) tw[i] = src[i];
+// The twiddle table in two halves, one entry per thread (N <= NT): the load
+// goes out with the block's other loads, the LDS store comes after them.
+template <typename T, int N, int NT>
+__device__ __forceinline__ cx<T> tw_fetch(const cx<T>* __restrict__ src) {
+  static_assert(N <= NT, "one twiddle entry per thread");
+  return (int)threadIdx.x < N ? src[threadIdx.x] : cx<T>{T(0), T(0)};
+}
+template <typename T, int N>
+__device__ __forceinline__ void tw_put(cx<T>* tw, cx<T> v) {
+  if ((int)threadIdx.x < N) tw[threadIdx.x] = v;
 }
 
 }  // namespace
@@ -208,7 +236,9 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_inv0_kernel(W3Args<T>
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  stage_twiddles(tw, a.tw[0], N0, NT);
+  // the table is staged first: the block barrier then comes before the
+  // column's loads, and each wave runs on to its transforms on its own
+  tw_put<T, N0>(tw, tw_fetch<T, N0, NT>(a.tw[0]));
   __syncthreads();
   cx<T>* buf = tw + N0 + (w * CPW + (act ? s : 0)) * N0;
   const long long gtile = vo + (long long)(b * G + cg) * N0 * kW3Group;
@@ -284,7 +314,6 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   cx<T>* seq = tw + N1;
-  stage_twiddles(tw, a.tw[1], N1, NT);
   const int G = a.G, N0 = a.N0;
   // block = (tile, output field), the field fastest: inverse u_0, u_1, u_2;
   // forward the two fields the axis-0 pass takes
@@ -303,15 +332,22 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
   const long long gtile = vo + ((long long)cg * N0 + ai) * kW3Group;
   const long long gstep = (long long)G * N0 * kW3Group;
   if constexpr (DIR > 0) {
-    // u_0 from field 0; u_1 (times xi_1 of the input index) and u_2 from field 1
-    tile_load<T, N1, NT>(seq, (al == 0 ? a.gl[0] : a.gl[1]) + gtile, gstep, al == 1 ? a.cinv[1] : 0.0);
+    // u_0 from field 0; u_1 (times xi_1 of the input index) and u_2 from field 1;
+    // the tile's loads go out before the twiddle table is staged
+    TileRegs<T, N1, NT> t;
+    tile_fetch<T, N1, NT>(t, (al == 0 ? a.gl[0] : a.gl[1]) + gtile, gstep);
+    tw_put<T, N1>(tw, tw_fetch<T, N1, NT>(a.tw[1]));
+    tile_put<T, N1, NT>(seq, t, al == 1 ? a.cinv[1] : 0.0);
     __syncthreads();
     wave_fft_lds<T, N1, DIR>(buf, tw, j, act);
     __syncthreads();
     tile_store<T, N1, NT>(w3_pick(a.hl, al) + htile, kW3Group, seq);
   } else {
     // field 0: F1 tau_0; field 1: xi_1 F1 tau_1 + F1 (xi_2 tau_2), written over tau_1
-    tile_load<T, N1, NT>(seq, (al == 0 ? a.hl[0] : a.hl[1]) + htile, kW3Group, 0.0);
+    TileRegs<T, N1, NT> t;
+    tile_fetch<T, N1, NT>(t, (al == 0 ? a.hl[0] : a.hl[1]) + htile, kW3Group);
+    tw_put<T, N1>(tw, tw_fetch<T, N1, NT>(a.tw[1]));
+    tile_put<T, N1, NT>(seq, t, 0.0);
     __syncthreads();
     wave_fft_lds<T, N1, DIR>(buf, tw, j, act);
     if (al == 1) {
@@ -319,7 +355,7 @@ __global__ __launch_bounds__(w3_col_threads<N1>()) void w3_col1_kernel(W3Args<T>
       if (act) {
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-          const T k1 = (T)((double)w3_freq(j + LPS * r, N1) * a.cinv[1]);
+          const T k1 = w3_xi<T>(w3_freq(j + LPS * r, N1), a.cinv[1]);
           const cx<T> z = buf[j + LPS * r];
           acc[r] = cx<T>{k1 * z.re, k1 * z.im};
         }
@@ -369,25 +405,6 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
   const long long nvox = nrows * N2;
   const uint8_t* phase = pe ? pe->phase : a.phase;
   const long long row0 = (long long)rb * RB;
-  stage_twiddles(tw, a.tw[2], N2, 256);
-  const T* csrc = a.cond + (long long)pb * kCondStride;
-  for (int i = threadIdx.x; i < a.n_phases; i += 256) cond[i] = csrc[i];
-  {
-    const long long rows_here = nrows - row0 < RB ? nrows - row0 : RB;
-    const int nb = (int)(rows_here * N2);
-    const uint8_t* src = phase + row0 * N2;
-    if ((reinterpret_cast<uintptr_t>(src) & 3u) == 0) {
-      const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
-      uint32_t* d4 = reinterpret_cast<uint32_t*>(phs);
-      for (int i = threadIdx.x; i < nb / 4; i += 256) d4[i] = s4[i];
-      for (int i = (nb / 4) * 4 + threadIdx.x; i < nb; i += 256) phs[i] = src[i];
-    } else {
-      for (int i = threadIdx.x; i < nb; i += 256) phs[i] = src[i];
-    }
-  }
-  __syncthreads();
-  const T l0 = pe ? (T)pe->l0 : a.l0;
-  const T Ea = (a.flags & ROWF_STATE_E) ? (T)st->E[al] : w3_pick(a.E, al);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int s = lane / LPS, j = lane - s * LPS;
   const bool lane_ok = s < SPW;
@@ -425,6 +442,59 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
   };
   // entry offset of half index mg 8 + (e & 7) within its row
   auto hoff_g = [&](int mg, int e) -> long long { return (long long)mg * N1 * kW3Group + (e & 7); };
+  // the wave's half-spectrum entries (not in the forward-from-real mode) are
+  // requested before the block stages its tables, so both latencies overlap
+  constexpr int HP = w3_groups(N2 / 2 + 1) * kW3Group;  // padded half length
+  constexpr int TOT = SPW * HP;                          // entries of the wave's rows
+  constexpr int IT = (TOT + 63) / 64;
+  const long long wrow = (long long)rb * RB + (long long)w * SPW * 2;  // the wave's first row
+  cx<T> A[IT], B[IT];
+  if constexpr (MODE != ROW_FWD) {
+    const cx<T>* src = w3_pick(a.hl, al);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = lane + 64 * it;
+      const int qq = pair_of(e), mg = group_of(e, it), m = mg * kW3Group + (e & 7);
+      const long long ra = wrow + 2 * qq;
+      const bool ok = e < TOT && m < h;
+      const long long ho = hoff_g(mg, e);
+      A[it] = (ok && ra < nrows) ? src[wbase(2 * qq) + ho] : cx<T>{T(0), T(0)};
+      B[it] = (ok && ra + 1 < nrows) ? src[wbase(2 * qq + 1) + ho] : cx<T>{T(0), T(0)};
+    }
+  }
+  // the block's tables: twiddles, conductivities, the phase bytes of its rows
+  // (as words when aligned); every load is issued before the LDS stores
+  const cx<T> twv = tw_fetch<T, N2, 256>(a.tw[2]);
+  const T* csrc = a.cond + (long long)pb * kCondStride;
+  {
+    const long long rows_here = nrows - row0 < RB ? nrows - row0 : RB;
+    const int nb = (int)(rows_here * N2);
+    const uint8_t* src = phase + row0 * N2;
+    if ((reinterpret_cast<uintptr_t>(src) & 3u) == 0) {
+      constexpr int PW = (RB * N2 / 4 + 255) / 256;  // phase words per thread
+      const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
+      uint32_t* d4 = reinterpret_cast<uint32_t*>(phs);
+      uint32_t pw[PW];
+#pragma unroll
+      for (int u = 0; u < PW; ++u) {
+        const int i = (int)threadIdx.x + 256 * u;
+        pw[u] = i < nb / 4 ? s4[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < PW; ++u) {
+        const int i = (int)threadIdx.x + 256 * u;
+        if (i < nb / 4) d4[i] = pw[u];
+      }
+      for (int i = (nb / 4) * 4 + threadIdx.x; i < nb; i += 256) phs[i] = src[i];
+    } else {
+      for (int i = threadIdx.x; i < nb; i += 256) phs[i] = src[i];
+    }
+  }
+  for (int i = threadIdx.x; i < a.n_phases; i += 256) cond[i] = csrc[i];
+  tw_put<T, N2>(tw, twv);
+  __syncthreads();
+  const T l0 = pe ? (T)pe->l0 : a.l0;
+  const T Ea = (a.flags & ROWF_STATE_E) ? (T)st->E[al] : w3_pick(a.E, al);
   cx<T> v[9];
   if constexpr (MODE == ROW_FWD) {
     // real rows in (or the constant E), times dL when asked
@@ -449,23 +519,7 @@ __global__ __launch_bounds__(256) void w3_row_kernel(W3Args<T> a) {
     // each stored half-spectrum entry m < h of the wave's rows is read once
     // (eight consecutive lanes on one 128-byte group of a row) and placed at
     // m and (its Hermitian image) N2 - m of the packed sequence
-    const cx<T>* src = w3_pick(a.hl, al);
-    constexpr int HP = w3_groups(N2 / 2 + 1) * kW3Group;  // padded half length
-    constexpr int TOT = SPW * HP;                          // entries of the wave's rows
-    constexpr int IT = (TOT + 63) / 64;
-    const long long wrow = (long long)rb * RB + (long long)w * SPW * 2;  // the wave's first row
     cx<T>* wseq = tw + N2 + w * SPW * N2;
-    cx<T> A[IT], B[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = lane + 64 * it;
-      const int qq = pair_of(e), mg = group_of(e, it), m = mg * kW3Group + (e & 7);
-      const long long ra = wrow + 2 * qq;
-      const bool ok = e < TOT && m < h;
-      const long long ho = hoff_g(mg, e);
-      A[it] = (ok && ra < nrows) ? src[wbase(2 * qq) + ho] : cx<T>{T(0), T(0)};
-      B[it] = (ok && ra + 1 < nrows) ? src[wbase(2 * qq + 1) + ho] : cx<T>{T(0), T(0)};
-    }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -573,7 +627,7 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   parts.base += (long long)pb * a.bt.pstride;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  stage_twiddles(tw, a.tw[0], N0, NT);
+  const cx<T> twv = tw_fetch<T, N0, NT>(a.tw[0]);
   __syncthreads();
   const int G = a.G, N1 = a.N1;
   const unsigned bx = blockIdx.x;
@@ -601,7 +655,10 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
 #pragma unroll 1
   for (int al = 0; al < 2; ++al) {
     __syncthreads();
-    tile_load<T, N0, NT>(tw + N0, (al == 0 ? a.hl[0] : a.hl[1]) + htile, hstep, 0.0);
+    TileRegs<T, N0, NT> tr;
+    tile_fetch<T, N0, NT>(tr, (al == 0 ? a.hl[0] : a.hl[1]) + htile, hstep);
+    if (al == 0) tw_put<T, N0>(tw, twv);
+    tile_put<T, N0, NT>(tw + N0, tr, 0.0);
     __syncthreads();
     cx<T> z[9];
     wave_fft_lds_regs<T, N0, -1>(buf, tw, j, act, z);
