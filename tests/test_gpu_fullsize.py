@@ -67,6 +67,29 @@ def test_3d_81_axis(shape):
     _fp64_parity(_two_phase(shape, 3 + sum(shape)), [1.0, 1e2], [0.3, -1.0, 0.6], 20)
 
 
+@pytest.mark.parametrize("graph_block", [0, 4])
+def test_wave_pass_every_stop_point(graph_block):
+    """The wave passes leave the CG update's x += alpha p to the next direction
+    step.  A solve stopped after n iterations ends in that step (mid-block) or
+    at the check after a block's last update, where a flush launch applies the
+    step: for n = 1..9, blocks of 4 captured iterations and eager blocks of 8,
+    the field equals the oracle's CG after n iterations."""
+    from paper_1004_1122_amd import lshom
+    shape = (27, 27, 27)
+    phase = _two_phase(shape, 91)
+    cond, E = [1.0, 50.0], [0.4, -1.0, 0.7]
+    lam = ms.lam_field(phase, cond)
+    s = lshom.Solver(phase, cond)
+    for n in range(1, 10):
+        print("n_iter", n, flush=True)
+        e, leff, info = s.solve(E, tol=0.0, max_iter=n, precision=0, allow_fail=True, graph_block=graph_block)
+        assert info["iterations"] == n and info["status"] == lshom.LSHOM_ERR_NOT_CONVERGED
+        ref = o.cg(lam, o.optimal_reference(lam), E, n_iter=n)
+        err = _rel(e.cpu().numpy(), ref["e"])
+        assert err < 1e-10, (n, err)
+    s.close()
+
+
 def test_wave_pass_batch_uneven_convergence():
     """A batch of 3-D problems on the wave passes whose contrasts differ (the
     launches drop the converged ones): every problem bit-identical to its
