@@ -5,6 +5,8 @@
 // spectral coordinate c of the admissible fields, u_hat = i khat c, and one
 // apply is
 //   axis-0 inverse (W3_INV0): c -> F0^-1 [i xi_0 c / |xi|], F0^-1 [i c / |xi|]   V -> Gl
+//                             (CG: also p = r + beta p and the x step the
+//                             last update left to it)
 //   axis-1 inverse (W3_COL1): F1^-1, u_1 also times xi_1                Gl -> Hl
 //   row pass       (W3_ROW):  u_2 times xi_2, F2^-1, dL (E + u), F2,
 //                             tau_2 times xi_2                          Hl -> Hl
@@ -21,10 +23,11 @@
 //
 // Every 1-D transform is a wave-level FFT (wave_fft.hpp): a block is a few
 // independent waves, each owning whole sequences, with one block barrier
-// after the twiddle table is staged.  A block owns one tile (8 columns of
-// one cg group, all points of the transformed axis) and writes it as one
-// contiguous region of its output layout; reads are strided in 128-byte
-// rows (column passes) or contiguous.
+// once the twiddle table (and the tile) are in LDS; the loads of a block's
+// data go out before its tables are stored, so their latencies overlap.  A
+// block owns one tile (8 columns of one cg group, all points of the
+// transformed axis) and writes it as one contiguous region of its output
+// layout; reads are strided in 128-byte rows (column passes) or contiguous.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -651,7 +654,6 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
   cx<T> t[9];
 #pragma unroll
   for (int r = 0; r < 9; ++r) t[r] = cx<T>{T(0), T(0)};
-  (void)x1;
 #pragma unroll 1
   for (int al = 0; al < 2; ++al) {
     __syncthreads();

@@ -32,11 +32,40 @@ KERNEL_SOURCES = ("passes.hip", "wave3d.hip", "wave_fft.hpp", "fft_engine.hpp", 
                   "radix_consts.hpp")
 
 
+def code_only(text):
+    """C++ source without its comments and blank lines, each line stripped of
+    surrounding white space (string and character literals kept as they are),
+    so that an edit of the comments does not change the hash of the code."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    lines = (line.strip() for line in "".join(out).split("\n"))
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash():
+    """Hash of the code of the kernel sources (comments and layout excluded):
+    a traffic summary taken on other code does not describe these kernels."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(HERE, "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(HERE, "csrc", name), encoding="utf-8") as f:
+            h.update(code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
