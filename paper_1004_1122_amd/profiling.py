@@ -188,6 +188,54 @@ def traffic(args):
     print("\n".join(lines))
 
 
+def issue(args):
+    """SQ counters of the pass kernels per dispatch, inside each form's marker
+    window (window 1: FP64, 2: mixed), with the time their VALU instructions
+    take to issue against the pass time that pass_profile measured.  A wave64
+    VALU instruction occupies its SIMD for 4 cycles (FP32 as FP64, the packed
+    forms unused), so SQ_INSTS_VALU x 4 / (SIMDs x clock) is the time the
+    VALU needs if every SIMD issues back to back."""
+    counters = [c for c in args.counters.split(",") if c]
+    pattern = os.path.join(args.dir, "**", "*counter_collection.csv")
+    per = {c: _counter_sums(pattern, c) for c in counters}
+    with open(args.passes) as f:
+        pj = json.load(f)
+    kernels = [kv.split("=", 1) for kv in args.kernel]
+    mre = re.compile(args.marker)
+    lines = [f"# {args.title}", "", "Commands (GPU box, repository root in $R):", "", "```"] + args.command + ["```", ""]
+    if args.note:
+        lines += [args.note, ""]
+    lines += ["| Form | Pass | µs per launch | Waves | VALU instr. per wave | LDS instr. per wave | "
+              "VALU issue µs | VALU issue / pass time | LDS bank-conflict / LDS-active cycles |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    recs = []
+    for win, (form, tname) in enumerate((("fp64", "double"), ("mixed", "float")), start=1):
+        wc = {c: _window(per[c], mre, win) for c in counters}
+        for pname, rx in kernels:
+            kre = re.compile(rx.format(t=tname))
+            vals = {c: [v for (name, _), v in wc[c].items() if kre.search(name)] for c in counters}
+            if not all(vals.values()):
+                continue
+            m = {c: statistics.mean(v) for c, v in vals.items()}
+            us = pj["forms"][form]["passes"][pname]["ms"] * 1e3
+            waves = m.get("SQ_WAVES", 0.0)
+            valu_us = m.get("SQ_INSTS_VALU", 0.0) * 4.0 / (args.simds * args.clock_ghz * 1e3)
+            lds_act = m.get("SQ_ACTIVE_INST_LDS", 0.0)
+            conf = m.get("SQ_LDS_BANK_CONFLICT", 0.0) / lds_act if lds_act else float("nan")
+            rec = {"form": form, "pass": pname, "us": us, "dispatches": len(vals[counters[0]])}
+            rec.update(m)
+            recs.append(rec)
+            lines.append(f"| {form} | {pname} | {us:.1f} | {waves:.0f} | "
+                         f"{m.get('SQ_INSTS_VALU', 0.0) / max(waves, 1.0):.0f} | "
+                         f"{m.get('SQ_INSTS_LDS', 0.0) / max(waves, 1.0):.0f} | {valu_us:.1f} | "
+                         f"{valu_us / us:.2f} | {conf:.3f} |")
+    lines += ["", f"Model: {args.simds} SIMDs at {args.clock_ghz} GHz, 4 cycles per wave64 VALU instruction.", "",
+              "issue-json: " + json.dumps({"source_hash": kernel_source_hash(), "passes": recs}), ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -211,8 +259,22 @@ def main():
     t.add_argument("--window", type=int, default=0)
     t.add_argument("--marker", default=r"AbsFunctor")
     t.add_argument("--out", required=True)
+    i = sub.add_parser("issue")
+    i.add_argument("--dir", required=True)
+    i.add_argument("--passes", required=True, help="pass_profile JSON of the same workload")
+    i.add_argument("--kernel", action="append", required=True,
+                   help="pass=regex ({t} stands for the element type), repeated")
+    i.add_argument("--counters", default="SQ_WAVES,SQ_INSTS_VALU,SQ_INSTS_LDS,SQ_ACTIVE_INST_LDS,"
+                                         "SQ_LDS_BANK_CONFLICT,SQ_BUSY_CYCLES,SQ_WAVE_CYCLES,SQ_ACTIVE_INST_VALU")
+    i.add_argument("--simds", type=int, default=1024)
+    i.add_argument("--clock-ghz", type=float, default=2.4)
+    i.add_argument("--marker", default=r"AbsFunctor")
+    i.add_argument("--title", required=True)
+    i.add_argument("--command", action="append", required=True)
+    i.add_argument("--note", default="")
+    i.add_argument("--out", required=True)
     a = ap.parse_args()
-    stats(a) if a.cmd == "stats" else traffic(a)
+    {"stats": stats, "traffic": traffic, "issue": issue}[a.cmd](a)
 
 
 if __name__ == "__main__":
