@@ -90,6 +90,33 @@ def test_wave_pass_every_stop_point(graph_block):
     s.close()
 
 
+@pytest.mark.parametrize("refresh_every,graph_block", [(1, 4), (3, 4), (5, 0), (7, 16)])
+def test_wave_pass_mixed_refresh_points(refresh_every, graph_block):
+    """Mixed precision on the wave passes with refreshes at many points of the
+    iteration blocks.  A refresh is requested by the direction step that owes
+    the deferred x step; that step must reach the FP32 correction before the
+    refresh folds it into the FP64 iterate.  The field meets the bar of the
+    converged oracle (FP64 true residual <= 1e-6 lambda_min / l0, field within
+    1e-6 of the exact discrete solution)."""
+    from paper_1004_1122_amd import lshom
+    shape = (27, 27, 27)
+    phase = _two_phase(shape, 93)
+    cond, E = [1.0, 1e2], [1.0, -0.5, 0.25]
+    lam = ms.lam_field(phase, cond)
+    l0 = o.optimal_reference(lam)
+    tol = 1e-6 * lam.min() / l0
+    s = lshom.Solver(phase, cond)
+    e, leff, info = s.solve(E, tol=tol, precision=1, refresh_every=refresh_every, graph_block=graph_block)
+    print("refresh_every", refresh_every, "graph_block", graph_block, "iterations", info["iterations"],
+          "refreshes", info["refreshes"], flush=True)
+    assert info["status"] == 0 and info["refreshes"] >= info["iterations"] // refresh_every
+    assert info["rel_res_true"] <= tol * 1.0001
+    exact = o.cg(lam, l0, E, tol=1e-13, max_iter=20000)
+    err = _rel(e.cpu().numpy(), exact["e"])
+    assert err <= 1e-6, err
+    s.close()
+
+
 def test_wave_pass_batch_uneven_convergence():
     """A batch of 3-D problems on the wave passes whose contrasts differ (the
     launches drop the converged ones): every problem bit-identical to its
