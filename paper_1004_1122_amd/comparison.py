@@ -18,10 +18,15 @@ FP64 through the C ABI:
 * ``progress``: (eta_r, eta_e) of every iterate for rho = 10 and 1e3, with
   the observed mean contraction beside the bounds of Eq. (23).
 
+With --methods it times instead every method of the library (CG in FP64 and
+mixed precision, the basic scheme, BiCG, pipelined CG) on the 729^2 circle
+cell and the 243^3 sphere cell.
+
 The eta_r test of Eq. (22) is l0 ||r|| / ||e0|| <= eps, i.e. the solver's
 relative residual test with tol = eps / l0.
 
   python -m paper_1004_1122_amd.comparison --out comparison.json
+  python -m paper_1004_1122_amd.comparison --methods --out methods.json
 """
 
 from __future__ import annotations
@@ -139,14 +144,66 @@ def progress(lshom, n, rho, max_iter):
     return out
 
 
+def methods(lshom, tol=1e-6, reps=2, cap_ffth=400):
+    """Every method of the library on two cells, FP64 unless noted, to the
+    relative residual tol: the 729^2 circle cell (contrast 1e2) and the 243^3
+    sphere cell (contrast 1e3).  The basic scheme runs cap_ffth steps (it
+    needs thousands at these contrasts); its time per step is what is
+    compared.  Device-resident inputs, wall time of the blocking solve, best
+    of `reps` after a warm-up solve."""
+    import torch
+    cells = [("729x729 circles seed 2, rho 1e2", ms.circles_729(seed=2), 1e2, (1.0, 0.0)),
+             ("243^3 spheres seed 3, rho 1e3", ms.spheres_243(seed=3), 1e3, (1.0, 0.0, 0.0))]
+    runs = [("cg", dict(method=lshom.METHOD_CG)),
+            ("cg_mixed", dict(method=lshom.METHOD_CG, precision=lshom.PRECISION_MIXED)),
+            ("ffth", dict(method=lshom.METHOD_FFTH)),
+            ("bicg", dict(method=lshom.METHOD_BICG)),
+            ("pipecg", dict(method=lshom.METHOD_PIPECG))]
+    out = []
+    for name, m, rho, E in cells:
+        s = lshom.Solver(m.phase, [1.0, rho])
+        row = {"cell": name, "voxels": int(m.phase.size), "tol": tol, "methods": {}}
+        for key, kw in runs:
+            opts = dict(kw)
+            if key == "ffth":
+                opts["max_iter"] = cap_ffth
+            s.solve(E, tol=tol, want_field=False, allow_fail=True, **opts)
+            best, info = None, None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, _, info = s.solve(E, tol=tol, want_field=False, allow_fail=True, **opts)
+                dt = time.perf_counter() - t
+                best = dt if best is None else min(best, dt)
+            it = max(info["iterations"], 1)
+            row["methods"][key] = {"iterations": info["iterations"], "status": info["status"],
+                                   "rel_res_true": info["rel_res_true"], "ms": best * 1e3,
+                                   "us_per_iteration": best * 1e6 / it,
+                                   "GVoxel_iters_per_s": m.phase.size * it / best / 1e9}
+            log(f"{name} {key}: {info['iterations']} iterations, {best * 1e3:.1f} ms, "
+                f"{best * 1e6 / it:.1f} us per iteration")
+        s.close()
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--methods", action="store_true",
+                    help="only the per-method timing on the 729^2 and 243^3 cells")
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--out", default=None)
     ap.add_argument("--max-iter", type=int, default=200000)
     ap.add_argument("--quick", action="store_true", help="fewer cases (a smoke run)")
     args = ap.parse_args()
     from . import lshom
+    if args.methods:
+        report = {"methods": methods(lshom)}
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(report, f)
+        print(json.dumps(report), flush=True)
+        return
     n = args.n
     if args.quick:
         omegas, rhos_om, rhos_c = [0.5, 1.0], [10.0], [10.0, 100.0]
