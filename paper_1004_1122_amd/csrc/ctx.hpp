@@ -176,7 +176,7 @@ lshom_status solve_bicg(Group& g, const DevState& init, const lshom_solve_opts& 
 lshom_status solve_pipecg(Group& g, const DevState& init, const lshom_solve_opts& o, double* e_out);
 lshom_status time_passes(Group& g, int precision, int reps, double* ms_out, double* bytes_out);
 // Algorithmic HBM bytes of each pass class for one problem and one CG iteration.
-void pass_model_bytes(const Group& g, int precision, double* out);
+void pass_model_bytes(const Group& g, int precision, double* out, bool basic_scheme = false);
 
 lshom_status fail(lshom_ctx* c, lshom_status s, const std::string& msg);
 // Serialises graph captures against host-staged uploads and events on the

@@ -1069,9 +1069,9 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
     }
   } eq_reset{g};
   g.eq = !mixed && (o.norm == LSHOM_NORM_EQUILIBRIUM || o.history_dev != nullptr);
-  // CG on a qualifying 3-D grid with an isotropic reference runs the wave
-  // passes (the basic scheme and the equilibrium sums keep the block passes)
-  g.w3 = g.w3ok && !g.eq && !ffth && !g.aniso && !g.tensor;
+  // CG and the basic scheme on a qualifying 3-D grid with an isotropic
+  // reference run the wave passes (the equilibrium sums keep the block passes)
+  g.w3 = g.w3ok && !g.eq && !g.aniso && !g.tensor;
   bool odd = true;
   for (int a = 0; a < g.d; ++a) odd = odd && (g.N[a] & 1);
   const int eq_final = odd ? 1 : 0;
@@ -1166,7 +1166,7 @@ lshom_status solve_group(Group& g, const std::vector<DevState>& init, const lsho
   const bool adapt = o.norm == LSHOM_NORM_RESIDUAL;
   if (tm.on) {
     tm.kinds.clear();
-    pass_model_bytes(g, o.precision, tm.unit_bytes);
+    pass_model_bytes(g, o.precision, tm.unit_bytes, ffth);
   }
   lshom_status s;
   // the blocks take the buffers (and launch shapes) current when they are
@@ -1433,7 +1433,7 @@ lshom_status solve_pipecg(Group& g, const DevState& init, const lshom_solve_opts
 // Per-kernel timing of one CG iteration's launches
 // ---------------------------------------------------------------------------
 
-void pass_model_bytes(const Group& g, int precision, double* out) {
+void pass_model_bytes(const Group& g, int precision, double* out, bool basic_scheme) {
   const double cs = precision == LSHOM_PRECISION_FP64 ? (double)sizeof(cx<double>) : (double)sizeof(cx<float>);
   const double nh = (double)g.nhalf;
   const int d = g.d;
@@ -1461,6 +1461,12 @@ void pass_model_bytes(const Group& g, int precision, double* out) {
     out[LSHOM_PASS_AXIS1_INVERSE] = 5.0 * nh * cs;
     out[LSHOM_PASS_AXIS1_FORWARD] = 5.0 * nh * cs;
     out[LSHOM_PASS_AXIS0_FORWARD] = 4.0 * nh * cs;
+  }
+  if (basic_scheme) {
+    // one apply per step: the axis-0 inverse reads the iterate c and writes
+    // the pass fields (two on the wave passes, d on the block passes); no update
+    out[LSHOM_PASS_AXIS0_INVERSE] = (1.0 + (g.w3 ? 2.0 : (double)d)) * nh * cs;
+    out[LSHOM_PASS_UPDATE] = 0.0;
   }
 }
 

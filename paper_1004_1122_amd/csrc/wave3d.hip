@@ -703,8 +703,15 @@ __global__ __launch_bounds__(w3_col_threads<N0>()) void w3_fwd0_kernel(W3Args<T>
       val.re += a.coef_base * bv[r].re;
       val.im += a.coef_base * bv[r].im;
       a.out[vcol + j + LPS * r] = val;
-      if (a.dot == 1) acc += wgt * ((double)bv[r].re * (double)val.re + (double)bv[r].im * (double)val.im);
-      else if (a.dot == 2) acc += wgt * ((double)val.re * (double)val.re + (double)val.im * (double)val.im);
+      if (a.dot == 1) {
+        acc += wgt * ((double)bv[r].re * (double)val.re + (double)bv[r].im * (double)val.im);
+      } else if (a.dot == 2) {
+        acc += wgt * ((double)val.re * (double)val.re + (double)val.im * (double)val.im);
+      } else if (a.dot == 3) {
+        // the step |out - base|^2 of the basic scheme
+        const double dr = (double)val.re - (double)bv[r].re, di = (double)val.im - (double)bv[r].im;
+        acc += wgt * (dr * dr + di * di);
+      }
     }
   }
   if (a.dot) {

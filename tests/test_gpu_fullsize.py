@@ -117,6 +117,42 @@ def test_wave_pass_mixed_refresh_points(refresh_every, graph_block):
     s.close()
 
 
+@pytest.mark.parametrize("shape", [(27, 27, 27), (27, 81, 27)], ids=lambda s: "x".join(map(str, s)))
+def test_wave_pass_basic_scheme(shape):
+    """The basic scheme (Sec. 2.3) on the wave passes, the step norm reduced
+    in the axis-0 forward pass: the oracle's iteration count and its field
+    within 1e-10."""
+    from paper_1004_1122_amd import lshom
+    print("case", shape, flush=True)
+    phase = _two_phase(shape, 95)
+    cond, E = [1.0, 20.0], [0.0, 1.0, 0.5]
+    lam = ms.lam_field(phase, cond)
+    s = lshom.Solver(phase, cond)
+    e, leff, info = s.solve(E, tol=1e-6, method=lshom.METHOD_FFTH)
+    ref = o.ffth(lam, o.optimal_reference(lam), E, tol=1e-6)
+    assert info["status"] == 0 and info["iterations"] == ref["iterations"], (info["iterations"], ref["iterations"])
+    err = _rel(e.cpu().numpy(), ref["e"])
+    assert err < 1e-10, err
+    s.close()
+
+
+def test_wave_pass_basic_scheme_batch_equals_single():
+    from paper_1004_1122_amd import lshom
+    shape = (27, 27, 27)
+    probs = [dict(phase=_two_phase(shape, 96 + i), cond=[1.0, rho], E=[1.0, 0.0, 0.5], tol=1e-7, want_field=True)
+             for i, rho in enumerate([3.0, 30.0])]
+    bs = lshom.BatchSolver()
+    bs.prepare(probs, precision=0)
+    fields, leffs, infos = bs.run(method=lshom.METHOD_FFTH, max_iter=50000)
+    for i, pr in enumerate(probs):
+        s = lshom.Solver(pr["phase"], pr["cond"])
+        e, leff, info = s.solve(pr["E"], tol=pr["tol"], method=lshom.METHOD_FFTH, max_iter=50000)
+        assert infos[i]["status"] == 0 and infos[i]["iterations"] == info["iterations"], i
+        assert torch.equal(fields[i], e) and np.array_equal(leffs[i, :3], leff), i
+        s.close()
+    bs.close()
+
+
 def test_wave_pass_batch_uneven_convergence():
     """A batch of 3-D problems on the wave passes whose contrasts differ (the
     launches drop the converged ones): every problem bit-identical to its
