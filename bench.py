@@ -311,8 +311,8 @@ def main():
                     help="after the run, copy a device buffer of this size (the counter calibration kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has "
-              "no multi-GPU path in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver runs each "
+              "problem on one GPU and has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
 

@@ -50,7 +50,7 @@ typedef int32_t lshom_status;
 #define LSHOM_ERR_HIP (-4)           /* a HIP runtime call failed */
 #define LSHOM_ERR_NOT_CONVERGED (-5) /* max_iter reached; last iterate returned */
 #define LSHOM_ERR_BREAKDOWN (-6)     /* (p, A p) <= 0 or not finite; last iterate returned */
-#define LSHOM_ERR_UNSUPPORTED (-7)   /* valid input outside what this build handles */
+#define LSHOM_ERR_UNSUPPORTED (-7)   /* valid input outside what the library handles */
 
 #define LSHOM_PRECISION_FP64 0  /* every step in FP64 */
 #define LSHOM_PRECISION_MIXED 1 /* FP32 operator and vectors, FP64 dots and refresh */

@@ -102,7 +102,7 @@ def stats(args):
             rec["dur"].append(dur)
         if grid and wg:
             rec["shapes"].add((tuple(g // w for g, w in zip(grid, wg)), wg[0]))
-    lines = [f"# {args.title}", "", "Command (GPU box, repository root in $R):", "", "```", args.command, "```", ""]
+    lines = [f"# {args.title}", "", "Command (on the GPU host, repository root in $R):", "", "```", args.command, "```", ""]
     if args.note:
         lines += [args.note, ""]
     lines += ["| Kernel | Calls | Total ns | Average ns | Median ns | Min ns | Max ns | % | Blocks x threads |",
@@ -173,7 +173,7 @@ def traffic(args):
     }
     lines = [
         f"# HBM traffic of `{args.kernel}` ({args.pass_name}, {args.form})", "",
-        "Counter runs (GPU box, repository root in $R):", "", "```", args.command_fetch, args.command_write, "```", "",
+        "Counter runs (on the GPU host, repository root in $R):", "", "```", args.command_fetch, args.command_write, "```", "",
         f"Calibration: the copy kernel matching `{args.copy}` reads and writes {args.copy_bytes} bytes; "
         f"FETCH_SIZE read {max(cf):.0f} KiB (scale {fetch_scale:.4f}), WRITE_SIZE {max(cw):.0f} KiB "
         f"(scale {write_scale:.4f}).", "",
@@ -202,7 +202,7 @@ def issue(args):
         pj = json.load(f)
     kernels = [kv.split("=", 1) for kv in args.kernel]
     mre = re.compile(args.marker)
-    lines = [f"# {args.title}", "", "Commands (GPU box, repository root in $R):", "", "```"] + args.command + ["```", ""]
+    lines = [f"# {args.title}", "", "Commands (on the GPU host, repository root in $R):", "", "```"] + args.command + ["```", ""]
     if args.note:
         lines += [args.note, ""]
     lines += ["| Form | Pass | µs per launch | Waves | VALU instr. per wave | LDS instr. per wave | "
